@@ -1,0 +1,155 @@
+/*
+ * nnps.h — fixed-radius neighbour search for SPH particles on AMD MI355X (gfx950).
+ *
+ * The operation (SPH method section: Eq. 2 and the text after it, Fig. 3):
+ * given n particle positions in a box, a background cell size and a search
+ * radius R, return for every particle i the list of particles j != i with
+ * |p_j - p_i| <= R, in the exact sense of the binary64 predicate
+ *     r2 = ((dx0*dx0) + (dx1*dx1)) + (dx2*dx2) <= R*R,   dx_k = p_j[k] - p_i[k],
+ * evaluated left to right with round-to-nearest and no fused multiply-add.
+ * Rows are returned as CSR: row_ptr[n+1] (int64), col[nnz] ascending within each
+ * row (int32), dist[nnz] (float32, within 1e-6 relative of (float)sqrt(r2)).
+ *
+ * How it is computed (the relative-coordinate link list, RCLL; Mixed-precision
+ * SPH section, Eq. 5-7, Fig. 5): particles are binned into cells of width
+ * w = max(cell_size, R)(1 + 2^-30) (cell link list, Fig. 3b), sorted by cell, and
+ * stored as FP16 coordinates relative to their cell centre (Eq. 6 scale, [-1, 1]).
+ * A pair's squared distance is evaluated in FP16 from the two relative coordinates
+ * plus the integer offset of the two cells (Eq. 7, with the factor 1/2 Eq. 7 drops).
+ * Pairs whose FP16 r2 lies within a guard band of the cutoff are decided again in
+ * FP64 from the caller's positions, so the neighbour set is exactly the binary64
+ * one above. FP64 is used on the GPU only for cell assignment and that recheck.
+ *
+ * Memory: every pointer named d_* is device memory on the context's device.
+ * The caller owns positions and all outputs; the library owns the context and
+ * the cell structure (and their device scratch). A cell structure keeps a
+ * pointer to the caller's positions (the recheck reads them): they must stay
+ * alive and unchanged until the last call on that structure has completed on
+ * its stream.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the null stream). Every call is
+ * stream-ordered and returns without waiting, except where stated. Errors the
+ * device detects (positions outside the box, an output buffer too small) are
+ * recorded on the device and reported by the next call that synchronises
+ * (nnps_count with a host nnz pointer, nnps_stats_get, nnps_search).
+ *
+ * Errors: every call returns an nnps_status and never aborts or throws.
+ */
+#ifndef NNPS_H
+#define NNPS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum nnps_status {
+    NNPS_OK = 0,
+    NNPS_EINVAL = -1,         /* bad argument: see nnps_validate */
+    NNPS_EDOMAIN = -2,        /* a position is NaN/Inf or outside [lo, hi] */
+    NNPS_ENOMEM = -3,         /* device or host allocation failed */
+    NNPS_ECAPACITY = -4,      /* output capacity below nnz; *nnz_out holds the need */
+    NNPS_EDEVICE = -5,        /* a HIP runtime call failed */
+    NNPS_ETOOMANYCELLS = -6,  /* the grid would exceed 2^30 cells */
+    NNPS_EORDER = -7,         /* calls out of order (fill before count, ...) */
+    NNPS_EUNSUPPORTED = -8    /* a row longer than the library supports */
+} nnps_status;
+
+typedef enum nnps_mode {
+    NNPS_MODE_FP16_RCLL = 0,      /* FP16 relative coordinates + FP64 guard-band recheck */
+    NNPS_MODE_FP64_BASELINE = 1,  /* plain FP64 cell list (thread per particle, global loads) */
+    NNPS_MODE_RECHECK_ALL = 2     /* debug: FP16 pass plus FP64 on every candidate; the FP64
+                                     decision is used and FP16 disagreements outside the band
+                                     are counted (must be 0) */
+} nnps_mode;
+
+/* One search problem. Positions are d_pos[i*dim + k] (row-major, float64).
+ * Valid when: dim is 2 or 3; 0 <= n < 2^31; lo[k] < hi[k], all finite, for k < dim;
+ * 0 < radius <= cell_size, finite; mode is an nnps_mode. Entries lo/hi[k >= dim] are ignored. */
+typedef struct nnps_problem {
+    int32_t dim;
+    int32_t mode;
+    int64_t n;
+    double lo[3];
+    double hi[3];
+    double cell_size;
+    double radius;
+} nnps_problem;
+
+/* Statistics of the last count pass on a cell structure (nnps_stats_get). */
+typedef struct nnps_stats {
+    int64_t n;
+    int64_t nnz;                    /* total neighbour pairs (directed, self excluded) */
+    int64_t candidates;             /* pairs tested: j != i in the 3^d cells around i */
+    int64_t band_pairs;             /* FP16 r2 inside the guard band -> FP64 recheck */
+    int64_t fp16_false_pos;         /* naive FP16 test (r2_16 <= cutoff) says in, FP64 says out */
+    int64_t fp16_false_neg;         /* naive FP16 test says out, FP64 says in */
+    int64_t outside_band_disagree;  /* RECHECK_ALL only: FP16 decided outside the band but wrong */
+    int64_t heavy_rows;             /* rows handled by the long-row path */
+    int32_t dim, mode;
+    int32_t frac_bits;              /* F: fixed-point fraction bits per cell width */
+    int32_t ncell[3];
+    double cell_width;              /* w */
+    double band;                    /* guard band, in units of w^2 */
+} nnps_stats;
+
+typedef struct nnps_ctx nnps_ctx;
+typedef struct nnps_cells nnps_cells;
+
+/* Human-readable name of a status. Never NULL. */
+const char *nnps_status_str(nnps_status s);
+
+/* Host-only argument check (no device needed): NNPS_OK, NNPS_EINVAL or
+ * NNPS_ETOOMANYCELLS. Every call that takes a problem runs it first. */
+nnps_status nnps_validate(const nnps_problem *prob);
+
+/* Grid the library would use for `prob`: cell counts (ncell[3], unused axes 1),
+ * fixed-point fraction bits and cell width. Host only. */
+nnps_status nnps_grid(const nnps_problem *prob, int32_t ncell[3], int32_t *frac_bits,
+                      double *cell_width);
+
+/* Context on HIP device `device` (makes it current for the calling thread while
+ * in library calls). One context per host thread at a time. */
+nnps_status nnps_ctx_create(int device, nnps_ctx **out);
+void nnps_ctx_destroy(nnps_ctx *ctx);
+
+/* An empty cell structure; its device buffers grow on demand and are reused. */
+nnps_status nnps_cells_create(nnps_ctx *ctx, nnps_cells **out);
+void nnps_cells_destroy(nnps_cells *cells);
+
+/* Cell assignment, sort by cell, cell starts and the FP16 pack (paper: Eq. 5-6,
+ * Fig. 3b; spatial sort of the Results' memory section). d_pos: [n][dim] float64,
+ * device, caller-owned, must outlive the search. Asynchronous. */
+nnps_status nnps_cells_build(nnps_ctx *ctx, nnps_cells *cells, const nnps_problem *prob,
+                             const double *d_pos, void *stream);
+
+/* Count pass: writes d_row_ptr[0..n] (device int64, caller-owned, n+1 entries).
+ * If h_nnz is not NULL, waits for the stream and stores nnz = row_ptr[n] there
+ * (and reports device-detected errors); with h_nnz NULL it does not wait. */
+nnps_status nnps_count(nnps_ctx *ctx, nnps_cells *cells, int64_t *d_row_ptr, int64_t *h_nnz,
+                       void *stream);
+
+/* Fill pass: writes col and dist (device, caller-owned, `capacity` entries each)
+ * using the row_ptr written by nnps_count on the same structure. If row_ptr[n]
+ * exceeds capacity nothing past capacity is written and NNPS_ECAPACITY is
+ * reported at the next synchronising call. Asynchronous. */
+nnps_status nnps_fill(nnps_ctx *ctx, nnps_cells *cells, const int64_t *d_row_ptr,
+                      int32_t *d_col, float *d_dist, int64_t capacity, void *stream);
+
+/* Build + count + fill in one call; synchronises once (after the count) to learn
+ * nnz. If capacity < nnz it returns NNPS_ECAPACITY with *nnz_out = nnz and writes
+ * only row_ptr. */
+nnps_status nnps_search(nnps_ctx *ctx, nnps_cells *cells, const nnps_problem *prob,
+                        const double *d_pos, int64_t *d_row_ptr, int32_t *d_col, float *d_dist,
+                        int64_t capacity, int64_t *nnz_out, void *stream);
+
+/* Waits for the stream, then copies the statistics of the last count pass.
+ * Returns any device-detected error (NNPS_EDOMAIN, NNPS_ECAPACITY, NNPS_EUNSUPPORTED). */
+nnps_status nnps_stats_get(nnps_cells *cells, nnps_stats *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NNPS_H */

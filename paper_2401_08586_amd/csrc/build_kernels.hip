@@ -1,0 +1,423 @@
+// Cell build: FP64 cell assignment, a stable LDS radix sort by cell, cell starts by
+// a device-wide scan, the FP16 relative-coordinate pack and the work-block table.
+//
+// Paper: cell link list with cell size equal to the search radius (SPH method
+// section, Fig. 3b); cell-relative coordinates (Eq. 5-6, Fig. 5); spatial sorting
+// so that neighbouring threads work on neighbouring particles (Results, memory
+// section and Table 6).
+#include "build_kernels.h"
+
+namespace nnps {
+
+// ---------------------------------------------------------------------------
+// Exact int64 -> float32 (one rounding) for |v| < 2^44: v = hi*2^20 + lo with
+// hi exactly representable, lo < 2^20, and a single fused multiply-add rounds once.
+__device__ __forceinline__ float exact_i64_to_f32(int64_t v)
+{
+    const int32_t hi = static_cast<int32_t>(v >> 20);
+    const int32_t lo = static_cast<int32_t>(v & 0xFFFFF);
+    return __builtin_fmaf(static_cast<float>(hi), 1048576.0f, static_cast<float>(lo));
+}
+
+// ---------------------------------------------------------------------------
+// A1: cell assignment in FP64. X = rint((p - lo) * 2^F / w) (round half to even),
+// cell = X >> F, key = cx + ncx (cy + ncy cz). Positions outside [lo, hi] (or NaN)
+// raise the domain flag and are treated as lo so every index stays in range.
+template <int DIM>
+__global__ void __launch_bounds__(256)
+k_assign(const double* __restrict__ pos, Frame fr, int64_t* __restrict__ X,
+         uint32_t* __restrict__ key, int* __restrict__ cell_count, int* __restrict__ err)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= fr.n) return;
+    bool bad = false;
+    int64_t c[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        double p = pos[static_cast<size_t>(i) * DIM + k];
+        if (!(p >= fr.lo[k] && p <= fr.hi[k])) {
+            bad = true;
+            p = fr.lo[k];
+        }
+        const double d = __dsub_rn(p, fr.lo[k]);
+        const double t = __dmul_rn(d, fr.s);
+        const int64_t x = static_cast<int64_t>(rint(t));
+        X[static_cast<size_t>(k) * fr.n + i] = x;
+        c[k] = x >> fr.F;
+    }
+    const uint32_t kk = static_cast<uint32_t>(c[0] + fr.nc[0] * (c[1] + fr.nc[1] * c[2]));
+    key[i] = kk;
+    atomicAdd(&cell_count[kk], 1);
+    if (bad) atomicOr(err, kErrDomain);
+}
+
+// ---------------------------------------------------------------------------
+// Device-wide exclusive scan (int32 in, TOut out), three phases over tiles of
+// kScanTile elements: tile sums, a scan of the tile sums, then each tile scanned
+// with its offset. out[m] receives the total.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ __forceinline__ int64_t wave_incl_scan(int64_t v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+// Block-wide exclusive scan of one value per thread (256 threads); returns the
+// exclusive prefix and the block total.
+__device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t* total, int64_t* sh /*[4]*/)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t inc = wave_incl_scan(v);
+    if (lane == 63) sh[w] = inc;
+    __syncthreads();
+    int64_t base = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < kScanThreads / 64; ++k) {
+        if (k < w) base += sh[k];
+        tot += sh[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + inc - v;
+}
+
+template <typename TIn>
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_reduce(const TIn* __restrict__ in, int64_t m, int64_t* __restrict__ partial)
+{
+    __shared__ int64_t sh[4];
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile;
+    int64_t s = 0;
+    for (int r = 0; r < kScanItems; ++r) {
+        const int64_t idx = base + r * kScanThreads + threadIdx.x;
+        if (idx < m) s += static_cast<int64_t>(in[idx]);
+    }
+    int64_t tot;
+    block_excl_scan(s, &tot, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// One workgroup scans the tile sums in place (exclusive); partial[nt] = total.
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_partials(int64_t* __restrict__ partial, int64_t nt)
+{
+    __shared__ int64_t sh[4];
+    __shared__ int64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t b = 0; b < nt; b += kScanThreads) {
+        const int64_t idx = b + threadIdx.x;
+        const int64_t v = idx < nt ? partial[idx] : 0;
+        int64_t tot;
+        const int64_t ex = block_excl_scan(v, &tot, sh);
+        const int64_t c = carry;
+        if (idx < nt) partial[idx] = c + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry = c + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[nt] = carry;
+}
+
+template <typename TIn, typename TOut>
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_down(const TIn* __restrict__ in, int64_t m, const int64_t* __restrict__ partial,
+            TOut* __restrict__ out, int64_t nt)
+{
+    __shared__ int64_t sh[4];
+    // blocked layout: thread t owns kScanItems consecutive elements
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
+    TIn v[kScanItems];
+    int64_t s = 0;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        const int64_t idx = base + r;
+        v[r] = idx < m ? in[idx] : TIn(0);
+        s += static_cast<int64_t>(v[r]);
+    }
+    int64_t tot;
+    int64_t run = block_excl_scan(s, &tot, sh) + partial[blockIdx.x];
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        const int64_t idx = base + r;
+        if (idx < m) out[idx] = static_cast<TOut>(run);
+        run += static_cast<int64_t>(v[r]);
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[m] = static_cast<TOut>(partial[nt]);
+}
+
+template <typename TIn, typename TOut>
+hipError_t scan_exclusive(const TIn* in, int64_t m, TOut* out, int64_t* partial, hipStream_t st)
+{
+    const int64_t nt = (m + kScanTile - 1) / kScanTile;
+    if (nt == 0) {
+        // m == 0: out[0] = 0
+        return hipMemsetAsync(out, 0, sizeof(TOut), st);
+    }
+    hipLaunchKernelGGL(k_scan_reduce<TIn>, dim3(nt), dim3(kScanThreads), 0, st, in, m, partial);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, st, partial, nt);
+    hipLaunchKernelGGL((k_scan_down<TIn, TOut>), dim3(nt), dim3(kScanThreads), 0, st, in, m, partial,
+                       out, nt);
+    return hipGetLastError();
+}
+
+int64_t scan_partials_needed(int64_t m) { return (m + kScanTile - 1) / kScanTile + 1; }
+
+// ---------------------------------------------------------------------------
+// A2: stable LSD radix sort of (key, index) pairs, up to 11 bits per pass.
+// Tiles of kRsTile keys; each wave of a tile owns 1024 consecutive keys and ranks
+// them 64 at a time: lanes holding the same digit find each other with one ballot
+// per digit bit, and a per-wave LDS counter per digit keeps the order of rounds.
+// Tile order, then wave, then round, then lane equals index order: the sort is stable.
+constexpr int kRsThreads = 256;
+constexpr int kRsRounds = 16;
+constexpr int kRsTile = kRsThreads * kRsRounds;
+constexpr int kRsMaxBits = 11;
+
+__global__ void __launch_bounds__(kRsThreads)
+k_radix_hist(const uint32_t* __restrict__ keys, int n, int shift, int bits,
+             uint32_t* __restrict__ table, int ntiles)
+{
+    __shared__ uint32_t h[1 << kRsMaxBits];
+    const int bins = 1 << bits;
+    const uint32_t mask = bins - 1;
+    for (int i = threadIdx.x; i < bins; i += kRsThreads) h[i] = 0;
+    __syncthreads();
+    const int base = blockIdx.x * kRsTile;
+    for (int r = 0; r < kRsRounds; ++r) {
+        const int idx = base + r * kRsThreads + threadIdx.x;
+        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & mask], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < bins; i += kRsThreads) table[static_cast<size_t>(i) * ntiles + blockIdx.x] = h[i];
+}
+
+__global__ void __launch_bounds__(kRsThreads)
+k_radix_scatter(const uint32_t* __restrict__ kin, const int* __restrict__ vin,
+                uint32_t* __restrict__ kout, int* __restrict__ vout, int n, int shift, int bits,
+                const uint32_t* __restrict__ offs, int ntiles)
+{
+    __shared__ uint32_t cw[kRsThreads / 64][1 << kRsMaxBits];
+    const int bins = 1 << bits;
+    const uint32_t mask = bins - 1;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < (kRsThreads / 64) * bins; i += kRsThreads) cw[i / bins][i % bins] = 0;
+    __syncthreads();
+    const int base = blockIdx.x * kRsTile + w * (kRsRounds * 64);
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t myk[kRsRounds];
+    int myv[kRsRounds];
+    uint32_t rank[kRsRounds];
+#pragma unroll
+    for (int r = 0; r < kRsRounds; ++r) {
+        const int idx = base + r * 64 + lane;
+        const bool valid = idx < n;
+        const uint32_t k = valid ? kin[idx] : 0u;
+        const int v = valid ? (vin ? vin[idx] : idx) : 0;
+        const uint32_t d = (k >> shift) & mask;
+        uint64_t m = __ballot(valid);
+        for (int b = 0; b < bits; ++b) {
+            const bool set = (d >> b) & 1u;
+            const uint64_t bb = __ballot(set);
+            m &= set ? bb : ~bb;
+        }
+        const uint32_t rnk = __popcll(m & lt);
+        const uint32_t cnt = __popcll(m);
+        const uint32_t b0 = cw[w][d];
+        __builtin_amdgcn_wave_barrier();
+        if (valid && rnk == 0) cw[w][d] = b0 + cnt;
+        __builtin_amdgcn_wave_barrier();
+        myk[r] = k;
+        myv[r] = v;
+        rank[r] = b0 + rnk;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < bins; i += kRsThreads) {
+        uint32_t run = 0;
+#pragma unroll
+        for (int k = 0; k < kRsThreads / 64; ++k) {
+            const uint32_t t = cw[k][i];
+            cw[k][i] = run;
+            run += t;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRsRounds; ++r) {
+        const int idx = base + r * 64 + lane;
+        if (idx < n) {
+            const uint32_t d = (myk[r] >> shift) & mask;
+            const uint32_t p = offs[static_cast<size_t>(d) * ntiles + blockIdx.x] + cw[w][d] + rank[r];
+            kout[p] = myk[r];
+            vout[p] = myv[r];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// A4: pack in sorted order. q_k = f16(f32(D_k) 2^(1-F)) with D_k = X_k - c_k 2^F - 2^(F-1),
+// the Eq. 6 relative coordinate in [-1, 1]; the fourth half holds c_x mod 2^16.
+// The FP64 baseline instead gets a sorted copy of the caller's positions.
+template <int DIM>
+__global__ void __launch_bounds__(256)
+k_pack(Frame fr, const int* __restrict__ perm, const int64_t* __restrict__ X,
+       ushort4* __restrict__ q4, const double* __restrict__ pos, double* __restrict__ spos)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= fr.n) return;
+    const int o = perm[p];
+    if (spos) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) spos[static_cast<size_t>(p) * 4 + k] = pos[static_cast<size_t>(o) * DIM + k];
+    }
+    uint16_t h[4] = {0, 0, 0, 0};
+    const float scale = __builtin_ldexpf(1.0f, 1 - fr.F);
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        const int64_t x = X[static_cast<size_t>(k) * fr.n + o];
+        const int64_t c = x >> fr.F;
+        const int64_t D = x - (c << fr.F) - (int64_t(1) << (fr.F - 1));
+        const _Float16 q = static_cast<_Float16>(exact_i64_to_f32(D) * scale);
+        h[k] = __builtin_bit_cast(uint16_t, q);
+        if (k == 0) h[3] = static_cast<uint16_t>(c & 0xFFFF);
+    }
+    q4[p] = make_ushort4(h[0], h[1], h[2], h[3]);
+}
+
+// ---------------------------------------------------------------------------
+// Work blocks: runs of at most kWave sorted particles inside one (y, z) row of cells,
+// cut at the row start, every kWave particles, and every 2^kXSpanShift cells along x.
+__global__ void __launch_bounds__(256)
+k_block_flags(Frame fr, const uint32_t* __restrict__ skey, const int* __restrict__ cell_start,
+              int* __restrict__ flags)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= fr.n) return;
+    const uint32_t key = skey[p];
+    const uint32_t ncx = static_cast<uint32_t>(fr.nc[0]);
+    const uint32_t row = key / ncx;
+    const uint32_t x = key - row * ncx;
+    const int rs = cell_start[row * ncx];
+    int f = (p == rs) || (((p - rs) % kWave) == 0);
+    if (!f) {
+        const uint32_t kp = skey[p - 1];
+        const uint32_t xp = kp - (kp / ncx) * ncx;
+        f = (x >> kXSpanShift) != (xp >> kXSpanShift);
+    }
+    flags[p] = f;
+}
+
+__global__ void __launch_bounds__(256)
+k_block_write(int n, const int* __restrict__ flags, const int* __restrict__ bidx,
+              int* __restrict__ bstart)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n && flags[p]) bstart[bidx[p]] = p;
+    if (p == 0) bstart[bidx[n]] = n;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+hipError_t launch_assign(const double* pos, const Frame& fr, int64_t* X, uint32_t* key,
+                         int* cell_count, int* err, hipStream_t st)
+{
+    if (fr.n == 0) return hipSuccess;
+    const dim3 g((fr.n + 255) / 256), b(256);
+    if (fr.dim == 2)
+        hipLaunchKernelGGL(k_assign<2>, g, b, 0, st, pos, fr, X, key, cell_count, err);
+    else
+        hipLaunchKernelGGL(k_assign<3>, g, b, 0, st, pos, fr, X, key, cell_count, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_i32_i32(const int* in, int64_t m, int* out, int64_t* partial, hipStream_t st)
+{
+    return scan_exclusive<int, int>(in, m, out, partial, st);
+}
+
+hipError_t launch_scan_u32_u32(const uint32_t* in, int64_t m, uint32_t* out, int64_t* partial,
+                               hipStream_t st)
+{
+    return scan_exclusive<uint32_t, uint32_t>(in, m, out, partial, st);
+}
+
+hipError_t launch_scan_i32_i64(const int* in, int64_t m, int64_t* out, int64_t* partial,
+                               hipStream_t st)
+{
+    return scan_exclusive<int, int64_t>(in, m, out, partial, st);
+}
+
+int radix_tiles(int n) { return (n + kRsTile - 1) / kRsTile; }
+
+hipError_t launch_radix_sort(int n, int keybits, uint32_t* k0, int* v0, uint32_t* k1, int* v1,
+                             uint32_t* table, int64_t* partial, hipStream_t st, uint32_t** kfinal,
+                             int** vfinal)
+{
+    // first pass reads the identity permutation implicitly (vin == nullptr)
+    const int ntiles = radix_tiles(n);
+    const int passes = keybits <= 0 ? 1 : (keybits + kRsMaxBits - 1) / kRsMaxBits;
+    const int bits = keybits <= 0 ? 1 : (keybits + passes - 1) / passes;
+    uint32_t* kin = k0;
+    int* vin = nullptr;
+    uint32_t* kout = k1;
+    int* vout = v1;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = p * bits;
+        hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kRsThreads), 0, st, kin, n, shift, bits,
+                           table, ntiles);
+        hipError_t e = scan_exclusive<uint32_t, uint32_t>(table, static_cast<int64_t>(ntiles) << bits,
+                                                          table, partial, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(kRsThreads), 0, st, kin, vin, kout,
+                           vout, n, shift, bits, table, ntiles);
+        // ping-pong
+        if (p == 0) {
+            kin = k1;
+            vin = v1;
+            kout = k0;
+            vout = v0;
+        } else {
+            std::swap(kin, kout);
+            std::swap(vin, vout);
+        }
+    }
+    *kfinal = kin;
+    *vfinal = vin;
+    return hipGetLastError();
+}
+
+size_t radix_table_entries(int n) { return static_cast<size_t>(radix_tiles(n)) << kRsMaxBits; }
+
+hipError_t launch_pack(const Frame& fr, const int* perm, const int64_t* X, ushort4* q4,
+                       const double* pos, double* spos, hipStream_t st)
+{
+    if (fr.n == 0) return hipSuccess;
+    const dim3 g((fr.n + 255) / 256), b(256);
+    if (fr.dim == 2)
+        hipLaunchKernelGGL(k_pack<2>, g, b, 0, st, fr, perm, X, q4, pos, spos);
+    else
+        hipLaunchKernelGGL(k_pack<3>, g, b, 0, st, fr, perm, X, q4, pos, spos);
+    return hipGetLastError();
+}
+
+hipError_t launch_blocks(const Frame& fr, const uint32_t* skey, const int* cell_start, int* flags,
+                         int* bidx, int* bstart, int64_t* partial, hipStream_t st)
+{
+    if (fr.n == 0) return hipMemsetAsync(bidx, 0, sizeof(int), st);
+    const dim3 g((fr.n + 255) / 256), b(256);
+    hipLaunchKernelGGL(k_block_flags, g, b, 0, st, fr, skey, cell_start, flags);
+    hipError_t e = scan_exclusive<int, int>(flags, fr.n, bidx, partial, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_block_write, g, b, 0, st, fr.n, flags, bidx, bstart);
+    return hipGetLastError();
+}
+
+}  // namespace nnps

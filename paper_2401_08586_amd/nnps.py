@@ -1,0 +1,248 @@
+"""Python binding for libnnps.so (include/nnps.h): argument marshalling only.
+
+Every step of the search runs in the HIP library. PyTorch supplies device memory and
+streams: positions and outputs are torch CUDA tensors passed as raw pointers, and the
+stream is torch's current stream unless one is given. If the library is missing this
+module raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnnps.so")
+
+NNPS_OK = 0
+NNPS_EINVAL = -1
+NNPS_EDOMAIN = -2
+NNPS_ENOMEM = -3
+NNPS_ECAPACITY = -4
+NNPS_EDEVICE = -5
+NNPS_ETOOMANYCELLS = -6
+NNPS_EORDER = -7
+NNPS_EUNSUPPORTED = -8
+
+MODE_FP16_RCLL = 0
+MODE_FP64_BASELINE = 1
+MODE_RECHECK_ALL = 2
+
+
+class NnpsError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        super().__init__(f"{what}: {status_str(code)}" if what else status_str(code))
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("mode", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("cell_size", ctypes.c_double), ("radius", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("candidates", ctypes.c_int64),
+                ("band_pairs", ctypes.c_int64), ("fp16_false_pos", ctypes.c_int64),
+                ("fp16_false_neg", ctypes.c_int64), ("outside_band_disagree", ctypes.c_int64),
+                ("heavy_rows", ctypes.c_int64), ("dim", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("frac_bits", ctypes.c_int32), ("ncell", ctypes.c_int32 * 3),
+                ("cell_width", ctypes.c_double), ("band", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["ncell"] = list(self.ncell)
+        return d
+
+
+EXPORTS = ["nnps_status_str", "nnps_validate", "nnps_grid", "nnps_ctx_create", "nnps_ctx_destroy",
+           "nnps_cells_create", "nnps_cells_destroy", "nnps_cells_build", "nnps_count", "nnps_fill",
+           "nnps_search", "nnps_stats_get"]
+
+_lib = None
+
+
+def load():
+    """Load libnnps.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2401_08586_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    I64 = ctypes.c_int64
+    lib.nnps_status_str.argtypes = [ctypes.c_int]
+    lib.nnps_status_str.restype = ctypes.c_char_p
+    lib.nnps_validate.argtypes = [ctypes.POINTER(Problem)]
+    lib.nnps_grid.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_int32),
+                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
+    lib.nnps_ctx_create.argtypes = [ctypes.c_int, PP]
+    lib.nnps_ctx_destroy.argtypes = [P]
+    lib.nnps_ctx_destroy.restype = None
+    lib.nnps_cells_create.argtypes = [P, PP]
+    lib.nnps_cells_destroy.argtypes = [P]
+    lib.nnps_cells_destroy.restype = None
+    lib.nnps_cells_build.argtypes = [P, P, ctypes.POINTER(Problem), P, P]
+    lib.nnps_count.argtypes = [P, P, P, ctypes.POINTER(I64), P]
+    lib.nnps_fill.argtypes = [P, P, P, P, P, I64, P]
+    lib.nnps_search.argtypes = [P, P, ctypes.POINTER(Problem), P, P, P, P, I64, ctypes.POINTER(I64), P]
+    lib.nnps_stats_get.argtypes = [P, ctypes.POINTER(Stats), P]
+    for name in EXPORTS:
+        fn = getattr(lib, name)
+        if name not in ("nnps_status_str", "nnps_ctx_destroy", "nnps_cells_destroy"):
+            fn.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def status_str(code: int) -> str:
+    try:
+        return load().nnps_status_str(code).decode()
+    except ImportError:
+        return f"status {code}"
+
+
+def _check(code: int, what: str):
+    if code != NNPS_OK:
+        raise NnpsError(code, what)
+
+
+def make_problem(dim, n, lo, hi, cell_size, radius, mode=MODE_FP16_RCLL) -> Problem:
+    p = Problem()
+    p.dim = int(dim)
+    p.mode = int(mode)
+    p.n = int(n)
+    for k in range(3):
+        p.lo[k] = float(lo[k]) if k < dim else 0.0
+        p.hi[k] = float(hi[k]) if k < dim else 0.0
+    p.cell_size = float(cell_size)
+    p.radius = float(radius)
+    return p
+
+
+def validate(prob: Problem) -> int:
+    return load().nnps_validate(ctypes.byref(prob))
+
+
+def grid(prob: Problem):
+    nc = (ctypes.c_int32 * 3)()
+    fb = ctypes.c_int32()
+    w = ctypes.c_double()
+    _check(load().nnps_grid(ctypes.byref(prob), nc, ctypes.byref(fb), ctypes.byref(w)), "nnps_grid")
+    return list(nc), fb.value, w.value
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+class Context:
+    """A library context on one device, plus a reusable cell structure."""
+
+    def __init__(self, device: int = 0):
+        lib = load()
+        self._lib = lib
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(lib.nnps_ctx_create(device, ctypes.byref(h)), "nnps_ctx_create")
+        self._ctx = h
+        self._cells = []
+
+    def close(self):
+        for c in self._cells:
+            c.close()
+        self._cells = []
+        if self._ctx:
+            self._lib.nnps_ctx_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def cells(self) -> "Cells":
+        c = Cells(self)
+        self._cells.append(c)
+        return c
+
+
+class Cells:
+    """A device-resident cell structure (nnps_cells)."""
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+        self._lib = ctx._lib
+        h = ctypes.c_void_p()
+        _check(self._lib.nnps_cells_create(ctx._ctx, ctypes.byref(h)), "nnps_cells_create")
+        self._h = h
+        self.n = 0
+        self._pos = None
+
+    def close(self):
+        if self._h:
+            self._lib.nnps_cells_destroy(self._h)
+            self._h = None
+
+    def build(self, pos, lo, hi, cell_size, radius, mode=MODE_FP16_RCLL, stream=None):
+        """pos: torch float64 CUDA tensor [n, dim], contiguous."""
+        import torch
+        assert pos.is_cuda and pos.dtype == torch.float64 and pos.is_contiguous() and pos.dim() == 2
+        n, dim = pos.shape
+        prob = make_problem(dim, n, lo, hi, cell_size, radius, mode)
+        _check(self._lib.nnps_cells_build(self.ctx._ctx, self._h, ctypes.byref(prob), _ptr(pos),
+                                          _stream_ptr(stream)), "nnps_cells_build")
+        self.n = n
+        self._pos = pos  # keep alive: the recheck reads it
+        return self
+
+    def count(self, row_ptr, sync=True, stream=None):
+        """row_ptr: torch int64 CUDA tensor [n+1]. Returns nnz when sync, else None."""
+        nnz = ctypes.c_int64(-1)
+        _check(self._lib.nnps_count(self.ctx._ctx, self._h, _ptr(row_ptr),
+                                    ctypes.byref(nnz) if sync else None, _stream_ptr(stream)),
+               "nnps_count")
+        return nnz.value if sync else None
+
+    def fill(self, row_ptr, col, dist, stream=None):
+        cap = col.numel()
+        assert dist.numel() == cap
+        _check(self._lib.nnps_fill(self.ctx._ctx, self._h, _ptr(row_ptr), _ptr(col), _ptr(dist), cap,
+                                   _stream_ptr(stream)), "nnps_fill")
+
+    def stats(self, stream=None) -> dict:
+        st = Stats()
+        code = self._lib.nnps_stats_get(self._h, ctypes.byref(st), _stream_ptr(stream))
+        _check(code, "nnps_stats_get")
+        return st.as_dict()
+
+
+def search(pos, lo, hi, cell_size, radius, mode=MODE_FP16_RCLL, ctx: Context | None = None,
+           cells: Cells | None = None, stream=None):
+    """Build + count + fill. Returns (row_ptr int64 [n+1], col int32 [nnz], dist float32 [nnz])
+    as CUDA tensors, plus the cell structure used."""
+    import torch
+    own = ctx is None
+    if ctx is None:
+        ctx = Context(pos.device.index or 0)
+    if cells is None:
+        cells = ctx.cells()
+    cells.build(pos, lo, hi, cell_size, radius, mode, stream)
+    row_ptr = torch.empty(pos.shape[0] + 1, dtype=torch.int64, device=pos.device)
+    nnz = cells.count(row_ptr, sync=True, stream=stream)
+    col = torch.empty(max(nnz, 0), dtype=torch.int32, device=pos.device)
+    dist = torch.empty(max(nnz, 0), dtype=torch.float32, device=pos.device)
+    cells.fill(row_ptr, col, dist, stream)
+    if own:
+        cells.stats(stream)  # surfaces device-side errors before the context goes away
+    return row_ptr, col, dist, cells
