@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Neighbour-search throughput on one MI355X: FP16 relative-coordinate link list (with the
+FP64 guard-band recheck) beside the plain FP64 GPU cell list and the CPU oracle.
+
+One step = one whole search over the workload with the positions already in HBM:
+cell build (FP64 assignment, radix sort, cell starts, FP16 pack, block table) + count
+pass + row_ptr scan + fill pass. Output buffers are sized once from the warm-up count
+(the workload is fixed), so the timed steps do not stop for the nnz read-back.
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from paper_2401_08586_amd import workloads as W
+    return {"c0": W.c0, "c1": W.c1, "c2": W.c2}[name]()
+
+
+def describe(ps):
+    return {"workload": ps.name, "particles": ps.n, "dim": ps.dim, "radius": ps.radius,
+            "cell_size": ps.cell_size, "box": [list(ps.lo), list(ps.hi)],
+            "inputs": "jittered lattice, dx = radius/2.4, jitter U(+-0.1 dx), seeded"}
+
+
+def time_mode(ctx, pos, ps, mode, steps, warmup):
+    """Returns (ms per step, nnz, stats, per-phase mean ms) for one mode."""
+    import torch
+    from paper_2401_08586_amd import nnps
+    cells = ctx.cells()
+    n = ps.n
+    rp = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    cells.build(pos, ps.lo, ps.hi, ps.cell_size, ps.radius, mode)
+    nnz = cells.count(rp, sync=True)
+    col = torch.empty(nnz, dtype=torch.int32, device="cuda")
+    dist = torch.empty(nnz, dtype=torch.float32, device="cuda")
+    cells.fill(rp, col, dist)
+    st = cells.stats()
+
+    def step():
+        cells.build(pos, ps.lo, ps.hi, ps.cell_size, ps.radius, mode)
+        cells.count(rp, sync=False)
+        cells.fill(rp, col, dist)
+
+    for _ in range(warmup):
+        step()
+    cells.set_profiling(True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    ev_ms = e0.elapsed_time(e1)
+    ph = cells.phase_times()
+    cells.set_profiling(False)
+    st2 = cells.stats()  # surfaces any device-side error of the timed steps
+    assert st2["nnz"] == nnz
+    phases = {k: (v[0] / v[1] if v[1] else None) for k, v in ph.items()}
+    cells.close()
+    return max(wall_ms, ev_ms) / steps, nnz, st, phases
+
+
+def fill_bytes(ps, nnz, band_pairs):
+    """Algorithmic bytes of one fill launch: 8 per neighbour pair written (int32 col +
+    float32 dist), per particle its FP16 record (8), original index (4), fixed-point
+    position (8 d), cell key (4) and row bounds (8), and 8 d per FP64 recheck gather."""
+    d = ps.dim
+    return 8 * nnz + ps.n * (24 + 8 * d) + 8 * d * band_pairs
+
+
+def cpu_baseline(ps, budget_s=20.0):
+    """The oracle as it is (serial C, one thread) on the same workload."""
+    import oracle
+    runs = []
+    nnz = None
+    t_start = time.perf_counter()
+    while len(runs) < 3 and (time.perf_counter() - t_start) < budget_s:
+        t0 = time.perf_counter()
+        rp, col, dist = oracle.search_ps(ps)
+        runs.append(time.perf_counter() - t0)
+        nnz = int(rp[-1])
+    t = statistics.median(runs)
+    return {"value": nnz / t / 1e9, "unit": "Gpairs/s", "cores": 1, "kind": "oracle",
+            "sample": f"whole {ps.name} ({ps.n} particles, {nnz} pairs), median of {len(runs)} "
+                      f"single-thread runs of the serial C cell link list ({t:.2f} s each)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this library has no multi-GPU path "
+              "(run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2401_08586_amd import nnps
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    ps = workload(args.workload)
+    log(f"[bench] workload {ps.name} n={ps.n}")
+    pos = torch.from_numpy(ps.pos).cuda()
+    ctx = nnps.Context(0)
+
+    ms16, nnz, st16, ph16 = time_mode(ctx, pos, ps, nnps.MODE_FP16_RCLL, args.steps, args.warmup)
+    log(f"[bench] fp16-rcll {ms16:.3f} ms/step nnz={nnz} phases={ph16}")
+    res64 = None
+    if not args.no_fp64:
+        ms64, nnz64, st64, ph64 = time_mode(ctx, pos, ps, nnps.MODE_FP64_BASELINE, args.steps, args.warmup)
+        assert nnz64 == nnz
+        log(f"[bench] fp64-baseline {ms64:.3f} ms/step phases={ph64}")
+        res64 = {"value": nnz / (ms64 * 1e-3) / 1e9, "unit": "Gpairs/s", "ms_per_step": ms64,
+                 "phases_ms": ph64, "speedup_fp16_over_fp64": ms64 / ms16}
+    ctx.close()
+
+    fill_ms = ph16["fill"]
+    fb = fill_bytes(ps, nnz, st16["band_pairs"])
+    achieved = fb / (fill_ms * 1e-3) / 1e9
+    out = {
+        "metric": "Gpairs/s at 1M-particle 3D NNPS, FP16 RCLL vs FP64; p50/p99 request latency",
+        "value": nnz / (ms16 * 1e-3) / 1e9,
+        "unit": "Gpairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms16,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16",
+        "data": "synthetic",
+        "config": describe(ps),
+        "roofline": {"bound": "hbm", "kernel": "k_fill16 (fill pass)", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "algorithmic_bytes_per_launch": fb, "avg_launch_ms": fill_ms},
+        "particles_per_s": ps.n / (ms16 * 1e-3),
+        "nnz": nnz,
+        "phases_ms": ph16,
+        "fp16_stats": {k: st16[k] for k in ("candidates", "band_pairs", "fp16_false_pos",
+                                              "fp16_false_neg", "heavy_rows")},
+        "fp64_baseline": res64,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(ps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -148,6 +148,30 @@ nnps_status nnps_search(nnps_ctx *ctx, nnps_cells *cells, const nnps_problem *pr
  * Returns any device-detected error (NNPS_EDOMAIN, NNPS_ECAPACITY, NNPS_EUNSUPPORTED). */
 nnps_status nnps_stats_get(nnps_cells *cells, nnps_stats *out, void *stream);
 
+/* Phases timed when profiling is on, in launch order. */
+enum {
+    NNPS_PHASE_ASSIGN = 0,   /* FP64 cell assignment + cell histogram */
+    NNPS_PHASE_CELLSCAN,     /* exclusive scan of the histogram -> cell starts */
+    NNPS_PHASE_SORT,         /* radix sort of (cell key, index) */
+    NNPS_PHASE_PACK,         /* FP16 relative-coordinate pack (or sorted FP64 copy) */
+    NNPS_PHASE_BLOCKS,       /* work-block table */
+    NNPS_PHASE_COUNT,        /* count pass (stencil test + recheck) */
+    NNPS_PHASE_ROWSCAN,      /* counts -> row_ptr */
+    NNPS_PHASE_FILL,         /* fill pass (stencil test + recheck + sorted CSR writes) */
+    NNPS_PHASE_LONGROWS,     /* long-row path of the fill */
+    NNPS_NPHASES
+};
+
+/* Turn per-phase HIP-event timing on (on != 0) or off for a cell structure, and forget
+ * what was recorded. Events are recorded on the stream of each call; no extra
+ * synchronisation is added. */
+nnps_status nnps_cells_set_profiling(nnps_cells *cells, int on);
+
+/* Waits for the stream, then writes for each phase the summed device time in
+ * milliseconds (ms[NNPS_NPHASES]) and the number of timed launches (runs[NNPS_NPHASES])
+ * since profiling was turned on or last read, and starts a new tally. */
+nnps_status nnps_phase_times(nnps_cells *cells, double *ms, int32_t *runs, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -42,11 +42,13 @@ struct SearchArgs {
     int64_t capacity;
     int* heavy;               // sorted positions of long rows
     int* nheavy;
-    unsigned long long* stats;
+    unsigned long long* stats;      // [kStCount] totals
+    unsigned long long* blk_stats;  // [nblk_max][5] per-block partial statistics
     int* err;
 };
 
 hipError_t launch_count(const SearchArgs& a, int nblk_max, hipStream_t st);
 hipError_t launch_fill(const SearchArgs& a, int nblk_max, hipStream_t st);
+hipError_t launch_long_rows(const SearchArgs& a, hipStream_t st);
 
 }  // namespace nnps

@@ -293,8 +293,8 @@ k_pack(Frame fr, const int* __restrict__ perm, const int64_t* __restrict__ X,
 }
 
 // ---------------------------------------------------------------------------
-// Work blocks: runs of at most kWave sorted particles inside one (y, z) row of cells,
-// cut at the row start, every kWave particles, and every 2^kXSpanShift cells along x.
+// Work blocks: the particles of one x-window of fr.xwin cells inside one (y, z) row of
+// cells, split into runs of at most kWave particles.
 __global__ void __launch_bounds__(256)
 k_block_flags(Frame fr, const uint32_t* __restrict__ skey, const int* __restrict__ cell_start,
               int* __restrict__ flags)
@@ -305,14 +305,9 @@ k_block_flags(Frame fr, const uint32_t* __restrict__ skey, const int* __restrict
     const uint32_t ncx = static_cast<uint32_t>(fr.nc[0]);
     const uint32_t row = key / ncx;
     const uint32_t x = key - row * ncx;
-    const int rs = cell_start[row * ncx];
-    int f = (p == rs) || (((p - rs) % kWave) == 0);
-    if (!f) {
-        const uint32_t kp = skey[p - 1];
-        const uint32_t xp = kp - (kp / ncx) * ncx;
-        f = (x >> kXSpanShift) != (xp >> kXSpanShift);
-    }
-    flags[p] = f;
+    const uint32_t win = x / static_cast<uint32_t>(fr.xwin);
+    const int ws = cell_start[row * ncx + win * static_cast<uint32_t>(fr.xwin)];
+    flags[p] = (p == ws) || (((p - ws) % kWave) == 0);
 }
 
 __global__ void __launch_bounds__(256)

@@ -5,6 +5,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <utility>
+#include <vector>
 
 #include "../../include/nnps.h"
 #include "build_kernels.h"
@@ -122,6 +124,11 @@ nnps_status frame_of(const nnps_problem* p, Frame* fr)
     fr->t_lo = f16_bits(4.0 * (rho2 - band), -1);
     fr->t_hi = f16_bits(4.0 * (rho2 + band), +1);
     fr->t_mid = f16_bits(4.0 * rho2, 0);
+    // x-window of a work block: about 56 particles on average, so most windows fill one
+    // wavefront and the candidate union stays small
+    const double occ = static_cast<double>(p->n) / static_cast<double>(ncell);
+    int xwin = occ > 0.0 ? static_cast<int>(56.0 / occ) : kMaxXWin;
+    fr->xwin = std::max(1, std::min(kMaxXWin, xwin));
     return NNPS_OK;
 }
 
@@ -132,8 +139,56 @@ struct nnps_ctx {
     int64_t* h_pinned = nullptr;  // small pinned staging for synchronous readbacks
 };
 
+// Per-phase HIP-event timing. Every begin/end pair recorded since the last read is
+// kept, so a run of many calls can be summed without synchronising in between.
+struct PhaseTimer {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    int open[NNPS_NPHASES] = {};
+    std::vector<std::pair<int, int>> rec[NNPS_NPHASES];
+    hipEvent_t* next()
+    {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return &pool[used++];
+    }
+    void reset()
+    {
+        used = 0;
+        for (auto& r : rec) r.clear();
+    }
+    void release()
+    {
+        for (auto& e : pool) (void)hipEventDestroy(e);
+        pool.clear();
+        reset();
+        on = false;
+    }
+    void begin(int ph, hipStream_t s)
+    {
+        if (!on) return;
+        hipEvent_t* e = next();
+        if (!e) return;
+        open[ph] = static_cast<int>(e - pool.data());
+        (void)hipEventRecord(*e, s);
+    }
+    void end(int ph, hipStream_t s)
+    {
+        if (!on) return;
+        hipEvent_t* e = next();
+        if (!e) return;
+        (void)hipEventRecord(*e, s);
+        rec[ph].push_back({open[ph], static_cast<int>(e - pool.data())});
+    }
+};
+
 struct nnps_cells {
     nnps_ctx* ctx = nullptr;
+    PhaseTimer timer;
     Frame fr{};
     bool built = false, counted = false;
     const double* pos = nullptr;
@@ -141,7 +196,7 @@ struct nnps_cells {
     uint32_t* skey = nullptr;
     int* perm = nullptr;
     DevBuf X, k0, k1, v0, v1, cell_count, cell_start, q4, spos, flags, bidx, bstart, counts, table,
-        partial, stats, err, heavy, nheavy, nnz;
+        partial, stats, blk_stats, err, heavy, nheavy, nnz;
 };
 
 #define HIP_TRY(x)                                \
@@ -245,8 +300,9 @@ void nnps_cells_destroy(nnps_cells* c)
     DeviceGuard g(c->ctx->device);
     DevBuf* all[] = {&c->X, &c->k0, &c->k1, &c->v0, &c->v1, &c->cell_count, &c->cell_start, &c->q4,
                      &c->spos, &c->flags, &c->bidx, &c->bstart, &c->counts, &c->table, &c->partial,
-                     &c->stats, &c->err, &c->heavy, &c->nheavy, &c->nnz};
+                     &c->stats, &c->blk_stats, &c->err, &c->heavy, &c->nheavy, &c->nnz};
     for (DevBuf* b : all) b->release();
+    c->timer.release();
     delete c;
 }
 
@@ -265,8 +321,8 @@ nnps_status nnps_cells_build(nnps_ctx* ctx, nnps_cells* c, const nnps_problem* p
     const size_t nn = std::max<size_t>(n, 1);
     const size_t ncell = static_cast<size_t>(fr.ncell);
     const int64_t nrows = static_cast<int64_t>(fr.nc[1]) * fr.nc[2];
-    const int64_t xcuts = fr.nc[0] >> kXSpanShift;
-    const int64_t nblk_bound = static_cast<int64_t>(n / kWave) + nrows * (1 + xcuts) + 1;
+    const int64_t nwin = nrows * ((fr.nc[0] + fr.xwin - 1) / fr.xwin);
+    const int64_t nblk_bound = static_cast<int64_t>(n / kWave) + nwin + 1;
     c->nblk_max = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(n), nblk_bound));
     const size_t table_n = radix_table_entries(static_cast<int>(nn)) + 1;
     const int64_t scan_m = std::max<int64_t>({static_cast<int64_t>(nn) + 1, static_cast<int64_t>(ncell) + 1,
@@ -287,7 +343,8 @@ nnps_status nnps_cells_build(nnps_ctx* ctx, nnps_cells* c, const nnps_problem* p
         (e = c->partial.ensure(static_cast<size_t>(scan_partials_needed(scan_m) + 1) * 8)) != hipSuccess ||
         (e = c->stats.ensure(kStCount * 8)) != hipSuccess || (e = c->err.ensure(4)) != hipSuccess ||
         (e = c->heavy.ensure(nn * 4)) != hipSuccess || (e = c->nheavy.ensure(4)) != hipSuccess ||
-        (e = c->nnz.ensure(8)) != hipSuccess)
+        (e = c->nnz.ensure(8)) != hipSuccess ||
+        (e = c->blk_stats.ensure(static_cast<size_t>(std::max(c->nblk_max, 1)) * 5 * 8)) != hipSuccess)
         return e == hipErrorOutOfMemory ? NNPS_ENOMEM : NNPS_EDEVICE;
 
     c->fr = fr;
@@ -297,24 +354,35 @@ nnps_status nnps_cells_build(nnps_ctx* ctx, nnps_cells* c, const nnps_problem* p
     HIP_TRY(hipMemsetAsync(c->cell_count.p, 0, (ncell + 1) * 4, s));
     HIP_TRY(hipMemsetAsync(c->err.p, 0, 4, s));
     HIP_TRY(hipMemsetAsync(c->stats.p, 0, kStCount * 8, s));
+    PhaseTimer& tm = c->timer;
+    tm.begin(NNPS_PHASE_ASSIGN, s);
     HIP_TRY(launch_assign(d_pos, fr, c->X.as<int64_t>(), c->k0.as<uint32_t>(), c->cell_count.as<int>(),
                           c->err.as<int>(), s));
+    tm.end(NNPS_PHASE_ASSIGN, s);
+    tm.begin(NNPS_PHASE_CELLSCAN, s);
     HIP_TRY(launch_scan_i32_i32(c->cell_count.as<int>(), static_cast<int64_t>(ncell), c->cell_start.as<int>(),
                                 c->partial.as<int64_t>(), s));
+    tm.end(NNPS_PHASE_CELLSCAN, s);
     uint32_t* kf = c->k0.as<uint32_t>();
     int* vf = c->v0.as<int>();
+    tm.begin(NNPS_PHASE_SORT, s);
     if (fr.n > 0) {
         const int keybits = bitlen(static_cast<int64_t>(ncell) - 1);
         HIP_TRY(launch_radix_sort(fr.n, keybits, c->k0.as<uint32_t>(), c->v0.as<int>(), c->k1.as<uint32_t>(),
                                   c->v1.as<int>(), c->table.as<uint32_t>(), c->partial.as<int64_t>(), s, &kf,
                                   &vf));
     }
+    tm.end(NNPS_PHASE_SORT, s);
     c->skey = kf;
     c->perm = vf;
+    tm.begin(NNPS_PHASE_PACK, s);
     HIP_TRY(launch_pack(fr, c->perm, c->X.as<int64_t>(), c->q4.as<ushort4>(), d_pos,
                         base ? c->spos.as<double>() : nullptr, s));
+    tm.end(NNPS_PHASE_PACK, s);
+    tm.begin(NNPS_PHASE_BLOCKS, s);
     HIP_TRY(launch_blocks(fr, c->skey, c->cell_start.as<int>(), c->flags.as<int>(), c->bidx.as<int>(),
                           c->bstart.as<int>(), c->partial.as<int64_t>(), s));
+    tm.end(NNPS_PHASE_BLOCKS, s);
     c->built = true;
     return NNPS_OK;
 }
@@ -336,6 +404,7 @@ static SearchArgs args_of(nnps_cells* c)
     a.heavy = c->heavy.as<int>();
     a.nheavy = c->nheavy.as<int>();
     a.stats = c->stats.as<unsigned long long>();
+    a.blk_stats = c->blk_stats.as<unsigned long long>();
     a.err = c->err.as<int>();
     return a;
 }
@@ -357,8 +426,12 @@ nnps_status nnps_count(nnps_ctx* ctx, nnps_cells* c, int64_t* d_row_ptr, int64_t
     hipStream_t s = static_cast<hipStream_t>(stream);
     SearchArgs a = args_of(c);
     HIP_TRY(hipMemsetAsync(c->stats.p, 0, kStCount * 8, s));
+    c->timer.begin(NNPS_PHASE_COUNT, s);
     HIP_TRY(launch_count(a, c->nblk_max, s));
+    c->timer.end(NNPS_PHASE_COUNT, s);
+    c->timer.begin(NNPS_PHASE_ROWSCAN, s);
     HIP_TRY(launch_scan_i32_i64(c->counts.as<int>(), c->fr.n, d_row_ptr, c->partial.as<int64_t>(), s));
+    c->timer.end(NNPS_PHASE_ROWSCAN, s);
     HIP_TRY(hipMemcpyAsync(c->nnz.p, d_row_ptr + c->fr.n, 8, hipMemcpyDeviceToDevice, s));
     c->counted = true;
     if (h_nnz) {
@@ -388,7 +461,12 @@ nnps_status nnps_fill(nnps_ctx* ctx, nnps_cells* c, const int64_t* d_row_ptr, in
     a.dist = d_dist;
     a.capacity = capacity;
     HIP_TRY(hipMemsetAsync(c->nheavy.p, 0, 4, s));
+    c->timer.begin(NNPS_PHASE_FILL, s);
     HIP_TRY(launch_fill(a, c->nblk_max, s));
+    c->timer.end(NNPS_PHASE_FILL, s);
+    c->timer.begin(NNPS_PHASE_LONGROWS, s);
+    HIP_TRY(launch_long_rows(a, s));
+    c->timer.end(NNPS_PHASE_LONGROWS, s);
     return NNPS_OK;
 }
 
@@ -435,6 +513,39 @@ nnps_status nnps_stats_get(nnps_cells* c, nnps_stats* out, void* stream)
     out->cell_width = c->fr.w;
     out->band = ldexp(1.0, -7);
     return err_status(err);
+}
+
+nnps_status nnps_cells_set_profiling(nnps_cells* c, int on)
+{
+    if (!c) return NNPS_EINVAL;
+    DeviceGuard g(c->ctx->device);
+    if (!g.ok) return NNPS_EDEVICE;
+    c->timer.reset();
+    c->timer.on = on != 0;
+    return NNPS_OK;
+}
+
+nnps_status nnps_phase_times(nnps_cells* c, double* ms, int32_t* runs, void* stream)
+{
+    if (!c || !ms || !runs) return NNPS_EINVAL;
+    for (int k = 0; k < NNPS_NPHASES; ++k) {
+        ms[k] = 0.0;
+        runs[k] = 0;
+    }
+    if (!c->timer.on) return NNPS_EORDER;
+    DeviceGuard g(c->ctx->device);
+    if (!g.ok) return NNPS_EDEVICE;
+    HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    for (int k = 0; k < NNPS_NPHASES; ++k) {
+        for (const auto& pr : c->timer.rec[k]) {
+            float t = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&t, c->timer.pool[pr.first], c->timer.pool[pr.second]));
+            ms[k] += t;
+            runs[k] += 1;
+        }
+    }
+    c->timer.reset();
+    return NNPS_OK;
 }
 
 }  // extern "C"

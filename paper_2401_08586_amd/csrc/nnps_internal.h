@@ -8,15 +8,19 @@ namespace nnps {
 
 // Targets per work block: one wavefront, one target per lane.
 constexpr int kWave = 64;
-// Candidate positions staged in LDS per chunk (even).
-constexpr int kStage = 1024;
-// Per-lane row buffers in the fill pass (entries); longer rows take the long-row path.
-constexpr int kCap2 = 32;
-constexpr int kCap3 = 96;
+// Candidate positions staged in LDS per chunk in the count pass (even).
+constexpr int kStage = 512;
+// Fill pass: largest candidate union of a block (staged whole and ranked by original
+// index) and largest number of CSR entries of a block; blocks above either limit send
+// their rows to the long-row path.
+constexpr int kUnion2 = 512;
+constexpr int kUnion3 = 1024;
+constexpr int kFlat2 = 2048;
+constexpr int kFlat3 = 4608;
 // Longest row the long-row path sorts in LDS.
 constexpr int kHeavySortMax = 4096;
-// Block cuts every 512 cells along x, so the staged cell offsets stay exact in FP16.
-constexpr int kXSpanShift = 9;
+// Largest x-window (cells) of a block; keeps staged cell offsets exact in FP16.
+constexpr int kMaxXWin = 256;
 
 // Device error flags.
 constexpr int kErrDomain = 1;
@@ -47,6 +51,7 @@ struct Frame {
     double s;           // 2^F / w
     double R2;          // fl(R*R)
     float dist_scale;   // (float)(w * 2^-F)
+    int xwin;           // blocks never cross a multiple of xwin cells along x
     uint16_t t_lo, t_hi, t_mid;  // FP16 thresholds on r2 = 4|delta|^2 (bit patterns)
 };
 

@@ -163,11 +163,12 @@ struct Geom {
 
     __device__ __forceinline__ int global_of_any(int posl) const
     {
-        int r = 0;
+        // static indices only, so the segment tables stay in registers
+        int gi = posl - seg_base[0] + seg_g0[0];
 #pragma unroll
         for (int k = 1; k < NSEG; ++k)
-            if (posl >= seg_base[k]) r = k;
-        return global_of(r, posl);
+            if (posl >= seg_base[k]) gi = posl - seg_base[k] + seg_g0[k];
+        return gi;
     }
 };
 
@@ -250,7 +251,7 @@ __device__ __forceinline__ bool classify(const SearchArgs& a, const Geom<DIM>& g
                                          int cb, int* oj_out)
 {
     const Frame& fr = a.fr;
-    t.cand++;
+    if (MODE == 2) t.cand++;  // MODE 0 counts candidates from the lane's ranges
     const bool in16 = r2h < fr.t_lo;
     const bool band = !in16 && r2h <= fr.t_hi;
     bool nb;
@@ -273,7 +274,75 @@ __device__ __forceinline__ bool classify(const SearchArgs& a, const Geom<DIM>& g
 }
 
 // ---------------------------------------------------------------------------
-// Count pass (FP16 modes).
+// Branch-free classification of a pair of FP16 r2 values. Non-negative FP16 bit
+// patterns order like unsigned integers, so with d = r2 - T_lo per 16-bit half
+// (wrapping): the sign bit of d is set exactly when r2 < T_lo ("in"), and
+// sat16(d + 0xFFFE - (T_hi - T_lo)) is 0xFFFF exactly when r2 lies outside
+// [T_lo, T_hi] (not in the band). Halves to ignore get r2 bits >= 0x7C00 (+inf),
+// which land in neither class.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ u16x2 as_u16x2(uint32_t u) { return __builtin_bit_cast(u16x2, u); }
+__device__ __forceinline__ uint32_t u16x2_bits(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+
+struct Thresh {
+    u16x2 tlo2, bias2;
+    __device__ __forceinline__ void init(const Frame& fr)
+    {
+        tlo2 = u16x2{fr.t_lo, fr.t_lo};
+        const uint16_t b = static_cast<uint16_t>(0xFFFE - (fr.t_hi - fr.t_lo));
+        bias2 = u16x2{b, b};
+    }
+};
+
+constexpr uint32_t kInvLo = 0x7C00u, kInvHi = 0x7C000000u;
+
+// Per-lane queue of band pairs (logical position and FP16 r2 bits), held in registers
+// and rechecked after the loop so the FP64 work runs with the lanes converged. Band
+// pairs are rare (about two per target in 3D); a full queue makes the caller recheck
+// on the spot.
+struct BandQueue {
+    static constexpr int kCap = 4;
+    int p0 = 0, p1 = 0, p2 = 0, p3 = 0;
+    uint32_t r0 = 0, r1 = 0, r2 = 0, r3 = 0;
+    int n = 0;
+    // a shift register, so no entry is ever addressed by a runtime index
+    __device__ __forceinline__ bool push(int posl, uint32_t r2h)
+    {
+        if (n >= kCap) return false;
+        p3 = p2; p2 = p1; p1 = p0; p0 = posl;
+        r3 = r2; r2 = r1; r1 = r0; r0 = r2h;
+        ++n;
+        return true;
+    }
+    template <typename F>
+    __device__ __forceinline__ void drain(F&& f) const
+    {
+        if (n > 0) f(p0, r0);
+        if (n > 1) f(p1, r1);
+        if (n > 2) f(p2, r2);
+        if (n > 3) f(p3, r3);
+    }
+};
+
+// Visit the pair records covering logical positions [lo, hi) of one row segment:
+// the first and last records may hold a position outside the range, which is masked.
+template <typename F>
+__device__ __forceinline__ void for_pairs(int lo, int hi, F&& body)
+{
+    int m = lo >> 1;
+    const int mend = (hi + 1) >> 1;
+    if (m < mend) {
+        const uint32_t inv = ((lo & 1) ? kInvLo : 0u) | ((2 * m + 1 >= hi) ? kInvHi : 0u);
+        body(m, inv);
+        ++m;
+    }
+    const int mlast = (hi & 1) ? mend - 1 : mend;
+    for (; m < mlast; ++m) body(m, 0u);
+    if (m < mend) body(m, kInvHi);
+}
+
+// ---------------------------------------------------------------------------
+// Count pass, FP16 relative coordinates (MODE 0; MODE 2 decides every candidate in FP64).
 template <int DIM, int MODE>
 __global__ void __launch_bounds__(64)
 k_count16(SearchArgs a)
@@ -281,6 +350,7 @@ k_count16(SearchArgs a)
     __shared__ uint4 srec[kStage / 2];
     const int b = blockIdx.x;
     if (b >= *a.nblk) return;
+    const int lane = threadIdx.x & 63;
     Geom<DIM> g;
     g.init(a, b);
     const Frame& fr = a.fr;
@@ -291,6 +361,10 @@ k_count16(SearchArgs a)
     for (int k = 0; k < DIM; ++k) pi[k] = a.pos[static_cast<size_t>(oi) * DIM + k];
     Target16<DIM> tg;
     tg.init(a.q4[pp], g.x, g.sx0);
+    Thresh th;
+    th.init(fr);
+    BandQueue bq;
+    uint32_t cnt = 0;
     Tally t;
     for (int cb = 0; cb < g.U; cb += kStage) {
         const int ce = min(g.U, cb + kStage);
@@ -305,27 +379,96 @@ k_count16(SearchArgs a)
             const int dy = r % 3 - 1, dz = DIM == 3 ? r / 3 - 1 : 0;
             const h2 ay = splat(tg.qiy + static_cast<_Float16>(-2 * dy));
             const h2 az = splat(tg.qiz + static_cast<_Float16>(-2 * dz));
-            const int selfp = (r == Geom<DIM>::SELF) ? g.pself : -1;
-            for (int m = lo >> 1; m < (hi + 1) >> 1; ++m) {
-                const uint4 rec = srec[m - (cb >> 1)];
-                const uint32_t rb = r2_pair<DIM>(tg, ay, az, rec);
+            if constexpr (MODE == 2) {
+                const int selfp = (r == Geom<DIM>::SELF) ? g.pself : -1;
+                for_pairs(lo, hi, [&](int m, uint32_t inv) {
+                    const uint32_t rb = r2_pair<DIM>(tg, ay, az, srec[m - (cb >> 1)]);
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int posl = 2 * m + h;
-                    if (posl < lo || posl >= hi || posl == selfp) continue;
-                    int oj;
-                    t.cnt += classify<DIM, MODE>(a, g, pi, r, posl, (rb >> (16 * h)) & 0xFFFF, t,
-                                                 nullptr, cb, &oj);
+                    for (int h = 0; h < 2; ++h) {
+                        const int posl = 2 * m + h;
+                        if (((inv >> (16 * h)) & 0xFFFF) || posl == selfp) continue;
+                        int oj;
+                        cnt += classify<DIM, MODE>(a, g, pi, r, posl, (rb >> (16 * h)) & 0xFFFF, t, nullptr,
+                                                   cb, &oj);
+                    }
+                });
+            } else {
+                const uint4* rec = srec - (cb >> 1);
+                auto band = [&](int m, uint32_t rb, uint32_t x) {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        if (((x >> (16 * h)) & 0xFFFF) == 0xFFFF) continue;
+                        const int posl = 2 * m + h;
+                        const uint32_t r2h = (rb >> (16 * h)) & 0xFFFF;
+                        if (!bq.push(posl, r2h) && posl != g.pself) {
+                            int oj;
+                            cnt += classify<DIM, 0>(a, g, pi, r, posl, r2h, t, nullptr, cb, &oj);
+                        }
+                    }
+                };
+                auto one = [&](int m, uint32_t inv) {
+                    const uint32_t rb = r2_pair<DIM>(tg, ay, az, rec[m]) | inv;
+                    const u16x2 d = as_u16x2(rb) - th.tlo2;
+                    cnt += __builtin_popcount(u16x2_bits(d) & 0x80008000u);
+                    const uint32_t x = u16x2_bits(__builtin_elementwise_add_sat(d, th.bias2));
+                    if (x != 0xFFFFFFFFu) band(m, rb, x);
+                };
+                int m = lo >> 1;
+                const int mend = (hi + 1) >> 1;
+                if (m < mend) {
+                    one(m, ((lo & 1) ? kInvLo : 0u) | ((2 * m + 1 >= hi) ? kInvHi : 0u));
+                    ++m;
                 }
+                const int mlast = (hi & 1) ? mend - 1 : mend;
+                for (; m + 1 < mlast; m += 2) {
+                    const uint4 ra = rec[m], rc = rec[m + 1];
+                    const uint32_t A = r2_pair<DIM>(tg, ay, az, ra);
+                    const uint32_t B = r2_pair<DIM>(tg, ay, az, rc);
+                    const u16x2 dA = as_u16x2(A) - th.tlo2;
+                    const u16x2 dB = as_u16x2(B) - th.tlo2;
+                    cnt += __builtin_popcount(u16x2_bits(dA) & 0x80008000u) +
+                           __builtin_popcount(u16x2_bits(dB) & 0x80008000u);
+                    const uint32_t xA = u16x2_bits(__builtin_elementwise_add_sat(dA, th.bias2));
+                    const uint32_t xB = u16x2_bits(__builtin_elementwise_add_sat(dB, th.bias2));
+                    if ((xA & xB) != 0xFFFFFFFFu) {
+                        if (xA != 0xFFFFFFFFu) band(m, A, xA);
+                        if (xB != 0xFFFFFFFFu) band(m + 1, B, xB);
+                    }
+                }
+                if (m < mlast) {
+                    one(m, 0u);
+                    ++m;
+                }
+                if (m < mend) one(m, kInvHi);
             }
         }
     }
-    if (g.active) a.counts[oi] = t.cnt;
+    if constexpr (MODE == 0) {
+        // self (r2 = 0) was counted as "in" when T_lo > 0, or queued as a band pair
+        if (g.active && fr.t_lo > 0) cnt -= 1;
+        bq.drain([&](int posl, uint32_t r2h) {
+            if (posl == g.pself) return;
+            const int oj = a.perm[g.global_of_any(posl)];
+            const bool truth = recheck<DIM>(a.pos, pi, oj, fr.R2);
+            const bool naive = r2h <= fr.t_mid;
+            t.band++;
+            t.fpos += naive && !truth;
+            t.fneg += !naive && truth;
+            cnt += truth;
+        });
+        // candidates: the lane's ranges minus itself
+        if (g.active) {
+#pragma unroll
+            for (int r = 0; r < Geom<DIM>::NSEG; ++r) t.cand += g.lb[r] - g.la[r];
+            t.cand -= 1;
+        }
+    }
+    if (g.active) a.counts[oi] = static_cast<int>(cnt);
     unsigned long long v[5] = {t.cand, t.band, t.fpos, t.fneg, t.odis};
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-        const unsigned long long s = wave_sum_u64(v[k]);
-        if ((threadIdx.x & 63) == 0 && s) atomicAdd(&a.stats[k], s);
+        const unsigned long long sum = wave_sum_u64(v[k]);
+        if (lane == 0) a.blk_stats[static_cast<size_t>(b) * 5 + k] = sum;
     }
 }
 
@@ -347,65 +490,311 @@ k_count64(SearchArgs a)
 #pragma unroll
         for (int r = 0; r < Geom<DIM>::NSEG; ++r) {
             const int ga = g.global_of(r, g.la[r]), gb = g.global_of(r, g.lb[r]);
+            cand += gb - ga;
             for (int j = ga; j < gb; ++j) {
-                if (j == g.p) continue;
                 const double* pj = a.spos + static_cast<size_t>(j) * 4;
                 cnt += r2_fp64<DIM>(pix, pj) <= fr.R2;
-                cand++;
             }
         }
+        cnt -= 1;  // itself (r2 = 0)
+        cand -= 1;
         a.counts[a.perm[g.p]] = cnt;
     }
     const unsigned long long s = wave_sum_u64(cand);
-    if ((threadIdx.x & 63) == 0) atomicAdd(&a.stats[kStCandidates], s);
+    if ((threadIdx.x & 63) < 5)
+        a.blk_stats[static_cast<size_t>(b) * 5 + (threadIdx.x & 63)] = (threadIdx.x & 63) == 0 ? s : 0ull;
 }
 
-// ---------------------------------------------------------------------------
-// Fill pass helpers: per-lane row buffers in LDS, sorted by insertion, then written
-// cooperatively: the wave walks the concatenation of its 64 rows, 64 entries at a time,
-// so consecutive lanes store consecutive CSR slots.
-template <int CAP>
-__device__ __forceinline__ void lane_sort(int* lst, int len)
+// Sum of the per-block statistics (one workgroup; no contended atomics).
+__global__ void __launch_bounds__(1024)
+k_reduce_stats(const unsigned long long* __restrict__ blk, const int* __restrict__ nblk,
+               unsigned long long* __restrict__ out)
 {
-    for (int i = 1; i < len; ++i) {
-        const int v = lst[i];
-        int k = i - 1;
-        while (k >= 0 && lst[k] > v) {
-            lst[k + 1] = lst[k];
-            --k;
-        }
-        lst[k + 1] = v;
+    __shared__ unsigned long long sh[16][5];
+    const int nb = *nblk;
+    unsigned long long acc[5] = {0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nb; b += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < 5; ++k) acc[k] += blk[static_cast<size_t>(b) * 5 + k];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const unsigned long long s = wave_sum_u64(acc[k]);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        unsigned long long s = 0;
+        for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) s += sh[w][threadIdx.x];
+        out[threadIdx.x] = s;
     }
 }
 
-template <int DIM, int MODE, int CAP>
-__device__ __forceinline__ void emit_rows(const SearchArgs& a, int* lists, int mylen, bool mine,
-                                          int oi, int* soff, long long* srow, int* soi)
+// ---------------------------------------------------------------------------
+// Fill pass. The block's whole candidate union is staged and sorted once by original
+// index (a bitonic network over the wavefront's registers); each lane then records its
+// accepted neighbours as a bitmask over those ranks, so reading the bits in order gives
+// the row in ascending original index with no per-row sort. The rows are compacted into
+// one flat list per block and written 64 entries at a time: consecutive lanes store
+// consecutive CSR slots.
+template <int DIM>
+struct FillCfg {
+    static constexpr int UCAP = DIM == 3 ? kUnion3 : kUnion2;
+    static constexpr int MW = UCAP / 32;    // mask words per lane
+    static constexpr int FCAP = DIM == 3 ? kFlat3 : kFlat2;
+    static constexpr int SHIFT = DIM == 3 ? 10 : 9;  // log2(UCAP): key = orig << SHIFT | pos
+};
+
+// Bitonic sort of 64*EPL keys held blocked across the wavefront (element e = lane*EPL + i).
+template <int EPL>
+__device__ __forceinline__ void wave_bitonic(uint32_t (&v)[EPL])
 {
     const int lane = threadIdx.x & 63;
+    constexpr int P = 64 * EPL;
+#pragma unroll
+    for (int k = 2; k <= P; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= EPL) {
+                const int lx = j / EPL;
+                const bool lower = (lane & lx) == 0;
+                const bool asc = ((lane * EPL) & k) == 0;
+#pragma unroll
+                for (int i = 0; i < EPL; ++i) {
+                    const uint32_t w = static_cast<uint32_t>(__shfl_xor(static_cast<int>(v[i]), lx, 64));
+                    const uint32_t mn = min(v[i], w), mx = max(v[i], w);
+                    v[i] = (lower == asc) ? mn : mx;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < EPL; ++i) {
+                    if (i & j) continue;
+                    const bool asc = ((lane * EPL + i) & k) == 0;
+                    const uint32_t x = v[i], y = v[i | j];
+                    const uint32_t mn = min(x, y), mx = max(x, y);
+                    v[i] = asc ? mn : mx;
+                    v[i | j] = asc ? mx : mn;
+                }
+            }
+        }
+    }
+}
+
+// Ranks of the staged union by original index: rank_of[pos] and, in place of the
+// per-position original indices, orig[rank].
+template <int EPL, int SHIFT>
+__device__ __forceinline__ void rank_union(int U, int* sorig, uint16_t* rank_of)
+{
+    const int lane = threadIdx.x & 63;
+    uint32_t v[EPL];
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) {
+        const int e = lane * EPL + i;
+        v[i] = e < U ? (static_cast<uint32_t>(sorig[e]) << SHIFT) | static_cast<uint32_t>(e) : 0xFFFFFFFFu;
+    }
+    __builtin_amdgcn_wave_barrier();
+    wave_bitonic<EPL>(v);
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) {
+        const int e = lane * EPL + i;
+        if (e < U) {
+            rank_of[v[i] & ((1u << SHIFT) - 1)] = static_cast<uint16_t>(e);
+            sorig[e] = static_cast<int>(v[i] >> SHIFT);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int SHIFT>
+__device__ __forceinline__ void rank_union_any(int U, int* sorig, uint16_t* rank_of)
+{
+    if (U <= 64) rank_union<1, SHIFT>(U, sorig, rank_of);
+    else if (U <= 128) rank_union<2, SHIFT>(U, sorig, rank_of);
+    else if (U <= 256) rank_union<4, SHIFT>(U, sorig, rank_of);
+    else if (U <= 512) rank_union<8, SHIFT>(U, sorig, rank_of);
+    else rank_union<16, SHIFT>(U, sorig, rank_of);
+}
+
+template <int DIM, int MODE>
+__global__ void __launch_bounds__(64)
+k_fill(SearchArgs a)
+{
+    using C = FillCfg<DIM>;
+    // LDS: the pair records and rank table are dead once the rows are
+    // compacted, so the flat entry list reuses their space.
+    constexpr int kRecBytes = (C::UCAP / 2) * 16;
+    constexpr int kQBytes = 0;
+    constexpr int kRankBytes = C::UCAP * 2;
+    constexpr int kFlatBytes = C::FCAP * 3;
+    constexpr int kPhaseA = kRecBytes + kQBytes + kRankBytes;
+    constexpr int kShared = kPhaseA > kFlatBytes ? kPhaseA : kFlatBytes;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[kShared];
+    __shared__ int sorig[C::UCAP];
+    __shared__ uint32_t masks[64 * (C::MW + 1)];
+    __shared__ int soff[65];
+    __shared__ long long srow[64];
+    __shared__ int soi[64];
+    __shared__ long long sxi[64 * DIM];
+    uint4* srec = reinterpret_cast<uint4*>(smem);
+    uint16_t* rank_of = reinterpret_cast<uint16_t*>(smem + kRecBytes + kQBytes);
+    uint16_t* flat_rank = reinterpret_cast<uint16_t*>(smem);
+    uint8_t* flat_row = smem + C::FCAP * 2;
+
+    const int b = blockIdx.x;
+    if (b >= *a.nblk) return;
+    const int lane = threadIdx.x & 63;
+    Geom<DIM> g;
+    g.init(a, b);
+    const Frame& fr = a.fr;
+    const int pp = g.active ? g.p : g.p1 - 1;
+    const int oi = a.perm[pp];
+    const long long rs = a.row_ptr[oi];
+    const int rlen = g.active ? static_cast<int>(a.row_ptr[oi + 1] - rs) : 0;
     int E;
-    const int off = wave_excl_scan_i32(mine ? mylen : 0, &E);
+    const int off = wave_excl_scan_i32(rlen, &E);
+    if (g.U > C::UCAP || E > C::FCAP) {
+        // too big for this path: every row of the block goes to the long-row path
+        if (g.active) a.heavy[atomicAdd(a.nheavy, 1)] = g.p;
+        return;
+    }
+    // stage the union: original indices (all modes) and FP16 pair records
+    const int U = g.U;
+    if constexpr (MODE != 1) stage<DIM, true>(a, g, 0, U, srec, sorig);
+    else
+        for (int e = lane; e < U; e += 64) sorig[e] = a.perm[g.global_of_any(e)];
+    uint32_t* mk = masks + lane * (C::MW + 1);
+#pragma unroll
+    for (int w = 0; w < C::MW; ++w) mk[w] = 0;
+    __syncthreads();
+    rank_union_any<C::SHIFT>(U, sorig, rank_of);
+    __syncthreads();
+    const uint32_t* rank32 = reinterpret_cast<const uint32_t*>(rank_of);
+
+    double pi[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) pi[k] = a.pos[static_cast<size_t>(oi) * DIM + k];
+    BandQueue bq;
+    auto setbit = [&](uint32_t rk) { atomicOr(&mk[rk >> 5], 1u << (rk & 31)); };
+
+    if (g.active) {
+        if constexpr (MODE == 1) {
+            const double* ps = a.spos + static_cast<size_t>(g.p) * 4;
+            const double pix[3] = {ps[0], ps[1], DIM == 3 ? ps[2] : 0.0};
+#pragma unroll
+            for (int r = 0; r < Geom<DIM>::NSEG; ++r) {
+                const int ga = g.global_of(r, g.la[r]), gb = g.global_of(r, g.lb[r]);
+                for (int j = ga; j < gb; ++j) {
+                    const double* pj = a.spos + static_cast<size_t>(j) * 4;
+                    if (r2_fp64<DIM>(pix, pj) <= fr.R2) setbit(rank_of[j - g.seg_g0[r] + g.seg_base[r]]);
+                }
+            }
+        } else {
+            Target16<DIM> tg;
+            tg.init(a.q4[pp], g.x, g.sx0);
+            Thresh th;
+            th.init(fr);
+            Tally t;
+#pragma unroll
+            for (int r = 0; r < Geom<DIM>::NSEG; ++r) {
+                const int lo = g.la[r], hi = g.lb[r];
+                if (lo >= hi) continue;
+                const int dy = r % 3 - 1, dz = DIM == 3 ? r / 3 - 1 : 0;
+                const h2 ay = splat(tg.qiy + static_cast<_Float16>(-2 * dy));
+                const h2 az = splat(tg.qiz + static_cast<_Float16>(-2 * dz));
+                if constexpr (MODE == 2) {
+                    for_pairs(lo, hi, [&](int m, uint32_t inv) {
+                        const uint32_t rb = r2_pair<DIM>(tg, ay, az, srec[m]);
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const int posl = 2 * m + h;
+                            if ((inv >> (16 * h)) & 0xFFFF) continue;
+                            int oj;
+                            if (classify<DIM, 2>(a, g, pi, r, posl, (rb >> (16 * h)) & 0xFFFF, t, nullptr, 0, &oj))
+                                setbit(rank_of[posl]);
+                        }
+                    });
+                } else {
+                    for_pairs(lo, hi, [&](int m, uint32_t inv) {
+                        const uint32_t rb = r2_pair<DIM>(tg, ay, az, srec[m]) | inv;
+                        const u16x2 d = as_u16x2(rb) - th.tlo2;
+                        const uint32_t inb = u16x2_bits(d) & 0x80008000u;
+                        if (inb) {
+                            const uint32_t rk2 = rank32[m];
+                            if (inb & 0x8000u) setbit(rk2 & 0xFFFF);
+                            if (inb & 0x80000000u) setbit(rk2 >> 16);
+                        }
+                        const uint32_t x = u16x2_bits(__builtin_elementwise_add_sat(d, th.bias2));
+                        if (x != 0xFFFFFFFFu) {
+#pragma unroll
+                            for (int h = 0; h < 2; ++h) {
+                                if (((x >> (16 * h)) & 0xFFFF) == 0xFFFF) continue;
+                                const int posl = 2 * m + h;
+                                const uint32_t r2h = (rb >> (16 * h)) & 0xFFFF;
+                                if (!bq.push(posl, r2h) && posl != g.pself) {
+                                    const int oj = a.perm[g.global_of_any(posl)];
+                                    if (recheck<DIM>(a.pos, pi, oj, fr.R2)) setbit(rank_of[posl]);
+                                }
+                            }
+                        }
+                    });
+                }
+            }
+            bq.drain([&](int posl, uint32_t) {
+                if (posl == g.pself) return;
+                const int oj = a.perm[g.global_of_any(posl)];
+                if (recheck<DIM>(a.pos, pi, oj, fr.R2)) setbit(rank_of[posl]);
+            });
+        }
+        // the target itself is never its own neighbour
+        const uint32_t rself = rank_of[g.pself];
+        mk[rself >> 5] &= ~(1u << (rself & 31));
+    }
+    // compaction: each lane walks its mask in rank order
     soff[lane] = off;
     if (lane == 63) soff[64] = E;
-    srow[lane] = mine ? a.row_ptr[oi] : 0;
+    srow[lane] = rs;
     soi[lane] = oi;
+    if (MODE != 1) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) sxi[lane * DIM + k] = a.X[static_cast<size_t>(k) * fr.n + oi];
+    }
+    __syncthreads();  // rank table, queue and records are dead from here on
+    int got = 0;
+    if (g.active) {
+        const int nw = (U + 31) >> 5;
+        for (int w = 0; w < nw; ++w) {
+            uint32_t bits = mk[w];
+            while (bits) {
+                const int bi = __builtin_ctz(bits);
+                bits &= bits - 1;
+                if (got < rlen) {
+                    flat_rank[off + got] = static_cast<uint16_t>(w * 32 + bi);
+                    flat_row[off + got] = static_cast<uint8_t>(lane);
+                }
+                ++got;
+            }
+        }
+        if (got != rlen) atomicOr(a.err, kErrLongRow);
+    }
     __syncthreads();
     for (int e0 = 0; e0 < E; e0 += 64) {
         const int e = e0 + lane;
         if (e >= E) break;
-        int lo = 0, hi = 63;  // largest t with soff[t] <= e
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (soff[mid] <= e) lo = mid;
-            else hi = mid - 1;
-        }
-        const int t = lo;
+        const int t = flat_row[e];
+        const int oj = sorig[flat_rank[e]];
         const int k = e - soff[t];
-        const int oj = lists[t * (CAP + 1) + k];
-        const int ot = soi[t];
         float d;
-        if (MODE == 1) d = dist_fp64<DIM>(a.pos, ot, oj);
-        else d = dist_fixed<DIM>(a.X, a.fr.n, ot, oj, a.fr.dist_scale);
+        if constexpr (MODE == 1) {
+            d = dist_fp64<DIM>(a.pos, soi[t], oj);
+        } else {
+            float s2 = 0.0f;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                const int64_t dx = a.X[static_cast<size_t>(c) * fr.n + oj] - sxi[t * DIM + c];
+                const float f = exact_i64_to_f32_s(dx);
+                s2 = s2 + f * f;
+            }
+            d = __builtin_sqrtf(s2) * fr.dist_scale;
+        }
         const long long idx = srow[t] + k;
         if (idx < a.capacity) {
             a.col[idx] = oj;
@@ -414,123 +803,6 @@ __device__ __forceinline__ void emit_rows(const SearchArgs& a, int* lists, int m
             atomicOr(a.err, kErrCapacity);
         }
     }
-}
-
-template <int DIM, int MODE>
-__global__ void __launch_bounds__(64)
-k_fill16(SearchArgs a)
-{
-    constexpr int CAP = DIM == 3 ? kCap3 : kCap2;
-    __shared__ uint4 srec[kStage / 2];
-    __shared__ int sorig[kStage];
-    __shared__ int lists[64 * (CAP + 1)];
-    __shared__ int soff[65];
-    __shared__ long long srow[64];
-    __shared__ int soi[64];
-    const int b = blockIdx.x;
-    if (b >= *a.nblk) return;
-    const int lane = threadIdx.x & 63;
-    Geom<DIM> g;
-    g.init(a, b);
-    const Frame& fr = a.fr;
-    const int pp = g.active ? g.p : g.p1 - 1;
-    const int oi = a.perm[pp];
-    const long long rlen = g.active ? a.row_ptr[oi + 1] - a.row_ptr[oi] : 0;
-    const bool heavy = g.active && rlen > CAP;
-    const bool work = g.active && !heavy;
-    if (heavy) {
-        const int h = atomicAdd(a.nheavy, 1);
-        a.heavy[h] = g.p;
-    }
-    double pi[3] = {0, 0, 0};
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) pi[k] = a.pos[static_cast<size_t>(oi) * DIM + k];
-    Target16<DIM> tg;
-    tg.init(a.q4[pp], g.x, g.sx0);
-    int* lst = lists + lane * (CAP + 1);
-    int len = 0;
-    Tally t;
-    for (int cb = 0; cb < g.U; cb += kStage) {
-        const int ce = min(g.U, cb + kStage);
-        __syncthreads();
-        stage<DIM, true>(a, g, cb, ce, srec, sorig);
-        __syncthreads();
-        if (!work) continue;
-#pragma unroll
-        for (int r = 0; r < Geom<DIM>::NSEG; ++r) {
-            const int lo = max(g.la[r], cb), hi = min(g.lb[r], ce);
-            if (lo >= hi) continue;
-            const int dy = r % 3 - 1, dz = DIM == 3 ? r / 3 - 1 : 0;
-            const h2 ay = splat(tg.qiy + static_cast<_Float16>(-2 * dy));
-            const h2 az = splat(tg.qiz + static_cast<_Float16>(-2 * dz));
-            const int selfp = (r == Geom<DIM>::SELF) ? g.pself : -1;
-            for (int m = lo >> 1; m < (hi + 1) >> 1; ++m) {
-                const uint4 rec = srec[m - (cb >> 1)];
-                const uint32_t rb = r2_pair<DIM>(tg, ay, az, rec);
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int posl = 2 * m + h;
-                    if (posl < lo || posl >= hi || posl == selfp) continue;
-                    int oj;
-                    if (classify<DIM, MODE>(a, g, pi, r, posl, (rb >> (16 * h)) & 0xFFFF, t, sorig, cb,
-                                            &oj)) {
-                        if (len < CAP) lst[len] = oj;
-                        ++len;
-                    }
-                }
-            }
-        }
-    }
-    if (work && len != rlen) atomicOr(a.err, kErrLongRow);
-    if (work) lane_sort<CAP>(lst, len < CAP ? len : CAP);
-    emit_rows<DIM, MODE, CAP>(a, lists, len < CAP ? len : CAP, work, oi, soff, srow, soi);
-}
-
-template <int DIM>
-__global__ void __launch_bounds__(64)
-k_fill64(SearchArgs a)
-{
-    constexpr int CAP = DIM == 3 ? kCap3 : kCap2;
-    __shared__ int lists[64 * (CAP + 1)];
-    __shared__ int soff[65];
-    __shared__ long long srow[64];
-    __shared__ int soi[64];
-    const int b = blockIdx.x;
-    if (b >= *a.nblk) return;
-    const int lane = threadIdx.x & 63;
-    Geom<DIM> g;
-    g.init(a, b);
-    const Frame& fr = a.fr;
-    const int pp = g.active ? g.p : g.p1 - 1;
-    const int oi = a.perm[pp];
-    const long long rlen = g.active ? a.row_ptr[oi + 1] - a.row_ptr[oi] : 0;
-    const bool heavy = g.active && rlen > CAP;
-    const bool work = g.active && !heavy;
-    if (heavy) {
-        const int h = atomicAdd(a.nheavy, 1);
-        a.heavy[h] = g.p;
-    }
-    int* lst = lists + lane * (CAP + 1);
-    int len = 0;
-    if (work) {
-        const double* pi = a.spos + static_cast<size_t>(g.p) * 4;
-        const double pix[3] = {pi[0], pi[1], DIM == 3 ? pi[2] : 0.0};
-#pragma unroll
-        for (int r = 0; r < Geom<DIM>::NSEG; ++r) {
-            const int ga = g.global_of(r, g.la[r]), gb = g.global_of(r, g.lb[r]);
-            for (int j = ga; j < gb; ++j) {
-                if (j == g.p) continue;
-                const double* pj = a.spos + static_cast<size_t>(j) * 4;
-                if (r2_fp64<DIM>(pix, pj) <= fr.R2) {
-                    if (len < CAP) lst[len] = a.perm[j];
-                    ++len;
-                }
-            }
-        }
-        if (len != rlen) atomicOr(a.err, kErrLongRow);
-        lane_sort<CAP>(lst, len < CAP ? len : CAP);
-    }
-    emit_rows<DIM, 1, CAP>(a, lists, len < CAP ? len : CAP, work, oi, soff, srow, soi);
 }
 
 // ---------------------------------------------------------------------------
@@ -675,6 +947,7 @@ hipError_t launch_count(const SearchArgs& a, int nblk_max, hipStream_t st)
     else if (d == 3 && m == 2) hipLaunchKernelGGL((k_count16<3, 2>), g, b, 0, st, a);
     else if (d == 2) hipLaunchKernelGGL(k_count64<2>, g, b, 0, st, a);
     else hipLaunchKernelGGL(k_count64<3>, g, b, 0, st, a);
+    hipLaunchKernelGGL(k_reduce_stats, dim3(1), dim3(1024), 0, st, a.blk_stats, a.nblk, a.stats);
     return hipGetLastError();
 }
 
@@ -683,14 +956,19 @@ hipError_t launch_fill(const SearchArgs& a, int nblk_max, hipStream_t st)
     if (a.fr.n == 0 || nblk_max == 0) return hipSuccess;
     const dim3 g(nblk_max), b(64);
     const int d = a.fr.dim, m = a.fr.mode;
-    if (d == 2 && m == 0) hipLaunchKernelGGL((k_fill16<2, 0>), g, b, 0, st, a);
-    else if (d == 3 && m == 0) hipLaunchKernelGGL((k_fill16<3, 0>), g, b, 0, st, a);
-    else if (d == 2 && m == 2) hipLaunchKernelGGL((k_fill16<2, 2>), g, b, 0, st, a);
-    else if (d == 3 && m == 2) hipLaunchKernelGGL((k_fill16<3, 2>), g, b, 0, st, a);
-    else if (d == 2) hipLaunchKernelGGL(k_fill64<2>, g, b, 0, st, a);
-    else hipLaunchKernelGGL(k_fill64<3>, g, b, 0, st, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (d == 2 && m == 0) hipLaunchKernelGGL((k_fill<2, 0>), g, b, 0, st, a);
+    else if (d == 3 && m == 0) hipLaunchKernelGGL((k_fill<3, 0>), g, b, 0, st, a);
+    else if (d == 2 && m == 2) hipLaunchKernelGGL((k_fill<2, 2>), g, b, 0, st, a);
+    else if (d == 3 && m == 2) hipLaunchKernelGGL((k_fill<3, 2>), g, b, 0, st, a);
+    else if (d == 2) hipLaunchKernelGGL((k_fill<2, 1>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((k_fill<3, 1>), g, b, 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_long_rows(const SearchArgs& a, hipStream_t st)
+{
+    if (a.fr.n == 0) return hipSuccess;
+    const int d = a.fr.dim, m = a.fr.mode;
     const dim3 gh(512), bh(kHeavyThreads);
     if (d == 2 && m == 0) hipLaunchKernelGGL((k_heavy<2, 0>), gh, bh, 0, st, a);
     else if (d == 3 && m == 0) hipLaunchKernelGGL((k_heavy<3, 0>), gh, bh, 0, st, a);

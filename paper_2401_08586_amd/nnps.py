@@ -57,7 +57,9 @@ class Stats(ctypes.Structure):
 
 EXPORTS = ["nnps_status_str", "nnps_validate", "nnps_grid", "nnps_ctx_create", "nnps_ctx_destroy",
            "nnps_cells_create", "nnps_cells_destroy", "nnps_cells_build", "nnps_count", "nnps_fill",
-           "nnps_search", "nnps_stats_get"]
+           "nnps_search", "nnps_stats_get", "nnps_cells_set_profiling", "nnps_phase_times"]
+
+PHASES = ["assign", "cellscan", "sort", "pack", "blocks", "count", "rowscan", "fill", "longrows"]
 
 _lib = None
 
@@ -89,6 +91,8 @@ def load():
     lib.nnps_fill.argtypes = [P, P, P, P, P, I64, P]
     lib.nnps_search.argtypes = [P, P, ctypes.POINTER(Problem), P, P, P, P, I64, ctypes.POINTER(I64), P]
     lib.nnps_stats_get.argtypes = [P, ctypes.POINTER(Stats), P]
+    lib.nnps_cells_set_profiling.argtypes = [P, ctypes.c_int]
+    lib.nnps_phase_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), P]
     for name in EXPORTS:
         fn = getattr(lib, name)
         if name not in ("nnps_status_str", "nnps_ctx_destroy", "nnps_cells_destroy"):
@@ -219,6 +223,16 @@ class Cells:
         assert dist.numel() == cap
         _check(self._lib.nnps_fill(self.ctx._ctx, self._h, _ptr(row_ptr), _ptr(col), _ptr(dist), cap,
                                    _stream_ptr(stream)), "nnps_fill")
+
+    def set_profiling(self, on: bool = True):
+        _check(self._lib.nnps_cells_set_profiling(self._h, 1 if on else 0), "nnps_cells_set_profiling")
+
+    def phase_times(self, stream=None) -> dict:
+        """{phase: (summed device ms, launches)} since profiling was turned on or last read."""
+        ms = (ctypes.c_double * len(PHASES))()
+        runs = (ctypes.c_int32 * len(PHASES))()
+        _check(self._lib.nnps_phase_times(self._h, ms, runs, _stream_ptr(stream)), "nnps_phase_times")
+        return {k: (ms[i], runs[i]) for i, k in enumerate(PHASES)}
 
     def stats(self, stream=None) -> dict:
         st = Stats()
