@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 512 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path "
@@ -138,6 +140,13 @@ def main():
         res64 = {"value": nnz / (ms64 * 1e-3) / 1e9, "unit": "Gpairs/s", "ms_per_step": ms64,
                  "phases_ms": ph64, "speedup_fp16_over_fp64": ms64 / ms16}
     ctx.close()
+    if args.copy_probe:
+        src = torch.ones(1 << 27, dtype=torch.float32, device="cuda")  # 512 MiB
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     fill_ms = ph16["fill"]
     fb = fill_bytes(ps, nnz, st16["band_pairs"])

@@ -44,6 +44,7 @@ struct SearchArgs {
     int* nheavy;
     unsigned long long* stats;      // [kStCount] totals
     unsigned long long* blk_stats;  // [nblk_max][5] per-block partial statistics
+    uint32_t* cbits;                // accepted-candidate bits, word-major [words][n]
     int* err;
 };
 

@@ -20,7 +20,8 @@ __device__ __forceinline__ float exact_i64_to_f32(int64_t v)
 }
 
 // ---------------------------------------------------------------------------
-// A1: cell assignment in FP64. X = rint((p - lo) * 2^F / w) (round half to even),
+// A1: cell assignment in FP64. X = rint((p - lo) * 2^F / w) (round half to even, stored
+// per particle with stride x_stride),
 // cell = X >> F, key = cx + ncx (cy + ncy cz). Positions outside [lo, hi] (or NaN)
 // raise the domain flag and are treated as lo so every index stays in range.
 template <int DIM>
@@ -42,7 +43,7 @@ k_assign(const double* __restrict__ pos, Frame fr, int64_t* __restrict__ X,
         const double d = __dsub_rn(p, fr.lo[k]);
         const double t = __dmul_rn(d, fr.s);
         const int64_t x = static_cast<int64_t>(rint(t));
-        X[static_cast<size_t>(k) * fr.n + i] = x;
+        X[static_cast<size_t>(i) * x_stride(DIM) + k] = x;
         c[k] = x >> fr.F;
     }
     const uint32_t kk = static_cast<uint32_t>(c[0] + fr.nc[0] * (c[1] + fr.nc[1] * c[2]));
@@ -282,7 +283,7 @@ k_pack(Frame fr, const int* __restrict__ perm, const int64_t* __restrict__ X,
     const float scale = __builtin_ldexpf(1.0f, 1 - fr.F);
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-        const int64_t x = X[static_cast<size_t>(k) * fr.n + o];
+        const int64_t x = X[static_cast<size_t>(o) * x_stride(DIM) + k];
         const int64_t c = x >> fr.F;
         const int64_t D = x - (c << fr.F) - (int64_t(1) << (fr.F - 1));
         const _Float16 q = static_cast<_Float16>(exact_i64_to_f32(D) * scale);

@@ -196,7 +196,7 @@ struct nnps_cells {
     uint32_t* skey = nullptr;
     int* perm = nullptr;
     DevBuf X, k0, k1, v0, v1, cell_count, cell_start, q4, spos, flags, bidx, bstart, counts, table,
-        partial, stats, blk_stats, err, heavy, nheavy, nnz;
+        partial, stats, blk_stats, cbits, err, heavy, nheavy, nnz;
 };
 
 #define HIP_TRY(x)                                \
@@ -300,7 +300,7 @@ void nnps_cells_destroy(nnps_cells* c)
     DeviceGuard g(c->ctx->device);
     DevBuf* all[] = {&c->X, &c->k0, &c->k1, &c->v0, &c->v1, &c->cell_count, &c->cell_start, &c->q4,
                      &c->spos, &c->flags, &c->bidx, &c->bstart, &c->counts, &c->table, &c->partial,
-                     &c->stats, &c->blk_stats, &c->err, &c->heavy, &c->nheavy, &c->nnz};
+                     &c->stats, &c->blk_stats, &c->cbits, &c->err, &c->heavy, &c->nheavy, &c->nnz};
     for (DevBuf* b : all) b->release();
     c->timer.release();
     delete c;
@@ -330,7 +330,7 @@ nnps_status nnps_cells_build(nnps_ctx* ctx, nnps_cells* c, const nnps_problem* p
 
     const bool base = fr.mode == NNPS_MODE_FP64_BASELINE;
     hipError_t e = hipSuccess;
-    if ((e = c->X.ensure(nn * fr.dim * sizeof(int64_t))) != hipSuccess ||
+    if ((e = c->X.ensure(nn * x_stride(fr.dim) * sizeof(int64_t))) != hipSuccess ||
         (e = c->k0.ensure(nn * 4)) != hipSuccess || (e = c->k1.ensure(nn * 4)) != hipSuccess ||
         (e = c->v0.ensure(nn * 4)) != hipSuccess || (e = c->v1.ensure(nn * 4)) != hipSuccess ||
         (e = c->cell_count.ensure((ncell + 1) * 4)) != hipSuccess ||
@@ -344,7 +344,8 @@ nnps_status nnps_cells_build(nnps_ctx* ctx, nnps_cells* c, const nnps_problem* p
         (e = c->stats.ensure(kStCount * 8)) != hipSuccess || (e = c->err.ensure(4)) != hipSuccess ||
         (e = c->heavy.ensure(nn * 4)) != hipSuccess || (e = c->nheavy.ensure(4)) != hipSuccess ||
         (e = c->nnz.ensure(8)) != hipSuccess ||
-        (e = c->blk_stats.ensure(static_cast<size_t>(std::max(c->nblk_max, 1)) * 5 * 8)) != hipSuccess)
+        (e = c->blk_stats.ensure(static_cast<size_t>(std::max(c->nblk_max, 1)) * 5 * 8)) != hipSuccess ||
+        (e = c->cbits.ensure(nn * (fr.dim == 3 ? kCandWords3 : kCandWords2) * 4)) != hipSuccess)
         return e == hipErrorOutOfMemory ? NNPS_ENOMEM : NNPS_EDEVICE;
 
     c->fr = fr;
@@ -405,6 +406,7 @@ static SearchArgs args_of(nnps_cells* c)
     a.nheavy = c->nheavy.as<int>();
     a.stats = c->stats.as<unsigned long long>();
     a.blk_stats = c->blk_stats.as<unsigned long long>();
+    a.cbits = c->cbits.as<uint32_t>();
     a.err = c->err.as<int>();
     return a;
 }

@@ -17,6 +17,13 @@ constexpr int kUnion2 = 512;
 constexpr int kUnion3 = 1024;
 constexpr int kFlat2 = 2048;
 constexpr int kFlat3 = 4608;
+// Accepted-candidate bits the count pass keeps per target (32 candidates per word),
+// stored word-major so a wavefront's stores coalesce. Targets with more candidates
+// take the long-row path in the fill.
+constexpr int kCandWords2 = 8;
+constexpr int kCandWords3 = 24;
+// Fixed-point positions are stored per particle, padded to a power of two of int64.
+__host__ __device__ constexpr int x_stride(int dim) { return dim == 3 ? 4 : 2; }
 // Longest row the long-row path sorts in LDS.
 constexpr int kHeavySortMax = 4096;
 // Largest x-window (cells) of a block; keeps staged cell offsets exact in FP16.

@@ -61,11 +61,11 @@ __device__ __forceinline__ float dist_fixed(const int64_t* __restrict__ X, int n
     float s2 = 0.0f;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-        const int64_t d = X[static_cast<size_t>(k) * n + oj] - X[static_cast<size_t>(k) * n + oi];
+        const int64_t d = X[static_cast<size_t>(oj) * x_stride(DIM) + k] - X[static_cast<size_t>(oi) * x_stride(DIM) + k];
         const float f = exact_i64_to_f32_s(d);
         s2 = s2 + f * f;
     }
-    return __builtin_sqrtf(s2) * scale;
+    return __builtin_amdgcn_sqrtf(s2) * scale;  // <= 1 ulp; s2 >= 1 or 0
 }
 
 template <int DIM>
@@ -342,12 +342,60 @@ __device__ __forceinline__ void for_pairs(int lo, int hi, F&& body)
 }
 
 // ---------------------------------------------------------------------------
+// Per-lane record of accepted candidates, one bit per candidate in the lane's own
+// candidate order (row segment by row segment). Kept in LDS during the count pass and
+// written out word-major (cbits[w * n + p]) so the fill pass never repeats the test.
+template <int DIM>
+struct CandBits {
+    static constexpr int CW = DIM == 3 ? kCandWords3 : kCandWords2;
+    static constexpr int NSEG = Geom<DIM>::NSEG;
+    uint32_t* w;
+    int segoff[NSEG];
+    int total;
+    bool keep;
+    __device__ __forceinline__ void init(const Geom<DIM>& g, uint32_t* lds)
+    {
+        const int lane = threadIdx.x & 63;
+        w = lds + lane * (CW + 1);
+        total = 0;
+#pragma unroll
+        for (int r = 0; r < NSEG; ++r) {
+            segoff[r] = total;
+            total += g.lb[r] - g.la[r];
+        }
+        keep = g.active && total <= 32 * CW;
+#pragma unroll
+        for (int k = 0; k < CW; ++k) w[k] = 0;
+    }
+    __device__ __forceinline__ void set(int ci)
+    {
+        if (keep) atomicOr(&w[ci >> 5], 1u << (ci & 31));
+    }
+    // candidate index of a logical position inside the lane's ranges
+    __device__ __forceinline__ int index_of(const Geom<DIM>& g, int posl) const
+    {
+        int ci = 0;
+#pragma unroll
+        for (int r = 0; r < NSEG; ++r)
+            if (posl >= g.la[r] && posl < g.lb[r]) ci = segoff[r] + posl - g.la[r];
+        return ci;
+    }
+    __device__ __forceinline__ void store(const SearchArgs& a, int p) const
+    {
+        if (!keep) return;
+        const int nw = (total + 31) >> 5;
+        for (int k = 0; k < nw; ++k) a.cbits[static_cast<size_t>(k) * a.fr.n + p] = w[k];
+    }
+};
+
 // Count pass, FP16 relative coordinates (MODE 0; MODE 2 decides every candidate in FP64).
 template <int DIM, int MODE>
 __global__ void __launch_bounds__(64)
 k_count16(SearchArgs a)
 {
+    using CB = CandBits<DIM>;
     __shared__ uint4 srec[kStage / 2];
+    __shared__ uint32_t lbits[64 * (CB::CW + 1)];
     const int b = blockIdx.x;
     if (b >= *a.nblk) return;
     const int lane = threadIdx.x & 63;
@@ -363,6 +411,8 @@ k_count16(SearchArgs a)
     tg.init(a.q4[pp], g.x, g.sx0);
     Thresh th;
     th.init(fr);
+    CB cb_;
+    cb_.init(g, lbits);
     BandQueue bq;
     uint32_t cnt = 0;
     Tally t;
@@ -379,6 +429,7 @@ k_count16(SearchArgs a)
             const int dy = r % 3 - 1, dz = DIM == 3 ? r / 3 - 1 : 0;
             const h2 ay = splat(tg.qiy + static_cast<_Float16>(-2 * dy));
             const h2 az = splat(tg.qiz + static_cast<_Float16>(-2 * dz));
+            const int cbase = cb_.segoff[r] - g.la[r];  // candidate index = cbase + posl
             if constexpr (MODE == 2) {
                 const int selfp = (r == Geom<DIM>::SELF) ? g.pself : -1;
                 for_pairs(lo, hi, [&](int m, uint32_t inv) {
@@ -388,8 +439,11 @@ k_count16(SearchArgs a)
                         const int posl = 2 * m + h;
                         if (((inv >> (16 * h)) & 0xFFFF) || posl == selfp) continue;
                         int oj;
-                        cnt += classify<DIM, MODE>(a, g, pi, r, posl, (rb >> (16 * h)) & 0xFFFF, t, nullptr,
-                                                   cb, &oj);
+                        if (classify<DIM, MODE>(a, g, pi, r, posl, (rb >> (16 * h)) & 0xFFFF, t, nullptr, cb,
+                                                &oj)) {
+                            ++cnt;
+                            cb_.set(cbase + posl);
+                        }
                     }
                 });
             } else {
@@ -402,14 +456,23 @@ k_count16(SearchArgs a)
                         const uint32_t r2h = (rb >> (16 * h)) & 0xFFFF;
                         if (!bq.push(posl, r2h) && posl != g.pself) {
                             int oj;
-                            cnt += classify<DIM, 0>(a, g, pi, r, posl, r2h, t, nullptr, cb, &oj);
+                            if (classify<DIM, 0>(a, g, pi, r, posl, r2h, t, nullptr, cb, &oj)) {
+                                ++cnt;
+                                cb_.set(cbase + posl);
+                            }
                         }
                     }
+                };
+                auto accept = [&](int m, uint32_t inb) {
+                    cnt += __builtin_popcount(inb);
+                    if (inb & 0x8000u) cb_.set(cbase + 2 * m);
+                    if (inb & 0x80000000u) cb_.set(cbase + 2 * m + 1);
                 };
                 auto one = [&](int m, uint32_t inv) {
                     const uint32_t rb = r2_pair<DIM>(tg, ay, az, rec[m]) | inv;
                     const u16x2 d = as_u16x2(rb) - th.tlo2;
-                    cnt += __builtin_popcount(u16x2_bits(d) & 0x80008000u);
+                    const uint32_t inb = u16x2_bits(d) & 0x80008000u;
+                    if (inb) accept(m, inb);
                     const uint32_t x = u16x2_bits(__builtin_elementwise_add_sat(d, th.bias2));
                     if (x != 0xFFFFFFFFu) band(m, rb, x);
                 };
@@ -426,8 +489,12 @@ k_count16(SearchArgs a)
                     const uint32_t B = r2_pair<DIM>(tg, ay, az, rc);
                     const u16x2 dA = as_u16x2(A) - th.tlo2;
                     const u16x2 dB = as_u16x2(B) - th.tlo2;
-                    cnt += __builtin_popcount(u16x2_bits(dA) & 0x80008000u) +
-                           __builtin_popcount(u16x2_bits(dB) & 0x80008000u);
+                    const uint32_t inA = u16x2_bits(dA) & 0x80008000u;
+                    const uint32_t inB = u16x2_bits(dB) & 0x80008000u;
+                    if (inA | inB) {
+                        accept(m, inA);
+                        accept(m + 1, inB);
+                    }
                     const uint32_t xA = u16x2_bits(__builtin_elementwise_add_sat(dA, th.bias2));
                     const uint32_t xB = u16x2_bits(__builtin_elementwise_add_sat(dB, th.bias2));
                     if ((xA & xB) != 0xFFFFFFFFu) {
@@ -455,15 +522,13 @@ k_count16(SearchArgs a)
             t.fpos += naive && !truth;
             t.fneg += !naive && truth;
             cnt += truth;
+            if (truth) cb_.set(cb_.index_of(g, posl));
         });
         // candidates: the lane's ranges minus itself
-        if (g.active) {
-#pragma unroll
-            for (int r = 0; r < Geom<DIM>::NSEG; ++r) t.cand += g.lb[r] - g.la[r];
-            t.cand -= 1;
-        }
+        if (g.active) t.cand += cb_.total - 1;
     }
     if (g.active) a.counts[oi] = static_cast<int>(cnt);
+    cb_.store(a, g.p);
     unsigned long long v[5] = {t.cand, t.band, t.fpos, t.fneg, t.odis};
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
@@ -477,11 +542,15 @@ template <int DIM>
 __global__ void __launch_bounds__(64)
 k_count64(SearchArgs a)
 {
+    using CB = CandBits<DIM>;
+    __shared__ uint32_t lbits[64 * (CB::CW + 1)];
     const int b = blockIdx.x;
     if (b >= *a.nblk) return;
     Geom<DIM> g;
     g.init(a, b);
     const Frame& fr = a.fr;
+    CB cb_;
+    cb_.init(g, lbits);
     int cnt = 0;
     unsigned long long cand = 0;
     if (g.active) {
@@ -490,16 +559,21 @@ k_count64(SearchArgs a)
 #pragma unroll
         for (int r = 0; r < Geom<DIM>::NSEG; ++r) {
             const int ga = g.global_of(r, g.la[r]), gb = g.global_of(r, g.lb[r]);
+            const int cbase = cb_.segoff[r] - ga;
             cand += gb - ga;
             for (int j = ga; j < gb; ++j) {
                 const double* pj = a.spos + static_cast<size_t>(j) * 4;
-                cnt += r2_fp64<DIM>(pix, pj) <= fr.R2;
+                if (r2_fp64<DIM>(pix, pj) <= fr.R2) {
+                    ++cnt;
+                    cb_.set(cbase + j);
+                }
             }
         }
         cnt -= 1;  // itself (r2 = 0)
         cand -= 1;
         a.counts[a.perm[g.p]] = cnt;
     }
+    cb_.store(a, g.p);
     const unsigned long long s = wave_sum_u64(cand);
     if ((threadIdx.x & 63) < 5)
         a.blk_stats[static_cast<size_t>(b) * 5 + (threadIdx.x & 63)] = (threadIdx.x & 63) == 0 ? s : 0ull;
@@ -619,14 +693,12 @@ __global__ void __launch_bounds__(64)
 k_fill(SearchArgs a)
 {
     using C = FillCfg<DIM>;
-    // LDS: the pair records and rank table are dead once the rows are
-    // compacted, so the flat entry list reuses their space.
-    constexpr int kRecBytes = (C::UCAP / 2) * 16;
-    constexpr int kQBytes = 0;
+    using CB = CandBits<DIM>;
+    // LDS: the rank table is dead once the rows are compacted, so the flat entry list
+    // reuses its space.
     constexpr int kRankBytes = C::UCAP * 2;
-    constexpr int kFlatBytes = C::FCAP * 3;
-    constexpr int kPhaseA = kRecBytes + kQBytes + kRankBytes;
-    constexpr int kShared = kPhaseA > kFlatBytes ? kPhaseA : kFlatBytes;
+    constexpr int kFlatBytes = C::FCAP * 2;
+    constexpr int kShared = kRankBytes > kFlatBytes ? kRankBytes : kFlatBytes;
     __shared__ __attribute__((aligned(16))) unsigned char smem[kShared];
     __shared__ int sorig[C::UCAP];
     __shared__ uint32_t masks[64 * (C::MW + 1)];
@@ -634,10 +706,8 @@ k_fill(SearchArgs a)
     __shared__ long long srow[64];
     __shared__ int soi[64];
     __shared__ long long sxi[64 * DIM];
-    uint4* srec = reinterpret_cast<uint4*>(smem);
-    uint16_t* rank_of = reinterpret_cast<uint16_t*>(smem + kRecBytes + kQBytes);
+    uint16_t* rank_of = reinterpret_cast<uint16_t*>(smem);
     uint16_t* flat_rank = reinterpret_cast<uint16_t*>(smem);
-    uint8_t* flat_row = smem + C::FCAP * 2;
 
     const int b = blockIdx.x;
     if (b >= *a.nblk) return;
@@ -651,157 +721,139 @@ k_fill(SearchArgs a)
     const int rlen = g.active ? static_cast<int>(a.row_ptr[oi + 1] - rs) : 0;
     int E;
     const int off = wave_excl_scan_i32(rlen, &E);
-    if (g.U > C::UCAP || E > C::FCAP) {
+    // the lane's candidate order (row segment by row segment), as in the count pass
+    int segoff[Geom<DIM>::NSEG];
+    int ctotal = 0;
+#pragma unroll
+    for (int r = 0; r < Geom<DIM>::NSEG; ++r) {
+        segoff[r] = ctotal;
+        ctotal += g.lb[r] - g.la[r];
+    }
+    const bool fits = !g.active || ctotal <= 32 * CB::CW;
+    if (g.U > C::UCAP || E > C::FCAP || __ballot(!fits) != 0) {
         // too big for this path: every row of the block goes to the long-row path
         if (g.active) a.heavy[atomicAdd(a.nheavy, 1)] = g.p;
         return;
     }
-    // stage the union: original indices (all modes) and FP16 pair records
+    // stage the union's original indices and rank them
     const int U = g.U;
-    if constexpr (MODE != 1) stage<DIM, true>(a, g, 0, U, srec, sorig);
-    else
-        for (int e = lane; e < U; e += 64) sorig[e] = a.perm[g.global_of_any(e)];
+    for (int e = lane; e < U; e += 64) sorig[e] = a.perm[g.global_of_any(e)];
     uint32_t* mk = masks + lane * (C::MW + 1);
 #pragma unroll
     for (int w = 0; w < C::MW; ++w) mk[w] = 0;
     __syncthreads();
     rank_union_any<C::SHIFT>(U, sorig, rank_of);
     __syncthreads();
-    const uint32_t* rank32 = reinterpret_cast<const uint32_t*>(rank_of);
-
     double pi[3] = {0, 0, 0};
+    if (MODE == 1) {
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) pi[k] = a.pos[static_cast<size_t>(oi) * DIM + k];
-    BandQueue bq;
-    auto setbit = [&](uint32_t rk) { atomicOr(&mk[rk >> 5], 1u << (rk & 31)); };
-
+        for (int k = 0; k < DIM; ++k) pi[k] = a.pos[static_cast<size_t>(oi) * DIM + k];
+    }
     if (g.active) {
-        if constexpr (MODE == 1) {
-            const double* ps = a.spos + static_cast<size_t>(g.p) * 4;
-            const double pix[3] = {ps[0], ps[1], DIM == 3 ? ps[2] : 0.0};
+        // accepted candidates from the count pass, re-indexed by rank
 #pragma unroll
-            for (int r = 0; r < Geom<DIM>::NSEG; ++r) {
-                const int ga = g.global_of(r, g.la[r]), gb = g.global_of(r, g.lb[r]);
-                for (int j = ga; j < gb; ++j) {
-                    const double* pj = a.spos + static_cast<size_t>(j) * 4;
-                    if (r2_fp64<DIM>(pix, pj) <= fr.R2) setbit(rank_of[j - g.seg_g0[r] + g.seg_base[r]]);
+        for (int r = 0; r < Geom<DIM>::NSEG; ++r) {
+            const int c0 = segoff[r], c1 = c0 + (g.lb[r] - g.la[r]);
+            if (c0 >= c1) continue;
+            const int pbase = g.la[r] - c0;  // logical position = pbase + candidate index
+            for (int w = c0 >> 5; w <= ((c1 - 1) >> 5); ++w) {
+                uint32_t bits = a.cbits[static_cast<size_t>(w) * fr.n + g.p];
+                const int lo = c0 - 32 * w, hi = c1 - 32 * w;
+                if (lo > 0) bits &= ~0u << lo;
+                if (hi < 32) bits &= (1u << hi) - 1u;
+                while (bits) {
+                    const int ci = 32 * w + __builtin_ctz(bits);
+                    bits &= bits - 1;
+                    const uint32_t rk = rank_of[pbase + ci];
+                    atomicOr(&mk[rk >> 5], 1u << (rk & 31));
                 }
             }
-        } else {
-            Target16<DIM> tg;
-            tg.init(a.q4[pp], g.x, g.sx0);
-            Thresh th;
-            th.init(fr);
-            Tally t;
-#pragma unroll
-            for (int r = 0; r < Geom<DIM>::NSEG; ++r) {
-                const int lo = g.la[r], hi = g.lb[r];
-                if (lo >= hi) continue;
-                const int dy = r % 3 - 1, dz = DIM == 3 ? r / 3 - 1 : 0;
-                const h2 ay = splat(tg.qiy + static_cast<_Float16>(-2 * dy));
-                const h2 az = splat(tg.qiz + static_cast<_Float16>(-2 * dz));
-                if constexpr (MODE == 2) {
-                    for_pairs(lo, hi, [&](int m, uint32_t inv) {
-                        const uint32_t rb = r2_pair<DIM>(tg, ay, az, srec[m]);
-#pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            const int posl = 2 * m + h;
-                            if ((inv >> (16 * h)) & 0xFFFF) continue;
-                            int oj;
-                            if (classify<DIM, 2>(a, g, pi, r, posl, (rb >> (16 * h)) & 0xFFFF, t, nullptr, 0, &oj))
-                                setbit(rank_of[posl]);
-                        }
-                    });
-                } else {
-                    for_pairs(lo, hi, [&](int m, uint32_t inv) {
-                        const uint32_t rb = r2_pair<DIM>(tg, ay, az, srec[m]) | inv;
-                        const u16x2 d = as_u16x2(rb) - th.tlo2;
-                        const uint32_t inb = u16x2_bits(d) & 0x80008000u;
-                        if (inb) {
-                            const uint32_t rk2 = rank32[m];
-                            if (inb & 0x8000u) setbit(rk2 & 0xFFFF);
-                            if (inb & 0x80000000u) setbit(rk2 >> 16);
-                        }
-                        const uint32_t x = u16x2_bits(__builtin_elementwise_add_sat(d, th.bias2));
-                        if (x != 0xFFFFFFFFu) {
-#pragma unroll
-                            for (int h = 0; h < 2; ++h) {
-                                if (((x >> (16 * h)) & 0xFFFF) == 0xFFFF) continue;
-                                const int posl = 2 * m + h;
-                                const uint32_t r2h = (rb >> (16 * h)) & 0xFFFF;
-                                if (!bq.push(posl, r2h) && posl != g.pself) {
-                                    const int oj = a.perm[g.global_of_any(posl)];
-                                    if (recheck<DIM>(a.pos, pi, oj, fr.R2)) setbit(rank_of[posl]);
-                                }
-                            }
-                        }
-                    });
-                }
-            }
-            bq.drain([&](int posl, uint32_t) {
-                if (posl == g.pself) return;
-                const int oj = a.perm[g.global_of_any(posl)];
-                if (recheck<DIM>(a.pos, pi, oj, fr.R2)) setbit(rank_of[posl]);
-            });
         }
         // the target itself is never its own neighbour
         const uint32_t rself = rank_of[g.pself];
         mk[rself >> 5] &= ~(1u << (rself & 31));
     }
-    // compaction: each lane walks its mask in rank order
+    // compaction: each lane walks its mask in rank order into the block's flat list
     soff[lane] = off;
     if (lane == 63) soff[64] = E;
     srow[lane] = rs;
     soi[lane] = oi;
-    if (MODE != 1) {
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) sxi[lane * DIM + k] = a.X[static_cast<size_t>(k) * fr.n + oi];
+    for (int k = 0; k < DIM; ++k) {
+        // the target's own coordinates for the distance: fixed point, or FP64 bits (baseline)
+        sxi[lane * DIM + k] = MODE == 1 ? __builtin_bit_cast(long long, pi[k])
+                                        : a.X[static_cast<size_t>(oi) * x_stride(DIM) + k];
     }
-    __syncthreads();  // rank table, queue and records are dead from here on
-    int got = 0;
+    __syncthreads();  // rank table and records are dead from here on
     if (g.active) {
         const int nw = (U + 31) >> 5;
+        int got = 0;
         for (int w = 0; w < nw; ++w) {
             uint32_t bits = mk[w];
             while (bits) {
                 const int bi = __builtin_ctz(bits);
                 bits &= bits - 1;
-                if (got < rlen) {
-                    flat_rank[off + got] = static_cast<uint16_t>(w * 32 + bi);
-                    flat_row[off + got] = static_cast<uint8_t>(lane);
-                }
+                if (got < rlen) flat_rank[off + got] = static_cast<uint16_t>(w * 32 + bi);
                 ++got;
             }
         }
         if (got != rlen) atomicOr(a.err, kErrLongRow);
     }
     __syncthreads();
-    for (int e0 = 0; e0 < E; e0 += 64) {
-        const int e = e0 + lane;
-        if (e >= E) break;
-        const int t = flat_row[e];
-        const int oj = sorig[flat_rank[e]];
-        const int k = e - soff[t];
-        float d;
-        if constexpr (MODE == 1) {
-            d = dist_fp64<DIM>(a.pos, soi[t], oj);
-        } else {
-            float s2 = 0.0f;
+    // Emission, 64 entries per round. The next round's gathers are issued before this
+    // round's stores: vector-memory counters order loads and stores together, so a load
+    // issued after a store would wait for that store.
+    struct Ent {
+        int t, oj;
+        long long idx;
+        long long xj[DIM];
+    };
+    auto fetch = [&](int e, int tstart, Ent& s) {
+        s.t = tstart;
+        if (e >= E) return;
+        int t = tstart;
+        while (soff[t + 1] <= e) ++t;  // rows are short: a few steps at most
+        s.t = t;
+        s.oj = sorig[flat_rank[e]];
+        s.idx = srow[t] + (e - soff[t]);
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) {
-                const int64_t dx = a.X[static_cast<size_t>(c) * fr.n + oj] - sxi[t * DIM + c];
-                const float f = exact_i64_to_f32_s(dx);
-                s2 = s2 + f * f;
+        for (int c = 0; c < DIM; ++c)
+            s.xj[c] = MODE == 1 ? __builtin_bit_cast(long long, a.pos[static_cast<size_t>(s.oj) * DIM + c])
+                                : a.X[static_cast<size_t>(s.oj) * x_stride(DIM) + c];
+    };
+    Ent cur;
+    fetch(lane, 0, cur);
+    for (int e0 = 0; e0 < E; e0 += 64) {
+        Ent nxt;
+        const int tn = __shfl(cur.t, 63, 64);
+        fetch(e0 + 64 + lane, tn, nxt);
+        if (e0 + lane < E) {
+            float d;
+            if constexpr (MODE == 1) {
+                double pi2[3], pj2[3];
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    pi2[c] = __builtin_bit_cast(double, sxi[cur.t * DIM + c]);
+                    pj2[c] = __builtin_bit_cast(double, cur.xj[c]);
+                }
+                d = static_cast<float>(__dsqrt_rn(r2_fp64<DIM>(pi2, pj2)));
+            } else {
+                float s2 = 0.0f;
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    const float f = exact_i64_to_f32_s(cur.xj[c] - sxi[cur.t * DIM + c]);
+                    s2 = s2 + f * f;
+                }
+                d = __builtin_amdgcn_sqrtf(s2) * fr.dist_scale;  // <= 1 ulp; s2 >= 1 or 0
             }
-            d = __builtin_sqrtf(s2) * fr.dist_scale;
+            if (cur.idx < a.capacity) {
+                a.col[cur.idx] = cur.oj;
+                a.dist[cur.idx] = d;
+            } else {
+                atomicOr(a.err, kErrCapacity);
+            }
         }
-        const long long idx = srow[t] + k;
-        if (idx < a.capacity) {
-            a.col[idx] = oj;
-            a.dist[idx] = d;
-        } else {
-            atomicOr(a.err, kErrCapacity);
-        }
+        cur = nxt;
     }
 }
 
