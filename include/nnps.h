@@ -94,6 +94,20 @@ typedef struct nnps_stats {
     double band;                    /* guard band, in units of w^2 */
 } nnps_stats;
 
+/* Work-shape parameters (nnps_ctx_set_tuning; picked per workload by an autotuner).
+ * block_target: mean particles per work block; a block is an x-window of about
+ *   block_target / (mean cell occupancy) cells in one row of cells, at most 64 particles.
+ *   Default 56. Valid 8..4096.
+ * long_rows_grid: workgroups of the long-row path. Default 1024. Valid 1..2^20.
+ * long_rows_keys: row entries the long-row path sorts in LDS at once (longer rows are
+ *   sorted in chunks and merged); 0 = as many as the device's LDS allows. Valid 0 or
+ *   64..16384, a power of two. */
+typedef struct nnps_tuning {
+    int32_t block_target;
+    int32_t long_rows_grid;
+    int32_t long_rows_keys;
+} nnps_tuning;
+
 typedef struct nnps_ctx nnps_ctx;
 typedef struct nnps_cells nnps_cells;
 
@@ -113,6 +127,10 @@ nnps_status nnps_grid(const nnps_problem *prob, int32_t ncell[3], int32_t *frac_
  * in library calls). One context per host thread at a time. */
 nnps_status nnps_ctx_create(int device, nnps_ctx **out);
 void nnps_ctx_destroy(nnps_ctx *ctx);
+
+/* Work-shape parameters used by later calls on this context. */
+nnps_status nnps_ctx_set_tuning(nnps_ctx *ctx, const nnps_tuning *t);
+nnps_status nnps_ctx_get_tuning(const nnps_ctx *ctx, nnps_tuning *t);
 
 /* An empty cell structure; its device buffers grow on demand and are reused. */
 nnps_status nnps_cells_create(nnps_ctx *ctx, nnps_cells **out);
@@ -147,6 +165,39 @@ nnps_status nnps_search(nnps_ctx *ctx, nnps_cells *cells, const nnps_problem *pr
 /* Waits for the stream, then copies the statistics of the last count pass.
  * Returns any device-detected error (NNPS_EDOMAIN, NNPS_ECAPACITY, NNPS_EUNSUPPORTED). */
 nnps_status nnps_stats_get(nnps_cells *cells, nnps_stats *out, void *stream);
+
+/* ---- Batches: many independent particle sets searched together -------------------
+ * One cell structure holds all sets of a batch in one index space, so every pass is a
+ * single kernel launch over the work blocks of every set (uneven sizes welcome). All
+ * sets of a batch must share dim and mode. Arrays indexed by set (probs, d_pos,
+ * d_row_ptr, d_col, d_dist, capacity, nnz) are host arrays of nsets entries; the device
+ * buffers they point to follow the single-set rules above, per set (col holds set-local
+ * indices). The statistics of a batch are totals over its sets. */
+nnps_status nnps_batch_build(nnps_ctx *ctx, nnps_cells *cells, int32_t nsets, const nnps_problem *probs,
+                             const double *const *d_pos, void *stream);
+/* Writes each set's row_ptr; with h_nnz (nsets entries) not NULL, waits and returns each
+ * set's nnz there. */
+nnps_status nnps_batch_count(nnps_ctx *ctx, nnps_cells *cells, int64_t *const *d_row_ptr, int64_t *h_nnz,
+                             void *stream);
+nnps_status nnps_batch_fill(nnps_ctx *ctx, nnps_cells *cells, int64_t *const *d_row_ptr, int32_t *const *d_col,
+                            float *const *d_dist, const int64_t *capacity, void *stream);
+/* Build + count (waits once) + fill; NNPS_ECAPACITY if some capacity[s] < nnz_out[s]. */
+nnps_status nnps_batch_search(nnps_ctx *ctx, nnps_cells *cells, int32_t nsets, const nnps_problem *probs,
+                              const double *const *d_pos, int64_t *const *d_row_ptr, int32_t *const *d_col,
+                              float *const *d_dist, const int64_t *capacity, int64_t *nnz_out, void *stream);
+
+/* Build + count + fill without waiting (capacities known in advance, e.g. from an earlier
+ * step). With graphs on (nnps_cells_set_graphs) and a non-null stream, the whole
+ * sequence is captured as one HIP graph on first use and replayed while the problems,
+ * the tuning and the library's buffers stay the same; output and position pointers may
+ * change between replays. Capacity overruns are reported by the next synchronising call
+ * (nnps_batch_nnz, nnps_stats_get). */
+nnps_status nnps_batch_step(nnps_ctx *ctx, nnps_cells *cells, int32_t nsets, const nnps_problem *probs,
+                            const double *const *d_pos, int64_t *const *d_row_ptr, int32_t *const *d_col,
+                            float *const *d_dist, const int64_t *capacity, void *stream);
+nnps_status nnps_cells_set_graphs(nnps_cells *cells, int on);
+/* Waits for the stream and returns each set's nnz of the last count (nsets entries). */
+nnps_status nnps_batch_nnz(nnps_cells *cells, int64_t *h_nnz, void *stream);
 
 /* Phases timed when profiling is on, in launch order. */
 enum {

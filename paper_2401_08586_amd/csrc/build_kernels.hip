@@ -5,6 +5,9 @@
 // section, Fig. 3b); cell-relative coordinates (Eq. 5-6, Fig. 5); spatial sorting
 // so that neighbouring threads work on neighbouring particles (Results, memory
 // section and Table 6).
+#include <algorithm>
+#include <utility>
+
 #include "build_kernels.h"
 
 namespace nnps {
@@ -21,21 +24,25 @@ __device__ __forceinline__ float exact_i64_to_f32(int64_t v)
 
 // ---------------------------------------------------------------------------
 // A1: cell assignment in FP64. X = rint((p - lo) * 2^F / w) (round half to even, stored
-// per particle with stride x_stride),
-// cell = X >> F, key = cx + ncx (cy + ncy cz). Positions outside [lo, hi] (or NaN)
-// raise the domain flag and are treated as lo so every index stays in range.
+// per particle with stride x_stride), cell = X >> F, global key = coff + cx + ncx (cy +
+// ncy cz). Positions outside [lo, hi] (or NaN) raise the domain flag and are treated as
+// lo so every index stays in range.
 template <int DIM>
 __global__ void __launch_bounds__(256)
-k_assign(const double* __restrict__ pos, Frame fr, int64_t* __restrict__ X,
-         uint32_t* __restrict__ key, int* __restrict__ cell_count, int* __restrict__ err)
+k_assign(const SetDesc* __restrict__ sets, const int* __restrict__ poffs, int nsets, int ntot,
+         int64_t* __restrict__ X, uint32_t* __restrict__ key, int* __restrict__ cell_count,
+         int* __restrict__ err)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= fr.n) return;
+    if (i >= ntot) return;
+    const SetDesc& sd = sets[find_set(poffs, nsets, i)];
+    const Frame& fr = sd.fr;
+    const int li = i - sd.poff;
     bool bad = false;
     int64_t c[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-        double p = pos[static_cast<size_t>(i) * DIM + k];
+        double p = sd.pos[static_cast<size_t>(li) * DIM + k];
         if (!(p >= fr.lo[k] && p <= fr.hi[k])) {
             bad = true;
             p = fr.lo[k];
@@ -46,10 +53,20 @@ k_assign(const double* __restrict__ pos, Frame fr, int64_t* __restrict__ X,
         X[static_cast<size_t>(i) * x_stride(DIM) + k] = x;
         c[k] = x >> fr.F;
     }
-    const uint32_t kk = static_cast<uint32_t>(c[0] + fr.nc[0] * (c[1] + fr.nc[1] * c[2]));
+    const uint32_t kk = static_cast<uint32_t>(sd.coff + c[0] + fr.nc[0] * (c[1] + fr.nc[1] * c[2]));
     key[i] = kk;
     atomicAdd(&cell_count[kk], 1);
     if (bad) atomicOr(err, kErrDomain);
+}
+
+// Fill an int32 array with a value (a kernel rather than a memset node, so the sequence
+// can be captured in a graph).
+__global__ void __launch_bounds__(256)
+k_fill_i32(int* __restrict__ p, int64_t m, int v)
+{
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < m;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -155,13 +172,17 @@ k_scan_down(const TIn* __restrict__ in, int64_t m, const int64_t* __restrict__ p
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[m] = static_cast<TOut>(partial[nt]);
 }
 
+template <typename T>
+__global__ void k_zero_one(T* p) { *p = T(0); }
+
 template <typename TIn, typename TOut>
 hipError_t scan_exclusive(const TIn* in, int64_t m, TOut* out, int64_t* partial, hipStream_t st)
 {
     const int64_t nt = (m + kScanTile - 1) / kScanTile;
     if (nt == 0) {
         // m == 0: out[0] = 0
-        return hipMemsetAsync(out, 0, sizeof(TOut), st);
+        hipLaunchKernelGGL(k_zero_one<TOut>, dim3(1), dim3(1), 0, st, out);
+        return hipGetLastError();
     }
     hipLaunchKernelGGL(k_scan_reduce<TIn>, dim3(nt), dim3(kScanThreads), 0, st, in, m, partial);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, st, partial, nt);
@@ -269,15 +290,19 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const int* __restrict__ vin,
 // The FP64 baseline instead gets a sorted copy of the caller's positions.
 template <int DIM>
 __global__ void __launch_bounds__(256)
-k_pack(Frame fr, const int* __restrict__ perm, const int64_t* __restrict__ X,
-       ushort4* __restrict__ q4, const double* __restrict__ pos, double* __restrict__ spos)
+k_pack(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nsets, int ntot,
+       const uint32_t* __restrict__ skey, const int* __restrict__ perm, const int64_t* __restrict__ X,
+       ushort4* __restrict__ q4, double* __restrict__ spos)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= fr.n) return;
+    if (p >= ntot) return;
+    const SetDesc& sd = sets[find_set(coffs, nsets, static_cast<int>(skey[p]))];
+    const Frame& fr = sd.fr;
     const int o = perm[p];
     if (spos) {
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) spos[static_cast<size_t>(p) * 4 + k] = pos[static_cast<size_t>(o) * DIM + k];
+        for (int k = 0; k < DIM; ++k)
+            spos[static_cast<size_t>(p) * 4 + k] = sd.pos[static_cast<size_t>(o - sd.poff) * DIM + k];
     }
     uint16_t h[4] = {0, 0, 0, 0};
     const float scale = __builtin_ldexpf(1.0f, 1 - fr.F);
@@ -295,42 +320,77 @@ k_pack(Frame fr, const int* __restrict__ perm, const int64_t* __restrict__ X,
 
 // ---------------------------------------------------------------------------
 // Work blocks: the particles of one x-window of fr.xwin cells inside one (y, z) row of
-// cells, split into runs of at most kWave particles.
+// cells of one set, split into runs of at most kWave particles.
 __global__ void __launch_bounds__(256)
-k_block_flags(Frame fr, const uint32_t* __restrict__ skey, const int* __restrict__ cell_start,
-              int* __restrict__ flags)
+k_block_flags(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nsets, int ntot,
+              const uint32_t* __restrict__ skey, const int* __restrict__ cell_start, int* __restrict__ flags)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= fr.n) return;
+    if (p >= ntot) return;
     const uint32_t key = skey[p];
-    const uint32_t ncx = static_cast<uint32_t>(fr.nc[0]);
-    const uint32_t row = key / ncx;
-    const uint32_t x = key - row * ncx;
-    const uint32_t win = x / static_cast<uint32_t>(fr.xwin);
-    const int ws = cell_start[row * ncx + win * static_cast<uint32_t>(fr.xwin)];
+    const SetDesc& sd = sets[find_set(coffs, nsets, static_cast<int>(key))];
+    const uint32_t lk = key - static_cast<uint32_t>(sd.coff);
+    const uint32_t ncx = static_cast<uint32_t>(sd.fr.nc[0]);
+    const uint32_t row = lk / ncx;
+    const uint32_t x = lk - row * ncx;
+    const uint32_t win = x / static_cast<uint32_t>(sd.fr.xwin);
+    const int ws = cell_start[sd.coff + row * ncx + win * static_cast<uint32_t>(sd.fr.xwin)];
     flags[p] = (p == ws) || (((p - ws) % kWave) == 0);
 }
 
 __global__ void __launch_bounds__(256)
-k_block_write(int n, const int* __restrict__ flags, const int* __restrict__ bidx,
-              int* __restrict__ bstart)
+k_block_write(const int* __restrict__ coffs, int nsets, int ntot, const uint32_t* __restrict__ skey,
+              const int* __restrict__ flags, const int* __restrict__ bidx, int* __restrict__ bstart,
+              int* __restrict__ bset)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < n && flags[p]) bstart[bidx[p]] = p;
-    if (p == 0) bstart[bidx[n]] = n;
+    if (p < ntot && flags[p]) {
+        bstart[bidx[p]] = p;
+        bset[bidx[p]] = find_set(coffs, nsets, static_cast<int>(skey[p]));
+    }
+    if (p == 0) bstart[bidx[ntot]] = ntot;
+}
+
+// Per-set CSR row pointers from the global exclusive scan of the counts (one thread per
+// row boundary: set s has n_s + 1 of them), and each set's nnz.
+__global__ void __launch_bounds__(256)
+k_rowptr_scatter(const SetDesc* __restrict__ sets, const int* __restrict__ poffs, int nsets, int ntot,
+                 const int64_t* __restrict__ rowg, int64_t* __restrict__ nnz)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntot + nsets) return;
+    // boundary t belongs to the last set s with poffs[s] + s <= t
+    int lo = 0, hi = nsets - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (poffs[mid] + mid <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const SetDesc& sd = sets[lo];
+    const int i = t - (sd.poff + lo);  // 0 .. n_s
+    const int64_t v = rowg[sd.poff + i] - rowg[sd.poff];
+    if (sd.row_ptr) sd.row_ptr[i] = v;
+    if (i == sd.fr.n) nnz[lo] = v;
 }
 
 // ---------------------------------------------------------------------------
 // Host-side launchers.
-hipError_t launch_assign(const double* pos, const Frame& fr, int64_t* X, uint32_t* key,
-                         int* cell_count, int* err, hipStream_t st)
+hipError_t launch_fill_i32(int* p, int64_t m, int v, hipStream_t st)
 {
-    if (fr.n == 0) return hipSuccess;
-    const dim3 g((fr.n + 255) / 256), b(256);
-    if (fr.dim == 2)
-        hipLaunchKernelGGL(k_assign<2>, g, b, 0, st, pos, fr, X, key, cell_count, err);
+    if (m <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((m + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks), dim3(256), 0, st, p, m, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_assign(const Launch& L, int64_t* X, uint32_t* key, int* cell_count, int* err, hipStream_t st)
+{
+    if (L.ntot == 0) return hipSuccess;
+    const dim3 g((L.ntot + 255) / 256), b(256);
+    if (L.dim == 2)
+        hipLaunchKernelGGL(k_assign<2>, g, b, 0, st, L.sets, L.poffs, L.nsets, L.ntot, X, key, cell_count, err);
     else
-        hipLaunchKernelGGL(k_assign<3>, g, b, 0, st, pos, fr, X, key, cell_count, err);
+        hipLaunchKernelGGL(k_assign<3>, g, b, 0, st, L.sets, L.poffs, L.nsets, L.ntot, X, key, cell_count, err);
     return hipGetLastError();
 }
 
@@ -339,14 +399,7 @@ hipError_t launch_scan_i32_i32(const int* in, int64_t m, int* out, int64_t* part
     return scan_exclusive<int, int>(in, m, out, partial, st);
 }
 
-hipError_t launch_scan_u32_u32(const uint32_t* in, int64_t m, uint32_t* out, int64_t* partial,
-                               hipStream_t st)
-{
-    return scan_exclusive<uint32_t, uint32_t>(in, m, out, partial, st);
-}
-
-hipError_t launch_scan_i32_i64(const int* in, int64_t m, int64_t* out, int64_t* partial,
-                               hipStream_t st)
+hipError_t launch_scan_i32_i64(const int* in, int64_t m, int64_t* out, int64_t* partial, hipStream_t st)
 {
     return scan_exclusive<int, int64_t>(in, m, out, partial, st);
 }
@@ -392,27 +445,38 @@ hipError_t launch_radix_sort(int n, int keybits, uint32_t* k0, int* v0, uint32_t
 
 size_t radix_table_entries(int n) { return static_cast<size_t>(radix_tiles(n)) << kRsMaxBits; }
 
-hipError_t launch_pack(const Frame& fr, const int* perm, const int64_t* X, ushort4* q4,
-                       const double* pos, double* spos, hipStream_t st)
+hipError_t launch_pack(const Launch& L, const uint32_t* skey, const int* perm, const int64_t* X, ushort4* q4,
+                       double* spos, hipStream_t st)
 {
-    if (fr.n == 0) return hipSuccess;
-    const dim3 g((fr.n + 255) / 256), b(256);
-    if (fr.dim == 2)
-        hipLaunchKernelGGL(k_pack<2>, g, b, 0, st, fr, perm, X, q4, pos, spos);
+    if (L.ntot == 0) return hipSuccess;
+    const dim3 g((L.ntot + 255) / 256), b(256);
+    if (L.dim == 2)
+        hipLaunchKernelGGL(k_pack<2>, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, perm, X, q4, spos);
     else
-        hipLaunchKernelGGL(k_pack<3>, g, b, 0, st, fr, perm, X, q4, pos, spos);
+        hipLaunchKernelGGL(k_pack<3>, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, perm, X, q4, spos);
     return hipGetLastError();
 }
 
-hipError_t launch_blocks(const Frame& fr, const uint32_t* skey, const int* cell_start, int* flags,
-                         int* bidx, int* bstart, int64_t* partial, hipStream_t st)
+hipError_t launch_blocks(const Launch& L, const uint32_t* skey, const int* cell_start, int* flags, int* bidx,
+                         int* bstart, int* bset, int64_t* partial, hipStream_t st)
 {
-    if (fr.n == 0) return hipMemsetAsync(bidx, 0, sizeof(int), st);
-    const dim3 g((fr.n + 255) / 256), b(256);
-    hipLaunchKernelGGL(k_block_flags, g, b, 0, st, fr, skey, cell_start, flags);
-    hipError_t e = scan_exclusive<int, int>(flags, fr.n, bidx, partial, st);
+    if (L.ntot == 0) return launch_fill_i32(bidx, 1, 0, st);
+    const dim3 g((L.ntot + 255) / 256), b(256);
+    hipLaunchKernelGGL(k_block_flags, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, cell_start, flags);
+    hipError_t e = scan_exclusive<int, int>(flags, L.ntot, bidx, partial, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_block_write, g, b, 0, st, fr.n, flags, bidx, bstart);
+    hipLaunchKernelGGL(k_block_write, g, b, 0, st, L.coffs, L.nsets, L.ntot, skey, flags, bidx, bstart, bset);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowptr(const Launch& L, const int* counts, int64_t* rowg, int64_t* partial, int64_t* nnz,
+                         hipStream_t st)
+{
+    hipError_t e = scan_exclusive<int, int64_t>(counts, L.ntot, rowg, partial, st);
+    if (e != hipSuccess) return e;
+    const int m = L.ntot + L.nsets;
+    hipLaunchKernelGGL(k_rowptr_scatter, dim3((m + 255) / 256), dim3(256), 0, st, L.sets, L.poffs, L.nsets,
+                       L.ntot, rowg, nnz);
     return hipGetLastError();
 }
 

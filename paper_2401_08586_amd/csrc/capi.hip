@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cstring>
 #include <utility>
 #include <vector>
 
@@ -85,7 +86,7 @@ struct DeviceGuard {
     }
 };
 
-nnps_status frame_of(const nnps_problem* p, Frame* fr)
+nnps_status frame_of(const nnps_problem* p, Frame* fr, int block_target)
 {
     nnps_status st = nnps_validate(p);
     if (st != NNPS_OK) return st;
@@ -124,10 +125,10 @@ nnps_status frame_of(const nnps_problem* p, Frame* fr)
     fr->t_lo = f16_bits(4.0 * (rho2 - band), -1);
     fr->t_hi = f16_bits(4.0 * (rho2 + band), +1);
     fr->t_mid = f16_bits(4.0 * rho2, 0);
-    // x-window of a work block: about 56 particles on average, so most windows fill one
-    // wavefront and the candidate union stays small
+    // x-window of a work block: about block_target particles on average, so most windows
+    // fill one wavefront and the candidate union stays small
     const double occ = static_cast<double>(p->n) / static_cast<double>(ncell);
-    int xwin = occ > 0.0 ? static_cast<int>(56.0 / occ) : kMaxXWin;
+    int xwin = occ > 0.0 ? static_cast<int>(block_target / occ) : kMaxXWin;
     fr->xwin = std::max(1, std::min(kMaxXWin, xwin));
     return NNPS_OK;
 }
@@ -136,8 +137,12 @@ nnps_status frame_of(const nnps_problem* p, Frame* fr)
 
 struct nnps_ctx {
     int device = 0;
-    int64_t* h_pinned = nullptr;  // small pinned staging for synchronous readbacks
+    int64_t* h_pinned = nullptr;  // pinned staging for synchronous read-backs
+    int max_lds = 65536;          // LDS bytes a workgroup may use on this device
+    nnps_tuning tuning{56, 1024, 0};
 };
+
+namespace {
 
 // Per-phase HIP-event timing. Every begin/end pair recorded since the last read is
 // kept, so a run of many calls can be summed without synchronising in between.
@@ -186,23 +191,318 @@ struct PhaseTimer {
     }
 };
 
+// A captured build + count + fill sequence and the launch signature it was made for.
+struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    std::vector<unsigned char> sig;
+    void reset()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+        sig.clear();
+    }
+};
+
+}  // namespace
+
 struct nnps_cells {
     nnps_ctx* ctx = nullptr;
     PhaseTimer timer;
-    Frame fr{};
+    GraphCache graph;
+    bool use_graphs = false;
     bool built = false, counted = false;
-    const double* pos = nullptr;
-    int nblk_max = 0;
+    int nsets = 0, dim = 0, mode = 0, ntot = 0, ncell_tot = 0, nblk_max = 0;
+    std::vector<Frame> frames;
+    std::vector<int> offs;                // poffs[nsets + 1] then coffs[nsets + 1]
+    std::vector<const double*> pos;
+    SetDesc* h_sets = nullptr;            // pinned mirror of the set table
+    int* h_offs = nullptr;                // pinned mirror of the offsets
+    int h_cap = 0;                        // sets the pinned mirrors can hold
+    hipEvent_t upload_done = nullptr;     // last upload from the pinned mirrors
+    bool upload_pending = false;
+    uint64_t buf_gen = 0;                 // bumps whenever a device buffer moves
     uint32_t* skey = nullptr;
     int* perm = nullptr;
-    DevBuf X, k0, k1, v0, v1, cell_count, cell_start, q4, spos, flags, bidx, bstart, counts, table,
-        partial, stats, blk_stats, cbits, err, heavy, nheavy, nnz;
+    DevBuf d_sets, d_offs, X, k0, k1, v0, v1, cell_count, cell_start, q4, spos, flags, bidx, bstart, bset,
+        counts, table, partial, stats, blk_stats, cbits, err, heavy, nheavy, rowg, nnz;
 };
 
-#define HIP_TRY(x)                                \
-    do {                                          \
+#define HIP_TRY(x)                                  \
+    do {                                            \
         if ((x) != hipSuccess) return NNPS_EDEVICE; \
     } while (0)
+
+namespace {
+
+nnps_status err_status(int err)
+{
+    if (err & kErrDomain) return NNPS_EDOMAIN;
+    if (err & kErrCapacity) return NNPS_ECAPACITY;
+    if (err & kErrLongRow) return NNPS_EUNSUPPORTED;
+    return NNPS_OK;
+}
+
+// Make the pinned mirrors writable again: the previous upload must have been consumed.
+nnps_status wait_upload(nnps_cells* c)
+{
+    if (c->upload_pending) {
+        HIP_TRY(hipEventSynchronize(c->upload_done));
+        c->upload_pending = false;
+    }
+    return NNPS_OK;
+}
+
+nnps_status upload(nnps_cells* c, bool with_offsets, hipStream_t s)
+{
+    HIP_TRY(hipMemcpyAsync(c->d_sets.p, c->h_sets, sizeof(SetDesc) * c->nsets, hipMemcpyHostToDevice, s));
+    if (with_offsets)
+        HIP_TRY(hipMemcpyAsync(c->d_offs.p, c->h_offs, sizeof(int) * 2 * (c->nsets + 1), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(c->upload_done, s));
+    c->upload_pending = true;
+    return NNPS_OK;
+}
+
+Launch launch_of(const nnps_cells* c)
+{
+    Launch L{};
+    L.dim = c->dim;
+    L.mode = c->mode;
+    L.nsets = c->nsets;
+    L.ntot = c->ntot;
+    L.ncell_tot = c->ncell_tot;
+    L.sets = c->d_sets.as<SetDesc>();
+    L.poffs = c->d_offs.as<int>();
+    L.coffs = c->d_offs.as<int>() + c->nsets + 1;
+    return L;
+}
+
+SearchArgs args_of(const nnps_cells* c)
+{
+    SearchArgs a{};
+    a.L = launch_of(c);
+    a.skey = c->skey;
+    a.perm = c->perm;
+    a.cell_start = c->cell_start.as<int>();
+    a.q4 = c->q4.as<ushort4>();
+    a.spos = c->mode == NNPS_MODE_FP64_BASELINE ? c->spos.as<double>() : nullptr;
+    a.X = c->X.as<int64_t>();
+    a.bstart = c->bstart.as<int>();
+    a.bset = c->bset.as<int>();
+    a.nblk = c->bidx.as<int>() + c->ntot;
+    a.counts = c->counts.as<int>();
+    a.heavy = c->heavy.as<int>();
+    a.nheavy = c->nheavy.as<int>();
+    a.stats = c->stats.as<unsigned long long>();
+    a.blk_stats = c->blk_stats.as<unsigned long long>();
+    a.cbits = c->cbits.as<uint32_t>();
+    int keys = 1;
+    while (keys * 2 <= std::min(c->ctx->max_lds - 1024, 64 * 1024) / 4) keys *= 2;
+    a.lr_keys = c->ctx->tuning.long_rows_keys > 0 ? std::min(c->ctx->tuning.long_rows_keys, keys) : keys;
+    a.err = c->err.as<int>();
+    return a;
+}
+
+// Validate a batch, lay out its grids and index spaces, size the device buffers and fill
+// the pinned set table (output pointers cleared). No device work is queued.
+nnps_status prepare(nnps_ctx* ctx, nnps_cells* c, int nsets, const nnps_problem* probs, const double* const* d_pos)
+{
+    if (nsets < 1 || !probs || !d_pos) return NNPS_EINVAL;
+    std::vector<Frame> frames(nsets);
+    int64_t ntot = 0, ncell = 0;
+    for (int s = 0; s < nsets; ++s) {
+        nnps_status st = frame_of(&probs[s], &frames[s], ctx->tuning.block_target);
+        if (st != NNPS_OK) return st;
+        if (probs[s].dim != probs[0].dim || probs[s].mode != probs[0].mode) return NNPS_EINVAL;
+        if (probs[s].n > 0 && !d_pos[s]) return NNPS_EINVAL;
+        ntot += probs[s].n;
+        ncell += frames[s].ncell;
+    }
+    if (ntot >= (int64_t(1) << 31)) return NNPS_EINVAL;
+    if (ncell >= (int64_t(1) << 31)) return NNPS_ETOOMANYCELLS;
+    nnps_status st = wait_upload(c);
+    if (st != NNPS_OK) return st;
+    if (nsets > c->h_cap) {
+        if (c->h_sets) (void)hipHostFree(c->h_sets);
+        if (c->h_offs) (void)hipHostFree(c->h_offs);
+        c->h_sets = nullptr;
+        c->h_offs = nullptr;
+        c->h_cap = 0;
+        if (hipHostMalloc(reinterpret_cast<void**>(&c->h_sets), sizeof(SetDesc) * nsets, hipHostMallocDefault) !=
+                hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void**>(&c->h_offs), sizeof(int) * 2 * (nsets + 1),
+                          hipHostMallocDefault) != hipSuccess)
+            return NNPS_ENOMEM;
+        c->h_cap = nsets;
+    }
+    if (!c->upload_done && hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming) != hipSuccess)
+        return NNPS_EDEVICE;
+    c->nsets = nsets;
+    c->dim = probs[0].dim;
+    c->mode = probs[0].mode;
+    c->ntot = static_cast<int>(ntot);
+    c->ncell_tot = static_cast<int>(ncell);
+    c->frames = frames;
+    c->pos.assign(d_pos, d_pos + nsets);
+    int poff = 0, coff = 0;
+    int64_t nblk_bound = 0;
+    for (int s = 0; s < nsets; ++s) {
+        SetDesc& sd = c->h_sets[s];
+        memset(&sd, 0, sizeof(sd));
+        sd.fr = frames[s];
+        sd.poff = poff;
+        sd.coff = coff;
+        sd.pos = d_pos[s];
+        c->h_offs[s] = poff;
+        c->h_offs[nsets + 1 + s] = coff;
+        const Frame& fr = frames[s];
+        const int64_t nrows = static_cast<int64_t>(fr.nc[1]) * fr.nc[2];
+        const int64_t nwin = nrows * ((fr.nc[0] + fr.xwin - 1) / fr.xwin);
+        nblk_bound += std::min<int64_t>(fr.n, fr.n / kWave + nwin + 1);
+        poff += fr.n;
+        coff += fr.ncell;
+    }
+    c->h_offs[nsets] = poff;
+    c->h_offs[2 * nsets + 1] = coff;
+    c->nblk_max = static_cast<int>(std::min<int64_t>(nblk_bound, ntot));
+
+    const size_t n = static_cast<size_t>(ntot);
+    const size_t nn = std::max<size_t>(n, 1);
+    const size_t nc = static_cast<size_t>(ncell);
+    const size_t table_n = radix_table_entries(static_cast<int>(nn)) + 1;
+    const int64_t scan_m = std::max<int64_t>({static_cast<int64_t>(nn) + 1, static_cast<int64_t>(nc) + 1,
+                                              static_cast<int64_t>(table_n)});
+    const bool base = c->mode == NNPS_MODE_FP64_BASELINE;
+    const int cw = c->dim == 3 ? kCandWords3 : kCandWords2;
+    struct Need {
+        DevBuf* b;
+        size_t bytes;
+    } need[] = {
+        {&c->d_sets, sizeof(SetDesc) * nsets},
+        {&c->d_offs, sizeof(int) * 2 * (nsets + 1)},
+        {&c->X, nn * x_stride(c->dim) * sizeof(int64_t)},
+        {&c->k0, nn * 4}, {&c->k1, nn * 4}, {&c->v0, nn * 4}, {&c->v1, nn * 4},
+        {&c->cell_count, (nc + 1) * 4}, {&c->cell_start, (nc + 1) * 4},
+        {&c->q4, nn * sizeof(ushort4)},
+        {&c->spos, base ? nn * 4 * sizeof(double) : 0},
+        {&c->flags, nn * 4}, {&c->bidx, (nn + 1) * 4}, {&c->bstart, (nn + 2) * 4}, {&c->bset, (nn + 1) * 4},
+        {&c->counts, nn * 4},
+        {&c->table, table_n * 4},
+        {&c->partial, static_cast<size_t>(scan_partials_needed(scan_m) + 1) * 8},
+        {&c->stats, kStCount * 8},
+        {&c->blk_stats, static_cast<size_t>(std::max(c->nblk_max, 1)) * 5 * 8},
+        {&c->cbits, nn * cw * 4},
+        {&c->err, 4}, {&c->heavy, nn * 4}, {&c->nheavy, 4},
+        {&c->rowg, (nn + 1) * 8},
+        {&c->nnz, sizeof(int64_t) * nsets},
+    };
+    for (auto& q : need) {
+        if (q.bytes == 0) continue;
+        void* before = q.b->p;
+        hipError_t e = q.b->ensure(q.bytes);
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? NNPS_ENOMEM : NNPS_EDEVICE;
+        if (q.b->p != before) ++c->buf_gen;
+    }
+    c->built = false;
+    c->counted = false;
+    return NNPS_OK;
+}
+
+// The stream-ordered build: assign, cell starts, sort, pack, blocks.
+nnps_status enqueue_build(nnps_cells* c, hipStream_t s)
+{
+    const Launch L = launch_of(c);
+    PhaseTimer& tm = c->timer;
+    HIP_TRY(launch_fill_i32(c->cell_count.as<int>(), static_cast<int64_t>(c->ncell_tot) + 1, 0, s));
+    HIP_TRY(launch_fill_i32(c->err.as<int>(), 1, 0, s));
+    tm.begin(NNPS_PHASE_ASSIGN, s);
+    HIP_TRY(launch_assign(L, c->X.as<int64_t>(), c->k0.as<uint32_t>(), c->cell_count.as<int>(), c->err.as<int>(), s));
+    tm.end(NNPS_PHASE_ASSIGN, s);
+    tm.begin(NNPS_PHASE_CELLSCAN, s);
+    HIP_TRY(launch_scan_i32_i32(c->cell_count.as<int>(), c->ncell_tot, c->cell_start.as<int>(),
+                                c->partial.as<int64_t>(), s));
+    tm.end(NNPS_PHASE_CELLSCAN, s);
+    uint32_t* kf = c->k0.as<uint32_t>();
+    int* vf = c->v0.as<int>();
+    tm.begin(NNPS_PHASE_SORT, s);
+    if (c->ntot > 0) {
+        const int keybits = bitlen(static_cast<int64_t>(c->ncell_tot) - 1);
+        HIP_TRY(launch_radix_sort(c->ntot, keybits, c->k0.as<uint32_t>(), c->v0.as<int>(), c->k1.as<uint32_t>(),
+                                  c->v1.as<int>(), c->table.as<uint32_t>(), c->partial.as<int64_t>(), s, &kf, &vf));
+    }
+    tm.end(NNPS_PHASE_SORT, s);
+    c->skey = kf;
+    c->perm = vf;
+    tm.begin(NNPS_PHASE_PACK, s);
+    HIP_TRY(launch_pack(L, c->skey, c->perm, c->X.as<int64_t>(), c->q4.as<ushort4>(),
+                        c->mode == NNPS_MODE_FP64_BASELINE ? c->spos.as<double>() : nullptr, s));
+    tm.end(NNPS_PHASE_PACK, s);
+    tm.begin(NNPS_PHASE_BLOCKS, s);
+    HIP_TRY(launch_blocks(L, c->skey, c->cell_start.as<int>(), c->flags.as<int>(), c->bidx.as<int>(),
+                          c->bstart.as<int>(), c->bset.as<int>(), c->partial.as<int64_t>(), s));
+    tm.end(NNPS_PHASE_BLOCKS, s);
+    c->built = true;
+    c->counted = false;
+    return NNPS_OK;
+}
+
+// Count pass and row pointers (written into the row_ptr arrays of the set table).
+nnps_status enqueue_count(nnps_cells* c, hipStream_t s)
+{
+    SearchArgs a = args_of(c);
+    HIP_TRY(launch_fill_i32(c->stats.as<int>(), 2 * kStCount, 0, s));
+    c->timer.begin(NNPS_PHASE_COUNT, s);
+    HIP_TRY(launch_count(a, c->nblk_max, s));
+    c->timer.end(NNPS_PHASE_COUNT, s);
+    c->timer.begin(NNPS_PHASE_ROWSCAN, s);
+    HIP_TRY(launch_rowptr(a.L, c->counts.as<int>(), c->rowg.as<int64_t>(), c->partial.as<int64_t>(),
+                          c->nnz.as<int64_t>(), s));
+    c->timer.end(NNPS_PHASE_ROWSCAN, s);
+    c->counted = true;
+    return NNPS_OK;
+}
+
+nnps_status enqueue_fill(nnps_cells* c, hipStream_t s)
+{
+    SearchArgs a = args_of(c);
+    HIP_TRY(launch_fill_i32(c->nheavy.as<int>(), 1, 0, s));
+    c->timer.begin(NNPS_PHASE_FILL, s);
+    HIP_TRY(launch_fill(a, c->nblk_max, s));
+    c->timer.end(NNPS_PHASE_FILL, s);
+    c->timer.begin(NNPS_PHASE_LONGROWS, s);
+    HIP_TRY(launch_long_rows(a, c->ctx->tuning.long_rows_grid, s));
+    c->timer.end(NNPS_PHASE_LONGROWS, s);
+    return NNPS_OK;
+}
+
+void set_outputs(nnps_cells* c, int64_t* const* row_ptr, int32_t* const* col, float* const* dist,
+                 const int64_t* capacity)
+{
+    for (int s = 0; s < c->nsets; ++s) {
+        SetDesc& sd = c->h_sets[s];
+        if (row_ptr) sd.row_ptr = row_ptr[s];
+        if (col) sd.col = col[s];
+        if (dist) sd.dist = dist[s];
+        if (capacity) sd.capacity = capacity[s];
+    }
+}
+
+nnps_status read_nnz(nnps_cells* c, int64_t* h_nnz, hipStream_t s)
+{
+    int64_t* hp = c->ctx->h_pinned;
+    nnps_status st = NNPS_OK;
+    // the pinned staging holds 64 values; larger batches are read in pieces
+    for (int s0 = 0; s0 < c->nsets; s0 += 63) {
+        const int k = std::min(63, c->nsets - s0);
+        HIP_TRY(hipMemcpyAsync(hp, c->nnz.as<int64_t>() + s0, 8 * k, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(hp + 63, c->err.p, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int i = 0; i < k; ++i) h_nnz[s0 + i] = hp[i];
+        st = err_status(static_cast<int>(hp[63] & 0xFFFFFFFF));
+    }
+    return st;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -215,9 +515,9 @@ const char* nnps_status_str(nnps_status s)
     case NNPS_ENOMEM: return "NNPS_ENOMEM: allocation failed";
     case NNPS_ECAPACITY: return "NNPS_ECAPACITY: output capacity below the neighbour count";
     case NNPS_EDEVICE: return "NNPS_EDEVICE: HIP runtime error";
-    case NNPS_ETOOMANYCELLS: return "NNPS_ETOOMANYCELLS: more than 2^30 cells";
+    case NNPS_ETOOMANYCELLS: return "NNPS_ETOOMANYCELLS: too many cells";
     case NNPS_EORDER: return "NNPS_EORDER: call out of order";
-    case NNPS_EUNSUPPORTED: return "NNPS_EUNSUPPORTED: a neighbour row is longer than supported";
+    case NNPS_EUNSUPPORTED: return "NNPS_EUNSUPPORTED: internal limit exceeded";
     }
     return "NNPS_UNKNOWN";
 }
@@ -230,24 +530,20 @@ nnps_status nnps_validate(const nnps_problem* p)
     if (p->n < 0 || p->n >= (int64_t(1) << 31)) return NNPS_EINVAL;
     if (!(p->radius > 0.0) || !isfinite(p->radius)) return NNPS_EINVAL;
     if (!(p->cell_size >= p->radius) || !isfinite(p->cell_size)) return NNPS_EINVAL;
-    double wmax = 0.0;
-    for (int k = 0; k < p->dim; ++k) {
+    for (int k = 0; k < p->dim; ++k)
         if (!isfinite(p->lo[k]) || !isfinite(p->hi[k]) || !(p->hi[k] > p->lo[k])) return NNPS_EINVAL;
-        wmax = std::max(wmax, p->hi[k] - p->lo[k]);
-    }
     // cell count guard before any integer conversion
     const double w = std::max(p->cell_size, p->radius);
     double cells = 1.0;
     for (int k = 0; k < p->dim; ++k) cells *= floor((p->hi[k] - p->lo[k]) / w) + 1.0;
     if (cells > ldexp(1.0, 30)) return NNPS_ETOOMANYCELLS;
-    (void)wmax;
     return NNPS_OK;
 }
 
 nnps_status nnps_grid(const nnps_problem* prob, int32_t ncell[3], int32_t* frac_bits, double* cell_width)
 {
     Frame fr;
-    nnps_status st = frame_of(prob, &fr);
+    nnps_status st = frame_of(prob, &fr, 56);
     if (st != NNPS_OK) return st;
     if (ncell)
         for (int k = 0; k < 3; ++k) ncell[k] = fr.nc[k];
@@ -267,7 +563,10 @@ nnps_status nnps_ctx_create(int device, nnps_ctx** out)
     nnps_ctx* c = new (std::nothrow) nnps_ctx;
     if (!c) return NNPS_ENOMEM;
     c->device = device;
-    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_pinned), 8 * sizeof(int64_t), hipHostMallocDefault) !=
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+        c->max_lds = lds;
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_pinned), 64 * sizeof(int64_t), hipHostMallocDefault) !=
         hipSuccess) {
         delete c;
         return NNPS_ENOMEM;
@@ -284,6 +583,24 @@ void nnps_ctx_destroy(nnps_ctx* c)
     delete c;
 }
 
+nnps_status nnps_ctx_set_tuning(nnps_ctx* ctx, const nnps_tuning* t)
+{
+    if (!ctx || !t) return NNPS_EINVAL;
+    if (t->block_target < 8 || t->block_target > 4096 || t->long_rows_grid < 1 || t->long_rows_grid > (1 << 20))
+        return NNPS_EINVAL;
+    const int k = t->long_rows_keys;
+    if (k != 0 && (k < 64 || k > 16384 || (k & (k - 1)) != 0)) return NNPS_EINVAL;
+    ctx->tuning = *t;
+    return NNPS_OK;
+}
+
+nnps_status nnps_ctx_get_tuning(const nnps_ctx* ctx, nnps_tuning* t)
+{
+    if (!ctx || !t) return NNPS_EINVAL;
+    *t = ctx->tuning;
+    return NNPS_OK;
+}
+
 nnps_status nnps_cells_create(nnps_ctx* ctx, nnps_cells** out)
 {
     if (!ctx || !out) return NNPS_EINVAL;
@@ -298,192 +615,204 @@ void nnps_cells_destroy(nnps_cells* c)
 {
     if (!c) return;
     DeviceGuard g(c->ctx->device);
-    DevBuf* all[] = {&c->X, &c->k0, &c->k1, &c->v0, &c->v1, &c->cell_count, &c->cell_start, &c->q4,
-                     &c->spos, &c->flags, &c->bidx, &c->bstart, &c->counts, &c->table, &c->partial,
-                     &c->stats, &c->blk_stats, &c->cbits, &c->err, &c->heavy, &c->nheavy, &c->nnz};
+    if (c->upload_pending) (void)hipEventSynchronize(c->upload_done);
+    DevBuf* all[] = {&c->d_sets, &c->d_offs, &c->X, &c->k0, &c->k1, &c->v0, &c->v1, &c->cell_count,
+                     &c->cell_start, &c->q4, &c->spos, &c->flags, &c->bidx, &c->bstart, &c->bset, &c->counts,
+                     &c->table, &c->partial, &c->stats, &c->blk_stats, &c->cbits, &c->err, &c->heavy,
+                     &c->nheavy, &c->rowg, &c->nnz};
     for (DevBuf* b : all) b->release();
     c->timer.release();
+    c->graph.reset();
+    if (c->upload_done) (void)hipEventDestroy(c->upload_done);
+    if (c->h_sets) (void)hipHostFree(c->h_sets);
+    if (c->h_offs) (void)hipHostFree(c->h_offs);
     delete c;
+}
+
+nnps_status nnps_batch_build(nnps_ctx* ctx, nnps_cells* c, int32_t nsets, const nnps_problem* probs,
+                             const double* const* d_pos, void* stream)
+{
+    if (!ctx || !c || c->ctx != ctx) return NNPS_EINVAL;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return NNPS_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    nnps_status st = prepare(ctx, c, nsets, probs, d_pos);
+    if (st != NNPS_OK) return st;
+    st = upload(c, true, s);
+    if (st != NNPS_OK) return st;
+    return enqueue_build(c, s);
 }
 
 nnps_status nnps_cells_build(nnps_ctx* ctx, nnps_cells* c, const nnps_problem* prob, const double* d_pos,
                              void* stream)
 {
-    if (!ctx || !c || !prob || c->ctx != ctx) return NNPS_EINVAL;
-    Frame fr;
-    nnps_status st = frame_of(prob, &fr);
-    if (st != NNPS_OK) return st;
-    if (fr.n > 0 && !d_pos) return NNPS_EINVAL;
-    DeviceGuard g(ctx->device);
-    if (!g.ok) return NNPS_EDEVICE;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const size_t n = static_cast<size_t>(fr.n);
-    const size_t nn = std::max<size_t>(n, 1);
-    const size_t ncell = static_cast<size_t>(fr.ncell);
-    const int64_t nrows = static_cast<int64_t>(fr.nc[1]) * fr.nc[2];
-    const int64_t nwin = nrows * ((fr.nc[0] + fr.xwin - 1) / fr.xwin);
-    const int64_t nblk_bound = static_cast<int64_t>(n / kWave) + nwin + 1;
-    c->nblk_max = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(n), nblk_bound));
-    const size_t table_n = radix_table_entries(static_cast<int>(nn)) + 1;
-    const int64_t scan_m = std::max<int64_t>({static_cast<int64_t>(nn) + 1, static_cast<int64_t>(ncell) + 1,
-                                              static_cast<int64_t>(table_n)});
-
-    const bool base = fr.mode == NNPS_MODE_FP64_BASELINE;
-    hipError_t e = hipSuccess;
-    if ((e = c->X.ensure(nn * x_stride(fr.dim) * sizeof(int64_t))) != hipSuccess ||
-        (e = c->k0.ensure(nn * 4)) != hipSuccess || (e = c->k1.ensure(nn * 4)) != hipSuccess ||
-        (e = c->v0.ensure(nn * 4)) != hipSuccess || (e = c->v1.ensure(nn * 4)) != hipSuccess ||
-        (e = c->cell_count.ensure((ncell + 1) * 4)) != hipSuccess ||
-        (e = c->cell_start.ensure((ncell + 1) * 4)) != hipSuccess ||
-        (e = c->q4.ensure(nn * sizeof(ushort4))) != hipSuccess ||
-        (base && (e = c->spos.ensure(nn * 4 * sizeof(double))) != hipSuccess) ||
-        (e = c->flags.ensure(nn * 4)) != hipSuccess || (e = c->bidx.ensure((nn + 1) * 4)) != hipSuccess ||
-        (e = c->bstart.ensure((nn + 2) * 4)) != hipSuccess || (e = c->counts.ensure(nn * 4)) != hipSuccess ||
-        (e = c->table.ensure(table_n * 4)) != hipSuccess ||
-        (e = c->partial.ensure(static_cast<size_t>(scan_partials_needed(scan_m) + 1) * 8)) != hipSuccess ||
-        (e = c->stats.ensure(kStCount * 8)) != hipSuccess || (e = c->err.ensure(4)) != hipSuccess ||
-        (e = c->heavy.ensure(nn * 4)) != hipSuccess || (e = c->nheavy.ensure(4)) != hipSuccess ||
-        (e = c->nnz.ensure(8)) != hipSuccess ||
-        (e = c->blk_stats.ensure(static_cast<size_t>(std::max(c->nblk_max, 1)) * 5 * 8)) != hipSuccess ||
-        (e = c->cbits.ensure(nn * (fr.dim == 3 ? kCandWords3 : kCandWords2) * 4)) != hipSuccess)
-        return e == hipErrorOutOfMemory ? NNPS_ENOMEM : NNPS_EDEVICE;
-
-    c->fr = fr;
-    c->pos = d_pos;
-    c->built = false;
-    c->counted = false;
-    HIP_TRY(hipMemsetAsync(c->cell_count.p, 0, (ncell + 1) * 4, s));
-    HIP_TRY(hipMemsetAsync(c->err.p, 0, 4, s));
-    HIP_TRY(hipMemsetAsync(c->stats.p, 0, kStCount * 8, s));
-    PhaseTimer& tm = c->timer;
-    tm.begin(NNPS_PHASE_ASSIGN, s);
-    HIP_TRY(launch_assign(d_pos, fr, c->X.as<int64_t>(), c->k0.as<uint32_t>(), c->cell_count.as<int>(),
-                          c->err.as<int>(), s));
-    tm.end(NNPS_PHASE_ASSIGN, s);
-    tm.begin(NNPS_PHASE_CELLSCAN, s);
-    HIP_TRY(launch_scan_i32_i32(c->cell_count.as<int>(), static_cast<int64_t>(ncell), c->cell_start.as<int>(),
-                                c->partial.as<int64_t>(), s));
-    tm.end(NNPS_PHASE_CELLSCAN, s);
-    uint32_t* kf = c->k0.as<uint32_t>();
-    int* vf = c->v0.as<int>();
-    tm.begin(NNPS_PHASE_SORT, s);
-    if (fr.n > 0) {
-        const int keybits = bitlen(static_cast<int64_t>(ncell) - 1);
-        HIP_TRY(launch_radix_sort(fr.n, keybits, c->k0.as<uint32_t>(), c->v0.as<int>(), c->k1.as<uint32_t>(),
-                                  c->v1.as<int>(), c->table.as<uint32_t>(), c->partial.as<int64_t>(), s, &kf,
-                                  &vf));
-    }
-    tm.end(NNPS_PHASE_SORT, s);
-    c->skey = kf;
-    c->perm = vf;
-    tm.begin(NNPS_PHASE_PACK, s);
-    HIP_TRY(launch_pack(fr, c->perm, c->X.as<int64_t>(), c->q4.as<ushort4>(), d_pos,
-                        base ? c->spos.as<double>() : nullptr, s));
-    tm.end(NNPS_PHASE_PACK, s);
-    tm.begin(NNPS_PHASE_BLOCKS, s);
-    HIP_TRY(launch_blocks(fr, c->skey, c->cell_start.as<int>(), c->flags.as<int>(), c->bidx.as<int>(),
-                          c->bstart.as<int>(), c->partial.as<int64_t>(), s));
-    tm.end(NNPS_PHASE_BLOCKS, s);
-    c->built = true;
-    return NNPS_OK;
+    if (!prob) return NNPS_EINVAL;
+    const double* pp[1] = {d_pos};
+    return nnps_batch_build(ctx, c, 1, prob, pp, stream);
 }
 
-static SearchArgs args_of(nnps_cells* c)
-{
-    SearchArgs a{};
-    a.fr = c->fr;
-    a.pos = c->pos;
-    a.skey = c->skey;
-    a.perm = c->perm;
-    a.cell_start = c->cell_start.as<int>();
-    a.q4 = c->q4.as<ushort4>();
-    a.spos = c->fr.mode == NNPS_MODE_FP64_BASELINE ? c->spos.as<double>() : nullptr;
-    a.X = c->X.as<int64_t>();
-    a.bstart = c->bstart.as<int>();
-    a.nblk = c->bidx.as<int>() + c->fr.n;
-    a.counts = c->counts.as<int>();
-    a.heavy = c->heavy.as<int>();
-    a.nheavy = c->nheavy.as<int>();
-    a.stats = c->stats.as<unsigned long long>();
-    a.blk_stats = c->blk_stats.as<unsigned long long>();
-    a.cbits = c->cbits.as<uint32_t>();
-    a.err = c->err.as<int>();
-    return a;
-}
-
-static nnps_status err_status(int err)
-{
-    if (err & kErrDomain) return NNPS_EDOMAIN;
-    if (err & kErrCapacity) return NNPS_ECAPACITY;
-    if (err & kErrLongRow) return NNPS_EUNSUPPORTED;
-    return NNPS_OK;
-}
-
-nnps_status nnps_count(nnps_ctx* ctx, nnps_cells* c, int64_t* d_row_ptr, int64_t* h_nnz, void* stream)
+nnps_status nnps_batch_count(nnps_ctx* ctx, nnps_cells* c, int64_t* const* d_row_ptr, int64_t* h_nnz,
+                             void* stream)
 {
     if (!ctx || !c || c->ctx != ctx || !d_row_ptr) return NNPS_EINVAL;
+    for (int s = 0; s < c->nsets; ++s)
+        if (!d_row_ptr[s]) return NNPS_EINVAL;
     if (!c->built) return NNPS_EORDER;
     DeviceGuard g(ctx->device);
     if (!g.ok) return NNPS_EDEVICE;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    SearchArgs a = args_of(c);
-    HIP_TRY(hipMemsetAsync(c->stats.p, 0, kStCount * 8, s));
-    c->timer.begin(NNPS_PHASE_COUNT, s);
-    HIP_TRY(launch_count(a, c->nblk_max, s));
-    c->timer.end(NNPS_PHASE_COUNT, s);
-    c->timer.begin(NNPS_PHASE_ROWSCAN, s);
-    HIP_TRY(launch_scan_i32_i64(c->counts.as<int>(), c->fr.n, d_row_ptr, c->partial.as<int64_t>(), s));
-    c->timer.end(NNPS_PHASE_ROWSCAN, s);
-    HIP_TRY(hipMemcpyAsync(c->nnz.p, d_row_ptr + c->fr.n, 8, hipMemcpyDeviceToDevice, s));
-    c->counted = true;
-    if (h_nnz) {
-        int64_t* hp = ctx->h_pinned;
-        HIP_TRY(hipMemcpyAsync(hp, d_row_ptr + c->fr.n, 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(hp + 1, c->err.p, 4, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        *h_nnz = hp[0];
-        const int err = static_cast<int>(hp[1] & 0xFFFFFFFF);
-        return err_status(err);
+    nnps_status st = wait_upload(c);
+    if (st != NNPS_OK) return st;
+    set_outputs(c, d_row_ptr, nullptr, nullptr, nullptr);
+    st = upload(c, false, s);
+    if (st != NNPS_OK) return st;
+    st = enqueue_count(c, s);
+    if (st != NNPS_OK) return st;
+    return h_nnz ? read_nnz(c, h_nnz, s) : NNPS_OK;
+}
+
+nnps_status nnps_count(nnps_ctx* ctx, nnps_cells* c, int64_t* d_row_ptr, int64_t* h_nnz, void* stream)
+{
+    if (!c || c->nsets != 1) return c ? NNPS_EORDER : NNPS_EINVAL;
+    int64_t* rp[1] = {d_row_ptr};
+    return nnps_batch_count(ctx, c, rp, h_nnz, stream);
+}
+
+nnps_status nnps_batch_fill(nnps_ctx* ctx, nnps_cells* c, int64_t* const* d_row_ptr, int32_t* const* d_col,
+                            float* const* d_dist, const int64_t* capacity, void* stream)
+{
+    if (!ctx || !c || c->ctx != ctx || !d_row_ptr || !d_col || !d_dist || !capacity) return NNPS_EINVAL;
+    for (int s = 0; s < c->nsets; ++s) {
+        if (!d_row_ptr[s] || capacity[s] < 0) return NNPS_EINVAL;
+        if (capacity[s] > 0 && (!d_col[s] || !d_dist[s])) return NNPS_EINVAL;
     }
-    return NNPS_OK;
+    if (!c->counted) return NNPS_EORDER;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return NNPS_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    nnps_status st = wait_upload(c);
+    if (st != NNPS_OK) return st;
+    set_outputs(c, d_row_ptr, d_col, d_dist, capacity);
+    st = upload(c, false, s);
+    if (st != NNPS_OK) return st;
+    return enqueue_fill(c, s);
 }
 
 nnps_status nnps_fill(nnps_ctx* ctx, nnps_cells* c, const int64_t* d_row_ptr, int32_t* d_col, float* d_dist,
                       int64_t capacity, void* stream)
 {
-    if (!ctx || !c || c->ctx != ctx || !d_row_ptr || capacity < 0) return NNPS_EINVAL;
-    if (capacity > 0 && (!d_col || !d_dist)) return NNPS_EINVAL;
-    if (!c->counted) return NNPS_EORDER;
-    DeviceGuard g(ctx->device);
-    if (!g.ok) return NNPS_EDEVICE;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    SearchArgs a = args_of(c);
-    a.row_ptr = d_row_ptr;
-    a.col = d_col;
-    a.dist = d_dist;
-    a.capacity = capacity;
-    HIP_TRY(hipMemsetAsync(c->nheavy.p, 0, 4, s));
-    c->timer.begin(NNPS_PHASE_FILL, s);
-    HIP_TRY(launch_fill(a, c->nblk_max, s));
-    c->timer.end(NNPS_PHASE_FILL, s);
-    c->timer.begin(NNPS_PHASE_LONGROWS, s);
-    HIP_TRY(launch_long_rows(a, s));
-    c->timer.end(NNPS_PHASE_LONGROWS, s);
-    return NNPS_OK;
+    if (!c || c->nsets != 1) return c ? NNPS_EORDER : NNPS_EINVAL;
+    if (capacity < 0) return NNPS_EINVAL;
+    int64_t* rp[1] = {const_cast<int64_t*>(d_row_ptr)};
+    int32_t* cp[1] = {d_col};
+    float* dp[1] = {d_dist};
+    return nnps_batch_fill(ctx, c, rp, cp, dp, &capacity, stream);
+}
+
+nnps_status nnps_batch_search(nnps_ctx* ctx, nnps_cells* c, int32_t nsets, const nnps_problem* probs,
+                              const double* const* d_pos, int64_t* const* d_row_ptr, int32_t* const* d_col,
+                              float* const* d_dist, const int64_t* capacity, int64_t* nnz_out, void* stream)
+{
+    if (!nnz_out || !capacity) return NNPS_EINVAL;
+    nnps_status st = nnps_batch_build(ctx, c, nsets, probs, d_pos, stream);
+    if (st != NNPS_OK) return st;
+    st = nnps_batch_count(ctx, c, d_row_ptr, nnz_out, stream);
+    if (st != NNPS_OK) return st;
+    for (int s = 0; s < nsets; ++s)
+        if (nnz_out[s] > capacity[s]) return NNPS_ECAPACITY;
+    return nnps_batch_fill(ctx, c, d_row_ptr, d_col, d_dist, capacity, stream);
 }
 
 nnps_status nnps_search(nnps_ctx* ctx, nnps_cells* c, const nnps_problem* prob, const double* d_pos,
                         int64_t* d_row_ptr, int32_t* d_col, float* d_dist, int64_t capacity, int64_t* nnz_out,
                         void* stream)
 {
-    nnps_status st = nnps_cells_build(ctx, c, prob, d_pos, stream);
+    if (!prob || !nnz_out) return NNPS_EINVAL;
+    const double* pp[1] = {d_pos};
+    int64_t* rp[1] = {d_row_ptr};
+    int32_t* cp[1] = {d_col};
+    float* dp[1] = {d_dist};
+    return nnps_batch_search(ctx, c, 1, prob, pp, rp, cp, dp, &capacity, nnz_out, stream);
+}
+
+nnps_status nnps_cells_set_graphs(nnps_cells* c, int on)
+{
+    if (!c) return NNPS_EINVAL;
+    c->use_graphs = on != 0;
+    if (!c->use_graphs) c->graph.reset();
+    return NNPS_OK;
+}
+
+nnps_status nnps_batch_step(nnps_ctx* ctx, nnps_cells* c, int32_t nsets, const nnps_problem* probs,
+                            const double* const* d_pos, int64_t* const* d_row_ptr, int32_t* const* d_col,
+                            float* const* d_dist, const int64_t* capacity, void* stream)
+{
+    if (!ctx || !c || c->ctx != ctx || !d_row_ptr || !d_col || !d_dist || !capacity) return NNPS_EINVAL;
+    for (int s = 0; s < nsets; ++s) {
+        if (!d_row_ptr[s] || capacity[s] < 0) return NNPS_EINVAL;
+        if (capacity[s] > 0 && (!d_col[s] || !d_dist[s])) return NNPS_EINVAL;
+    }
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return NNPS_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const uint64_t gen0 = c->buf_gen;
+    nnps_status st = prepare(ctx, c, nsets, probs, d_pos);
     if (st != NNPS_OK) return st;
-    int64_t nnz = 0;
-    st = nnps_count(ctx, c, d_row_ptr, &nnz, stream);
-    if (nnz_out) *nnz_out = nnz;
+    set_outputs(c, d_row_ptr, d_col, d_dist, capacity);
+    st = upload(c, true, s);
     if (st != NNPS_OK) return st;
-    if (nnz > capacity) return NNPS_ECAPACITY;
-    return nnps_fill(ctx, c, d_row_ptr, d_col, d_dist, capacity, stream);
+    const bool graphs = c->use_graphs && s != nullptr && !c->timer.on;
+    if (!graphs) {
+        if ((st = enqueue_build(c, s)) != NNPS_OK) return st;
+        if ((st = enqueue_count(c, s)) != NNPS_OK) return st;
+        return enqueue_fill(c, s);
+    }
+    // the graph depends on the sizes (grids), the device buffers and the tuning; the
+    // per-set pointers travel in the uploaded set table
+    std::vector<unsigned char> sig(sizeof(nnps_problem) * nsets + sizeof(uint64_t) + sizeof(nnps_tuning) + 4);
+    unsigned char* q = sig.data();
+    memcpy(q, probs, sizeof(nnps_problem) * nsets);
+    q += sizeof(nnps_problem) * nsets;
+    memcpy(q, &c->buf_gen, sizeof(uint64_t));
+    q += sizeof(uint64_t);
+    memcpy(q, &ctx->tuning, sizeof(nnps_tuning));
+    q += sizeof(nnps_tuning);
+    memcpy(q, &nsets, 4);
+    (void)gen0;
+    if (!c->graph.exec || c->graph.sig != sig) {
+        c->graph.reset();
+        hipGraph_t graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        nnps_status cst = enqueue_build(c, s);
+        if (cst == NNPS_OK) cst = enqueue_count(c, s);
+        if (cst == NNPS_OK) cst = enqueue_fill(c, s);
+        const hipError_t ee = hipStreamEndCapture(s, &graph);
+        if (cst != NNPS_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return cst;
+        }
+        if (ee != hipSuccess) return NNPS_EDEVICE;
+        const hipError_t ie = hipGraphInstantiate(&c->graph.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+            c->graph.exec = nullptr;
+            return NNPS_EDEVICE;
+        }
+        c->graph.sig = sig;
+    }
+    HIP_TRY(hipGraphLaunch(c->graph.exec, s));
+    c->built = true;
+    c->counted = true;
+    return NNPS_OK;
+}
+
+nnps_status nnps_batch_nnz(nnps_cells* c, int64_t* h_nnz, void* stream)
+{
+    if (!c || !h_nnz) return NNPS_EINVAL;
+    if (!c->counted) return NNPS_EORDER;
+    DeviceGuard g(c->ctx->device);
+    if (!g.ok) return NNPS_EDEVICE;
+    return read_nnz(c, h_nnz, static_cast<hipStream_t>(stream));
 }
 
 nnps_status nnps_stats_get(nnps_cells* c, nnps_stats* out, void* stream)
@@ -500,19 +829,25 @@ nnps_status nnps_stats_get(nnps_cells* c, nnps_stats* out, void* stream)
     HIP_TRY(hipMemcpy(st, c->stats.p, sizeof(st), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(&err, c->err.p, 4, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(&nh, c->nheavy.p, 4, hipMemcpyDeviceToHost));
-    out->n = c->fr.n;
-    if (c->counted) HIP_TRY(hipMemcpy(&out->nnz, c->nnz.p, 8, hipMemcpyDeviceToHost));
+    out->n = c->ntot;
+    if (c->counted) {
+        std::vector<int64_t> nz(c->nsets);
+        HIP_TRY(hipMemcpy(nz.data(), c->nnz.p, 8 * c->nsets, hipMemcpyDeviceToHost));
+        for (int64_t v : nz) out->nnz += v;
+    }
     out->candidates = static_cast<int64_t>(st[kStCandidates]);
     out->band_pairs = static_cast<int64_t>(st[kStBand]);
     out->fp16_false_pos = static_cast<int64_t>(st[kStFalsePos]);
     out->fp16_false_neg = static_cast<int64_t>(st[kStFalseNeg]);
     out->outside_band_disagree = static_cast<int64_t>(st[kStOutsideDisagree]);
     out->heavy_rows = nh;
-    out->dim = c->fr.dim;
-    out->mode = c->fr.mode;
-    out->frac_bits = c->fr.F;
-    for (int k = 0; k < 3; ++k) out->ncell[k] = c->fr.nc[k];
-    out->cell_width = c->fr.w;
+    out->dim = c->dim;
+    out->mode = c->mode;
+    if (!c->frames.empty()) {
+        out->frac_bits = c->frames[0].F;
+        for (int k = 0; k < 3; ++k) out->ncell[k] = c->frames[0].nc[k];
+        out->cell_width = c->frames[0].w;
+    }
     out->band = ldexp(1.0, -7);
     return err_status(err);
 }

@@ -24,8 +24,6 @@ constexpr int kCandWords2 = 8;
 constexpr int kCandWords3 = 24;
 // Fixed-point positions are stored per particle, padded to a power of two of int64.
 __host__ __device__ constexpr int x_stride(int dim) { return dim == 3 ? 4 : 2; }
-// Longest row the long-row path sorts in LDS.
-constexpr int kHeavySortMax = 4096;
 // Largest x-window (cells) of a block; keeps staged cell offsets exact in FP16.
 constexpr int kMaxXWin = 256;
 
@@ -45,7 +43,7 @@ enum StatSlot {
     kStCount
 };
 
-// Everything a kernel needs to know about the grid and the thresholds.
+// Everything a kernel needs to know about one particle set's grid and thresholds.
 struct Frame {
     int dim;
     int mode;
@@ -61,5 +59,30 @@ struct Frame {
     int xwin;           // blocks never cross a multiple of xwin cells along x
     uint16_t t_lo, t_hi, t_mid;  // FP16 thresholds on r2 = 4|delta|^2 (bit patterns)
 };
+
+// One particle set of a launch. All sets of a launch share one global particle index
+// space (set s owns [poff, poff + n)) and one global cell index space ([coff, coff +
+// ncell)), so one sort and one kernel launch per pass cover every set.
+struct SetDesc {
+    Frame fr;                // fr.n = this set's particle count
+    int poff, coff;          // first global particle / cell index
+    const double* pos;       // caller's positions [n][dim] (float64)
+    int64_t* row_ptr;        // caller's CSR row pointers [n + 1]
+    int32_t* col;            // caller's CSR column indices (set-local)
+    float* dist;             // caller's CSR distances
+    int64_t capacity;        // entries available in col and dist
+};
+
+// Index of the set owning global index v, given offs[0..nsets] ascending.
+__device__ __forceinline__ int find_set(const int* __restrict__ offs, int nsets, int v)
+{
+    int lo = 0, hi = nsets - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (offs[mid] <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 
 }  // namespace nnps

@@ -55,8 +55,7 @@ __device__ __forceinline__ bool recheck(const double* __restrict__ pos, const do
 // FP32 distance from the fixed-point positions: the int64 displacement is exact and
 // is rounded once to FP32 (|dX| < 2^41 for any pair within the radius).
 template <int DIM>
-__device__ __forceinline__ float dist_fixed(const int64_t* __restrict__ X, int n, int oi, int oj,
-                                           float scale)
+__device__ __forceinline__ float dist_fixed(const int64_t* __restrict__ X, int oi, int oj, float scale)
 {
     float s2 = 0.0f;
 #pragma unroll
@@ -111,10 +110,15 @@ struct Geom {
     int U;
     int seg_g0[NSEG], seg_base[NSEG], la[NSEG], lb[NSEG];
     int pself;
+    const SetDesc* sd;  // the block's set
+    Frame fr;
 
     __device__ __forceinline__ void init(const SearchArgs& a, int b)
     {
-        const Frame& fr = a.fr;
+        sd = a.L.sets + a.bset[b];
+        fr = sd->fr;
+        const uint32_t coff = static_cast<uint32_t>(sd->coff);
+        const int* cs = a.cell_start + coff;
         const int lane = threadIdx.x & 63;
         p0 = a.bstart[b];
         p1 = a.bstart[b + 1];
@@ -122,14 +126,14 @@ struct Geom {
         active = p < p1;
         const uint32_t ncx = static_cast<uint32_t>(fr.nc[0]);
         const int ncy = fr.nc[1], ncz = fr.nc[2];
-        const uint32_t k0 = a.skey[p0];
+        const uint32_t k0 = a.skey[p0] - coff;
         const uint32_t row0 = k0 / ncx;
         const int xa = static_cast<int>(k0 - row0 * ncx);
         const int y0 = static_cast<int>(row0 % static_cast<uint32_t>(ncy));
         const int z0 = static_cast<int>(row0 / static_cast<uint32_t>(ncy));
-        const uint32_t kl = a.skey[p1 - 1];
+        const uint32_t kl = a.skey[p1 - 1] - coff;
         const int xb = static_cast<int>(kl - (kl / ncx) * ncx);
-        const uint32_t mk = a.skey[active ? p : p1 - 1];
+        const uint32_t mk = a.skey[active ? p : p1 - 1] - coff;
         x = static_cast<int>(mk - (mk / ncx) * ncx);
         sx0 = xa > 0 ? xa - 1 : 0;
         const int sx1 = xb + 1 < static_cast<int>(ncx) ? xb + 1 : static_cast<int>(ncx) - 1;
@@ -144,10 +148,10 @@ struct Geom {
             int g0 = 0, g1 = 0, ga = 0, gb = 0;
             if (yy >= 0 && yy < ncy && zz >= 0 && zz < ncz) {
                 const int rb = (zz * ncy + yy) * static_cast<int>(ncx);
-                g0 = a.cell_start[rb + sx0];
-                g1 = a.cell_start[rb + sx1 + 1];
-                ga = a.cell_start[rb + lx0];
-                gb = a.cell_start[rb + lx1 + 1];
+                g0 = cs[rb + sx0];
+                g1 = cs[rb + sx1 + 1];
+                ga = cs[rb + lx0];
+                gb = cs[rb + lx1 + 1];
             }
             seg_g0[r] = g0;
             seg_base[r] = U;
@@ -250,7 +254,7 @@ __device__ __forceinline__ bool classify(const SearchArgs& a, const Geom<DIM>& g
                                          int r, int posl, uint32_t r2h, Tally& t, const int* sorig,
                                          int cb, int* oj_out)
 {
-    const Frame& fr = a.fr;
+    const Frame& fr = g.fr;
     if (MODE == 2) t.cand++;  // MODE 0 counts candidates from the lane's ranges
     const bool in16 = r2h < fr.t_lo;
     const bool band = !in16 && r2h <= fr.t_hi;
@@ -258,7 +262,7 @@ __device__ __forceinline__ bool classify(const SearchArgs& a, const Geom<DIM>& g
     int oj = -1;
     if (MODE == 2 || band) {
         oj = sorig ? sorig[posl - cb] : a.perm[g.global_of(r, posl)];
-        const bool truth = recheck<DIM>(a.pos, pi, oj, fr.R2);
+        const bool truth = recheck<DIM>(g.sd->pos, pi, oj - g.sd->poff, fr.R2);
         const bool naive = r2h <= fr.t_mid;
         t.band += band;
         t.fpos += naive && !truth;
@@ -384,7 +388,7 @@ struct CandBits {
     {
         if (!keep) return;
         const int nw = (total + 31) >> 5;
-        for (int k = 0; k < nw; ++k) a.cbits[static_cast<size_t>(k) * a.fr.n + p] = w[k];
+        for (int k = 0; k < nw; ++k) a.cbits[static_cast<size_t>(k) * a.L.ntot + p] = w[k];
     }
 };
 
@@ -401,12 +405,14 @@ k_count16(SearchArgs a)
     const int lane = threadIdx.x & 63;
     Geom<DIM> g;
     g.init(a, b);
-    const Frame& fr = a.fr;
+    const Frame& fr = g.fr;
     const int pp = g.active ? g.p : g.p1 - 1;
     const int oi = a.perm[pp];
+    const double* spos_set = g.sd->pos;
+    const int poff = g.sd->poff;
     double pi[3] = {0, 0, 0};
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) pi[k] = a.pos[static_cast<size_t>(oi) * DIM + k];
+    for (int k = 0; k < DIM; ++k) pi[k] = spos_set[static_cast<size_t>(oi - poff) * DIM + k];
     Target16<DIM> tg;
     tg.init(a.q4[pp], g.x, g.sx0);
     Thresh th;
@@ -516,7 +522,7 @@ k_count16(SearchArgs a)
         bq.drain([&](int posl, uint32_t r2h) {
             if (posl == g.pself) return;
             const int oj = a.perm[g.global_of_any(posl)];
-            const bool truth = recheck<DIM>(a.pos, pi, oj, fr.R2);
+            const bool truth = recheck<DIM>(spos_set, pi, oj - poff, fr.R2);
             const bool naive = r2h <= fr.t_mid;
             t.band++;
             t.fpos += naive && !truth;
@@ -548,7 +554,7 @@ k_count64(SearchArgs a)
     if (b >= *a.nblk) return;
     Geom<DIM> g;
     g.init(a, b);
-    const Frame& fr = a.fr;
+    const Frame& fr = g.fr;
     CB cb_;
     cb_.init(g, lbits);
     int cnt = 0;
@@ -714,11 +720,13 @@ k_fill(SearchArgs a)
     const int lane = threadIdx.x & 63;
     Geom<DIM> g;
     g.init(a, b);
-    const Frame& fr = a.fr;
+    const Frame& fr = g.fr;
+    const SetDesc& sd = *g.sd;
     const int pp = g.active ? g.p : g.p1 - 1;
     const int oi = a.perm[pp];
-    const long long rs = a.row_ptr[oi];
-    const int rlen = g.active ? static_cast<int>(a.row_ptr[oi + 1] - rs) : 0;
+    const int li = oi - sd.poff;
+    const long long rs = sd.row_ptr[li];
+    const int rlen = g.active ? static_cast<int>(sd.row_ptr[li + 1] - rs) : 0;
     int E;
     const int off = wave_excl_scan_i32(rlen, &E);
     // the lane's candidate order (row segment by row segment), as in the count pass
@@ -747,7 +755,7 @@ k_fill(SearchArgs a)
     double pi[3] = {0, 0, 0};
     if (MODE == 1) {
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) pi[k] = a.pos[static_cast<size_t>(oi) * DIM + k];
+        for (int k = 0; k < DIM; ++k) pi[k] = sd.pos[static_cast<size_t>(li) * DIM + k];
     }
     if (g.active) {
         // accepted candidates from the count pass, re-indexed by rank
@@ -757,7 +765,7 @@ k_fill(SearchArgs a)
             if (c0 >= c1) continue;
             const int pbase = g.la[r] - c0;  // logical position = pbase + candidate index
             for (int w = c0 >> 5; w <= ((c1 - 1) >> 5); ++w) {
-                uint32_t bits = a.cbits[static_cast<size_t>(w) * fr.n + g.p];
+                uint32_t bits = a.cbits[static_cast<size_t>(w) * a.L.ntot + g.p];
                 const int lo = c0 - 32 * w, hi = c1 - 32 * w;
                 if (lo > 0) bits &= ~0u << lo;
                 if (hi < 32) bits &= (1u << hi) - 1u;
@@ -818,7 +826,7 @@ k_fill(SearchArgs a)
         s.idx = srow[t] + (e - soff[t]);
 #pragma unroll
         for (int c = 0; c < DIM; ++c)
-            s.xj[c] = MODE == 1 ? __builtin_bit_cast(long long, a.pos[static_cast<size_t>(s.oj) * DIM + c])
+            s.xj[c] = MODE == 1 ? __builtin_bit_cast(long long, sd.pos[static_cast<size_t>(s.oj - sd.poff) * DIM + c])
                                 : a.X[static_cast<size_t>(s.oj) * x_stride(DIM) + c];
     };
     Ent cur;
@@ -846,9 +854,9 @@ k_fill(SearchArgs a)
                 }
                 d = __builtin_amdgcn_sqrtf(s2) * fr.dist_scale;  // <= 1 ulp; s2 >= 1 or 0
             }
-            if (cur.idx < a.capacity) {
-                a.col[cur.idx] = cur.oj;
-                a.dist[cur.idx] = d;
+            if (cur.idx < sd.capacity) {
+                sd.col[cur.idx] = cur.oj - sd.poff;
+                sd.dist[cur.idx] = d;
             } else {
                 atomicOr(a.err, kErrCapacity);
             }
@@ -858,37 +866,49 @@ k_fill(SearchArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Long rows: one workgroup per target, candidates spread over its threads, entries
-// appended to the row in any order and then sorted in LDS (bitonic network in which
-// every comparator puts the smaller key first, so padding at +inf never moves).
-constexpr int kHeavyThreads = 256;
+// Long rows (blocks whose union, entry count or candidate count exceed the fill's
+// limits): one workgroup per target. Its candidates are tested across the workgroup and
+// the accepted original indices appended to the row in any order; the row is then sorted
+// in place (LDS bitonic network for up to lr_keys entries, in which every comparator puts
+// the smaller key first so padding at +inf never moves; longer rows are sorted in chunks
+// and merged pairwise by rank, using the row's distance slots as scratch), and finally
+// the distances are computed from the sorted column indices.
+constexpr int kLongThreads = 256;
 
 template <int DIM, int MODE>
-__global__ void __launch_bounds__(kHeavyThreads)
-k_heavy(SearchArgs a)
+__global__ void __launch_bounds__(kLongThreads)
+k_long(SearchArgs a)
 {
-    __shared__ unsigned long long keys[kHeavySortMax];
+    extern __shared__ uint32_t keys[];  // a.lr_keys entries
     __shared__ int fill;
-    const Frame& fr = a.fr;
-    const uint32_t ncx = static_cast<uint32_t>(fr.nc[0]);
-    const int ncy = fr.nc[1], ncz = fr.nc[2];
     const int nh = *a.nheavy;
+    const int T = kLongThreads;
     for (int h = blockIdx.x; h < nh; h += gridDim.x) {
         const int p = a.heavy[h];
-        const int oi = a.perm[p];
-        const uint32_t key = a.skey[p];
+        const uint32_t gkey = a.skey[p];
+        const SetDesc& sd = a.L.sets[find_set(a.L.coffs, a.L.nsets, static_cast<int>(gkey))];
+        const Frame& fr = sd.fr;
+        const int* cs = a.cell_start + sd.coff;
+        const uint32_t ncx = static_cast<uint32_t>(fr.nc[0]);
+        const int ncy = fr.nc[1], ncz = fr.nc[2];
+        const uint32_t key = gkey - static_cast<uint32_t>(sd.coff);
         const uint32_t row = key / ncx;
         const int x = static_cast<int>(key - row * ncx);
         const int y0 = static_cast<int>(row % static_cast<uint32_t>(ncy));
         const int z0 = static_cast<int>(row / static_cast<uint32_t>(ncy));
-        const long long rs = a.row_ptr[oi];
-        const long long rlen = a.row_ptr[oi + 1] - rs;
+        const int oi = a.perm[p];
+        const int li = oi - sd.poff;
+        const long long rs = sd.row_ptr[li];
+        const int rlen = static_cast<int>(sd.row_ptr[li + 1] - rs);
         double pi[3] = {0, 0, 0};
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) pi[k] = a.pos[static_cast<size_t>(oi) * DIM + k];
+        for (int k = 0; k < DIM; ++k) pi[k] = sd.pos[static_cast<size_t>(li) * DIM + k];
         const ushort4 qi = a.q4[p];
         if (threadIdx.x == 0) fill = 0;
         __syncthreads();
+        const bool room = rs + rlen <= sd.capacity;
+        int32_t* col = sd.col + rs;
+        // 1. test every candidate; append accepted set-local indices in any order
         constexpr int NSEG = DIM == 3 ? 9 : 3;
         const int lx0 = x > 0 ? x - 1 : 0;
         const int lx1 = x + 1 < static_cast<int>(ncx) ? x + 1 : static_cast<int>(ncx) - 1;
@@ -897,20 +917,18 @@ k_heavy(SearchArgs a)
             const int yy = y0 + dy, zz = z0 + dz;
             if (yy < 0 || yy >= ncy || zz < 0 || zz >= ncz) continue;
             const int rb = (zz * ncy + yy) * static_cast<int>(ncx);
-            const int ga = a.cell_start[rb + lx0], gb = a.cell_start[rb + lx1 + 1];
+            const int ga = cs[rb + lx0], gb = cs[rb + lx1 + 1];
             const _Float16 ay = as_f16(qi.y) + static_cast<_Float16>(-2 * dy);
             const _Float16 az = as_f16(qi.z) + static_cast<_Float16>(-2 * dz);
-            for (int j = ga + static_cast<int>(threadIdx.x); j < gb; j += kHeavyThreads) {
+            for (int j = ga + static_cast<int>(threadIdx.x); j < gb; j += T) {
                 if (j == p) continue;
                 bool nb;
                 const int oj = a.perm[j];
                 if (MODE == 1) {
-                    const double* pj = a.spos + static_cast<size_t>(j) * 4;
-                    const double* pis = a.spos + static_cast<size_t>(p) * 4;
-                    nb = r2_fp64<DIM>(pis, pj) <= fr.R2;
+                    nb = r2_fp64<DIM>(a.spos + static_cast<size_t>(p) * 4, a.spos + static_cast<size_t>(j) * 4) <= fr.R2;
                 } else {
                     const ushort4 v = a.q4[j];
-                    const uint32_t kj = a.skey[j];
+                    const uint32_t kj = a.skey[j] - static_cast<uint32_t>(sd.coff);
                     const int cjx = static_cast<int>(kj - (kj / ncx) * ncx);
                     const _Float16 s = as_f16(qi.x) - as_f16(v.x);
                     const _Float16 tx = s + static_cast<_Float16>(2 * (x - cjx));
@@ -927,40 +945,32 @@ k_heavy(SearchArgs a)
                     const uint16_t r2h = __builtin_bit_cast(uint16_t, r2);
                     const bool in16 = r2h < fr.t_lo;
                     const bool band = !in16 && r2h <= fr.t_hi;
-                    nb = (MODE == 2 || band) ? recheck<DIM>(a.pos, pi, oj, fr.R2) : in16;
+                    nb = (MODE == 2 || band) ? recheck<DIM>(sd.pos, pi, oj - sd.poff, fr.R2) : in16;
                 }
                 if (nb) {
                     const int slot = atomicAdd(&fill, 1);
-                    const float d = MODE == 1 ? dist_fp64<DIM>(a.pos, oi, oj)
-                                              : dist_fixed<DIM>(a.X, fr.n, oi, oj, fr.dist_scale);
-                    const long long idx = rs + slot;
-                    if (slot < rlen && idx < a.capacity) {
-                        a.col[idx] = oj;
-                        a.dist[idx] = d;
-                    } else {
-                        atomicOr(a.err, slot < rlen ? kErrCapacity : kErrLongRow);
-                    }
+                    if (slot < rlen && room) col[slot] = oj - sd.poff;
                 }
             }
         }
         __syncthreads();
         const int L = fill;
-        if (L != rlen) {
-            if (threadIdx.x == 0) atomicOr(a.err, kErrLongRow);
-        } else if (L > kHeavySortMax) {
-            if (threadIdx.x == 0) atomicOr(a.err, kErrLongRow);
-        } else if (rs + L <= a.capacity) {
+        if (L != rlen || !room) {
+            if (threadIdx.x == 0) atomicOr(a.err, !room ? kErrCapacity : kErrLongRow);
+            __syncthreads();
+            continue;
+        }
+        // 2. sort the row's column indices (distinct keys)
+        const int K = a.lr_keys;
+        for (int c0 = 0; c0 < L; c0 += K) {
+            const int len = min(K, L - c0);
             int P = 1;
-            while (P < L) P <<= 1;
-            for (int i = threadIdx.x; i < P; i += kHeavyThreads) {
-                keys[i] = i < L ? (static_cast<unsigned long long>(static_cast<uint32_t>(a.col[rs + i])) << 32) |
-                                      __builtin_bit_cast(uint32_t, a.dist[rs + i])
-                                : ~0ull;
-            }
+            while (P < len) P <<= 1;
+            for (int i = threadIdx.x; i < P; i += T) keys[i] = i < len ? static_cast<uint32_t>(col[c0 + i]) : 0xFFFFFFFFu;
             __syncthreads();
             for (int k = 2; k <= P; k <<= 1) {
                 for (int j = k >> 1; j > 0; j >>= 1) {
-                    for (int t = threadIdx.x; t < P / 2; t += kHeavyThreads) {
+                    for (int t = threadIdx.x; t < P / 2; t += T) {
                         int i0, i1;
                         if (j == (k >> 1)) {
                             i0 = (t / j) * k + (t % j);
@@ -969,7 +979,7 @@ k_heavy(SearchArgs a)
                             i0 = (t / j) * 2 * j + (t % j);
                             i1 = i0 + j;
                         }
-                        const unsigned long long u = keys[i0], v = keys[i1];
+                        const uint32_t u = keys[i0], v = keys[i1];
                         if (u > v) {
                             keys[i0] = v;
                             keys[i1] = u;
@@ -978,10 +988,46 @@ k_heavy(SearchArgs a)
                     __syncthreads();
                 }
             }
-            for (int i = threadIdx.x; i < L; i += kHeavyThreads) {
-                a.col[rs + i] = static_cast<int32_t>(keys[i] >> 32);
-                a.dist[rs + i] = __builtin_bit_cast(float, static_cast<uint32_t>(keys[i]));
+            for (int i = threadIdx.x; i < len; i += T) col[c0 + i] = static_cast<int32_t>(keys[i]);
+            __syncthreads();
+        }
+        // merge sorted runs of width K, 2K, ... between the column slots and the
+        // distance slots (reinterpreted as 32-bit keys)
+        uint32_t* src = reinterpret_cast<uint32_t*>(col);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(sd.dist + rs);
+        for (int width = K; width < L; width <<= 1) {
+            for (int e = threadIdx.x; e < L; e += T) {
+                const int run = e / width;
+                const int base = (run & ~1) * width;           // start of the pair of runs
+                const int mid = min(base + width, L), end = min(base + 2 * width, L);
+                const uint32_t v = src[e];
+                // position among the other run: keys are distinct
+                int lo, hi, own;
+                if (e < mid) { lo = mid; hi = end; own = e - base; }
+                else { lo = base; hi = mid; own = e - mid; }
+                int cnt = 0, l = lo, r = hi;
+                while (l < r) {
+                    const int m = (l + r) >> 1;
+                    if (src[m] < v) l = m + 1;
+                    else r = m;
+                }
+                cnt = l - lo;
+                dst[base + own + cnt] = v;
             }
+            __syncthreads();
+            uint32_t* tmp = src;
+            src = dst;
+            dst = tmp;
+        }
+        if (src != reinterpret_cast<uint32_t*>(col)) {
+            for (int e = threadIdx.x; e < L; e += T) col[e] = static_cast<int32_t>(src[e]);
+            __syncthreads();
+        }
+        // 3. distances of the sorted row
+        for (int e = threadIdx.x; e < L; e += T) {
+            const int lj = col[e];
+            sd.dist[rs + e] = MODE == 1 ? dist_fp64<DIM>(sd.pos, li, lj)
+                                        : dist_fixed<DIM>(a.X, oi, lj + sd.poff, fr.dist_scale);
         }
         __syncthreads();
     }
@@ -990,9 +1036,9 @@ k_heavy(SearchArgs a)
 // ---------------------------------------------------------------------------
 hipError_t launch_count(const SearchArgs& a, int nblk_max, hipStream_t st)
 {
-    if (a.fr.n == 0 || nblk_max == 0) return hipSuccess;
+    if (a.L.ntot == 0 || nblk_max == 0) return hipSuccess;
     const dim3 g(nblk_max), b(64);
-    const int d = a.fr.dim, m = a.fr.mode;
+    const int d = a.L.dim, m = a.L.mode;
     if (d == 2 && m == 0) hipLaunchKernelGGL((k_count16<2, 0>), g, b, 0, st, a);
     else if (d == 3 && m == 0) hipLaunchKernelGGL((k_count16<3, 0>), g, b, 0, st, a);
     else if (d == 2 && m == 2) hipLaunchKernelGGL((k_count16<2, 2>), g, b, 0, st, a);
@@ -1005,9 +1051,9 @@ hipError_t launch_count(const SearchArgs& a, int nblk_max, hipStream_t st)
 
 hipError_t launch_fill(const SearchArgs& a, int nblk_max, hipStream_t st)
 {
-    if (a.fr.n == 0 || nblk_max == 0) return hipSuccess;
+    if (a.L.ntot == 0 || nblk_max == 0) return hipSuccess;
     const dim3 g(nblk_max), b(64);
-    const int d = a.fr.dim, m = a.fr.mode;
+    const int d = a.L.dim, m = a.L.mode;
     if (d == 2 && m == 0) hipLaunchKernelGGL((k_fill<2, 0>), g, b, 0, st, a);
     else if (d == 3 && m == 0) hipLaunchKernelGGL((k_fill<3, 0>), g, b, 0, st, a);
     else if (d == 2 && m == 2) hipLaunchKernelGGL((k_fill<2, 2>), g, b, 0, st, a);
@@ -1017,17 +1063,18 @@ hipError_t launch_fill(const SearchArgs& a, int nblk_max, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_long_rows(const SearchArgs& a, hipStream_t st)
+hipError_t launch_long_rows(const SearchArgs& a, int grid, hipStream_t st)
 {
-    if (a.fr.n == 0) return hipSuccess;
-    const int d = a.fr.dim, m = a.fr.mode;
-    const dim3 gh(512), bh(kHeavyThreads);
-    if (d == 2 && m == 0) hipLaunchKernelGGL((k_heavy<2, 0>), gh, bh, 0, st, a);
-    else if (d == 3 && m == 0) hipLaunchKernelGGL((k_heavy<3, 0>), gh, bh, 0, st, a);
-    else if (d == 2 && m == 2) hipLaunchKernelGGL((k_heavy<2, 2>), gh, bh, 0, st, a);
-    else if (d == 3 && m == 2) hipLaunchKernelGGL((k_heavy<3, 2>), gh, bh, 0, st, a);
-    else if (d == 2) hipLaunchKernelGGL((k_heavy<2, 1>), gh, bh, 0, st, a);
-    else hipLaunchKernelGGL((k_heavy<3, 1>), gh, bh, 0, st, a);
+    if (a.L.ntot == 0) return hipSuccess;
+    const int d = a.L.dim, m = a.L.mode;
+    const dim3 gh(grid), bh(kLongThreads);
+    const size_t lds = static_cast<size_t>(a.lr_keys) * 4;
+    if (d == 2 && m == 0) hipLaunchKernelGGL((k_long<2, 0>), gh, bh, lds, st, a);
+    else if (d == 3 && m == 0) hipLaunchKernelGGL((k_long<3, 0>), gh, bh, lds, st, a);
+    else if (d == 2 && m == 2) hipLaunchKernelGGL((k_long<2, 2>), gh, bh, lds, st, a);
+    else if (d == 3 && m == 2) hipLaunchKernelGGL((k_long<3, 2>), gh, bh, lds, st, a);
+    else if (d == 2) hipLaunchKernelGGL((k_long<2, 1>), gh, bh, lds, st, a);
+    else hipLaunchKernelGGL((k_long<3, 1>), gh, bh, lds, st, a);
     return hipGetLastError();
 }
 

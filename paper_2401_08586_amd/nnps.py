@@ -55,9 +55,17 @@ class Stats(ctypes.Structure):
         return d
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("block_target", ctypes.c_int32), ("long_rows_grid", ctypes.c_int32),
+                ("long_rows_keys", ctypes.c_int32)]
+
+
 EXPORTS = ["nnps_status_str", "nnps_validate", "nnps_grid", "nnps_ctx_create", "nnps_ctx_destroy",
+           "nnps_ctx_set_tuning", "nnps_ctx_get_tuning",
            "nnps_cells_create", "nnps_cells_destroy", "nnps_cells_build", "nnps_count", "nnps_fill",
-           "nnps_search", "nnps_stats_get", "nnps_cells_set_profiling", "nnps_phase_times"]
+           "nnps_search", "nnps_stats_get", "nnps_cells_set_profiling", "nnps_phase_times",
+           "nnps_batch_build", "nnps_batch_count", "nnps_batch_fill", "nnps_batch_search",
+           "nnps_batch_step", "nnps_cells_set_graphs", "nnps_batch_nnz"]
 
 PHASES = ["assign", "cellscan", "sort", "pack", "blocks", "count", "rowscan", "fill", "longrows"]
 
@@ -92,6 +100,15 @@ def load():
     lib.nnps_search.argtypes = [P, P, ctypes.POINTER(Problem), P, P, P, P, I64, ctypes.POINTER(I64), P]
     lib.nnps_stats_get.argtypes = [P, ctypes.POINTER(Stats), P]
     lib.nnps_cells_set_profiling.argtypes = [P, ctypes.c_int]
+    lib.nnps_ctx_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+    lib.nnps_ctx_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+    lib.nnps_batch_build.argtypes = [P, P, ctypes.c_int32, ctypes.POINTER(Problem), P, P]
+    lib.nnps_batch_count.argtypes = [P, P, P, P, P]
+    lib.nnps_batch_fill.argtypes = [P, P, P, P, P, P, P]
+    lib.nnps_batch_search.argtypes = [P, P, ctypes.c_int32, ctypes.POINTER(Problem), P, P, P, P, P, P, P]
+    lib.nnps_batch_step.argtypes = [P, P, ctypes.c_int32, ctypes.POINTER(Problem), P, P, P, P, P, P]
+    lib.nnps_cells_set_graphs.argtypes = [P, ctypes.c_int]
+    lib.nnps_batch_nnz.argtypes = [P, P, P]
     lib.nnps_phase_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), P]
     for name in EXPORTS:
         fn = getattr(lib, name)
@@ -175,6 +192,16 @@ class Context:
         except Exception:
             pass
 
+    def set_tuning(self, block_target: int = 56, long_rows_grid: int = 1024, long_rows_keys: int = 0):
+        t = Tuning(int(block_target), int(long_rows_grid), int(long_rows_keys))
+        _check(self._lib.nnps_ctx_set_tuning(self._ctx, ctypes.byref(t)), "nnps_ctx_set_tuning")
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        _check(self._lib.nnps_ctx_get_tuning(self._ctx, ctypes.byref(t)), "nnps_ctx_get_tuning")
+        return {"block_target": t.block_target, "long_rows_grid": t.long_rows_grid,
+                "long_rows_keys": t.long_rows_keys}
+
     def cells(self) -> "Cells":
         c = Cells(self)
         self._cells.append(c)
@@ -224,6 +251,46 @@ class Cells:
         _check(self._lib.nnps_fill(self.ctx._ctx, self._h, _ptr(row_ptr), _ptr(col), _ptr(dist), cap,
                                    _stream_ptr(stream)), "nnps_fill")
 
+    # ---- batches ------------------------------------------------------------------
+    def batch_build(self, sets, mode=MODE_FP16_RCLL, stream=None):
+        """sets: list of (pos tensor [n, dim] float64 CUDA, lo, hi, cell_size, radius)."""
+        probs, ptrs = _batch_args(sets, mode)
+        _check(self._lib.nnps_batch_build(self.ctx._ctx, self._h, len(sets), probs, ptrs,
+                                          _stream_ptr(stream)), "nnps_batch_build")
+        self.nsets = len(sets)
+        self._pos = [t[0] for t in sets]
+        return self
+
+    def batch_count(self, row_ptrs, sync=True, stream=None):
+        rp = _ptr_array(row_ptrs)
+        nnz = (ctypes.c_int64 * len(row_ptrs))()
+        _check(self._lib.nnps_batch_count(self.ctx._ctx, self._h, rp, nnz if sync else None,
+                                          _stream_ptr(stream)), "nnps_batch_count")
+        return list(nnz) if sync else None
+
+    def batch_fill(self, row_ptrs, cols, dists, stream=None):
+        cap = (ctypes.c_int64 * len(cols))(*[c.numel() for c in cols])
+        _check(self._lib.nnps_batch_fill(self.ctx._ctx, self._h, _ptr_array(row_ptrs), _ptr_array(cols),
+                                         _ptr_array(dists), cap, _stream_ptr(stream)), "nnps_batch_fill")
+
+    def batch_step(self, sets, row_ptrs, cols, dists, mode=MODE_FP16_RCLL, stream=None):
+        """Build + count + fill without waiting; outputs must already be large enough."""
+        probs, ptrs = _batch_args(sets, mode)
+        cap = (ctypes.c_int64 * len(cols))(*[c.numel() for c in cols])
+        _check(self._lib.nnps_batch_step(self.ctx._ctx, self._h, len(sets), probs, ptrs,
+                                         _ptr_array(row_ptrs), _ptr_array(cols), _ptr_array(dists), cap,
+                                         _stream_ptr(stream)), "nnps_batch_step")
+        self.nsets = len(sets)
+        self._pos = [t[0] for t in sets]
+
+    def batch_nnz(self, stream=None):
+        nnz = (ctypes.c_int64 * self.nsets)()
+        _check(self._lib.nnps_batch_nnz(self._h, nnz, _stream_ptr(stream)), "nnps_batch_nnz")
+        return list(nnz)
+
+    def set_graphs(self, on: bool = True):
+        _check(self._lib.nnps_cells_set_graphs(self._h, 1 if on else 0), "nnps_cells_set_graphs")
+
     def set_profiling(self, on: bool = True):
         _check(self._lib.nnps_cells_set_profiling(self._h, 1 if on else 0), "nnps_cells_set_profiling")
 
@@ -239,6 +306,42 @@ class Cells:
         code = self._lib.nnps_stats_get(self._h, ctypes.byref(st), _stream_ptr(stream))
         _check(code, "nnps_stats_get")
         return st.as_dict()
+
+
+def _ptr_array(tensors):
+    arr = (ctypes.c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = t.data_ptr() if t is not None and t.numel() > 0 else None
+    return arr
+
+
+def _batch_args(sets, mode):
+    probs = (Problem * len(sets))()
+    ptrs = (ctypes.c_void_p * len(sets))()
+    for i, (pos, lo, hi, cell_size, radius) in enumerate(sets):
+        n, dim = pos.shape
+        probs[i] = make_problem(dim, n, lo, hi, cell_size, radius, mode)
+        ptrs[i] = pos.data_ptr() if n > 0 else None
+    return probs, ptrs
+
+
+def search_batch(sets, mode=MODE_FP16_RCLL, ctx: Context | None = None, cells: Cells | None = None,
+                 stream=None):
+    """Search every set of `sets` (list of (pos, lo, hi, cell_size, radius)) in one batch.
+    Returns a list of (row_ptr, col, dist) CUDA tensors, one per set, and the cells."""
+    import torch
+    if ctx is None:
+        ctx = Context(sets[0][0].device.index or 0)
+    if cells is None:
+        cells = ctx.cells()
+    cells.batch_build(sets, mode, stream)
+    dev = sets[0][0].device
+    rps = [torch.empty(t[0].shape[0] + 1, dtype=torch.int64, device=dev) for t in sets]
+    nnz = cells.batch_count(rps, sync=True, stream=stream)
+    cols = [torch.empty(max(k, 0), dtype=torch.int32, device=dev) for k in nnz]
+    dists = [torch.empty(max(k, 0), dtype=torch.float32, device=dev) for k in nnz]
+    cells.batch_fill(rps, cols, dists, stream)
+    return list(zip(rps, cols, dists)), cells
 
 
 def search(pos, lo, hi, cell_size, radius, mode=MODE_FP16_RCLL, ctx: Context | None = None,

@@ -1,0 +1,166 @@
+"""GPU parity for batches: many uneven particle sets searched in one launch per pass,
+the graph-captured step and its replays, and the long-row path (chunked sort + merge),
+each set checked element by element against the CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_08586_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2401_08586_amd import nnps  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = nnps.Context(0)
+    yield c
+    c.close()
+
+
+def as_sets(pss):
+    return [(torch.from_numpy(np.ascontiguousarray(ps.pos)).cuda(), ps.lo, ps.hi, ps.cell_size, ps.radius)
+            for ps in pss]
+
+
+def check(got, ps, mode, name):
+    rp, col, dist = (t.cpu().numpy() for t in got)
+    wrp, wcol, wdist = oracle.search_ps(ps)
+    np.testing.assert_array_equal(rp, wrp, err_msg=f"{name} row_ptr")
+    np.testing.assert_array_equal(col, wcol, err_msg=f"{name} col")
+    if mode == nnps.MODE_FP64_BASELINE:
+        np.testing.assert_array_equal(dist.view(np.uint32), wdist.view(np.uint32), err_msg=f"{name} dist")
+    else:
+        wd = wdist.astype(np.float64)
+        assert np.all(np.abs(dist - wd) <= 1e-6 * wd), name
+        assert np.all(dist[wdist == 0] == 0)
+
+
+def uneven_batch(dim=3, seed=0, k=7):
+    rng = np.random.default_rng(seed)
+    sizes = np.floor(np.exp(rng.uniform(np.log(300), np.log(12000), size=k))).astype(int)
+    sets = [W.clustered(int(n), seed * 100 + i, dim=dim) for i, n in enumerate(sizes)]
+    sets.append(W.lattice(dim, 14 if dim == 3 else 60, 1 / (14 if dim == 3 else 60), 0.1, seed=seed))
+    return sets
+
+
+@pytest.mark.parametrize("mode", [nnps.MODE_FP16_RCLL, nnps.MODE_FP64_BASELINE, nnps.MODE_RECHECK_ALL],
+                         ids=["fp16", "fp64", "recheck_all"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_batch_parity(ctx, dim, mode):
+    pss = uneven_batch(dim, seed=dim)
+    print(f"[gpu] batch dim={dim} mode={mode} sizes={[p.n for p in pss]}", flush=True)
+    cells = ctx.cells()
+    res, _ = nnps.search_batch(as_sets(pss), mode=mode, ctx=ctx, cells=cells)
+    st = cells.stats()
+    for got, ps in zip(res, pss):
+        check(got, ps, mode, ps.name)
+    assert st["nnz"] == sum(int(r[0][-1]) for r in res)
+    assert st["outside_band_disagree"] == 0
+    cells.close()
+
+
+def test_batch_with_empty_and_tiny_sets(ctx):
+    rng = np.random.default_rng(3)
+    pss = [W.ParticleSet(np.zeros((0, 3)), (0, 0, 0), (1, 1, 1), 0.1, 0.1, "empty"),
+           W.ParticleSet(rng.uniform(0, 1, (1, 3)), (0, 0, 0), (1, 1, 1), 0.1, 0.1, "one"),
+           W.clustered(3000, 5, dim=3),
+           W.ParticleSet(np.zeros((0, 3)), (0, 0, 0), (2, 2, 2), 0.2, 0.2, "empty2"),
+           W.uniform(3, 5000, seed=6)]
+    print("[gpu] batch with empty sets", flush=True)
+    cells = ctx.cells()
+    res, _ = nnps.search_batch(as_sets(pss), ctx=ctx, cells=cells)
+    for got, ps in zip(res, pss):
+        check(got, ps, 0, ps.name)
+    cells.close()
+
+
+def test_single_equals_batch(ctx):
+    """A set's result is the same alone and inside a batch."""
+    pss = uneven_batch(3, seed=9, k=5)
+    cells = ctx.cells()
+    res, _ = nnps.search_batch(as_sets(pss), ctx=ctx, cells=cells)
+    for got, ps in zip(res, pss):
+        alone = nnps.search(torch.from_numpy(ps.pos).cuda(), ps.lo, ps.hi, ps.cell_size, ps.radius, ctx=ctx)[:3]
+        for x, y in zip(got, alone):
+            assert torch.equal(x, y), ps.name
+    cells.close()
+
+
+def test_graph_step_replays(ctx):
+    """The captured step gives the eager result on every replay, also after the
+    positions move (same sizes: the graph is replayed with the new pointers)."""
+    pss = uneven_batch(3, seed=4, k=4)
+    sets = as_sets(pss)
+    eager_cells = ctx.cells()
+    ref, _ = nnps.search_batch(sets, ctx=ctx, cells=eager_cells)
+    cells = ctx.cells()
+    cells.set_graphs(True)
+    rps = [torch.empty_like(r[0]) for r in ref]
+    cols = [torch.empty(r[1].numel() + 64, dtype=torch.int32, device="cuda") for r in ref]
+    dists = [torch.empty(r[2].numel() + 64, dtype=torch.float32, device="cuda") for r in ref]
+    stream = torch.cuda.Stream()
+    print("[gpu] graph replays", flush=True)
+    for rep in range(4):
+        with torch.cuda.stream(stream):
+            cells.batch_step(sets, rps, cols, dists, stream=stream)
+        stream.synchronize()
+        nnz = cells.batch_nnz(stream=stream)
+        for s, (r, k) in enumerate(zip(ref, nnz)):
+            assert k == r[1].numel()
+            assert torch.equal(rps[s], r[0])
+            assert torch.equal(cols[s][:k], r[1])
+            assert torch.equal(dists[s][:k], r[2])
+        # eager work between replays
+        torch.cuda.synchronize()
+        _ = (sets[0][0] * 2.0).sum().item()
+    # move the particles (same sizes): replay reads the new positions
+    moved = [W.ParticleSet(W.step_displacement(ps, 1, seed=7), ps.lo, ps.hi, ps.cell_size, ps.radius, ps.name)
+             for ps in pss]
+    msets = as_sets(moved)
+    nnz_new = None
+    for rep in range(2):
+        with torch.cuda.stream(stream):
+            mrps = [torch.empty_like(r) for r in rps]
+            big = [torch.empty(c.numel() + 20000, dtype=torch.int32, device="cuda") for c in cols]
+            bigd = [torch.empty(c.numel() + 20000, dtype=torch.float32, device="cuda") for c in cols]
+            cells.batch_step(msets, mrps, big, bigd, stream=stream)
+        stream.synchronize()
+        nnz_new = cells.batch_nnz(stream=stream)
+        for s, ps in enumerate(moved):
+            check((mrps[s], big[s][:nnz_new[s]], bigd[s][:nnz_new[s]]), ps, 0, ps.name + "_moved")
+    cells.close()
+    eager_cells.close()
+
+
+def test_long_rows_chunked_merge(ctx):
+    """Rows far longer than the LDS sort chunk: chunks sorted, then merged pairwise."""
+    rng = np.random.default_rng(8)
+    pos = np.clip(np.concatenate([rng.normal(0.5, 0.015, size=(2500, 3)), rng.uniform(0, 1, size=(500, 3))]), 0, 1)
+    ps = W.ParticleSet(pos, (0, 0, 0), (1, 1, 1), 0.06, 0.06, "dense_ball")
+    for keys in (64, 256, 0):
+        ctx.set_tuning(block_target=56, long_rows_grid=256, long_rows_keys=keys)
+        print(f"[gpu] long rows keys={keys}", flush=True)
+        for mode in (nnps.MODE_FP16_RCLL, nnps.MODE_FP64_BASELINE):
+            cells = ctx.cells()
+            rp, col, dist, _ = nnps.search(torch.from_numpy(ps.pos).cuda(), ps.lo, ps.hi, ps.cell_size, ps.radius,
+                                           mode=mode, ctx=ctx, cells=cells)
+            st = cells.stats()
+            assert st["heavy_rows"] > 0
+            check((rp, col, dist), ps, mode, f"{ps.name}_k{keys}_m{mode}")
+            cells.close()
+    ctx.set_tuning()
+
+
+@pytest.mark.parametrize("bt", [16, 32, 64, 128])
+def test_block_target_tuning_keeps_results(ctx, bt):
+    ps = W.lattice(3, 20, 1 / 20, 0.1, seed=2)
+    ctx.set_tuning(block_target=bt)
+    print(f"[gpu] block_target={bt}", flush=True)
+    rp, col, dist, _ = nnps.search(torch.from_numpy(ps.pos).cuda(), ps.lo, ps.hi, ps.cell_size, ps.radius, ctx=ctx)
+    check((rp, col, dist), ps, 0, f"bt{bt}")
+    ctx.set_tuning()
