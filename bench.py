@@ -81,6 +81,50 @@ def time_mode(ctx, pos, ps, mode, steps, warmup):
     return max(wall_ms, ev_ms) / steps, nnz, st, phases
 
 
+def time_batch(ctx, pss, mode, steps, warmup, graphs=True):
+    """Batch of particle sets: one graph-captured step (build + count + fill) per timed
+    step. Returns (ms per step, total nnz, stats, per-phase mean ms)."""
+    import torch
+    from paper_2401_08586_amd import nnps
+    sets = [(torch.from_numpy(p.pos).cuda(), p.lo, p.hi, p.cell_size, p.radius) for p in pss]
+    cells = ctx.cells()
+    cells.batch_build(sets, mode)
+    rps = [torch.empty(p.n + 1, dtype=torch.int64, device="cuda") for p in pss]
+    nnz = cells.batch_count(rps, sync=True)
+    cols = [torch.empty(k, dtype=torch.int32, device="cuda") for k in nnz]
+    dists = [torch.empty(k, dtype=torch.float32, device="cuda") for k in nnz]
+    cells.batch_fill(rps, cols, dists)
+    st = cells.stats()
+    stream = torch.cuda.Stream()
+    cells.set_graphs(graphs)
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            cells.batch_step(sets, rps, cols, dists, mode, stream=stream)
+        stream.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(steps):
+            cells.batch_step(sets, rps, cols, dists, mode, stream=stream)
+        e1.record(stream)
+        stream.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    assert cells.batch_nnz(stream=stream) == nnz
+    # per-phase times of one more (eager) step
+    cells.set_graphs(False)
+    cells.set_profiling(True)
+    with torch.cuda.stream(stream):
+        cells.batch_step(sets, rps, cols, dists, mode, stream=stream)
+    ph = cells.phase_times(stream=stream)
+    cells.set_profiling(False)
+    cells.close()
+    del cols, dists
+    torch.cuda.empty_cache()
+    return (max(wall, e0.elapsed_time(e1)) / steps, int(sum(nnz)), st,
+            {k: (v[0] / v[1] if v[1] else None) for k, v in ph.items()})
+
+
 def fill_bytes(ps, nnz, band_pairs):
     """Algorithmic bytes of one fill launch: 8 per neighbour pair written (int32 col +
     float32 dist), per particle its FP16 record (8), original index (4), fixed-point
@@ -111,7 +155,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2"])
+    ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2", "c3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -125,6 +169,8 @@ def main():
     import torch
     from paper_2401_08586_amd import nnps
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "c3":
+        return bench_batch(args)
     ps = workload(args.workload)
     log(f"[bench] workload {ps.name} n={ps.n}")
     pos = torch.from_numpy(ps.pos).cuda()
@@ -178,6 +224,31 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(ps)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """32 clustered 3D sets (sizes log-uniform in [1e4, 1e6]) searched as one batch."""
+    from paper_2401_08586_amd import nnps
+    from paper_2401_08586_amd import workloads as W
+    pss = W.clustered_batch()
+    ntot = sum(p.n for p in pss)
+    log(f"[bench] batch of {len(pss)} clustered sets, {ntot} particles")
+    ctx = nnps.Context(0)
+    ms, nnz, st, ph = time_batch(ctx, pss, nnps.MODE_FP16_RCLL, args.steps, args.warmup)
+    log(f"[bench] batch fp16-rcll {ms:.3f} ms/step nnz={nnz} phases={ph}")
+    ctx.close()
+    out = {
+        "metric": "Gpairs/s, batched clustered 3D NNPS (32 sets, FP16 RCLL)",
+        "value": nnz / (ms * 1e-3) / 1e9, "unit": "Gpairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f16", "data": "synthetic",
+        "config": {"workload": "clustered_batch_32", "sets": len(pss), "particles": ntot,
+                   "sizes": sorted(p.n for p in pss)},
+        "nnz": nnz, "particles_per_s": ntot / (ms * 1e-3), "phases_ms": ph,
+        "fp16_stats": {k: st[k] for k in ("candidates", "band_pairs", "fp16_false_pos", "fp16_false_neg",
+                                          "heavy_rows")},
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -660,16 +660,17 @@ __device__ __forceinline__ void wave_bitonic(uint32_t (&v)[EPL])
 }
 
 // Ranks of the staged union by original index: rank_of[pos] and, in place of the
-// per-position original indices, orig[rank].
+// per-position original indices, orig[rank]. Fast form: one 32-bit key per entry,
+// (orig - base) << SHIFT | pos, valid when the union's index range is below 2^(32-SHIFT).
 template <int EPL, int SHIFT>
-__device__ __forceinline__ void rank_union(int U, int* sorig, uint16_t* rank_of)
+__device__ __forceinline__ void rank_union(int U, int* sorig, uint16_t* rank_of, int base)
 {
     const int lane = threadIdx.x & 63;
     uint32_t v[EPL];
 #pragma unroll
     for (int i = 0; i < EPL; ++i) {
         const int e = lane * EPL + i;
-        v[i] = e < U ? (static_cast<uint32_t>(sorig[e]) << SHIFT) | static_cast<uint32_t>(e) : 0xFFFFFFFFu;
+        v[i] = e < U ? (static_cast<uint32_t>(sorig[e] - base) << SHIFT) | static_cast<uint32_t>(e) : 0xFFFFFFFFu;
     }
     __builtin_amdgcn_wave_barrier();
     wave_bitonic<EPL>(v);
@@ -678,20 +679,65 @@ __device__ __forceinline__ void rank_union(int U, int* sorig, uint16_t* rank_of)
         const int e = lane * EPL + i;
         if (e < U) {
             rank_of[v[i] & ((1u << SHIFT) - 1)] = static_cast<uint16_t>(e);
-            sorig[e] = static_cast<int>(v[i] >> SHIFT);
+            sorig[e] = static_cast<int>(v[i] >> SHIFT) + base;
         }
     }
     __builtin_amdgcn_wave_barrier();
 }
 
-template <int SHIFT>
-__device__ __forceinline__ void rank_union_any(int U, int* sorig, uint16_t* rank_of)
+// Wide form: the (distinct) original indices alone are sorted in place; ranks are then
+// found by binary search (the caller re-reads each position's index).
+template <int EPL>
+__device__ __forceinline__ void sort_union(int U, int* sorig)
 {
-    if (U <= 64) rank_union<1, SHIFT>(U, sorig, rank_of);
-    else if (U <= 128) rank_union<2, SHIFT>(U, sorig, rank_of);
-    else if (U <= 256) rank_union<4, SHIFT>(U, sorig, rank_of);
-    else if (U <= 512) rank_union<8, SHIFT>(U, sorig, rank_of);
-    else rank_union<16, SHIFT>(U, sorig, rank_of);
+    const int lane = threadIdx.x & 63;
+    uint32_t v[EPL];
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) {
+        const int e = lane * EPL + i;
+        v[i] = e < U ? static_cast<uint32_t>(sorig[e]) : 0xFFFFFFFFu;
+    }
+    __builtin_amdgcn_wave_barrier();
+    wave_bitonic<EPL>(v);
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) {
+        const int e = lane * EPL + i;
+        if (e < U) sorig[e] = static_cast<int>(v[i]);
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int SHIFT>
+__device__ __forceinline__ void rank_union_any(int U, int* sorig, uint16_t* rank_of, int base)
+{
+    if (U <= 64) rank_union<1, SHIFT>(U, sorig, rank_of, base);
+    else if (U <= 128) rank_union<2, SHIFT>(U, sorig, rank_of, base);
+    else if (U <= 256) rank_union<4, SHIFT>(U, sorig, rank_of, base);
+    else if (U <= 512) rank_union<8, SHIFT>(U, sorig, rank_of, base);
+    else rank_union<16, SHIFT>(U, sorig, rank_of, base);
+}
+
+__device__ __forceinline__ void sort_union_any(int U, int* sorig)
+{
+    if (U <= 64) sort_union<1>(U, sorig);
+    else if (U <= 128) sort_union<2>(U, sorig);
+    else if (U <= 256) sort_union<4>(U, sorig);
+    else if (U <= 512) sort_union<8>(U, sorig);
+    else sort_union<16>(U, sorig);
+}
+
+__device__ __forceinline__ int wave_min_i32(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max_i32(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
 }
 
 template <int DIM, int MODE>
@@ -745,12 +791,35 @@ k_fill(SearchArgs a)
     }
     // stage the union's original indices and rank them
     const int U = g.U;
-    for (int e = lane; e < U; e += 64) sorig[e] = a.perm[g.global_of_any(e)];
+    int omin = 0x7FFFFFFF, omax = 0;
+    for (int e = lane; e < U; e += 64) {
+        const int o = a.perm[g.global_of_any(e)];
+        sorig[e] = o;
+        omin = min(omin, o);
+        omax = max(omax, o);
+    }
+    omin = wave_min_i32(omin);
+    omax = wave_max_i32(omax);
     uint32_t* mk = masks + lane * (C::MW + 1);
 #pragma unroll
     for (int w = 0; w < C::MW; ++w) mk[w] = 0;
     __syncthreads();
-    rank_union_any<C::SHIFT>(U, sorig, rank_of);
+    if (static_cast<uint32_t>(omax - omin) < (1u << (32 - C::SHIFT))) {
+        rank_union_any<C::SHIFT>(U, sorig, rank_of, omin);
+    } else {
+        sort_union_any(U, sorig);
+        __syncthreads();
+        for (int e = lane; e < U; e += 64) {
+            const int o = a.perm[g.global_of_any(e)];
+            int l = 0, r = U;
+            while (l < r) {
+                const int m = (l + r) >> 1;
+                if (sorig[m] < o) l = m + 1;
+                else r = m;
+            }
+            rank_of[e] = static_cast<uint16_t>(l);
+        }
+    }
     __syncthreads();
     double pi[3] = {0, 0, 0};
     if (MODE == 1) {

@@ -164,3 +164,29 @@ def test_block_target_tuning_keeps_results(ctx, bt):
     rp, col, dist, _ = nnps.search(torch.from_numpy(ps.pos).cuda(), ps.lo, ps.hi, ps.cell_size, ps.radius, ctx=ctx)
     check((rp, col, dist), ps, 0, f"bt{bt}")
     ctx.set_tuning()
+
+
+def test_batch_global_indices_past_the_packed_key_range(ctx):
+    """A batch whose global particle indices pass 2^22: the fill ranks a block's union
+    by original index with a 32-bit key holding the index above the union position. The
+    first set (4.5M uniform points in random order) has unions whose index range does not
+    fit that key (sampled rows + properties of the whole CSR); the second lies past 2^22
+    in the global index space (checked whole)."""
+    big = W.uniform(3, 4_500_000, seed=21, radius_factor=1.8)
+    small = W.clustered(20000, 22, dim=3)
+    print("[gpu] batch past 2^22 global indices", flush=True)
+    cells = ctx.cells()
+    res, _ = nnps.search_batch(as_sets([big, small]), ctx=ctx, cells=cells)
+    check(res[1], small, 0, "small_after_big")
+    rp, col, dist = res[0]
+    rpc = rp.cpu().numpy()
+    rows = np.random.default_rng(5).choice(big.n, size=3000, replace=False)
+    wrp, wcol, wdist = oracle.search_rows(big.pos, big.lo, big.hi, big.cell_size, big.radius, rows)
+    np.testing.assert_array_equal(np.diff(rpc)[rows], np.diff(wrp))
+    got = np.concatenate([col[int(rpc[r]):int(rpc[r + 1])].cpu().numpy() for r in rows])
+    np.testing.assert_array_equal(got, wcol)
+    assert int(col.min()) >= 0 and int(col.max()) < big.n
+    down = torch.nonzero(col[1:] <= col[:-1]).flatten().cpu().numpy() + 1
+    lens = np.diff(rpc)
+    assert set(down.tolist()) <= set(rpc[1:-1][lens[1:] > 0].tolist())
+    cells.close()
