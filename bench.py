@@ -158,6 +158,9 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2", "c3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-mix leg")
+    ap.add_argument("--no-autotune", action="store_true", help="batch workload: keep the default tuning")
+    ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 512 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -218,13 +221,44 @@ def main():
         "nnz": nnz,
         "phases_ms": ph16,
         "fp16_stats": {k: st16[k] for k in ("candidates", "band_pairs", "fp16_false_pos",
-                                              "fp16_false_neg", "heavy_rows")},
+                                              "fp16_false_neg", "heavy_rows", "dense_rows")},
         "fp64_baseline": res64,
     }
+    if not args.no_serving:
+        out["serving"] = bench_serving(args)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(ps)
     print(json.dumps(out), flush=True)
+
+
+def bench_serving(args, nsims=64, slots=2, load=0.7):
+    """Serving mix: 64 simulations (half 2D, half 3D lattices, 1e3..2e6 particles), each
+    request one time step (move, rebuild, search). The saturated request rate is measured
+    closed-loop first; then Poisson arrivals at `load` times that rate. Latency = arrival
+    to CSR ready (device event), over the requests after a warm-up."""
+    from paper_2401_08586_amd import serving as S
+    from paper_2401_08586_amd import workloads as W
+    sims = W.serving_sims(nsims)
+    log(f"[bench] serving: {nsims} sims, {sum(p.n for p in sims)} particles")
+    srv = S.Server(sims, slots=slots)
+    sat = srv.run([], closed_loop=5 * nsims)
+    cal = S.summarize(sat, warmup=nsims)
+    rate = load * cal["requests_per_s"]
+    warm = max(args.serving_requests // 10, nsims)
+    arrivals = S.poisson_arrivals(rate, args.serving_requests + warm, nsims, seed=11)
+    log(f"[bench] serving: saturated {cal['requests_per_s']:.0f} req/s; Poisson at {rate:.0f} req/s")
+    done = srv.run(arrivals)
+    res = S.summarize(done, warmup=warm)
+    srv.close()
+    log(f"[bench] serving: p50 {res['p50_ms']:.3f} ms p99 {res['p99_ms']:.3f} ms "
+        f"{res['gpairs_per_s']:.2f} Gpairs/s mean batch {res['mean_batch']:.1f}")
+    res.update({"sims": nsims, "slots": slots, "particles": sum(p.n for p in sims),
+                "saturated_requests_per_s": cal["requests_per_s"], "saturated_gpairs_per_s": cal["gpairs_per_s"],
+                "arrival_rate_per_s": rate, "load": load, "warmup_requests": warm,
+                "workload": "64 jittered lattices (32 2D, 32 3D), n log-uniform 1e3..2e6, per-step move "
+                            "U(+-0.05 dx), Poisson arrivals"})
+    return res
 
 
 def bench_batch(args):
@@ -235,6 +269,18 @@ def bench_batch(args):
     ntot = sum(p.n for p in pss)
     log(f"[bench] batch of {len(pss)} clustered sets, {ntot} particles")
     ctx = nnps.Context(0)
+    tuned = None
+    if not args.no_autotune:
+        import torch
+        from paper_2401_08586_amd import autotune as A
+        sets = [(torch.from_numpy(p.pos).cuda(), p.lo, p.hi, p.cell_size, p.radius) for p in pss]
+        t0 = time.perf_counter()
+        best, best_ms, evals = A.tune(ctx, sets, pss, nnps.MODE_FP16_RCLL, use_cache=False, log=log)
+        tuned = {"params": best, "ms_per_step_at_tuning": best_ms, "evaluations": evals,
+                 "tuning_s": time.perf_counter() - t0}
+        del sets
+        torch.cuda.empty_cache()
+        log(f"[bench] autotuned {best} ({evals} settings, {tuned['tuning_s']:.1f} s)")
     ms, nnz, st, ph = time_batch(ctx, pss, nnps.MODE_FP16_RCLL, args.steps, args.warmup)
     log(f"[bench] batch fp16-rcll {ms:.3f} ms/step nnz={nnz} phases={ph}")
     ctx.close()
@@ -247,7 +293,8 @@ def bench_batch(args):
                    "sizes": sorted(p.n for p in pss)},
         "nnz": nnz, "particles_per_s": ntot / (ms * 1e-3), "phases_ms": ph,
         "fp16_stats": {k: st[k] for k in ("candidates", "band_pairs", "fp16_false_pos", "fp16_false_neg",
-                                          "heavy_rows")},
+                                          "heavy_rows", "dense_rows", "dense_entries")},
+        "autotune": tuned,
     }
     print(json.dumps(out), flush=True)
 

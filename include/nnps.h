@@ -87,6 +87,8 @@ typedef struct nnps_stats {
     int64_t fp16_false_neg;         /* naive FP16 test says out, FP64 says in */
     int64_t outside_band_disagree;  /* RECHECK_ALL only: FP16 decided outside the band but wrong */
     int64_t heavy_rows;             /* rows handled by the long-row path */
+    int64_t dense_rows;             /* rows handled by the dense-cell path */
+    int64_t dense_entries;          /* summed stencil-union sizes of the dense cells */
     int32_t dim, mode;
     int32_t frac_bits;              /* F: fixed-point fraction bits per cell width */
     int32_t ncell[3];
@@ -101,11 +103,26 @@ typedef struct nnps_stats {
  * long_rows_grid: workgroups of the long-row path. Default 1024. Valid 1..2^20.
  * long_rows_keys: row entries the long-row path sorts in LDS at once (longer rows are
  *   sorted in chunks and merged); 0 = as many as the device's LDS allows. Valid 0 or
- *   64..16384, a power of two. */
+ *   64..16384, a power of two.
+ * dense_min_union: an x-window of cells is searched by the dense-cell path when one of
+ *   its cells has more than this many particles in its 3^d stencil (the particles every
+ *   target of that cell must test). The dense path stages each such cell's stencil
+ *   union, sorted by original index, once per chunk for all of the cell's targets.
+ *   0 = default (512 in 3D, 160 in 2D); -1 = never. Valid -1..2^30.
+ * dense_grid: workgroups of the dense-cell kernels (persistent). 0 = default (1024).
+ *   Valid 0..2^20.
+ * dense_max_entries: bound on the summed stencil-union sizes of dense cells per build
+ *   (device scratch: 16 bytes per entry, allocated as min(3^d n, bound)). Beyond it a
+ *   build falls back to the block and long-row paths. 0 = default (2^28). Valid
+ *   0..2^31-1. */
 typedef struct nnps_tuning {
     int32_t block_target;
     int32_t long_rows_grid;
     int32_t long_rows_keys;
+    int32_t dense_min_union;
+    int32_t dense_grid;
+    int32_t reserved;
+    int64_t dense_max_entries;
 } nnps_tuning;
 
 typedef struct nnps_ctx nnps_ctx;
@@ -206,10 +223,13 @@ enum {
     NNPS_PHASE_SORT,         /* radix sort of (cell key, index) */
     NNPS_PHASE_PACK,         /* FP16 relative-coordinate pack (or sorted FP64 copy) */
     NNPS_PHASE_BLOCKS,       /* work-block table */
+    NNPS_PHASE_UNIONS,       /* dense cells: stencil-union lists sorted by original index */
     NNPS_PHASE_COUNT,        /* count pass (stencil test + recheck) */
+    NNPS_PHASE_DCOUNT,       /* count pass of the dense-cell path */
     NNPS_PHASE_ROWSCAN,      /* counts -> row_ptr */
     NNPS_PHASE_FILL,         /* fill pass (stencil test + recheck + sorted CSR writes) */
     NNPS_PHASE_LONGROWS,     /* long-row path of the fill */
+    NNPS_PHASE_DFILL,        /* fill pass of the dense-cell path */
     NNPS_NPHASES
 };
 

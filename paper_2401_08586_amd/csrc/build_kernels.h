@@ -27,9 +27,37 @@ hipError_t launch_radix_sort(int n, int keybits, uint32_t* k0, int* v0, uint32_t
                              uint32_t* table, int64_t* partial, hipStream_t st, uint32_t** kfinal,
                              int** vfinal);
 hipError_t launch_pack(const Launch& L, const uint32_t* skey, const int* perm, const int64_t* X, ushort4* q4,
-                       double* spos, hipStream_t st);
-hipError_t launch_blocks(const Launch& L, const uint32_t* skey, const int* cell_start, int* flags, int* bidx,
-                         int* bstart, int* bset, int64_t* partial, hipStream_t st);
+                       double* spos, int* inv, hipStream_t st);
+hipError_t launch_blocks(const Launch& L, const uint32_t* skey, const int* cell_start, const int* wdense, int* flags,
+                         int* bidx, int* bstart, int* bset, int64_t* partial, hipStream_t st);
+
+// Dense-cell path: device tables of one build. A cell is "dense" when it is occupied and
+// lies in an x-window where some cell's stencil holds more than `thresh` particles; such
+// windows get no work blocks. Each dense cell g owns the list ulist[uoff[g] ..
+// uoff[g] + usz[g]) of the sorted positions of the particles in its 3^d stencil, in
+// ascending original index, and ceil(occupancy / kDenseSlice) work units.
+struct DenseBuild {
+    int thresh;             // stencil size above which a window is dense
+    int64_t cap;            // capacity of the union lists (entries)
+    int* usz;               // [ncell_tot] stencil size of dense cells, else 0
+    int* wdense;            // [ncell_tot] 1 for every cell of a dense window
+    int64_t* uoff;          // [ncell_tot + 1] exclusive scan of usz
+    int* nsl;               // [ncell_tot] work units per cell
+    int* unit_off;          // [ncell_tot + 1] exclusive scan of nsl
+    int* ucell;             // [ntot] cell of each work unit
+    int* dn;                // [1] entries in use; 0 when the dense path is off for the build
+    int* ecnt;              // [ntot] dense stencils each particle belongs to
+    int* epos;              // [ntot + 1] exclusive scan of ecnt
+    uint32_t *uk0, *uk1;    // [cap] sort keys (dense cell)
+    int *uv0, *uv1;         // [cap] sort values (sorted position)
+    uint32_t* table;        // radix scratch
+    int64_t* partial;       // scan scratch
+};
+// Before the block table: stencil sizes, dense windows, union offsets and work units.
+hipError_t launch_dense_cells(const Launch& L, const int* cell_start, const DenseBuild& d, hipStream_t st);
+// After the sort and pack: the union lists. *ulist receives the sorted list array.
+hipError_t launch_dense_unions(const Launch& L, const uint32_t* skey, const int* inv, const DenseBuild& d,
+                               hipStream_t st, int** ulist);
 hipError_t launch_rowptr(const Launch& L, const int* counts, int64_t* rowg, int64_t* partial, int64_t* nnz,
                          hipStream_t st);
 
@@ -56,10 +84,23 @@ struct SearchArgs {
     int64_t lrscratch_words;        // its size per workgroup (32-bit words)
     int lr_keys;                    // keys a long-row workgroup sorts in LDS
     int* err;
+    // dense-cell path (wdense == nullptr: off)
+    const int* wdense;
+    const int* usz;
+    const int64_t* uoff;
+    const int* ulist;
+    const int* unit_off;
+    const int* ucell;
+    const int* dn;
+    int* ucount;                    // work-unit counter (zeroed before each launch)
+    unsigned long long* dstats;     // [dgrid][kDenseStats] per-workgroup statistics
+    int dgrid;
 };
 
 hipError_t launch_count(const SearchArgs& a, int nblk_max, hipStream_t st);
 hipError_t launch_fill(const SearchArgs& a, int nblk_max, hipStream_t st);
 hipError_t launch_long_rows(const SearchArgs& a, int grid, hipStream_t st);
+hipError_t launch_dense(const SearchArgs& a, bool fill, hipStream_t st);
+hipError_t launch_stats(const SearchArgs& a, hipStream_t st);
 
 }  // namespace nnps

@@ -107,10 +107,13 @@ __device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t* total, in
     return base + inc - v;
 }
 
+// A non-null `gate` pointing at 0 turns a scan kernel into a no-op (work that depends
+// on a count known only on the device).
 template <typename TIn>
 __global__ void __launch_bounds__(kScanThreads)
-k_scan_reduce(const TIn* __restrict__ in, int64_t m, int64_t* __restrict__ partial)
+k_scan_reduce(const TIn* __restrict__ in, int64_t m, int64_t* __restrict__ partial, const int* gate)
 {
+    if (gate && *gate == 0) return;
     __shared__ int64_t sh[4];
     const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile;
     int64_t s = 0;
@@ -125,8 +128,9 @@ k_scan_reduce(const TIn* __restrict__ in, int64_t m, int64_t* __restrict__ parti
 
 // One workgroup scans the tile sums in place (exclusive); partial[nt] = total.
 __global__ void __launch_bounds__(kScanThreads)
-k_scan_partials(int64_t* __restrict__ partial, int64_t nt)
+k_scan_partials(int64_t* __restrict__ partial, int64_t nt, const int* gate)
 {
+    if (gate && *gate == 0) return;
     __shared__ int64_t sh[4];
     __shared__ int64_t carry;
     if (threadIdx.x == 0) carry = 0;
@@ -148,8 +152,9 @@ k_scan_partials(int64_t* __restrict__ partial, int64_t nt)
 template <typename TIn, typename TOut>
 __global__ void __launch_bounds__(kScanThreads)
 k_scan_down(const TIn* __restrict__ in, int64_t m, const int64_t* __restrict__ partial,
-            TOut* __restrict__ out, int64_t nt)
+            TOut* __restrict__ out, int64_t nt, const int* gate)
 {
+    if (gate && *gate == 0) return;
     __shared__ int64_t sh[4];
     // blocked layout: thread t owns kScanItems consecutive elements
     const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
@@ -176,7 +181,8 @@ template <typename T>
 __global__ void k_zero_one(T* p) { *p = T(0); }
 
 template <typename TIn, typename TOut>
-hipError_t scan_exclusive(const TIn* in, int64_t m, TOut* out, int64_t* partial, hipStream_t st)
+hipError_t scan_exclusive(const TIn* in, int64_t m, TOut* out, int64_t* partial, hipStream_t st,
+                          const int* gate = nullptr)
 {
     const int64_t nt = (m + kScanTile - 1) / kScanTile;
     if (nt == 0) {
@@ -184,10 +190,10 @@ hipError_t scan_exclusive(const TIn* in, int64_t m, TOut* out, int64_t* partial,
         hipLaunchKernelGGL(k_zero_one<TOut>, dim3(1), dim3(1), 0, st, out);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_scan_reduce<TIn>, dim3(nt), dim3(kScanThreads), 0, st, in, m, partial);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, st, partial, nt);
+    hipLaunchKernelGGL(k_scan_reduce<TIn>, dim3(nt), dim3(kScanThreads), 0, st, in, m, partial, gate);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, st, partial, nt, gate);
     hipLaunchKernelGGL((k_scan_down<TIn, TOut>), dim3(nt), dim3(kScanThreads), 0, st, in, m, partial,
-                       out, nt);
+                       out, nt, gate);
     return hipGetLastError();
 }
 
@@ -206,8 +212,13 @@ constexpr int kRsMaxBits = 11;
 
 __global__ void __launch_bounds__(kRsThreads)
 k_radix_hist(const uint32_t* __restrict__ keys, int n, int shift, int bits,
-             uint32_t* __restrict__ table, int ntiles)
+             uint32_t* __restrict__ table, int ntiles, const int* ndev)
 {
+    // ndev: the number of keys is on the device (at most n; 0 skips the pass)
+    if (ndev) {
+        if (*ndev == 0) return;
+        n = min(n, *ndev);
+    }
     __shared__ uint32_t h[1 << kRsMaxBits];
     const int bins = 1 << bits;
     const uint32_t mask = bins - 1;
@@ -225,8 +236,12 @@ k_radix_hist(const uint32_t* __restrict__ keys, int n, int shift, int bits,
 __global__ void __launch_bounds__(kRsThreads)
 k_radix_scatter(const uint32_t* __restrict__ kin, const int* __restrict__ vin,
                 uint32_t* __restrict__ kout, int* __restrict__ vout, int n, int shift, int bits,
-                const uint32_t* __restrict__ offs, int ntiles)
+                const uint32_t* __restrict__ offs, int ntiles, const int* ndev)
 {
+    if (ndev) {
+        if (*ndev == 0) return;
+        n = min(n, *ndev);
+    }
     __shared__ uint32_t cw[kRsThreads / 64][1 << kRsMaxBits];
     const int bins = 1 << bits;
     const uint32_t mask = bins - 1;
@@ -292,13 +307,14 @@ template <int DIM>
 __global__ void __launch_bounds__(256)
 k_pack(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nsets, int ntot,
        const uint32_t* __restrict__ skey, const int* __restrict__ perm, const int64_t* __restrict__ X,
-       ushort4* __restrict__ q4, double* __restrict__ spos)
+       ushort4* __restrict__ q4, double* __restrict__ spos, int* __restrict__ inv)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= ntot) return;
     const SetDesc& sd = sets[find_set(coffs, nsets, static_cast<int>(skey[p]))];
     const Frame& fr = sd.fr;
     const int o = perm[p];
+    if (inv) inv[o] = p;
     if (spos) {
 #pragma unroll
         for (int k = 0; k < DIM; ++k)
@@ -320,10 +336,12 @@ k_pack(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nset
 
 // ---------------------------------------------------------------------------
 // Work blocks: the particles of one x-window of fr.xwin cells inside one (y, z) row of
-// cells of one set, split into runs of at most kWave particles.
+// cells of one set, split into runs of at most kWave particles. A window of the
+// dense-cell path is one block that the block kernels skip.
 __global__ void __launch_bounds__(256)
 k_block_flags(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nsets, int ntot,
-              const uint32_t* __restrict__ skey, const int* __restrict__ cell_start, int* __restrict__ flags)
+              const uint32_t* __restrict__ skey, const int* __restrict__ cell_start,
+              const int* __restrict__ wdense, int* __restrict__ flags)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= ntot) return;
@@ -335,7 +353,8 @@ k_block_flags(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, i
     const uint32_t x = lk - row * ncx;
     const uint32_t win = x / static_cast<uint32_t>(sd.fr.xwin);
     const int ws = cell_start[sd.coff + row * ncx + win * static_cast<uint32_t>(sd.fr.xwin)];
-    flags[p] = (p == ws) || (((p - ws) % kWave) == 0);
+    if (wdense && wdense[key]) flags[p] = p == ws;
+    else flags[p] = (p == ws) || (((p - ws) % kWave) == 0);
 }
 
 __global__ void __launch_bounds__(256)
@@ -374,6 +393,158 @@ k_rowptr_scatter(const SetDesc* __restrict__ sets, const int* __restrict__ poffs
 }
 
 // ---------------------------------------------------------------------------
+// Dense-cell path tables. Where clustering piles hundreds or thousands of particles
+// into a cell, every target of the cell tests the same stencil union, and its rows are
+// long. For such cells the search stages the union once per chunk for all the cell's
+// targets, in ascending original index, so each row comes out sorted with no per-row
+// sort. The union lists come from one stable sort: every particle, visited in original
+// order, emits (dense cell, sorted position) for each dense cell whose stencil holds it.
+
+// Global cell index -> local coordinates of its set.
+struct CellXYZ {
+    int x, y, z, ncx, ncy, ncz;
+    __device__ __forceinline__ CellXYZ(const Frame& fr, int lk)
+    {
+        ncx = fr.nc[0];
+        ncy = fr.nc[1];
+        ncz = fr.nc[2];
+        x = lk % ncx;
+        const int row = lk / ncx;
+        y = row % ncy;
+        z = row / ncy;
+    }
+};
+
+// One thread per x-window (at its first cell): stencil sizes of the window's occupied
+// cells, and whether any exceeds the threshold (then the whole window is dense).
+template <int DIM>
+__global__ void __launch_bounds__(256)
+k_dense_cells(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nsets, int ncell_tot,
+              const int* __restrict__ cell_start, int thresh, int* __restrict__ usz, int* __restrict__ wdense)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ncell_tot) return;
+    const SetDesc& sd = sets[find_set(coffs, nsets, g)];
+    const Frame& fr = sd.fr;
+    const int lk = g - sd.coff;
+    const CellXYZ c(fr, lk);
+    if (c.x % fr.xwin != 0) return;
+    const int* cs = cell_start + sd.coff;
+    const int xe = min(c.x + fr.xwin, c.ncx);
+    bool any = false;
+    for (int xx = c.x; xx < xe; ++xx) {
+        const int l = lk + (xx - c.x);
+        int u = 0;
+        if (cs[l + 1] > cs[l]) {
+            const int x0 = xx > 0 ? xx - 1 : 0;
+            const int x1 = xx + 1 < c.ncx ? xx + 1 : c.ncx - 1;
+            for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz) {
+                const int zz = c.z + dz;
+                if (zz < 0 || zz >= c.ncz) continue;
+                for (int dy = -1; dy <= 1; ++dy) {
+                    const int yy = c.y + dy;
+                    if (yy < 0 || yy >= c.ncy) continue;
+                    const int rb = (zz * c.ncy + yy) * c.ncx;
+                    u += cs[rb + x1 + 1] - cs[rb + x0];
+                }
+            }
+        }
+        usz[g + (xx - c.x)] = u;
+        any = any || u > thresh;
+    }
+    for (int xx = c.x; xx < xe; ++xx) {
+        wdense[g + (xx - c.x)] = any ? 1 : 0;
+        if (!any) usz[g + (xx - c.x)] = 0;
+    }
+}
+
+// After the scan of the stencil sizes: if the lists would not fit, the build falls back
+// to the block path (every window normal); otherwise each dense cell gets its work
+// units. dn receives the number of list entries in use (0 = path off).
+__global__ void __launch_bounds__(256)
+k_dense_units(int ncell_tot, const int* __restrict__ cell_start, const int64_t* __restrict__ uoff, int64_t cap,
+              int* __restrict__ usz, int* __restrict__ wdense, int* __restrict__ nsl, int* __restrict__ dn)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ue = uoff[ncell_tot];
+    const bool over = ue > cap;
+    if (g == 0) *dn = over ? 0 : static_cast<int>(ue);
+    if (g >= ncell_tot) return;
+    if (over) {
+        usz[g] = 0;
+        wdense[g] = 0;
+    }
+    const int occ = cell_start[g + 1] - cell_start[g];
+    nsl[g] = (!over && usz[g] > 0) ? (occ + kDenseSlice - 1) / kDenseSlice : 0;
+}
+
+__global__ void __launch_bounds__(256)
+k_dense_unit_cells(int ncell_tot, const int* __restrict__ nsl, const int* __restrict__ unit_off,
+                   const int* __restrict__ dn, int* __restrict__ ucell)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ncell_tot || *dn == 0) return;
+    const int k = nsl[g], u0 = unit_off[g];
+    for (int s = 0; s < k; ++s) ucell[u0 + s] = g;
+}
+
+// Visit the dense cells whose stencil holds the particle at sorted position j.
+template <int DIM, typename F>
+__device__ __forceinline__ void for_dense_stencils(const SetDesc* __restrict__ sets, const int* __restrict__ coffs,
+                                                   int nsets, const uint32_t* __restrict__ skey,
+                                                   const int* __restrict__ usz, int j, F&& f)
+{
+    const int gk = static_cast<int>(skey[j]);
+    const SetDesc& sd = sets[find_set(coffs, nsets, gk)];
+    const CellXYZ c(sd.fr, gk - sd.coff);
+    for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz) {
+        const int zz = c.z + dz;
+        if (zz < 0 || zz >= c.ncz) continue;
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int yy = c.y + dy;
+            if (yy < 0 || yy >= c.ncy) continue;
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int xx = c.x + dx;
+                if (xx < 0 || xx >= c.ncx) continue;
+                const int g2 = gk + dx + c.ncx * (dy + c.ncy * dz);
+                if (usz[g2] > 0) f(g2);
+            }
+        }
+    }
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(256)
+k_union_count(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nsets, int ntot,
+              const uint32_t* __restrict__ skey, const int* __restrict__ inv, const int* __restrict__ usz,
+              const int* __restrict__ dn, int* __restrict__ ecnt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ntot || *dn == 0) return;
+    int k = 0;
+    for_dense_stencils<DIM>(sets, coffs, nsets, skey, usz, inv[i], [&](int) { ++k; });
+    ecnt[i] = k;
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(256)
+k_union_emit(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nsets, int ntot,
+             const uint32_t* __restrict__ skey, const int* __restrict__ inv, const int* __restrict__ usz,
+             const int* __restrict__ dn, const int* __restrict__ epos, uint32_t* __restrict__ ukey,
+             int* __restrict__ uval)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ntot || *dn == 0) return;
+    const int j = inv[i];
+    int m = epos[i];
+    for_dense_stencils<DIM>(sets, coffs, nsets, skey, usz, j, [&](int g2) {
+        ukey[m] = static_cast<uint32_t>(g2);
+        uval[m] = j;
+        ++m;
+    });
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launchers.
 hipError_t launch_fill_i32(int* p, int64_t m, int v, hipStream_t st)
 {
@@ -406,11 +577,38 @@ hipError_t launch_scan_i32_i64(const int* in, int64_t m, int64_t* out, int64_t* 
 
 int radix_tiles(int n) { return (n + kRsTile - 1) / kRsTile; }
 
+// Stable LSD sort of (key, value) pairs held in (k0, v0), with (k1, v1) as the second
+// buffers; the number of pairs is read on the device (*ndev <= n; 0 skips the sort).
+hipError_t radix_sort_kv_dev(int n, const int* ndev, int keybits, uint32_t* k0, int* v0, uint32_t* k1, int* v1,
+                             uint32_t* table, int64_t* partial, hipStream_t st, uint32_t** kfinal, int** vfinal)
+{
+    const int ntiles = radix_tiles(n);
+    const int passes = keybits <= 0 ? 1 : (keybits + kRsMaxBits - 1) / kRsMaxBits;
+    const int bits = keybits <= 0 ? 1 : (keybits + passes - 1) / passes;
+    uint32_t *kin = k0, *kout = k1;
+    int *vin = v0, *vout = v1;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = p * bits;
+        hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kRsThreads), 0, st, kin, n, shift, bits,
+                           table, ntiles, ndev);
+        hipError_t e = scan_exclusive<uint32_t, uint32_t>(table, static_cast<int64_t>(ntiles) << bits,
+                                                          table, partial, st, ndev);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(kRsThreads), 0, st, kin, vin, kout,
+                           vout, n, shift, bits, table, ntiles, ndev);
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+    }
+    *kfinal = kin;
+    *vfinal = vin;
+    return hipGetLastError();
+}
+
 hipError_t launch_radix_sort(int n, int keybits, uint32_t* k0, int* v0, uint32_t* k1, int* v1,
                              uint32_t* table, int64_t* partial, hipStream_t st, uint32_t** kfinal,
                              int** vfinal)
 {
-    // first pass reads the identity permutation implicitly (vin == nullptr)
+    // the first pass reads the identity permutation implicitly; v0 is the second value buffer
     const int ntiles = radix_tiles(n);
     const int passes = keybits <= 0 ? 1 : (keybits + kRsMaxBits - 1) / kRsMaxBits;
     const int bits = keybits <= 0 ? 1 : (keybits + passes - 1) / passes;
@@ -421,13 +619,12 @@ hipError_t launch_radix_sort(int n, int keybits, uint32_t* k0, int* v0, uint32_t
     for (int p = 0; p < passes; ++p) {
         const int shift = p * bits;
         hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kRsThreads), 0, st, kin, n, shift, bits,
-                           table, ntiles);
+                           table, ntiles, static_cast<const int*>(nullptr));
         hipError_t e = scan_exclusive<uint32_t, uint32_t>(table, static_cast<int64_t>(ntiles) << bits,
                                                           table, partial, st);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(kRsThreads), 0, st, kin, vin, kout,
-                           vout, n, shift, bits, table, ntiles);
-        // ping-pong
+                           vout, n, shift, bits, table, ntiles, static_cast<const int*>(nullptr));
         if (p == 0) {
             kin = k1;
             vin = v1;
@@ -446,26 +643,75 @@ hipError_t launch_radix_sort(int n, int keybits, uint32_t* k0, int* v0, uint32_t
 size_t radix_table_entries(int n) { return static_cast<size_t>(radix_tiles(n)) << kRsMaxBits; }
 
 hipError_t launch_pack(const Launch& L, const uint32_t* skey, const int* perm, const int64_t* X, ushort4* q4,
-                       double* spos, hipStream_t st)
+                       double* spos, int* inv, hipStream_t st)
 {
     if (L.ntot == 0) return hipSuccess;
     const dim3 g((L.ntot + 255) / 256), b(256);
     if (L.dim == 2)
-        hipLaunchKernelGGL(k_pack<2>, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, perm, X, q4, spos);
+        hipLaunchKernelGGL(k_pack<2>, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, perm, X, q4, spos, inv);
     else
-        hipLaunchKernelGGL(k_pack<3>, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, perm, X, q4, spos);
+        hipLaunchKernelGGL(k_pack<3>, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, perm, X, q4, spos, inv);
     return hipGetLastError();
 }
 
-hipError_t launch_blocks(const Launch& L, const uint32_t* skey, const int* cell_start, int* flags, int* bidx,
-                         int* bstart, int* bset, int64_t* partial, hipStream_t st)
+hipError_t launch_blocks(const Launch& L, const uint32_t* skey, const int* cell_start, const int* wdense, int* flags,
+                         int* bidx, int* bstart, int* bset, int64_t* partial, hipStream_t st)
 {
     if (L.ntot == 0) return launch_fill_i32(bidx, 1, 0, st);
     const dim3 g((L.ntot + 255) / 256), b(256);
-    hipLaunchKernelGGL(k_block_flags, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, cell_start, flags);
+    hipLaunchKernelGGL(k_block_flags, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, cell_start, wdense,
+                       flags);
     hipError_t e = scan_exclusive<int, int>(flags, L.ntot, bidx, partial, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_block_write, g, b, 0, st, L.coffs, L.nsets, L.ntot, skey, flags, bidx, bstart, bset);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_cells(const Launch& L, const int* cell_start, const DenseBuild& d, hipStream_t st)
+{
+    const int nc = L.ncell_tot;
+    const dim3 g((nc + 255) / 256), b(256);
+    if (L.dim == 2)
+        hipLaunchKernelGGL(k_dense_cells<2>, g, b, 0, st, L.sets, L.coffs, L.nsets, nc, cell_start, d.thresh, d.usz,
+                           d.wdense);
+    else
+        hipLaunchKernelGGL(k_dense_cells<3>, g, b, 0, st, L.sets, L.coffs, L.nsets, nc, cell_start, d.thresh, d.usz,
+                           d.wdense);
+    hipError_t e = scan_exclusive<int, int64_t>(d.usz, nc, d.uoff, d.partial, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dense_units, dim3((nc + 256) / 256), b, 0, st, nc, cell_start, d.uoff, d.cap, d.usz,
+                       d.wdense, d.nsl, d.dn);
+    e = scan_exclusive<int, int>(d.nsl, nc, d.unit_off, d.partial, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dense_unit_cells, g, b, 0, st, nc, d.nsl, d.unit_off, d.dn, d.ucell);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_unions(const Launch& L, const uint32_t* skey, const int* inv, const DenseBuild& d,
+                               hipStream_t st, int** ulist)
+{
+    *ulist = d.uv0;
+    if (L.ntot == 0 || d.cap == 0) return hipSuccess;
+    const dim3 g((L.ntot + 255) / 256), b(256);
+    if (L.dim == 2)
+        hipLaunchKernelGGL(k_union_count<2>, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, inv, d.usz, d.dn,
+                           d.ecnt);
+    else
+        hipLaunchKernelGGL(k_union_count<3>, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, inv, d.usz, d.dn,
+                           d.ecnt);
+    hipError_t e = scan_exclusive<int, int>(d.ecnt, L.ntot, d.epos, d.partial, st, d.dn);
+    if (e != hipSuccess) return e;
+    if (L.dim == 2)
+        hipLaunchKernelGGL(k_union_emit<2>, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, inv, d.usz, d.dn,
+                           d.epos, d.uk0, d.uv0);
+    else
+        hipLaunchKernelGGL(k_union_emit<3>, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, inv, d.usz, d.dn,
+                           d.epos, d.uk0, d.uv0);
+    const int keybits = std::max(1, 32 - __builtin_clz(static_cast<unsigned>(std::max(L.ncell_tot - 1, 1))));
+    uint32_t* kf = nullptr;
+    e = radix_sort_kv_dev(static_cast<int>(d.cap), d.dn, keybits, d.uk0, d.uv0, d.uk1, d.uv1, d.table, d.partial,
+                          st, &kf, ulist);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 // C-ABI entry points (include/nnps.h): argument checks, grid set-up, device buffers
 // and the stream-ordered sequence of cell-build and search kernels.
 #include <math.h>
+#include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -139,7 +140,7 @@ struct nnps_ctx {
     int device = 0;
     int64_t* h_pinned = nullptr;  // pinned staging for synchronous read-backs
     int max_lds = 65536;          // LDS bytes a workgroup may use on this device
-    nnps_tuning tuning{56, 1024, 0};
+    nnps_tuning tuning{56, 1024, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -225,6 +226,12 @@ struct nnps_cells {
     int* perm = nullptr;
     DevBuf d_sets, d_offs, X, k0, k1, v0, v1, cell_count, cell_start, q4, spos, flags, bidx, bstart, bset,
         counts, table, partial, stats, blk_stats, cbits, err, heavy, nheavy, rowg, nnz;
+    // dense-cell path (see DenseBuild)
+    bool dense = false;
+    int dthresh = 0, dgrid = 0;
+    int64_t dcap = 0;
+    int* ulist = nullptr;
+    DevBuf usz, wdense, uoff, nsl, unit_off, ucell, dn, ecnt, epos, uk0, uk1, uv0, uv1, inv, ucount, dstats;
 };
 
 #define HIP_TRY(x)                                  \
@@ -299,7 +306,42 @@ SearchArgs args_of(const nnps_cells* c)
     while (keys * 2 <= std::min(c->ctx->max_lds - 1024, 64 * 1024) / 4) keys *= 2;
     a.lr_keys = c->ctx->tuning.long_rows_keys > 0 ? std::min(c->ctx->tuning.long_rows_keys, keys) : keys;
     a.err = c->err.as<int>();
+    if (c->dense) {
+        a.wdense = c->wdense.as<int>();
+        a.usz = c->usz.as<int>();
+        a.uoff = c->uoff.as<int64_t>();
+        a.ulist = c->ulist;
+        a.unit_off = c->unit_off.as<int>();
+        a.ucell = c->ucell.as<int>();
+        a.dn = c->dn.as<int>();
+        a.ucount = c->ucount.as<int>();
+        a.dstats = c->dstats.as<unsigned long long>();
+        a.dgrid = c->dgrid;
+    }
     return a;
+}
+
+DenseBuild dense_of(nnps_cells* c)
+{
+    DenseBuild d{};
+    d.thresh = c->dthresh;
+    d.cap = c->dcap;
+    d.usz = c->usz.as<int>();
+    d.wdense = c->wdense.as<int>();
+    d.uoff = c->uoff.as<int64_t>();
+    d.nsl = c->nsl.as<int>();
+    d.unit_off = c->unit_off.as<int>();
+    d.ucell = c->ucell.as<int>();
+    d.dn = c->dn.as<int>();
+    d.ecnt = c->ecnt.as<int>();
+    d.epos = c->epos.as<int>();
+    d.uk0 = c->uk0.as<uint32_t>();
+    d.uk1 = c->uk1.as<uint32_t>();
+    d.uv0 = c->uv0.as<int>();
+    d.uv1 = c->uv1.as<int>();
+    d.table = c->table.as<uint32_t>();
+    d.partial = c->partial.as<int64_t>();
+    return d;
 }
 
 // Validate a batch, lay out its grids and index spaces, size the device buffers and fill
@@ -368,7 +410,17 @@ nnps_status prepare(nnps_ctx* ctx, nnps_cells* c, int nsets, const nnps_problem*
     const size_t n = static_cast<size_t>(ntot);
     const size_t nn = std::max<size_t>(n, 1);
     const size_t nc = static_cast<size_t>(ncell);
-    const size_t table_n = radix_table_entries(static_cast<int>(nn)) + 1;
+    // dense-cell path: list capacity min(3^d n, bound)
+    const nnps_tuning& tu = ctx->tuning;
+    c->dense = tu.dense_min_union >= 0;
+    c->dthresh = tu.dense_min_union > 0 ? tu.dense_min_union : (c->dim == 3 ? kDenseUnion3 : kDenseUnion2);
+    c->dgrid = tu.dense_grid > 0 ? tu.dense_grid : kDenseGrid;
+    const int64_t dmax = tu.dense_max_entries > 0 ? tu.dense_max_entries : kDenseMaxEntries;
+    c->dcap = c->dense ? std::max<int64_t>(1, std::min<int64_t>((c->dim == 3 ? 27 : 9) * static_cast<int64_t>(nn), dmax))
+                       : 0;
+    const size_t dcap = static_cast<size_t>(c->dcap);
+    const size_t table_n = std::max(radix_table_entries(static_cast<int>(nn)),
+                                    c->dense ? radix_table_entries(static_cast<int>(dcap)) : size_t(0)) + 1;
     const int64_t scan_m = std::max<int64_t>({static_cast<int64_t>(nn) + 1, static_cast<int64_t>(nc) + 1,
                                               static_cast<int64_t>(table_n)});
     const bool base = c->mode == NNPS_MODE_FP64_BASELINE;
@@ -394,6 +446,13 @@ nnps_status prepare(nnps_ctx* ctx, nnps_cells* c, int nsets, const nnps_problem*
         {&c->err, 4}, {&c->heavy, nn * 4}, {&c->nheavy, 4},
         {&c->rowg, (nn + 1) * 8},
         {&c->nnz, sizeof(int64_t) * nsets},
+        {&c->usz, c->dense ? (nc + 1) * 4 : 0}, {&c->wdense, c->dense ? (nc + 1) * 4 : 0},
+        {&c->uoff, c->dense ? (nc + 1) * 8 : 0}, {&c->nsl, c->dense ? (nc + 1) * 4 : 0},
+        {&c->unit_off, c->dense ? (nc + 1) * 4 : 0}, {&c->ucell, c->dense ? (nn + 1) * 4 : 0},
+        {&c->dn, c->dense ? size_t(4) : size_t(0)}, {&c->ecnt, c->dense ? nn * 4 : 0}, {&c->epos, c->dense ? (nn + 1) * 4 : 0},
+        {&c->uk0, dcap * 4}, {&c->uk1, dcap * 4}, {&c->uv0, dcap * 4}, {&c->uv1, dcap * 4},
+        {&c->inv, c->dense ? nn * 4 : 0}, {&c->ucount, c->dense ? size_t(4) : size_t(0)},
+        {&c->dstats, c->dense ? static_cast<size_t>(c->dgrid) * kDenseStats * 8 : 0},
     };
     for (auto& q : need) {
         if (q.bytes == 0) continue;
@@ -434,11 +493,20 @@ nnps_status enqueue_build(nnps_cells* c, hipStream_t s)
     c->perm = vf;
     tm.begin(NNPS_PHASE_PACK, s);
     HIP_TRY(launch_pack(L, c->skey, c->perm, c->X.as<int64_t>(), c->q4.as<ushort4>(),
-                        c->mode == NNPS_MODE_FP64_BASELINE ? c->spos.as<double>() : nullptr, s));
+                        c->mode == NNPS_MODE_FP64_BASELINE ? c->spos.as<double>() : nullptr,
+                        c->dense ? c->inv.as<int>() : nullptr, s));
     tm.end(NNPS_PHASE_PACK, s);
+    if (c->dense) {
+        tm.begin(NNPS_PHASE_UNIONS, s);
+        const DenseBuild d = dense_of(c);
+        HIP_TRY(launch_dense_cells(L, c->cell_start.as<int>(), d, s));
+        HIP_TRY(launch_dense_unions(L, c->skey, c->inv.as<int>(), d, s, &c->ulist));
+        tm.end(NNPS_PHASE_UNIONS, s);
+    }
     tm.begin(NNPS_PHASE_BLOCKS, s);
-    HIP_TRY(launch_blocks(L, c->skey, c->cell_start.as<int>(), c->flags.as<int>(), c->bidx.as<int>(),
-                          c->bstart.as<int>(), c->bset.as<int>(), c->partial.as<int64_t>(), s));
+    HIP_TRY(launch_blocks(L, c->skey, c->cell_start.as<int>(), c->dense ? c->wdense.as<int>() : nullptr,
+                          c->flags.as<int>(), c->bidx.as<int>(), c->bstart.as<int>(), c->bset.as<int>(),
+                          c->partial.as<int64_t>(), s));
     tm.end(NNPS_PHASE_BLOCKS, s);
     c->built = true;
     c->counted = false;
@@ -453,6 +521,12 @@ nnps_status enqueue_count(nnps_cells* c, hipStream_t s)
     c->timer.begin(NNPS_PHASE_COUNT, s);
     HIP_TRY(launch_count(a, c->nblk_max, s));
     c->timer.end(NNPS_PHASE_COUNT, s);
+    if (c->dense) {
+        c->timer.begin(NNPS_PHASE_DCOUNT, s);
+        HIP_TRY(launch_dense(a, false, s));
+        c->timer.end(NNPS_PHASE_DCOUNT, s);
+    }
+    HIP_TRY(launch_stats(a, s));
     c->timer.begin(NNPS_PHASE_ROWSCAN, s);
     HIP_TRY(launch_rowptr(a.L, c->counts.as<int>(), c->rowg.as<int64_t>(), c->partial.as<int64_t>(),
                           c->nnz.as<int64_t>(), s));
@@ -471,6 +545,11 @@ nnps_status enqueue_fill(nnps_cells* c, hipStream_t s)
     c->timer.begin(NNPS_PHASE_LONGROWS, s);
     HIP_TRY(launch_long_rows(a, c->ctx->tuning.long_rows_grid, s));
     c->timer.end(NNPS_PHASE_LONGROWS, s);
+    if (c->dense) {
+        c->timer.begin(NNPS_PHASE_DFILL, s);
+        HIP_TRY(launch_dense(a, true, s));
+        c->timer.end(NNPS_PHASE_DFILL, s);
+    }
     return NNPS_OK;
 }
 
@@ -590,7 +669,11 @@ nnps_status nnps_ctx_set_tuning(nnps_ctx* ctx, const nnps_tuning* t)
         return NNPS_EINVAL;
     const int k = t->long_rows_keys;
     if (k != 0 && (k < 64 || k > 16384 || (k & (k - 1)) != 0)) return NNPS_EINVAL;
+    if (t->dense_min_union < -1 || t->dense_min_union > (1 << 30)) return NNPS_EINVAL;
+    if (t->dense_grid < 0 || t->dense_grid > (1 << 20)) return NNPS_EINVAL;
+    if (t->dense_max_entries < 0 || t->dense_max_entries > INT32_MAX) return NNPS_EINVAL;
     ctx->tuning = *t;
+    ctx->tuning.reserved = 0;
     return NNPS_OK;
 }
 
@@ -619,7 +702,9 @@ void nnps_cells_destroy(nnps_cells* c)
     DevBuf* all[] = {&c->d_sets, &c->d_offs, &c->X, &c->k0, &c->k1, &c->v0, &c->v1, &c->cell_count,
                      &c->cell_start, &c->q4, &c->spos, &c->flags, &c->bidx, &c->bstart, &c->bset, &c->counts,
                      &c->table, &c->partial, &c->stats, &c->blk_stats, &c->cbits, &c->err, &c->heavy,
-                     &c->nheavy, &c->rowg, &c->nnz};
+                     &c->nheavy, &c->rowg, &c->nnz, &c->usz, &c->wdense, &c->uoff, &c->nsl, &c->unit_off,
+                     &c->ucell, &c->dn, &c->ecnt, &c->epos, &c->uk0, &c->uk1, &c->uv0, &c->uv1, &c->inv,
+                     &c->ucount, &c->dstats};
     for (DevBuf* b : all) b->release();
     c->timer.release();
     c->graph.reset();
@@ -841,6 +926,12 @@ nnps_status nnps_stats_get(nnps_cells* c, nnps_stats* out, void* stream)
     out->fp16_false_neg = static_cast<int64_t>(st[kStFalseNeg]);
     out->outside_band_disagree = static_cast<int64_t>(st[kStOutsideDisagree]);
     out->heavy_rows = nh;
+    out->dense_rows = static_cast<int64_t>(st[kStDenseRows]);
+    if (c->dense) {
+        int dn = 0;
+        HIP_TRY(hipMemcpy(&dn, c->dn.p, 4, hipMemcpyDeviceToHost));
+        out->dense_entries = dn;
+    }
     out->dim = c->dim;
     out->mode = c->mode;
     if (!c->frames.empty()) {

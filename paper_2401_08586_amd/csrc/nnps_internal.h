@@ -26,6 +26,16 @@ constexpr int kCandWords3 = 24;
 __host__ __device__ constexpr int x_stride(int dim) { return dim == 3 ? 4 : 2; }
 // Largest x-window (cells) of a block; keeps staged cell offsets exact in FP16.
 constexpr int kMaxXWin = 256;
+// Dense-cell path: candidates staged per chunk, targets per work unit (a workgroup of
+// four wavefronts, 64 targets each) and the default thresholds.
+constexpr int kDenseChunk = 1024;
+constexpr int kDenseThreads = 256;
+constexpr int kDenseSlice = 256;
+constexpr int kDenseUnion3 = 512;
+constexpr int kDenseUnion2 = 160;
+constexpr int kDenseGrid = 1024;
+constexpr int64_t kDenseMaxEntries = int64_t(1) << 28;
+constexpr int kDenseStats = 6;  // candidates, band, false pos, false neg, outside disagree, rows
 
 // Device error flags.
 constexpr int kErrDomain = 1;
@@ -40,6 +50,7 @@ enum StatSlot {
     kStFalseNeg,
     kStOutsideDisagree,
     kStHeavy,
+    kStDenseRows,
     kStCount
 };
 

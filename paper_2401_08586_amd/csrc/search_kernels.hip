@@ -176,6 +176,12 @@ struct Geom {
     }
 };
 
+// Blocks of the dense-cell path's windows are left to that path.
+__device__ __forceinline__ bool dense_block(const SearchArgs& a, int b)
+{
+    return a.wdense && a.wdense[a.skey[a.bstart[b]]];
+}
+
 // Stage logical positions [cb, ce) as pair records; with ORIG also the original indices.
 template <int DIM, bool ORIG>
 __device__ __forceinline__ void stage(const SearchArgs& a, const Geom<DIM>& g, int cb, int ce,
@@ -403,6 +409,10 @@ k_count16(SearchArgs a)
     const int b = blockIdx.x;
     if (b >= *a.nblk) return;
     const int lane = threadIdx.x & 63;
+    if (dense_block(a, b)) {
+        if (lane < 5) a.blk_stats[static_cast<size_t>(b) * 5 + lane] = 0;
+        return;
+    }
     Geom<DIM> g;
     g.init(a, b);
     const Frame& fr = g.fr;
@@ -552,6 +562,10 @@ k_count64(SearchArgs a)
     __shared__ uint32_t lbits[64 * (CB::CW + 1)];
     const int b = blockIdx.x;
     if (b >= *a.nblk) return;
+    if (dense_block(a, b)) {
+        if ((threadIdx.x & 63) < 5) a.blk_stats[static_cast<size_t>(b) * 5 + (threadIdx.x & 63)] = 0;
+        return;
+    }
     Geom<DIM> g;
     g.init(a, b);
     const Frame& fr = g.fr;
@@ -585,27 +599,32 @@ k_count64(SearchArgs a)
         a.blk_stats[static_cast<size_t>(b) * 5 + (threadIdx.x & 63)] = (threadIdx.x & 63) == 0 ? s : 0ull;
 }
 
-// Sum of the per-block statistics (one workgroup; no contended atomics).
+// Sum of the per-block statistics and of the dense path's per-workgroup statistics
+// (one workgroup; no contended atomics).
 __global__ void __launch_bounds__(1024)
 k_reduce_stats(const unsigned long long* __restrict__ blk, const int* __restrict__ nblk,
-               unsigned long long* __restrict__ out)
+               const unsigned long long* __restrict__ dst, int ndst, unsigned long long* __restrict__ out)
 {
-    __shared__ unsigned long long sh[16][5];
+    __shared__ unsigned long long sh[16][kDenseStats];
     const int nb = *nblk;
-    unsigned long long acc[5] = {0, 0, 0, 0, 0};
+    unsigned long long acc[kDenseStats] = {0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nb; b += blockDim.x)
 #pragma unroll
         for (int k = 0; k < 5; ++k) acc[k] += blk[static_cast<size_t>(b) * 5 + k];
+    for (int w = threadIdx.x; w < ndst; w += blockDim.x)
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
+        for (int k = 0; k < kDenseStats; ++k) acc[k] += dst[static_cast<size_t>(w) * kDenseStats + k];
+#pragma unroll
+    for (int k = 0; k < kDenseStats; ++k) {
         const unsigned long long s = wave_sum_u64(acc[k]);
         if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6][k] = s;
     }
     __syncthreads();
-    if (threadIdx.x < 5) {
+    if (threadIdx.x < kDenseStats) {
         unsigned long long s = 0;
         for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) s += sh[w][threadIdx.x];
-        out[threadIdx.x] = s;
+        // slots 0..4 as in StatSlot; the sixth (rows of the dense path) goes to kStDenseRows
+        out[threadIdx.x < 5 ? threadIdx.x : kStDenseRows] = s;
     }
 }
 
@@ -762,7 +781,7 @@ k_fill(SearchArgs a)
     uint16_t* flat_rank = reinterpret_cast<uint16_t*>(smem);
 
     const int b = blockIdx.x;
-    if (b >= *a.nblk) return;
+    if (b >= *a.nblk || dense_block(a, b)) return;
     const int lane = threadIdx.x & 63;
     Geom<DIM> g;
     g.init(a, b);
@@ -1114,7 +1133,14 @@ hipError_t launch_count(const SearchArgs& a, int nblk_max, hipStream_t st)
     else if (d == 3 && m == 2) hipLaunchKernelGGL((k_count16<3, 2>), g, b, 0, st, a);
     else if (d == 2) hipLaunchKernelGGL(k_count64<2>, g, b, 0, st, a);
     else hipLaunchKernelGGL(k_count64<3>, g, b, 0, st, a);
-    hipLaunchKernelGGL(k_reduce_stats, dim3(1), dim3(1024), 0, st, a.blk_stats, a.nblk, a.stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats(const SearchArgs& a, hipStream_t st)
+{
+    if (a.L.ntot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_stats, dim3(1), dim3(1024), 0, st, a.blk_stats, a.nblk,
+                       static_cast<const unsigned long long*>(a.dstats), a.dstats ? a.dgrid : 0, a.stats);
     return hipGetLastError();
 }
 
@@ -1144,6 +1170,390 @@ hipError_t launch_long_rows(const SearchArgs& a, int grid, hipStream_t st)
     else if (d == 3 && m == 2) hipLaunchKernelGGL((k_long<3, 2>), gh, bh, lds, st, a);
     else if (d == 2) hipLaunchKernelGGL((k_long<2, 1>), gh, bh, lds, st, a);
     else hipLaunchKernelGGL((k_long<3, 1>), gh, bh, lds, st, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Dense-cell path. A work unit is up to kDenseSlice targets of one dense cell, all with
+// the same stencil union (the cell's list, ascending original index). A workgroup of
+// four wavefronts takes units from a counter; for each chunk of kDenseChunk candidates it
+// stages their FP16 pair records (and, for the fill, original indices and fixed-point
+// positions) in LDS, then each wavefront runs its targets one at a time over the chunk:
+// a lane tests two consecutive candidates per packed FP16 instruction with the same op
+// sequence as the block kernels, band pairs are settled by the FP64 recheck, and the
+// accepted candidates of each 128-candidate step are written with one ballot prefix, so
+// consecutive lanes store consecutive CSR entries and the row comes out ascending.
+// Wavefront w of a unit holds targets w, w + 4, ...: lane k keeps target w + 4k's data
+// in registers, read by the whole wavefront with readlane when its turn comes.
+__device__ __forceinline__ int rl32(int v, int k) { return __builtin_amdgcn_readlane(v, k); }
+__device__ __forceinline__ long long rl64(long long v, int k)
+{
+    const int lo = __builtin_amdgcn_readlane(static_cast<int>(v & 0xFFFFFFFF), k);
+    const int hi = __builtin_amdgcn_readlane(static_cast<int>(v >> 32), k);
+    return (static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo);
+}
+__device__ __forceinline__ double rlf64(double v, int k)
+{
+    return __builtin_bit_cast(double, rl64(__builtin_bit_cast(long long, v), k));
+}
+
+template <int DIM, int MODE, bool FILL>
+__global__ void __launch_bounds__(kDenseThreads)
+k_dense(SearchArgs a)
+{
+    constexpr int K = kDenseChunk;
+    constexpr bool F16 = MODE != 1;
+    __shared__ uint4 recA[F16 ? K / 2 : 1];               // qx, qy, qz, 2(c_x - c_jx) pairs
+    __shared__ uint2 recB[F16 ? K / 2 : 1];               // 2(c_y - c_jy), 2(c_z - c_jz) pairs
+    __shared__ double spj[F16 ? 1 : K * DIM];             // baseline: candidate positions
+    __shared__ int sorig[K];
+    __shared__ long long sX[(FILL && F16) ? K * DIM : 1];  // fixed-point positions (distances)
+    __shared__ int s_unit;
+    __shared__ unsigned long long s_red[kDenseThreads / 64][kDenseStats];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const int nunits = *a.dn > 0 ? a.unit_off[a.L.ncell_tot] : 0;
+    unsigned long long tc[kDenseStats] = {0, 0, 0, 0, 0, 0};
+    for (;;) {
+        __syncthreads();  // the previous unit is done with s_unit and the staged chunk
+        if (threadIdx.x == 0) s_unit = atomicAdd(a.ucount, 1);
+        __syncthreads();
+        const int u = s_unit;
+        if (u >= nunits) break;
+        const int g = a.ucell[u];
+        const int slice = u - a.unit_off[g];
+        const SetDesc& sd = a.L.sets[find_set(a.L.coffs, a.L.nsets, g)];
+        const int poff = sd.poff;
+        const double R2 = sd.fr.R2;
+        const float dscale = sd.fr.dist_scale;
+        const int ncx = sd.fr.nc[0], ncy = sd.fr.nc[1];
+        const uint32_t coff = static_cast<uint32_t>(sd.coff);
+        const int lk = g - sd.coff;
+        const int cx = lk % ncx, crow = lk / ncx, cy = crow % ncy, cz = crow / ncy;
+        const int t0 = a.cell_start[g] + slice * kDenseSlice;
+        const int t1 = min(a.cell_start[g + 1], t0 + kDenseSlice);
+        const int U = a.usz[g];
+        const int64_t ub = a.uoff[g];
+        Thresh th;
+        th.init(sd.fr);
+        const uint16_t tmid = sd.fr.t_mid;
+        // this lane's target (held for the wavefront)
+        const int pk = t0 + wv + 4 * lane;
+        const bool vk = pk < t1;
+        const int nt = (t1 - t0 > wv) ? (t1 - t0 - wv + 3) / 4 : 0;
+        int oi_k = 0, q01_k = 0, q2_k = 0, acc_k = 0, rl_k = 0;
+        long long rs_k = 0, xi_k[3] = {0, 0, 0};
+        double pi_k[3] = {0, 0, 0};
+        if (vk) {
+            oi_k = a.perm[pk];
+            const int li = oi_k - poff;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) pi_k[k] = sd.pos[static_cast<size_t>(li) * DIM + k];
+            if (F16) {
+                const ushort4 q = a.q4[pk];
+                q01_k = static_cast<int>(static_cast<uint32_t>(q.x) | (static_cast<uint32_t>(q.y) << 16));
+                q2_k = static_cast<int>(q.z);
+            }
+            if (FILL) {
+                rs_k = sd.row_ptr[li];
+                rl_k = static_cast<int>(sd.row_ptr[li + 1] - rs_k);
+                if (F16) {
+#pragma unroll
+                    for (int k = 0; k < DIM; ++k) xi_k[k] = a.X[static_cast<size_t>(oi_k) * x_stride(DIM) + k];
+                }
+            } else {
+                tc[0] += static_cast<unsigned long long>(U - 1);
+                tc[5] += 1;
+            }
+        }
+        for (int c0 = 0; c0 < U; c0 += K) {
+            const int nc = min(K, U - c0);
+            __syncthreads();
+            // stage the chunk (padding tests as +inf / far away: never a neighbour)
+            if (F16) {
+                for (int m = threadIdx.x; m < K / 2; m += kDenseThreads) {
+                    uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int e = 2 * m + h;
+                        const uint32_t sh = 16u * h;
+                        if (e < nc) {
+                            const int j = a.ulist[ub + c0 + e];
+                            const ushort4 v = a.q4[j];
+                            const uint32_t kj = a.skey[j] - coff;
+                            const int xj = static_cast<int>(kj % static_cast<uint32_t>(ncx));
+                            const uint32_t rj = kj / static_cast<uint32_t>(ncx);
+                            const int yj = static_cast<int>(rj % static_cast<uint32_t>(ncy));
+                            const int zj = static_cast<int>(rj / static_cast<uint32_t>(ncy));
+                            const _Float16 c2x = static_cast<_Float16>(2 * (cx - xj));
+                            const _Float16 c2y = static_cast<_Float16>(2 * (cy - yj));
+                            const _Float16 c2z = static_cast<_Float16>(2 * (cz - zj));
+                            w0 |= static_cast<uint32_t>(v.x) << sh;
+                            w1 |= static_cast<uint32_t>(v.y) << sh;
+                            w2 |= static_cast<uint32_t>(v.z) << sh;
+                            w3 |= static_cast<uint32_t>(__builtin_bit_cast(uint16_t, c2x)) << sh;
+                            w4 |= static_cast<uint32_t>(__builtin_bit_cast(uint16_t, c2y)) << sh;
+                            w5 |= static_cast<uint32_t>(__builtin_bit_cast(uint16_t, c2z)) << sh;
+                            const int oj = a.perm[j];
+                            sorig[e] = oj;
+                            if (FILL) {
+#pragma unroll
+                                for (int k = 0; k < DIM; ++k)
+                                    sX[e * DIM + k] = a.X[static_cast<size_t>(oj) * x_stride(DIM) + k];
+                            }
+                        } else {
+                            w0 |= 0x7C00u << sh;  // qx = +inf: r2 = +inf
+                            sorig[e] = -1;
+                        }
+                    }
+                    recA[m] = make_uint4(w0, w1, w2, w3);
+                    recB[m] = make_uint2(w4, w5);
+                }
+            } else {
+                for (int e = threadIdx.x; e < K; e += kDenseThreads) {
+                    if (e < nc) {
+                        const int j = a.ulist[ub + c0 + e];
+                        sorig[e] = a.perm[j];
+#pragma unroll
+                        for (int k = 0; k < DIM; ++k) spj[e * DIM + k] = a.spos[static_cast<size_t>(j) * 4 + k];
+                    } else {
+                        sorig[e] = -1;
+#pragma unroll
+                        for (int k = 0; k < DIM; ++k) spj[e * DIM + k] = 1e300;  // r2 = +inf
+                    }
+                }
+            }
+            __syncthreads();
+            const int nit = (nc + 127) >> 7;
+            for (int k = 0; k < nt; ++k) {
+                const int oi = rl32(oi_k, k);
+                double pi[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) pi[d] = rlf64(pi_k[d], k);
+                uint32_t inb = 0, bnd = 0;
+                h2 qix2, qiy2, qiz2;
+                if (F16) {
+                    const uint32_t q01 = static_cast<uint32_t>(rl32(q01_k, k));
+                    const uint32_t q2 = static_cast<uint32_t>(rl32(q2_k, k));
+                    qix2 = splat(as_f16(static_cast<uint16_t>(q01 & 0xFFFF)));
+                    qiy2 = splat(as_f16(static_cast<uint16_t>(q01 >> 16)));
+                    qiz2 = splat(as_f16(static_cast<uint16_t>(q2 & 0xFFFF)));
+                }
+                for (int it = 0; it < nit; ++it) {
+                    const int m = it * 64 + lane;
+                    uint32_t in2, bd2;
+                    if (F16) {
+                        const uint4 A = recA[m];
+                        const uint2 B = recB[m];
+                        const h2 s = qix2 - as_h2(A.x);
+                        const h2 tx = s + as_h2(A.w);
+                        const h2 ay = qiy2 + as_h2(B.x);
+                        const h2 ty = ay - as_h2(A.y);
+                        h2 r2;
+                        if (DIM == 3) {
+                            const h2 az = qiz2 + as_h2(B.y);
+                            const h2 tz = az - as_h2(A.z);
+                            r2 = tz * tz;
+                            r2 = __builtin_elementwise_fma(ty, ty, r2);
+                        } else {
+                            r2 = ty * ty;
+                        }
+                        r2 = __builtin_elementwise_fma(tx, tx, r2);
+                        const u16x2 dd = as_u16x2(as_u32(r2)) - th.tlo2;
+                        const uint32_t ib = u16x2_bits(dd) & 0x80008000u;
+                        const uint32_t xb = u16x2_bits(__builtin_elementwise_add_sat(dd, th.bias2));
+                        in2 = ((ib >> 15) & 1u) | ((ib >> 30) & 2u);
+                        bd2 = ((xb & 0xFFFFu) != 0xFFFFu ? 1u : 0u) | ((xb >> 16) != 0xFFFFu ? 2u : 0u);
+                    } else {
+                        in2 = 0;
+                        bd2 = 0;
+#pragma unroll
+                        for (int h = 0; h < 2; ++h)
+                            if (r2_fp64<DIM>(pi, spj + (2 * m + h) * DIM) <= R2) in2 |= 1u << h;
+                    }
+                    inb |= in2 << (2 * it);
+                    bnd |= bd2 << (2 * it);
+                }
+                if (MODE == 2) {
+                    // every candidate decided in FP64; the FP16 classes are only compared
+                    uint32_t all = 0;
+                    for (int it = 0; it < nit; ++it) {
+                        const int e0 = it * 128 + 2 * lane;
+                        all |= ((e0 < nc ? 1u : 0u) | (e0 + 1 < nc ? 2u : 0u)) << (2 * it);
+                    }
+                    uint32_t dec = 0;
+                    while (all) {
+                        const int bb = __builtin_ctz(all);
+                        all &= all - 1;
+                        const int e = (bb >> 1) * 128 + 2 * lane + (bb & 1);
+                        const int oj = sorig[e];
+                        if (oj == oi) continue;
+                        const bool truth = recheck<DIM>(sd.pos, pi, oj - poff, R2);
+                        if (truth) dec |= 1u << bb;
+                        if (!FILL) {
+                            const bool band = (bnd >> bb) & 1u;
+                            const bool in16 = (inb >> bb) & 1u;
+                            // naive FP16 test: r2 <= RN16(4 rho^2), from the staged record
+                            const uint4 A = recA[e >> 1];
+                            const uint2 B = recB[e >> 1];
+                            const h2 s = qix2 - as_h2(A.x);
+                            const h2 tx = s + as_h2(A.w);
+                            const h2 ty = (qiy2 + as_h2(B.x)) - as_h2(A.y);
+                            h2 r2;
+                            if (DIM == 3) {
+                                const h2 tz = (qiz2 + as_h2(B.y)) - as_h2(A.z);
+                                r2 = tz * tz;
+                                r2 = __builtin_elementwise_fma(ty, ty, r2);
+                            } else {
+                                r2 = ty * ty;
+                            }
+                            r2 = __builtin_elementwise_fma(tx, tx, r2);
+                            const uint16_t r2h = static_cast<uint16_t>((as_u32(r2) >> (16 * (e & 1))) & 0xFFFF);
+                            const bool naive = r2h <= tmid;
+                            tc[1] += band;
+                            tc[2] += naive && !truth;
+                            tc[3] += !naive && truth;
+                            tc[4] += !band && (in16 != truth);
+                        }
+                    }
+                    inb = dec;
+                } else if (MODE == 0) {
+                    uint32_t bb_all = bnd;
+                    while (bb_all) {
+                        const int bb = __builtin_ctz(bb_all);
+                        bb_all &= bb_all - 1;
+                        const int e = (bb >> 1) * 128 + 2 * lane + (bb & 1);
+                        const int oj = sorig[e];
+                        if (oj == oi) continue;  // itself (a band pair only when T_lo = 0)
+                        const bool truth = recheck<DIM>(sd.pos, pi, oj - poff, R2);
+                        if (truth) inb |= 1u << bb;
+                        if (!FILL) {
+                            const uint4 A = recA[e >> 1];
+                            const uint2 B = recB[e >> 1];
+                            const h2 s = qix2 - as_h2(A.x);
+                            const h2 tx = s + as_h2(A.w);
+                            const h2 ty = (qiy2 + as_h2(B.x)) - as_h2(A.y);
+                            h2 r2;
+                            if (DIM == 3) {
+                                const h2 tz = (qiz2 + as_h2(B.y)) - as_h2(A.z);
+                                r2 = tz * tz;
+                                r2 = __builtin_elementwise_fma(ty, ty, r2);
+                            } else {
+                                r2 = ty * ty;
+                            }
+                            r2 = __builtin_elementwise_fma(tx, tx, r2);
+                            const uint16_t r2h = static_cast<uint16_t>((as_u32(r2) >> (16 * (e & 1))) & 0xFFFF);
+                            const bool naive = r2h <= tmid;
+                            tc[1] += 1;
+                            tc[2] += naive && !truth;
+                            tc[3] += !naive && truth;
+                        }
+                    }
+                }
+                if (!FILL) {
+                    const int tot = static_cast<int>(wave_sum_u64(static_cast<unsigned long long>(__builtin_popcount(inb))));
+                    if (lane == k) acc_k += tot;
+                } else {
+                    // ascending emission: candidate order is original-index order
+                    const long long rs = rl64(rs_k, k);
+                    const int rl = rl32(rl_k, k);
+                    const int done = rl32(acc_k, k);
+                    const bool room = rs + rl <= sd.capacity;
+                    long long xi[3];
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) xi[d] = rl64(xi_k[d], k);
+                    const double* pis = pi;
+                    int w = done;
+                    for (int it = 0; it < nit; ++it) {
+                        uint32_t b2 = (inb >> (2 * it)) & 3u;
+                        const int e0 = it * 128 + 2 * lane;
+                        int o0 = 0, o1 = 0;
+                        if (b2 & 1u) {
+                            o0 = sorig[e0];
+                            if (o0 == oi) b2 &= ~1u;
+                        }
+                        if (b2 & 2u) {
+                            o1 = sorig[e0 + 1];
+                            if (o1 == oi) b2 &= ~2u;
+                        }
+                        const uint64_t B0 = __ballot(b2 & 1u);
+                        const uint64_t B1 = __ballot((b2 >> 1) & 1u);
+                        if ((B0 | B1) == 0) continue;
+                        const int pre = __popcll(B0 & lt) + __popcll(B1 & lt);
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            if (!((b2 >> h) & 1u)) continue;
+                            const int slot = w + pre + (h == 1 ? static_cast<int>(b2 & 1u) : 0);
+                            if (slot >= rl || !room) continue;
+                            const int e = e0 + h;
+                            const int oj = h == 0 ? o0 : o1;
+                            float dv;
+                            if (F16) {
+                                float s2 = 0.0f;
+#pragma unroll
+                                for (int d = 0; d < DIM; ++d) {
+                                    const float f = exact_i64_to_f32_s(sX[e * DIM + d] - xi[d]);
+                                    s2 = s2 + f * f;
+                                }
+                                dv = __builtin_amdgcn_sqrtf(s2) * dscale;
+                            } else {
+                                dv = static_cast<float>(__dsqrt_rn(r2_fp64<DIM>(pis, spj + e * DIM)));
+                            }
+                            sd.col[rs + slot] = oj - poff;
+                            sd.dist[rs + slot] = dv;
+                        }
+                        w += __popcll(B0) + __popcll(B1);
+                    }
+                    if (!room && lane == 0 && w > done) atomicOr(a.err, kErrCapacity);
+                    if (lane == k) acc_k = w;
+                }
+            }
+        }
+        if (vk) {
+            if (!FILL) {
+                // itself: "in" in FP16 when T_lo > 0, always in the FP64 baseline; never
+                // counted when every candidate is decided in FP64 (it is skipped there)
+                const int self = MODE == 1 ? 1 : (MODE == 2 ? 0 : (sd.fr.t_lo > 0 ? 1 : 0));
+                a.counts[oi_k] = acc_k - self;
+            } else if (acc_k != rl_k) {
+                atomicOr(a.err, kErrLongRow);
+            }
+        }
+    }
+    if (!FILL) {
+#pragma unroll
+        for (int k = 0; k < kDenseStats; ++k) {
+            const unsigned long long sum = wave_sum_u64(tc[k]);
+            if (lane == 0) s_red[wv][k] = sum;
+        }
+        __syncthreads();
+        if (threadIdx.x < kDenseStats) {
+            unsigned long long sum = 0;
+            for (int w = 0; w < kDenseThreads / 64; ++w) sum += s_red[w][threadIdx.x];
+            a.dstats[static_cast<size_t>(blockIdx.x) * kDenseStats + threadIdx.x] = sum;
+        }
+    }
+}
+
+hipError_t launch_dense(const SearchArgs& a, bool fill, hipStream_t st)
+{
+    if (a.L.ntot == 0 || !a.wdense) return hipSuccess;
+    hipError_t e = launch_fill_i32(a.ucount, 1, 0, st);
+    if (e != hipSuccess) return e;
+    const dim3 g(a.dgrid), b(kDenseThreads);
+    const int d = a.L.dim, m = a.L.mode;
+#define NNPS_DENSE(D, M)                                                                      \
+    do {                                                                                      \
+        if (fill) hipLaunchKernelGGL((k_dense<D, M, true>), g, b, 0, st, a);                  \
+        else hipLaunchKernelGGL((k_dense<D, M, false>), g, b, 0, st, a);                      \
+    } while (0)
+    if (d == 2 && m == 0) NNPS_DENSE(2, 0);
+    else if (d == 3 && m == 0) NNPS_DENSE(3, 0);
+    else if (d == 2 && m == 1) NNPS_DENSE(2, 1);
+    else if (d == 3 && m == 1) NNPS_DENSE(3, 1);
+    else if (d == 2) NNPS_DENSE(2, 2);
+    else NNPS_DENSE(3, 2);
+#undef NNPS_DENSE
     return hipGetLastError();
 }
 

@@ -45,7 +45,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("candidates", ctypes.c_int64),
                 ("band_pairs", ctypes.c_int64), ("fp16_false_pos", ctypes.c_int64),
                 ("fp16_false_neg", ctypes.c_int64), ("outside_band_disagree", ctypes.c_int64),
-                ("heavy_rows", ctypes.c_int64), ("dim", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("heavy_rows", ctypes.c_int64), ("dense_rows", ctypes.c_int64),
+                ("dense_entries", ctypes.c_int64), ("dim", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("frac_bits", ctypes.c_int32), ("ncell", ctypes.c_int32 * 3),
                 ("cell_width", ctypes.c_double), ("band", ctypes.c_double)]
 
@@ -57,7 +58,12 @@ class Stats(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("block_target", ctypes.c_int32), ("long_rows_grid", ctypes.c_int32),
-                ("long_rows_keys", ctypes.c_int32)]
+                ("long_rows_keys", ctypes.c_int32), ("dense_min_union", ctypes.c_int32),
+                ("dense_grid", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("dense_max_entries", ctypes.c_int64)]
+
+    NAMES = ("block_target", "long_rows_grid", "long_rows_keys", "dense_min_union", "dense_grid",
+             "dense_max_entries")
 
 
 EXPORTS = ["nnps_status_str", "nnps_validate", "nnps_grid", "nnps_ctx_create", "nnps_ctx_destroy",
@@ -67,7 +73,8 @@ EXPORTS = ["nnps_status_str", "nnps_validate", "nnps_grid", "nnps_ctx_create", "
            "nnps_batch_build", "nnps_batch_count", "nnps_batch_fill", "nnps_batch_search",
            "nnps_batch_step", "nnps_cells_set_graphs", "nnps_batch_nnz"]
 
-PHASES = ["assign", "cellscan", "sort", "pack", "blocks", "count", "rowscan", "fill", "longrows"]
+PHASES = ["assign", "cellscan", "sort", "pack", "blocks", "unions", "count", "dcount", "rowscan", "fill",
+          "longrows", "dfill"]
 
 _lib = None
 
@@ -192,15 +199,16 @@ class Context:
         except Exception:
             pass
 
-    def set_tuning(self, block_target: int = 56, long_rows_grid: int = 1024, long_rows_keys: int = 0):
-        t = Tuning(int(block_target), int(long_rows_grid), int(long_rows_keys))
+    def set_tuning(self, block_target: int = 56, long_rows_grid: int = 1024, long_rows_keys: int = 0,
+                   dense_min_union: int = 0, dense_grid: int = 0, dense_max_entries: int = 0):
+        t = Tuning(int(block_target), int(long_rows_grid), int(long_rows_keys), int(dense_min_union),
+                   int(dense_grid), 0, int(dense_max_entries))
         _check(self._lib.nnps_ctx_set_tuning(self._ctx, ctypes.byref(t)), "nnps_ctx_set_tuning")
 
     def get_tuning(self) -> dict:
         t = Tuning()
         _check(self._lib.nnps_ctx_get_tuning(self._ctx, ctypes.byref(t)), "nnps_ctx_get_tuning")
-        return {"block_target": t.block_target, "long_rows_grid": t.long_rows_grid,
-                "long_rows_keys": t.long_rows_keys}
+        return {k: getattr(t, k) for k in Tuning.NAMES}
 
     def cells(self) -> "Cells":
         c = Cells(self)
@@ -283,9 +291,14 @@ class Cells:
         self.nsets = len(sets)
         self._pos = [t[0] for t in sets]
 
-    def batch_nnz(self, stream=None):
+    def batch_nnz(self, stream=None, check: bool = True):
+        """Each set's nnz of the last count (waits for the stream). With check=False returns
+        (nnz list, status) instead of raising on a device-reported error."""
         nnz = (ctypes.c_int64 * self.nsets)()
-        _check(self._lib.nnps_batch_nnz(self._h, nnz, _stream_ptr(stream)), "nnps_batch_nnz")
+        code = self._lib.nnps_batch_nnz(self._h, nnz, _stream_ptr(stream))
+        if not check:
+            return list(nnz), code
+        _check(code, "nnps_batch_nnz")
         return list(nnz)
 
     def set_graphs(self, on: bool = True):

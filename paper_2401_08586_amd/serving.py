@@ -1,0 +1,355 @@
+"""Serving loop: neighbour-search requests from many concurrent simulations on one GPU.
+
+Each simulation keeps its particles resident in HBM between time steps; a request asks
+for one step (the particles move, then a rebuild + search of that simulation). The loop
+does continuous batching: whenever one of its stream slots is free, every queued request
+whose simulation is idle joins the next batch (up to a particle budget per batch), and
+the batch runs as one library batch call (one launch per pass for all its sets) on that
+slot's stream while other slots' batches run beside it. Simulations are admitted into
+HBM by a byte budget: before a batch runs, idle simulations are evicted (positions to
+pinned host memory, outputs freed) in least-recently-used order until the batch fits.
+
+The scheduler (`Scheduler`) is host logic only and is tested on the CPU; `Server` drives
+the library through the binding in `nnps.py`. Every search runs in the HIP library; the
+particle motion between steps (the simulation's own work, not the search) is a few
+elementwise torch operations on the slot's stream, ordered before the sim's next search
+by an event.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import math
+import time
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Request:
+    sim: int
+    arrival: float                 # seconds after the run's start
+    issued: float | None = None    # host time the batch holding it was launched (s)
+    done_ms: float | None = None   # device completion time (ms after the run's start)
+    nnz: int = 0
+    batch: int = -1
+    step: int = -1
+
+    @property
+    def latency_ms(self) -> float:
+        return self.done_ms - 1e3 * self.arrival
+
+
+class Scheduler:
+    """Queue, batch formation and HBM admission (host logic, no device calls).
+
+    sizes[s] = particles of simulation s; nbytes[s] = its resident footprint in bytes
+    (positions + CSR outputs). At most one request per simulation is in flight; later
+    requests of a busy simulation wait in arrival order."""
+
+    def __init__(self, sizes, nbytes, budget_bytes: float = math.inf, max_batch_particles: int = 1 << 23):
+        self.sizes = list(sizes)
+        self.nbytes = list(nbytes)
+        self.budget = budget_bytes
+        self.max_batch = max_batch_particles
+        self.queue: collections.deque[Request] = collections.deque()
+        self.busy: set[int] = set()
+        self.resident: collections.OrderedDict[int, None] = collections.OrderedDict()  # LRU order
+        self.evictions = 0
+        self.admissions = 0
+
+    def push(self, req: Request):
+        self.queue.append(req)
+
+    def pending(self) -> int:
+        return len(self.queue)
+
+    def resident_bytes(self) -> int:
+        return sum(self.nbytes[s] for s in self.resident)
+
+    def next_batch(self) -> list[Request]:
+        """Requests for the next batch, in arrival order: each idle simulation's oldest
+        request, until the particle budget is reached (the first one always fits)."""
+        chosen: list[Request] = []
+        taken: set[int] = set()
+        total = 0
+        keep: collections.deque[Request] = collections.deque()
+        while self.queue:
+            r = self.queue.popleft()
+            if r.sim in self.busy or r.sim in taken or (chosen and total + self.sizes[r.sim] > self.max_batch):
+                keep.append(r)
+                continue
+            chosen.append(r)
+            taken.add(r.sim)
+            total += self.sizes[r.sim]
+        self.queue = keep
+        return chosen
+
+    def admit(self, sims) -> tuple[list[int], list[int]]:
+        """Make `sims` resident within the budget. Returns (to_admit, to_evict): idle
+        resident simulations outside `sims` are evicted least recently used first. A batch
+        larger than the budget on its own is still admitted, with everything else evicted."""
+        need = [s for s in sims if s not in self.resident]
+        want = sum(self.nbytes[s] for s in need)
+        evict: list[int] = []
+        have = self.resident_bytes()
+        for s in list(self.resident):
+            if have + want <= self.budget:
+                break
+            if s in sims or s in self.busy:
+                continue
+            evict.append(s)
+            have -= self.nbytes[s]
+        for s in evict:
+            del self.resident[s]
+        for s in sims:
+            self.resident[s] = None
+            self.resident.move_to_end(s)
+        self.evictions += len(evict)
+        self.admissions += len(need)
+        return need, evict
+
+    def start(self, sims):
+        self.busy.update(sims)
+
+    def finish(self, sims):
+        self.busy.difference_update(sims)
+
+
+def poisson_arrivals(rate: float, count: int, nsims: int, seed: int = 0, start: float = 0.0):
+    """`count` arrivals of a Poisson process of `rate` per second, each for a simulation
+    drawn uniformly; returns [(time_s, sim)] in time order."""
+    rng = np.random.default_rng(seed)
+    t = start + np.cumsum(rng.exponential(1.0 / rate, size=count))
+    sims = rng.integers(0, nsims, size=count)
+    return [(float(a), int(b)) for a, b in zip(t, sims)]
+
+
+def percentile(values, q):
+    v = np.sort(np.asarray(values, dtype=np.float64))
+    if v.size == 0:
+        return float("nan")
+    return float(np.percentile(v, q))
+
+
+class Server:
+    """Runs the request loop on one GPU. `sims` are workloads.ParticleSet; `slots` is the
+    number of batches that may be on the device at once (one stream each)."""
+
+    def __init__(self, sims, slots: int = 2, budget_bytes: float = math.inf, max_batch_particles: int = 1 << 23,
+                 seed: int = 4, frac: float = 0.05, headroom: float = 1.1, ctx=None, keep_results: bool = False):
+        import torch
+        from . import nnps
+        self.torch = torch
+        self.nnps = nnps
+        self.ctx = ctx or nnps.Context(0)
+        self.own_ctx = ctx is None
+        self.sims = sims
+        self.seed = seed
+        self.frac = frac
+        self.headroom = headroom
+        self.keep_results = keep_results
+        self.results = {}  # (sim, step) -> (pos, row_ptr, col, dist) copies when keep_results
+        n = len(sims)
+        self.step = [0] * n
+        self.pos = [None] * n       # device positions (resident) or None
+        self.host = [None] * n      # pinned host positions while evicted
+        self.rp = [None] * n
+        self.col = [None] * n
+        self.dist = [None] * n
+        self.cap = [0] * n
+        self.ready = [None] * n     # event: positions of the next step are in place
+        self.box = [(torch.tensor(ps.lo, dtype=torch.float64, device="cuda"),
+                     torch.tensor(ps.hi, dtype=torch.float64, device="cuda")) for ps in sims]
+        # initial capacity estimate per simulation from one search of its starting positions
+        cells = self.ctx.cells()
+        for s, ps in enumerate(sims):
+            self.host[s] = torch.from_numpy(np.ascontiguousarray(ps.pos)).pin_memory()
+            pos = self.host[s].cuda()
+            rp, col, _, _ = nnps.search(pos, ps.lo, ps.hi, ps.cell_size, ps.radius, ctx=self.ctx, cells=cells)
+            self.cap[s] = int(col.numel() * headroom) + 4096
+            del pos, rp, col
+        cells.close()
+        nbytes = [ps.n * ps.dim * 8 + (ps.n + 1) * 8 + self.cap[s] * 8 for s, ps in enumerate(sims)]
+        self.sched = Scheduler([ps.n for ps in sims], nbytes, budget_bytes, max_batch_particles)
+        self.slots = []
+        for _ in range(slots):
+            c = self.ctx.cells()
+            self.slots.append({"stream": torch.cuda.Stream(), "cells": c, "batch": None, "done": None})
+        self.batches = 0
+        torch.cuda.synchronize()
+
+    # -- resident state ------------------------------------------------------------------
+    def _admit(self, s, stream):
+        torch = self.torch
+        ps = self.sims[s]
+        with torch.cuda.stream(stream):
+            self.pos[s] = self.host[s].to("cuda", non_blocking=True)
+            self.rp[s] = torch.empty(ps.n + 1, dtype=torch.int64, device="cuda")
+            self.col[s] = torch.empty(self.cap[s], dtype=torch.int32, device="cuda")
+            self.dist[s] = torch.empty(self.cap[s], dtype=torch.float32, device="cuda")
+        self.host[s] = None
+
+    def _evict(self, s):
+        torch = self.torch
+        # an idle simulation: its last step (and motion) finished; wait for that motion
+        if self.ready[s] is not None:
+            self.ready[s].synchronize()
+        host = torch.empty(self.pos[s].shape, dtype=torch.float64, pin_memory=True)
+        host.copy_(self.pos[s])
+        self.host[s] = host
+        self.pos[s] = self.rp[s] = self.col[s] = self.dist[s] = None
+        self.ready[s] = None
+
+    def _move(self, s, stream):
+        """The simulation's time step: every particle moves by U(-frac dx, +frac dx) per
+        component, dx = radius / 2.4, walls reflect (seeded per simulation and step)."""
+        torch = self.torch
+        ps = self.sims[s]
+        g = torch.Generator(device="cuda")
+        g.manual_seed(self.seed * 1_000_003 + s * 65_537 + self.step[s])
+        dx = ps.radius / 2.4
+        with torch.cuda.stream(stream):
+            p = self.pos[s]
+            d = torch.rand(p.shape, dtype=torch.float64, device="cuda", generator=g)
+            p.add_(d.mul_(2 * self.frac * dx).sub_(self.frac * dx))
+            lo, hi = self.box[s]
+            p.copy_(torch.where(p < lo, 2 * lo - p, p))
+            p.copy_(torch.where(p > hi, 2 * hi - p, p))
+            p.copy_(torch.minimum(torch.maximum(p, lo), hi))
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        self.ready[s] = ev
+
+    # -- the loop -------------------------------------------------------------------------
+    def _launch(self, slot, reqs, t0):
+        torch, nnps = self.torch, self.nnps
+        stream = slot["stream"]
+        sims = [r.sim for r in reqs]
+        admit, evict = self.sched.admit(sims)
+        for s in evict:
+            self._evict(s)
+        for s in admit:
+            self._admit(s, stream)
+        for s in sims:
+            if self.ready[s] is not None:
+                stream.wait_event(self.ready[s])
+        sets = [(self.pos[s], self.sims[s].lo, self.sims[s].hi, self.sims[s].cell_size, self.sims[s].radius)
+                for s in sims]
+        with torch.cuda.stream(stream):
+            slot["cells"].batch_step(sets, [self.rp[s] for s in sims], [self.col[s] for s in sims],
+                                     [self.dist[s] for s in sims], stream=stream)
+            done = torch.cuda.Event(enable_timing=True)
+            done.record(stream)
+        now = time.perf_counter() - t0
+        for r in reqs:
+            r.issued = now
+            r.batch = self.batches
+            r.step = self.step[r.sim]
+        self.sched.start(sims)
+        slot["batch"] = reqs
+        slot["done"] = done
+        self.batches += 1
+
+    def _finish(self, slot, ref):
+        torch, nnps = self.torch, self.nnps
+        reqs = slot["batch"]
+        stream = slot["stream"]
+        done_ms = ref.elapsed_time(slot["done"])
+        nnz, code = slot["cells"].batch_nnz(stream=stream, check=False)
+        sims = [r.sim for r in reqs]
+        redo = []
+        for r, k in zip(reqs, nnz):
+            s = r.sim
+            if k > self.cap[s]:
+                redo.append(r)
+                continue
+            r.nnz = int(k)
+            r.done_ms = done_ms
+            if self.keep_results:  # copies ordered before the motion on the same stream
+                with torch.cuda.stream(stream):
+                    self.results[(s, self.step[s])] = (self.pos[s].clone(), self.rp[s].clone(),
+                                                       self.col[s][:k].clone(), self.dist[s][:k].clone())
+            self.step[s] += 1
+            self._move(s, stream)
+        if code not in (nnps.NNPS_OK, nnps.NNPS_ECAPACITY):
+            raise nnps.NnpsError(code, "serving batch")
+        for r in redo:  # outputs too small: grow them and run that step again first
+            s = r.sim
+            self.cap[s] = int(nnz[sims.index(s)] * self.headroom) + 4096
+            self.sched.nbytes[s] = self.sims[s].n * self.sims[s].dim * 8 + (self.sims[s].n + 1) * 8 + self.cap[s] * 8
+            with torch.cuda.stream(stream):
+                self.col[s] = torch.empty(self.cap[s], dtype=torch.int32, device="cuda")
+                self.dist[s] = torch.empty(self.cap[s], dtype=torch.float32, device="cuda")
+            self.sched.queue.appendleft(r)
+        self.sched.finish(sims)
+        slot["batch"] = None
+        slot["done"] = None
+
+    def run(self, arrivals, closed_loop: int = 0):
+        """Serve `arrivals` ([(time_s, sim)], time order). With closed_loop = k > 0 the
+        arrivals are ignored and every simulation always has a request waiting (each
+        completion immediately issues the next) until k requests have completed: the
+        saturated rate. Returns the completed requests."""
+        torch = self.torch
+        torch.cuda.synchronize()
+        ref = torch.cuda.Event(enable_timing=True)
+        ref.record()
+        ref.synchronize()
+        t0 = time.perf_counter()
+        done: list[Request] = []
+        arr = collections.deque(arrivals)
+        if closed_loop:
+            for s in range(len(self.sims)):
+                self.sched.push(Request(s, 0.0))
+        total = closed_loop if closed_loop else len(arrivals)
+        while len(done) < total:
+            now = time.perf_counter() - t0
+            while arr and not closed_loop and arr[0][0] <= now:
+                a, s = arr.popleft()
+                self.sched.push(Request(s, a))
+            progressed = False
+            for slot in self.slots:
+                if slot["batch"] is not None and slot["done"].query():
+                    reqs = slot["batch"]
+                    self._finish(slot, ref)
+                    for r in reqs:
+                        if r.done_ms is not None:
+                            done.append(r)
+                            if closed_loop and len(done) + self.sched.pending() + len(self.sched.busy) < total:
+                                self.sched.push(Request(r.sim, time.perf_counter() - t0))
+                    progressed = True
+            for slot in self.slots:
+                if slot["batch"] is None and self.sched.pending():
+                    reqs = self.sched.next_batch()
+                    if reqs:
+                        self._launch(slot, reqs, t0)
+                        progressed = True
+            if not progressed:
+                time.sleep(20e-6)
+        torch.cuda.synchronize()
+        return done
+
+    def close(self):
+        for slot in self.slots:
+            slot["cells"].close()
+        if self.own_ctx:
+            self.ctx.close()
+
+
+def summarize(done, warmup: int = 0):
+    """p50/p99 latency (ms, arrival -> CSR ready), throughput and counts over the requests
+    after the first `warmup` completions (in arrival order)."""
+    reqs = sorted(done, key=lambda r: r.arrival)[warmup:]
+    if not reqs:
+        return {}
+    lat = [r.latency_ms for r in reqs]
+    t_first = min(r.arrival for r in reqs) * 1e3
+    t_last = max(r.done_ms for r in reqs)
+    pairs = sum(r.nnz for r in reqs)
+    span_s = max((t_last - t_first) * 1e-3, 1e-9)
+    return {"requests": len(reqs), "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+            "mean_ms": float(np.mean(lat)), "max_ms": float(np.max(lat)),
+            "gpairs_per_s": pairs / span_s / 1e9, "requests_per_s": len(reqs) / span_s,
+            "batches": len({r.batch for r in reqs}),
+            "mean_batch": len(reqs) / max(len({r.batch for r in reqs}), 1)}

@@ -143,7 +143,7 @@ def test_long_rows_chunked_merge(ctx):
     pos = np.clip(np.concatenate([rng.normal(0.5, 0.015, size=(2500, 3)), rng.uniform(0, 1, size=(500, 3))]), 0, 1)
     ps = W.ParticleSet(pos, (0, 0, 0), (1, 1, 1), 0.06, 0.06, "dense_ball")
     for keys in (64, 256, 0):
-        ctx.set_tuning(block_target=56, long_rows_grid=256, long_rows_keys=keys)
+        ctx.set_tuning(block_target=56, long_rows_grid=256, long_rows_keys=keys, dense_min_union=-1)
         print(f"[gpu] long rows keys={keys}", flush=True)
         for mode in (nnps.MODE_FP16_RCLL, nnps.MODE_FP64_BASELINE):
             cells = ctx.cells()

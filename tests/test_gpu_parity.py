@@ -150,10 +150,19 @@ def test_long_rows(ctx):
     pos = np.clip(pos, 0, 1)
     ps = W.ParticleSet(pos, (0, 0, 0), (1, 1, 1), 0.05, 0.05, "long_rows_3d")
     print(f"[gpu] long rows {ps.name}", flush=True)
-    for mode in MODES:
+    want = oracle.search_ps(ps)
+    ctx.set_tuning(dense_min_union=-1)  # the block and long-row paths only
+    try:
+        for mode in MODES:
+            got = gpu_search(ctx, ps, mode)
+            check_against_oracle(got, want, mode, ps.name)
+            assert got[3]["heavy_rows"] > 0
+    finally:
+        ctx.set_tuning()
+    for mode in MODES:  # default: the dense cells take the dense-cell path
         got = gpu_search(ctx, ps, mode)
-        check_against_oracle(got, oracle.search_ps(ps), mode, ps.name)
-        assert got[3]["heavy_rows"] > 0
+        check_against_oracle(got, want, mode, ps.name + "_dense")
+        assert got[3]["dense_rows"] > 0
 
 
 def test_deterministic(ctx):
