@@ -23,7 +23,7 @@ DEFAULTS = {"block_target": 56, "long_rows_grid": 1024, "long_rows_keys": 0, "de
 
 SPACE = {
     "block_target": [24, 32, 40, 48, 56, 64, 80, 96],
-    "dense_min_union": [128, 256, 384, 512, 768, 1024, -1],
+    "dense_min_union": [1, 128, 256, 384, 512, 768, 1024, -1],
     "dense_grid": [256, 512, 1024, 2048, 4096],
     "long_rows_grid": [256, 1024, 4096],
 }

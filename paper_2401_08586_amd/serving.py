@@ -47,8 +47,11 @@ class Scheduler:
     (positions + CSR outputs). At most one request per simulation is in flight; later
     requests of a busy simulation wait in arrival order."""
 
-    def __init__(self, sizes, nbytes, budget_bytes: float = math.inf, max_batch_particles: int = 1 << 23):
+    def __init__(self, sizes, nbytes, budget_bytes: float = math.inf, max_batch_particles: int = 1 << 23,
+                 groups=None):
         self.sizes = list(sizes)
+        # requests of one batch share a group (the library batches sets of one dimension)
+        self.groups = list(groups) if groups is not None else [0] * len(self.sizes)
         self.nbytes = list(nbytes)
         self.budget = budget_bytes
         self.max_batch = max_batch_particles
@@ -69,14 +72,17 @@ class Scheduler:
 
     def next_batch(self) -> list[Request]:
         """Requests for the next batch, in arrival order: each idle simulation's oldest
-        request, until the particle budget is reached (the first one always fits)."""
+        request of the first eligible request's group, until the particle budget is
+        reached (the first one always fits)."""
         chosen: list[Request] = []
         taken: set[int] = set()
         total = 0
         keep: collections.deque[Request] = collections.deque()
         while self.queue:
             r = self.queue.popleft()
-            if r.sim in self.busy or r.sim in taken or (chosen and total + self.sizes[r.sim] > self.max_batch):
+            if (r.sim in self.busy or r.sim in taken
+                    or (chosen and self.groups[r.sim] != self.groups[chosen[0].sim])
+                    or (chosen and total + self.sizes[r.sim] > self.max_batch)):
                 keep.append(r)
                 continue
             chosen.append(r)
@@ -171,7 +177,8 @@ class Server:
             del pos, rp, col
         cells.close()
         nbytes = [ps.n * ps.dim * 8 + (ps.n + 1) * 8 + self.cap[s] * 8 for s, ps in enumerate(sims)]
-        self.sched = Scheduler([ps.n for ps in sims], nbytes, budget_bytes, max_batch_particles)
+        self.sched = Scheduler([ps.n for ps in sims], nbytes, budget_bytes, max_batch_particles,
+                               groups=[ps.dim for ps in sims])
         self.slots = []
         for _ in range(slots):
             c = self.ctx.cells()

@@ -34,6 +34,14 @@ def test_batch_particle_budget():
     assert [r.sim for r in b] == [3]  # a request above the budget still runs, alone
 
 
+def test_batch_shares_one_group():
+    s = Scheduler(sizes=[1] * 5, nbytes=[1] * 5, groups=[2, 3, 2, 3, 2])
+    for sim in (1, 0, 3, 2, 4):
+        s.push(Request(sim, 0.0))
+    assert [r.sim for r in s.next_batch()] == [1, 3]      # the first request's group (3D)
+    assert [r.sim for r in s.next_batch()] == [0, 2, 4]   # then the 2D ones
+
+
 def test_admission_evicts_least_recently_used_idle_sims():
     s = Scheduler(sizes=[1] * 5, nbytes=[40, 30, 20, 50, 10], budget_bytes=100)
     assert s.admit([0, 1]) == ([0, 1], [])
