@@ -320,10 +320,11 @@ class Server:
                 if slot["batch"] is not None and slot["done"].query():
                     reqs = slot["batch"]
                     self._finish(slot, ref)
-                    for r in reqs:
-                        if r.done_ms is not None:
-                            done.append(r)
-                            if closed_loop and len(done) + self.sched.pending() + len(self.sched.busy) < total:
+                    finished = [r for r in reqs if r.done_ms is not None]
+                    done.extend(finished)
+                    if closed_loop:
+                        for r in finished:  # each completion issues that simulation's next step
+                            if len(done) + self.sched.pending() + len(self.sched.busy) < total:
                                 self.sched.push(Request(r.sim, time.perf_counter() - t0))
                     progressed = True
             for slot in self.slots:
