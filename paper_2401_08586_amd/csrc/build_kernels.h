@@ -14,6 +14,8 @@ struct Launch {
     const SetDesc* sets;       // [nsets] (device)
     const int* poffs;          // [nsets + 1] particle offsets (device)
     const int* coffs;          // [nsets + 1] cell offsets (device)
+    const int* roffs;          // [nsets + 1] offsets of the sets' rows of cells (device)
+    int nrows_tot;             // total rows of cells (x-lines)
 };
 
 hipError_t launch_fill_i32(int* p, int64_t m, int v, hipStream_t st);
@@ -31,9 +33,8 @@ hipError_t launch_pack(const Launch& L, const uint32_t* skey, const int* perm, c
 hipError_t launch_blocks(const Launch& L, const uint32_t* skey, const int* cell_start, const int* wdense, int* flags,
                          int* bidx, int* bstart, int* bset, int64_t* partial, hipStream_t st);
 
-// Dense-cell path: device tables of one build. A cell is "dense" when it is occupied and
-// lies in an x-window where some cell's stencil holds more than `thresh` particles; such
-// windows get no work blocks. Each dense cell g owns the list ulist[uoff[g] ..
+// Dense-cell path: device tables of one build. A cell is "dense" when its stencil holds
+// more than `thresh` particles; runs of dense cells get no work blocks. Each dense cell g owns the list ulist[uoff[g] ..
 // uoff[g] + usz[g]) of the sorted positions of the particles in its 3^d stencil, in
 // ascending original index, and ceil(occupancy / kDenseSlice) work units.
 struct DenseBuild {

@@ -335,26 +335,62 @@ k_pack(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nset
 }
 
 // ---------------------------------------------------------------------------
-// Work blocks: the particles of one x-window of fr.xwin cells inside one (y, z) row of
-// cells of one set, split into runs of at most kWave particles. A window of the
-// dense-cell path is one block that the block kernels skip.
+// Work blocks, one wavefront per row of cells of a set: walking the row in x, a block is
+// a run of at most kWave consecutive sorted particles whose cells span at most fr.xwin
+// cells; it starts where the previous one ended (so blocks are full unless the span or
+// the row ends them). A run of dense cells (the dense-cell path's) is one block that the
+// block kernels skip. flags (zeroed beforehand) receives 1 at every block start.
 __global__ void __launch_bounds__(256)
-k_block_flags(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nsets, int ntot,
-              const uint32_t* __restrict__ skey, const int* __restrict__ cell_start,
-              const int* __restrict__ wdense, int* __restrict__ flags)
+k_row_blocks(const SetDesc* __restrict__ sets, const int* __restrict__ roffs, int nsets, int nrows_tot,
+             const int* __restrict__ cell_start, const int* __restrict__ wdense, int* __restrict__ flags)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= ntot) return;
-    const uint32_t key = skey[p];
-    const SetDesc& sd = sets[find_set(coffs, nsets, static_cast<int>(key))];
-    const uint32_t lk = key - static_cast<uint32_t>(sd.coff);
-    const uint32_t ncx = static_cast<uint32_t>(sd.fr.nc[0]);
-    const uint32_t row = lk / ncx;
-    const uint32_t x = lk - row * ncx;
-    const uint32_t win = x / static_cast<uint32_t>(sd.fr.xwin);
-    const int ws = cell_start[sd.coff + row * ncx + win * static_cast<uint32_t>(sd.fr.xwin)];
-    if (wdense && wdense[key]) flags[p] = p == ws;
-    else flags[p] = (p == ws) || (((p - ws) % kWave) == 0);
+    const int r = blockIdx.x * (blockDim.x >> 6) + static_cast<int>(threadIdx.x >> 6);
+    if (r >= nrows_tot) return;
+    const int lane = threadIdx.x & 63;
+    const int s = find_set(roffs, nsets, r);
+    const SetDesc& sd = sets[s];
+    const int ncx = sd.fr.nc[0];
+    const int span = sd.fr.xwin;
+    const int g0 = sd.coff + (r - roffs[s]) * ncx;
+    // wavefront-uniform walk state
+    int bs = -1, xs = 0;
+    bool dense_open = false;
+    for (int base = 0; base < ncx; base += 64) {
+        const int x = base + lane;
+        int c0 = 0, c1 = 0, dn = 0;
+        if (x < ncx) {
+            c0 = cell_start[g0 + x];
+            c1 = cell_start[g0 + x + 1];
+            dn = wdense ? wdense[g0 + x] : 0;
+        }
+        const int m = min(64, ncx - base);
+        for (int i = 0; i < m; ++i) {
+            const int a0 = __builtin_amdgcn_readlane(c0, i);
+            const int a1 = __builtin_amdgcn_readlane(c1, i);
+            const int ad = __builtin_amdgcn_readlane(dn, i);
+            if (a1 == a0) continue;
+            const int xx = base + i;
+            if (ad) {
+                if (bs < 0 || !dense_open) {
+                    if (lane == i) flags[a0] = 1;
+                    bs = a0;
+                    dense_open = true;
+                }
+                continue;
+            }
+            if (bs < 0 || dense_open || xx - xs >= span) {
+                if (lane == i) flags[a0] = 1;
+                bs = a0;
+                xs = xx;
+                dense_open = false;
+            }
+            while (a1 - bs > kWave) {
+                bs += kWave;
+                if (lane == i) flags[bs] = 1;
+                xs = xx;
+            }
+        }
+    }
 }
 
 __global__ void __launch_bounds__(256)
@@ -395,7 +431,7 @@ k_rowptr_scatter(const SetDesc* __restrict__ sets, const int* __restrict__ poffs
 // ---------------------------------------------------------------------------
 // Dense-cell path tables. Where clustering piles hundreds or thousands of particles
 // into a cell, every target of the cell tests the same stencil union, and its rows are
-// long. For such cells the search stages the union once per chunk for all the cell's
+// long. A cell is dense when its stencil holds more than a threshold of particles. For such cells the search stages the union once per chunk for all the cell's
 // targets, in ascending original index, so each row comes out sorted with no per-row
 // sort. The union lists come from one stable sort: every particle, visited in original
 // order, emits (dense cell, sorted position) for each dense cell whose stencil holds it.
@@ -415,8 +451,7 @@ struct CellXYZ {
     }
 };
 
-// One thread per x-window (at its first cell): stencil sizes of the window's occupied
-// cells, and whether any exceeds the threshold (then the whole window is dense).
+// Stencil size of every occupied cell; a cell is dense when it exceeds the threshold.
 template <int DIM>
 __global__ void __launch_bounds__(256)
 k_dense_cells(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nsets, int ncell_tot,
@@ -425,37 +460,26 @@ k_dense_cells(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, i
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ncell_tot) return;
     const SetDesc& sd = sets[find_set(coffs, nsets, g)];
-    const Frame& fr = sd.fr;
-    const int lk = g - sd.coff;
-    const CellXYZ c(fr, lk);
-    if (c.x % fr.xwin != 0) return;
+    const CellXYZ c(sd.fr, g - sd.coff);
     const int* cs = cell_start + sd.coff;
-    const int xe = min(c.x + fr.xwin, c.ncx);
-    bool any = false;
-    for (int xx = c.x; xx < xe; ++xx) {
-        const int l = lk + (xx - c.x);
-        int u = 0;
-        if (cs[l + 1] > cs[l]) {
-            const int x0 = xx > 0 ? xx - 1 : 0;
-            const int x1 = xx + 1 < c.ncx ? xx + 1 : c.ncx - 1;
-            for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz) {
-                const int zz = c.z + dz;
-                if (zz < 0 || zz >= c.ncz) continue;
-                for (int dy = -1; dy <= 1; ++dy) {
-                    const int yy = c.y + dy;
-                    if (yy < 0 || yy >= c.ncy) continue;
-                    const int rb = (zz * c.ncy + yy) * c.ncx;
-                    u += cs[rb + x1 + 1] - cs[rb + x0];
-                }
+    int u = 0;
+    if (cell_start[g + 1] > cell_start[g]) {
+        const int x0 = c.x > 0 ? c.x - 1 : 0;
+        const int x1 = c.x + 1 < c.ncx ? c.x + 1 : c.ncx - 1;
+        for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz) {
+            const int zz = c.z + dz;
+            if (zz < 0 || zz >= c.ncz) continue;
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int yy = c.y + dy;
+                if (yy < 0 || yy >= c.ncy) continue;
+                const int rb = (zz * c.ncy + yy) * c.ncx;
+                u += cs[rb + x1 + 1] - cs[rb + x0];
             }
         }
-        usz[g + (xx - c.x)] = u;
-        any = any || u > thresh;
     }
-    for (int xx = c.x; xx < xe; ++xx) {
-        wdense[g + (xx - c.x)] = any ? 1 : 0;
-        if (!any) usz[g + (xx - c.x)] = 0;
-    }
+    const bool dense = u > thresh;
+    usz[g] = dense ? u : 0;
+    wdense[g] = dense ? 1 : 0;
 }
 
 // After the scan of the stencil sizes: if the lists would not fit, the build falls back
@@ -658,11 +682,13 @@ hipError_t launch_blocks(const Launch& L, const uint32_t* skey, const int* cell_
                          int* bidx, int* bstart, int* bset, int64_t* partial, hipStream_t st)
 {
     if (L.ntot == 0) return launch_fill_i32(bidx, 1, 0, st);
-    const dim3 g((L.ntot + 255) / 256), b(256);
-    hipLaunchKernelGGL(k_block_flags, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, cell_start, wdense,
-                       flags);
-    hipError_t e = scan_exclusive<int, int>(flags, L.ntot, bidx, partial, st);
+    hipError_t e = launch_fill_i32(flags, L.ntot, 0, st);
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_row_blocks, dim3((L.nrows_tot + 3) / 4), dim3(256), 0, st, L.sets, L.roffs, L.nsets,
+                       L.nrows_tot, cell_start, wdense, flags);
+    e = scan_exclusive<int, int>(flags, L.ntot, bidx, partial, st);
+    if (e != hipSuccess) return e;
+    const dim3 g((L.ntot + 255) / 256), b(256);
     hipLaunchKernelGGL(k_block_write, g, b, 0, st, L.coffs, L.nsets, L.ntot, skey, flags, bidx, bstart, bset);
     return hipGetLastError();
 }

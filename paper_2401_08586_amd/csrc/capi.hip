@@ -214,7 +214,7 @@ struct nnps_cells {
     bool built = false, counted = false;
     int nsets = 0, dim = 0, mode = 0, ntot = 0, ncell_tot = 0, nblk_max = 0;
     std::vector<Frame> frames;
-    std::vector<int> offs;                // poffs[nsets + 1] then coffs[nsets + 1]
+    int nrows_tot = 0;                    // rows of cells (x-lines) of all sets
     std::vector<const double*> pos;
     SetDesc* h_sets = nullptr;            // pinned mirror of the set table
     int* h_offs = nullptr;                // pinned mirror of the offsets
@@ -263,7 +263,7 @@ nnps_status upload(nnps_cells* c, bool with_offsets, hipStream_t s)
 {
     HIP_TRY(hipMemcpyAsync(c->d_sets.p, c->h_sets, sizeof(SetDesc) * c->nsets, hipMemcpyHostToDevice, s));
     if (with_offsets)
-        HIP_TRY(hipMemcpyAsync(c->d_offs.p, c->h_offs, sizeof(int) * 2 * (c->nsets + 1), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(c->d_offs.p, c->h_offs, sizeof(int) * 3 * (c->nsets + 1), hipMemcpyHostToDevice, s));
     HIP_TRY(hipEventRecord(c->upload_done, s));
     c->upload_pending = true;
     return NNPS_OK;
@@ -280,6 +280,8 @@ Launch launch_of(const nnps_cells* c)
     L.sets = c->d_sets.as<SetDesc>();
     L.poffs = c->d_offs.as<int>();
     L.coffs = c->d_offs.as<int>() + c->nsets + 1;
+    L.roffs = c->d_offs.as<int>() + 2 * (c->nsets + 1);
+    L.nrows_tot = c->nrows_tot;
     return L;
 }
 
@@ -371,7 +373,7 @@ nnps_status prepare(nnps_ctx* ctx, nnps_cells* c, int nsets, const nnps_problem*
         c->h_cap = 0;
         if (hipHostMalloc(reinterpret_cast<void**>(&c->h_sets), sizeof(SetDesc) * nsets, hipHostMallocDefault) !=
                 hipSuccess ||
-            hipHostMalloc(reinterpret_cast<void**>(&c->h_offs), sizeof(int) * 2 * (nsets + 1),
+            hipHostMalloc(reinterpret_cast<void**>(&c->h_offs), sizeof(int) * 3 * (nsets + 1),
                           hipHostMallocDefault) != hipSuccess)
             return NNPS_ENOMEM;
         c->h_cap = nsets;
@@ -385,7 +387,11 @@ nnps_status prepare(nnps_ctx* ctx, nnps_cells* c, int nsets, const nnps_problem*
     c->ncell_tot = static_cast<int>(ncell);
     c->frames = frames;
     c->pos.assign(d_pos, d_pos + nsets);
-    int poff = 0, coff = 0;
+    const nnps_tuning& tu = ctx->tuning;
+    c->dense = tu.dense_min_union >= 0;
+    c->dthresh = tu.dense_min_union > 0 ? tu.dense_min_union : (c->dim == 3 ? kDenseUnion3 : kDenseUnion2);
+    const int64_t stencil = c->dim == 3 ? 27 : 9;
+    int poff = 0, coff = 0, roff = 0;
     int64_t nblk_bound = 0;
     for (int s = 0; s < nsets; ++s) {
         SetDesc& sd = c->h_sets[s];
@@ -396,24 +402,29 @@ nnps_status prepare(nnps_ctx* ctx, nnps_cells* c, int nsets, const nnps_problem*
         sd.pos = d_pos[s];
         c->h_offs[s] = poff;
         c->h_offs[nsets + 1 + s] = coff;
+        c->h_offs[2 * (nsets + 1) + s] = roff;
         const Frame& fr = frames[s];
         const int64_t nrows = static_cast<int64_t>(fr.nc[1]) * fr.nc[2];
-        const int64_t nwin = nrows * ((fr.nc[0] + fr.xwin - 1) / fr.xwin);
-        nblk_bound += std::min<int64_t>(fr.n, fr.n / kWave + nwin + 1);
+        // blocks: full ones, at most one per span of xwin cells and one per row ending
+        // early, and around each run of dense cells one marker plus one cut short
+        int64_t b = fr.n / kWave + nrows * ((fr.nc[0] + fr.xwin - 1) / fr.xwin + 1);
+        if (c->dense)
+            b += 2 * std::min<int64_t>(fr.ncell, stencil * fr.n / (static_cast<int64_t>(c->dthresh) + 1));
+        nblk_bound += std::min<int64_t>(fr.n, b);
         poff += fr.n;
         coff += fr.ncell;
+        roff += static_cast<int>(nrows);
     }
     c->h_offs[nsets] = poff;
     c->h_offs[2 * nsets + 1] = coff;
+    c->h_offs[3 * nsets + 2] = roff;
+    c->nrows_tot = roff;
     c->nblk_max = static_cast<int>(std::min<int64_t>(nblk_bound, ntot));
 
     const size_t n = static_cast<size_t>(ntot);
     const size_t nn = std::max<size_t>(n, 1);
     const size_t nc = static_cast<size_t>(ncell);
     // dense-cell path: list capacity min(3^d n, bound)
-    const nnps_tuning& tu = ctx->tuning;
-    c->dense = tu.dense_min_union >= 0;
-    c->dthresh = tu.dense_min_union > 0 ? tu.dense_min_union : (c->dim == 3 ? kDenseUnion3 : kDenseUnion2);
     c->dgrid = tu.dense_grid > 0 ? tu.dense_grid : kDenseGrid;
     const int64_t dmax = tu.dense_max_entries > 0 ? tu.dense_max_entries : kDenseMaxEntries;
     c->dcap = c->dense ? std::max<int64_t>(1, std::min<int64_t>((c->dim == 3 ? 27 : 9) * static_cast<int64_t>(nn), dmax))
@@ -430,7 +441,7 @@ nnps_status prepare(nnps_ctx* ctx, nnps_cells* c, int nsets, const nnps_problem*
         size_t bytes;
     } need[] = {
         {&c->d_sets, sizeof(SetDesc) * nsets},
-        {&c->d_offs, sizeof(int) * 2 * (nsets + 1)},
+        {&c->d_offs, sizeof(int) * 3 * (nsets + 1)},
         {&c->X, nn * x_stride(c->dim) * sizeof(int64_t)},
         {&c->k0, nn * 4}, {&c->k1, nn * 4}, {&c->v0, nn * 4}, {&c->v1, nn * 4},
         {&c->cell_count, (nc + 1) * 4}, {&c->cell_start, (nc + 1) * 4},

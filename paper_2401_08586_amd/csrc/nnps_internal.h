@@ -24,7 +24,7 @@ constexpr int kCandWords2 = 8;
 constexpr int kCandWords3 = 24;
 // Fixed-point positions are stored per particle, padded to a power of two of int64.
 __host__ __device__ constexpr int x_stride(int dim) { return dim == 3 ? 4 : 2; }
-// Largest x-window (cells) of a block; keeps staged cell offsets exact in FP16.
+// Largest x-span (cells) of a work block; keeps staged cell offsets exact in FP16.
 constexpr int kMaxXWin = 256;
 // Dense-cell path: candidates staged per chunk, targets per work unit (a workgroup of
 // four wavefronts, 64 targets each) and the default thresholds.
@@ -67,7 +67,7 @@ struct Frame {
     double s;           // 2^F / w
     double R2;          // fl(R*R)
     float dist_scale;   // (float)(w * 2^-F)
-    int xwin;           // blocks never cross a multiple of xwin cells along x
+    int xwin;           // largest x-span of a work block, in cells
     uint16_t t_lo, t_hi, t_mid;  // FP16 thresholds on r2 = 4|delta|^2 (bit patterns)
 };
 

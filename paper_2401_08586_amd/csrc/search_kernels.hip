@@ -1210,6 +1210,7 @@ k_dense(SearchArgs a)
     __shared__ long long sX[(FILL && F16) ? K * DIM : 1];  // fixed-point positions (distances)
     __shared__ int s_unit;
     __shared__ unsigned long long s_red[kDenseThreads / 64][kDenseStats];
+    __shared__ uint16_t squeue[FILL ? kDenseThreads / 64 : 1][FILL ? 192 : 1];  // per-wave emission queue
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const int nunits = *a.dn > 0 ? a.unit_off[a.L.ncell_tot] : 0;
@@ -1450,11 +1451,14 @@ k_dense(SearchArgs a)
                         }
                     }
                 }
-                if (!FILL) {
+                if constexpr (!FILL) {
                     const int tot = static_cast<int>(wave_sum_u64(static_cast<unsigned long long>(__builtin_popcount(inb))));
                     if (lane == k) acc_k += tot;
                 } else {
-                    // ascending emission: candidate order is original-index order
+                    // ascending emission: candidate order is original-index order. The
+                    // accepted candidates are queued in LDS in that order and written 64 at
+                    // a time, one per lane: every lane computes a distance and the stores
+                    // cover consecutive CSR slots.
                     const long long rs = rl64(rs_k, k);
                     const int rl = rl32(rl_k, k);
                     const int done = rl32(acc_k, k);
@@ -1463,47 +1467,58 @@ k_dense(SearchArgs a)
 #pragma unroll
                     for (int d = 0; d < 3; ++d) xi[d] = rl64(xi_k[d], k);
                     const double* pis = pi;
-                    int w = done;
+                    uint16_t* q = squeue[wv];
+                    int w = done;  // CSR entries of this row written so far
+                    int qn = 0;    // queued entries (wave-uniform)
+                    auto flush = [&](int cnt) {
+                        __builtin_amdgcn_wave_barrier();
+                        if (lane < cnt) {
+                            const int e = q[lane];
+                            const int slot = w + lane;
+                            if (slot < rl && room) {
+                                float dv;
+                                if (F16) {
+                                    float s2 = 0.0f;
+#pragma unroll
+                                    for (int d = 0; d < DIM; ++d) {
+                                        const float f = exact_i64_to_f32_s(sX[e * DIM + d] - xi[d]);
+                                        s2 = s2 + f * f;
+                                    }
+                                    dv = __builtin_amdgcn_sqrtf(s2) * dscale;
+                                } else {
+                                    dv = static_cast<float>(__dsqrt_rn(r2_fp64<DIM>(pis, spj + e * DIM)));
+                                }
+                                sd.col[rs + slot] = sorig[e] - poff;
+                                sd.dist[rs + slot] = dv;
+                            }
+                        }
+                        w += cnt;
+                    };
                     for (int it = 0; it < nit; ++it) {
                         uint32_t b2 = (inb >> (2 * it)) & 3u;
                         const int e0 = it * 128 + 2 * lane;
-                        int o0 = 0, o1 = 0;
-                        if (b2 & 1u) {
-                            o0 = sorig[e0];
-                            if (o0 == oi) b2 &= ~1u;
-                        }
-                        if (b2 & 2u) {
-                            o1 = sorig[e0 + 1];
-                            if (o1 == oi) b2 &= ~2u;
-                        }
+                        if ((b2 & 1u) && sorig[e0] == oi) b2 &= ~1u;
+                        if ((b2 & 2u) && sorig[e0 + 1] == oi) b2 &= ~2u;
                         const uint64_t B0 = __ballot(b2 & 1u);
                         const uint64_t B1 = __ballot((b2 >> 1) & 1u);
                         if ((B0 | B1) == 0) continue;
-                        const int pre = __popcll(B0 & lt) + __popcll(B1 & lt);
-#pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            if (!((b2 >> h) & 1u)) continue;
-                            const int slot = w + pre + (h == 1 ? static_cast<int>(b2 & 1u) : 0);
-                            if (slot >= rl || !room) continue;
-                            const int e = e0 + h;
-                            const int oj = h == 0 ? o0 : o1;
-                            float dv;
-                            if (F16) {
-                                float s2 = 0.0f;
-#pragma unroll
-                                for (int d = 0; d < DIM; ++d) {
-                                    const float f = exact_i64_to_f32_s(sX[e * DIM + d] - xi[d]);
-                                    s2 = s2 + f * f;
-                                }
-                                dv = __builtin_amdgcn_sqrtf(s2) * dscale;
-                            } else {
-                                dv = static_cast<float>(__dsqrt_rn(r2_fp64<DIM>(pis, spj + e * DIM)));
-                            }
-                            sd.col[rs + slot] = oj - poff;
-                            sd.dist[rs + slot] = dv;
+                        const int pre = qn + __popcll(B0 & lt) + __popcll(B1 & lt);
+                        if (b2 & 1u) q[pre] = static_cast<uint16_t>(e0);
+                        if (b2 & 2u) q[pre + (b2 & 1u)] = static_cast<uint16_t>(e0 + 1);
+                        qn += __popcll(B0) + __popcll(B1);
+                        while (qn >= 64) {
+                            flush(64);
+                            qn -= 64;
+                            __builtin_amdgcn_wave_barrier();
+                            const int mv = lane < qn ? q[64 + lane] : 0;
+                            const int mv2 = lane + 64 < qn ? q[128 + lane] : 0;
+                            __builtin_amdgcn_wave_barrier();
+                            if (lane < qn) q[lane] = static_cast<uint16_t>(mv);
+                            if (lane + 64 < qn) q[64 + lane] = static_cast<uint16_t>(mv2);
                         }
-                        w += __popcll(B0) + __popcll(B1);
                     }
+                    if (qn > 0) flush(qn);
+                    __builtin_amdgcn_wave_barrier();
                     if (!room && lane == 0 && w > done) atomicOr(a.err, kErrCapacity);
                     if (lane == k) acc_k = w;
                 }
