@@ -85,6 +85,7 @@ struct SearchArgs {
     int64_t lrscratch_words;        // its size per workgroup (32-bit words)
     int lr_keys;                    // keys a long-row workgroup sorts in LDS
     int* err;
+    int* sink;                      // [2 * 64] per-lane dummy output slots
     // dense-cell path (wdense == nullptr: off)
     const int* wdense;
     const int* usz;

@@ -225,7 +225,7 @@ struct nnps_cells {
     uint32_t* skey = nullptr;
     int* perm = nullptr;
     DevBuf d_sets, d_offs, X, k0, k1, v0, v1, cell_count, cell_start, q4, spos, flags, bidx, bstart, bset,
-        counts, table, partial, stats, blk_stats, cbits, err, heavy, nheavy, rowg, nnz;
+        counts, table, partial, stats, blk_stats, cbits, err, heavy, nheavy, rowg, nnz, sink;
     // dense-cell path (see DenseBuild)
     bool dense = false;
     int dthresh = 0, dgrid = 0;
@@ -308,6 +308,7 @@ SearchArgs args_of(const nnps_cells* c)
     while (keys * 2 <= std::min(c->ctx->max_lds - 1024, 64 * 1024) / 4) keys *= 2;
     a.lr_keys = c->ctx->tuning.long_rows_keys > 0 ? std::min(c->ctx->tuning.long_rows_keys, keys) : keys;
     a.err = c->err.as<int>();
+    a.sink = c->sink.as<int>();
     if (c->dense) {
         a.wdense = c->wdense.as<int>();
         a.usz = c->usz.as<int>();
@@ -454,7 +455,7 @@ nnps_status prepare(nnps_ctx* ctx, nnps_cells* c, int nsets, const nnps_problem*
         {&c->stats, kStCount * 8},
         {&c->blk_stats, static_cast<size_t>(std::max(c->nblk_max, 1)) * 5 * 8},
         {&c->cbits, nn * cw * 4},
-        {&c->err, 4}, {&c->heavy, nn * 4}, {&c->nheavy, 4},
+        {&c->err, 4}, {&c->heavy, nn * 4}, {&c->nheavy, 4}, {&c->sink, 2 * 64 * 4},
         {&c->rowg, (nn + 1) * 8},
         {&c->nnz, sizeof(int64_t) * nsets},
         {&c->usz, c->dense ? (nc + 1) * 4 : 0}, {&c->wdense, c->dense ? (nc + 1) * 4 : 0},
@@ -713,7 +714,7 @@ void nnps_cells_destroy(nnps_cells* c)
     DevBuf* all[] = {&c->d_sets, &c->d_offs, &c->X, &c->k0, &c->k1, &c->v0, &c->v1, &c->cell_count,
                      &c->cell_start, &c->q4, &c->spos, &c->flags, &c->bidx, &c->bstart, &c->bset, &c->counts,
                      &c->table, &c->partial, &c->stats, &c->blk_stats, &c->cbits, &c->err, &c->heavy,
-                     &c->nheavy, &c->rowg, &c->nnz, &c->usz, &c->wdense, &c->uoff, &c->nsl, &c->unit_off,
+                     &c->nheavy, &c->rowg, &c->nnz, &c->sink, &c->usz, &c->wdense, &c->uoff, &c->nsl, &c->unit_off,
                      &c->ucell, &c->dn, &c->ecnt, &c->epos, &c->uk0, &c->uk1, &c->uv0, &c->uv1, &c->inv,
                      &c->ucount, &c->dstats};
     for (DevBuf* b : all) b->release();

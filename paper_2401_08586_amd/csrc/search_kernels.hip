@@ -176,6 +176,39 @@ struct Geom {
     }
 };
 
+// The fields of a set a kernel uses in its loops, read once into registers. Read through
+// the set table instead, they would be loaded again after every store (the compiler
+// cannot tell the stores from the table), each time waiting on memory. The outputs are
+// global-address-space pointers, so their stores are plain global stores.
+#define NNPS_GLOBAL __attribute__((address_space(1)))
+struct SetView {
+    const NNPS_GLOBAL double* pos;
+    const NNPS_GLOBAL int64_t* row_ptr;
+    NNPS_GLOBAL int32_t* col;
+    NNPS_GLOBAL float* dist;
+    int64_t capacity;
+    int poff;
+    __device__ __forceinline__ explicit SetView(const SetDesc& sd)
+        : pos((const NNPS_GLOBAL double*)sd.pos),
+          row_ptr((const NNPS_GLOBAL int64_t*)sd.row_ptr),
+          col((NNPS_GLOBAL int32_t*)sd.col),
+          dist((NNPS_GLOBAL float*)sd.dist),
+          capacity(sd.capacity),
+          poff(sd.poff)
+    {
+    }
+};
+
+template <int DIM>
+__device__ __forceinline__ bool recheck_g(const NNPS_GLOBAL double* __restrict__ pos, const double* pi, int oj,
+                                          double R2)
+{
+    double pj[3];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) pj[k] = pos[static_cast<size_t>(oj) * DIM + k];
+    return r2_fp64<DIM>(pi, pj) <= R2;
+}
+
 // Blocks of the dense-cell path's windows are left to that path.
 __device__ __forceinline__ bool dense_block(const SearchArgs& a, int b)
 {
@@ -786,7 +819,7 @@ k_fill(SearchArgs a)
     Geom<DIM> g;
     g.init(a, b);
     const Frame& fr = g.fr;
-    const SetDesc& sd = *g.sd;
+    const SetView sd(*g.sd);
     const int pp = g.active ? g.p : g.p1 - 1;
     const int oi = a.perm[pp];
     const int li = oi - sd.poff;
@@ -897,21 +930,27 @@ k_fill(SearchArgs a)
     }
     __syncthreads();
     // Emission, 64 entries per round. The next round's gathers are issued before this
-    // round's stores: vector-memory counters order loads and stores together, so a load
-    // issued after a store would wait for that store.
+    // round's stores, and every round issues the same memory instructions on every path:
+    // lanes past the list (or past the output capacity) gather particle 0 and store to a
+    // per-lane sink slot. Vector-memory counters count loads and stores in issue order,
+    // so with a fixed instruction count the wait for the prefetch need not include the
+    // previous round's stores.
     struct Ent {
         int t, oj;
         long long idx;
         long long xj[DIM];
     };
+    const int64_t cap = sd.capacity;
+    NNPS_GLOBAL int32_t* sink_col = (NNPS_GLOBAL int32_t*)a.sink + 2 * lane;
+    NNPS_GLOBAL float* sink_dist = (NNPS_GLOBAL float*)(a.sink + 2 * lane + 1);
     auto fetch = [&](int e, int tstart, Ent& s) {
-        s.t = tstart;
-        if (e >= E) return;
+        const bool ok = e < E;
         int t = tstart;
-        while (soff[t + 1] <= e) ++t;  // rows are short: a few steps at most
+        if (ok)
+            while (soff[t + 1] <= e) ++t;  // rows are short: a few steps at most
         s.t = t;
-        s.oj = sorig[flat_rank[e]];
-        s.idx = srow[t] + (e - soff[t]);
+        s.oj = ok ? sorig[flat_rank[e]] : sd.poff;
+        s.idx = ok ? srow[t] + (e - soff[t]) : -1;
 #pragma unroll
         for (int c = 0; c < DIM; ++c)
             s.xj[c] = MODE == 1 ? __builtin_bit_cast(long long, sd.pos[static_cast<size_t>(s.oj - sd.poff) * DIM + c])
@@ -923,32 +962,30 @@ k_fill(SearchArgs a)
         Ent nxt;
         const int tn = __shfl(cur.t, 63, 64);
         fetch(e0 + 64 + lane, tn, nxt);
-        if (e0 + lane < E) {
-            float d;
-            if constexpr (MODE == 1) {
-                double pi2[3], pj2[3];
+        float d;
+        if constexpr (MODE == 1) {
+            double pi2[3], pj2[3];
 #pragma unroll
-                for (int c = 0; c < DIM; ++c) {
-                    pi2[c] = __builtin_bit_cast(double, sxi[cur.t * DIM + c]);
-                    pj2[c] = __builtin_bit_cast(double, cur.xj[c]);
-                }
-                d = static_cast<float>(__dsqrt_rn(r2_fp64<DIM>(pi2, pj2)));
-            } else {
-                float s2 = 0.0f;
+            for (int c = 0; c < DIM; ++c) {
+                pi2[c] = __builtin_bit_cast(double, sxi[cur.t * DIM + c]);
+                pj2[c] = __builtin_bit_cast(double, cur.xj[c]);
+            }
+            d = static_cast<float>(__dsqrt_rn(r2_fp64<DIM>(pi2, pj2)));
+        } else {
+            float s2 = 0.0f;
 #pragma unroll
-                for (int c = 0; c < DIM; ++c) {
-                    const float f = exact_i64_to_f32_s(cur.xj[c] - sxi[cur.t * DIM + c]);
-                    s2 = s2 + f * f;
-                }
-                d = __builtin_amdgcn_sqrtf(s2) * fr.dist_scale;  // <= 1 ulp; s2 >= 1 or 0
+            for (int c = 0; c < DIM; ++c) {
+                const float f = exact_i64_to_f32_s(cur.xj[c] - sxi[cur.t * DIM + c]);
+                s2 = s2 + f * f;
             }
-            if (cur.idx < sd.capacity) {
-                sd.col[cur.idx] = cur.oj - sd.poff;
-                sd.dist[cur.idx] = d;
-            } else {
-                atomicOr(a.err, kErrCapacity);
-            }
+            d = __builtin_amdgcn_sqrtf(s2) * fr.dist_scale;  // <= 1 ulp; s2 >= 1 or 0
         }
+        const bool valid = cur.idx >= 0 && cur.idx < cap;
+        if (cur.idx >= cap) atomicOr(a.err, kErrCapacity);
+        NNPS_GLOBAL int32_t* pc = valid ? sd.col + cur.idx : sink_col;
+        NNPS_GLOBAL float* pd = valid ? sd.dist + cur.idx : sink_dist;
+        *pc = cur.oj - sd.poff;
+        *pd = d;
         cur = nxt;
     }
 }
@@ -974,12 +1011,14 @@ k_long(SearchArgs a)
     for (int h = blockIdx.x; h < nh; h += gridDim.x) {
         const int p = a.heavy[h];
         const uint32_t gkey = a.skey[p];
-        const SetDesc& sd = a.L.sets[find_set(a.L.coffs, a.L.nsets, static_cast<int>(gkey))];
-        const Frame& fr = sd.fr;
-        const int* cs = a.cell_start + sd.coff;
+        const SetDesc& sdesc = a.L.sets[find_set(a.L.coffs, a.L.nsets, static_cast<int>(gkey))];
+        const Frame fr = sdesc.fr;
+        const int* cs = a.cell_start + sdesc.coff;
+        const uint32_t scoff = static_cast<uint32_t>(sdesc.coff);
+        const SetView sd(sdesc);
         const uint32_t ncx = static_cast<uint32_t>(fr.nc[0]);
         const int ncy = fr.nc[1], ncz = fr.nc[2];
-        const uint32_t key = gkey - static_cast<uint32_t>(sd.coff);
+        const uint32_t key = gkey - scoff;
         const uint32_t row = key / ncx;
         const int x = static_cast<int>(key - row * ncx);
         const int y0 = static_cast<int>(row % static_cast<uint32_t>(ncy));
@@ -995,7 +1034,7 @@ k_long(SearchArgs a)
         if (threadIdx.x == 0) fill = 0;
         __syncthreads();
         const bool room = rs + rlen <= sd.capacity;
-        int32_t* col = sd.col + rs;
+        NNPS_GLOBAL int32_t* col = sd.col + rs;
         // 1. test every candidate; append accepted set-local indices in any order
         constexpr int NSEG = DIM == 3 ? 9 : 3;
         const int lx0 = x > 0 ? x - 1 : 0;
@@ -1016,7 +1055,7 @@ k_long(SearchArgs a)
                     nb = r2_fp64<DIM>(a.spos + static_cast<size_t>(p) * 4, a.spos + static_cast<size_t>(j) * 4) <= fr.R2;
                 } else {
                     const ushort4 v = a.q4[j];
-                    const uint32_t kj = a.skey[j] - static_cast<uint32_t>(sd.coff);
+                    const uint32_t kj = a.skey[j] - scoff;
                     const int cjx = static_cast<int>(kj - (kj / ncx) * ncx);
                     const _Float16 s = as_f16(qi.x) - as_f16(v.x);
                     const _Float16 tx = s + static_cast<_Float16>(2 * (x - cjx));
@@ -1033,7 +1072,7 @@ k_long(SearchArgs a)
                     const uint16_t r2h = __builtin_bit_cast(uint16_t, r2);
                     const bool in16 = r2h < fr.t_lo;
                     const bool band = !in16 && r2h <= fr.t_hi;
-                    nb = (MODE == 2 || band) ? recheck<DIM>(sd.pos, pi, oj - sd.poff, fr.R2) : in16;
+                    nb = (MODE == 2 || band) ? recheck_g<DIM>(sd.pos, pi, oj - sd.poff, fr.R2) : in16;
                 }
                 if (nb) {
                     const int slot = atomicAdd(&fill, 1);
@@ -1081,8 +1120,8 @@ k_long(SearchArgs a)
         }
         // merge sorted runs of width K, 2K, ... between the column slots and the
         // distance slots (reinterpreted as 32-bit keys)
-        uint32_t* src = reinterpret_cast<uint32_t*>(col);
-        uint32_t* dst = reinterpret_cast<uint32_t*>(sd.dist + rs);
+        NNPS_GLOBAL uint32_t* src = (NNPS_GLOBAL uint32_t*)col;
+        NNPS_GLOBAL uint32_t* dst = (NNPS_GLOBAL uint32_t*)(sd.dist + rs);
         for (int width = K; width < L; width <<= 1) {
             for (int e = threadIdx.x; e < L; e += T) {
                 const int run = e / width;
@@ -1103,18 +1142,18 @@ k_long(SearchArgs a)
                 dst[base + own + cnt] = v;
             }
             __syncthreads();
-            uint32_t* tmp = src;
+            NNPS_GLOBAL uint32_t* tmp = src;
             src = dst;
             dst = tmp;
         }
-        if (src != reinterpret_cast<uint32_t*>(col)) {
+        if (src != (NNPS_GLOBAL uint32_t*)col) {
             for (int e = threadIdx.x; e < L; e += T) col[e] = static_cast<int32_t>(src[e]);
             __syncthreads();
         }
         // 3. distances of the sorted row
         for (int e = threadIdx.x; e < L; e += T) {
             const int lj = col[e];
-            sd.dist[rs + e] = MODE == 1 ? dist_fp64<DIM>(sd.pos, li, lj)
+            sd.dist[rs + e] = MODE == 1 ? dist_fp64<DIM>(sdesc.pos, li, lj)
                                         : dist_fixed<DIM>(a.X, oi, lj + sd.poff, fr.dist_scale);
         }
         __syncthreads();
@@ -1223,21 +1262,23 @@ k_dense(SearchArgs a)
         if (u >= nunits) break;
         const int g = a.ucell[u];
         const int slice = u - a.unit_off[g];
-        const SetDesc& sd = a.L.sets[find_set(a.L.coffs, a.L.nsets, g)];
+        const SetDesc& sdesc = a.L.sets[find_set(a.L.coffs, a.L.nsets, g)];
+        const SetView sd(sdesc);
         const int poff = sd.poff;
-        const double R2 = sd.fr.R2;
-        const float dscale = sd.fr.dist_scale;
-        const int ncx = sd.fr.nc[0], ncy = sd.fr.nc[1];
-        const uint32_t coff = static_cast<uint32_t>(sd.coff);
-        const int lk = g - sd.coff;
+        const double R2 = sdesc.fr.R2;
+        const float dscale = sdesc.fr.dist_scale;
+        const int ncx = sdesc.fr.nc[0], ncy = sdesc.fr.nc[1];
+        const uint32_t coff = static_cast<uint32_t>(sdesc.coff);
+        const int lk = g - sdesc.coff;
         const int cx = lk % ncx, crow = lk / ncx, cy = crow % ncy, cz = crow / ncy;
         const int t0 = a.cell_start[g] + slice * kDenseSlice;
         const int t1 = min(a.cell_start[g + 1], t0 + kDenseSlice);
         const int U = a.usz[g];
         const int64_t ub = a.uoff[g];
         Thresh th;
-        th.init(sd.fr);
-        const uint16_t tmid = sd.fr.t_mid;
+        th.init(sdesc.fr);
+        const uint16_t tmid = sdesc.fr.t_mid;
+        const uint16_t tlo = sdesc.fr.t_lo;
         // this lane's target (held for the wavefront)
         const int pk = t0 + wv + 4 * lane;
         const bool vk = pk < t1;
@@ -1389,7 +1430,7 @@ k_dense(SearchArgs a)
                         const int e = (bb >> 1) * 128 + 2 * lane + (bb & 1);
                         const int oj = sorig[e];
                         if (oj == oi) continue;
-                        const bool truth = recheck<DIM>(sd.pos, pi, oj - poff, R2);
+                        const bool truth = recheck_g<DIM>(sd.pos, pi, oj - poff, R2);
                         if (truth) dec |= 1u << bb;
                         if (!FILL) {
                             const bool band = (bnd >> bb) & 1u;
@@ -1426,7 +1467,7 @@ k_dense(SearchArgs a)
                         const int e = (bb >> 1) * 128 + 2 * lane + (bb & 1);
                         const int oj = sorig[e];
                         if (oj == oi) continue;  // itself (a band pair only when T_lo = 0)
-                        const bool truth = recheck<DIM>(sd.pos, pi, oj - poff, R2);
+                        const bool truth = recheck_g<DIM>(sd.pos, pi, oj - poff, R2);
                         if (truth) inb |= 1u << bb;
                         if (!FILL) {
                             const uint4 A = recA[e >> 1];
@@ -1528,7 +1569,7 @@ k_dense(SearchArgs a)
             if (!FILL) {
                 // itself: "in" in FP16 when T_lo > 0, always in the FP64 baseline; never
                 // counted when every candidate is decided in FP64 (it is skipped there)
-                const int self = MODE == 1 ? 1 : (MODE == 2 ? 0 : (sd.fr.t_lo > 0 ? 1 : 0));
+                const int self = MODE == 1 ? 1 : (MODE == 2 ? 0 : (tlo > 0 ? 1 : 0));
                 a.counts[oi_k] = acc_k - self;
             } else if (acc_k != rl_k) {
                 atomicOr(a.err, kErrLongRow);
