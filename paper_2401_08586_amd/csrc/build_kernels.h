@@ -53,7 +53,10 @@ struct DenseBuild {
     int *uv0, *uv1;         // [cap] sort values (sorted position)
     uint32_t* table;        // radix scratch
     int64_t* partial;       // scan scratch
+    int* seen;              // [1] set to 1 when any cell is dense
 };
+// Stencil sizes and the dense flag only (the path is not used by this build).
+hipError_t launch_dense_detect(const Launch& L, const int* cell_start, const DenseBuild& d, hipStream_t st);
 // Before the block table: stencil sizes, dense windows, union offsets and work units.
 hipError_t launch_dense_cells(const Launch& L, const int* cell_start, const DenseBuild& d, hipStream_t st);
 // After the sort and pack: the union lists. *ulist receives the sorted list array.

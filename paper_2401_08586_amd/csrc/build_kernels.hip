@@ -455,7 +455,8 @@ struct CellXYZ {
 template <int DIM>
 __global__ void __launch_bounds__(256)
 k_dense_cells(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nsets, int ncell_tot,
-              const int* __restrict__ cell_start, int thresh, int* __restrict__ usz, int* __restrict__ wdense)
+              const int* __restrict__ cell_start, int thresh, int* __restrict__ usz, int* __restrict__ wdense,
+              int* __restrict__ seen)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ncell_tot) return;
@@ -480,6 +481,7 @@ k_dense_cells(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, i
     const bool dense = u > thresh;
     usz[g] = dense ? u : 0;
     wdense[g] = dense ? 1 : 0;
+    if (dense) *seen = 1;  // every writer writes the same value
 }
 
 // After the scan of the stencil sizes: if the lists would not fit, the build falls back
@@ -693,17 +695,28 @@ hipError_t launch_blocks(const Launch& L, const uint32_t* skey, const int* cell_
     return hipGetLastError();
 }
 
+hipError_t launch_dense_detect(const Launch& L, const int* cell_start, const DenseBuild& d, hipStream_t st)
+{
+    const int nc = L.ncell_tot;
+    hipError_t e = launch_fill_i32(d.seen, 1, 0, st);
+    if (e != hipSuccess) return e;
+    const dim3 g((nc + 255) / 256), b(256);
+    if (L.dim == 2)
+        hipLaunchKernelGGL(k_dense_cells<2>, g, b, 0, st, L.sets, L.coffs, L.nsets, nc, cell_start, d.thresh, d.usz,
+                           d.wdense, d.seen);
+    else
+        hipLaunchKernelGGL(k_dense_cells<3>, g, b, 0, st, L.sets, L.coffs, L.nsets, nc, cell_start, d.thresh, d.usz,
+                           d.wdense, d.seen);
+    return hipGetLastError();
+}
+
 hipError_t launch_dense_cells(const Launch& L, const int* cell_start, const DenseBuild& d, hipStream_t st)
 {
     const int nc = L.ncell_tot;
     const dim3 g((nc + 255) / 256), b(256);
-    if (L.dim == 2)
-        hipLaunchKernelGGL(k_dense_cells<2>, g, b, 0, st, L.sets, L.coffs, L.nsets, nc, cell_start, d.thresh, d.usz,
-                           d.wdense);
-    else
-        hipLaunchKernelGGL(k_dense_cells<3>, g, b, 0, st, L.sets, L.coffs, L.nsets, nc, cell_start, d.thresh, d.usz,
-                           d.wdense);
-    hipError_t e = scan_exclusive<int, int64_t>(d.usz, nc, d.uoff, d.partial, st);
+    hipError_t e = launch_dense_detect(L, cell_start, d, st);
+    if (e != hipSuccess) return e;
+    e = scan_exclusive<int, int64_t>(d.usz, nc, d.uoff, d.partial, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_dense_units, dim3((nc + 256) / 256), b, 0, st, nc, cell_start, d.uoff, d.cap, d.usz,
                        d.wdense, d.nsl, d.dn);

@@ -227,11 +227,13 @@ struct nnps_cells {
     DevBuf d_sets, d_offs, X, k0, k1, v0, v1, cell_count, cell_start, q4, spos, flags, bidx, bstart, bset,
         counts, table, partial, stats, blk_stats, cbits, err, heavy, nheavy, rowg, nnz, sink;
     // dense-cell path (see DenseBuild)
-    bool dense = false;
+    bool dense = false;         // the tuning allows the dense-cell path
+    bool dense_active = false;  // the last build uses it
+    int dense_seen = -1;        // dense cells at the last synchronising call: -1 unknown, 0, 1
     int dthresh = 0, dgrid = 0;
     int64_t dcap = 0;
     int* ulist = nullptr;
-    DevBuf usz, wdense, uoff, nsl, unit_off, ucell, dn, ecnt, epos, uk0, uk1, uv0, uv1, inv, ucount, dstats;
+    DevBuf usz, wdense, uoff, nsl, unit_off, ucell, dn, ecnt, epos, uk0, uk1, uv0, uv1, inv, ucount, dstats, dseen;
 };
 
 #define HIP_TRY(x)                                  \
@@ -309,7 +311,7 @@ SearchArgs args_of(const nnps_cells* c)
     a.lr_keys = c->ctx->tuning.long_rows_keys > 0 ? std::min(c->ctx->tuning.long_rows_keys, keys) : keys;
     a.err = c->err.as<int>();
     a.sink = c->sink.as<int>();
-    if (c->dense) {
+    if (c->dense_active) {
         a.wdense = c->wdense.as<int>();
         a.usz = c->usz.as<int>();
         a.uoff = c->uoff.as<int64_t>();
@@ -344,6 +346,7 @@ DenseBuild dense_of(nnps_cells* c)
     d.uv1 = c->uv1.as<int>();
     d.table = c->table.as<uint32_t>();
     d.partial = c->partial.as<int64_t>();
+    d.seen = c->dseen.as<int>();
     return d;
 }
 
@@ -465,6 +468,7 @@ nnps_status prepare(nnps_ctx* ctx, nnps_cells* c, int nsets, const nnps_problem*
         {&c->uk0, dcap * 4}, {&c->uk1, dcap * 4}, {&c->uv0, dcap * 4}, {&c->uv1, dcap * 4},
         {&c->inv, c->dense ? nn * 4 : 0}, {&c->ucount, c->dense ? size_t(4) : size_t(0)},
         {&c->dstats, c->dense ? static_cast<size_t>(c->dgrid) * kDenseStats * 8 : 0},
+        {&c->dseen, c->dense ? size_t(4) : size_t(0)},
     };
     for (auto& q : need) {
         if (q.bytes == 0) continue;
@@ -508,15 +512,22 @@ nnps_status enqueue_build(nnps_cells* c, hipStream_t s)
                         c->mode == NNPS_MODE_FP64_BASELINE ? c->spos.as<double>() : nullptr,
                         c->dense ? c->inv.as<int>() : nullptr, s));
     tm.end(NNPS_PHASE_PACK, s);
+    // The dense-cell path runs unless the last synchronising call saw no dense cell; the
+    // stencil sizes are computed either way, so a change is seen at the next such call.
+    c->dense_active = c->dense && c->dense_seen != 0;
     if (c->dense) {
         tm.begin(NNPS_PHASE_UNIONS, s);
         const DenseBuild d = dense_of(c);
-        HIP_TRY(launch_dense_cells(L, c->cell_start.as<int>(), d, s));
-        HIP_TRY(launch_dense_unions(L, c->skey, c->inv.as<int>(), d, s, &c->ulist));
+        if (c->dense_active) {
+            HIP_TRY(launch_dense_cells(L, c->cell_start.as<int>(), d, s));
+            HIP_TRY(launch_dense_unions(L, c->skey, c->inv.as<int>(), d, s, &c->ulist));
+        } else {
+            HIP_TRY(launch_dense_detect(L, c->cell_start.as<int>(), d, s));
+        }
         tm.end(NNPS_PHASE_UNIONS, s);
     }
     tm.begin(NNPS_PHASE_BLOCKS, s);
-    HIP_TRY(launch_blocks(L, c->skey, c->cell_start.as<int>(), c->dense ? c->wdense.as<int>() : nullptr,
+    HIP_TRY(launch_blocks(L, c->skey, c->cell_start.as<int>(), c->dense_active ? c->wdense.as<int>() : nullptr,
                           c->flags.as<int>(), c->bidx.as<int>(), c->bstart.as<int>(), c->bset.as<int>(),
                           c->partial.as<int64_t>(), s));
     tm.end(NNPS_PHASE_BLOCKS, s);
@@ -533,7 +544,7 @@ nnps_status enqueue_count(nnps_cells* c, hipStream_t s)
     c->timer.begin(NNPS_PHASE_COUNT, s);
     HIP_TRY(launch_count(a, c->nblk_max, s));
     c->timer.end(NNPS_PHASE_COUNT, s);
-    if (c->dense) {
+    if (c->dense_active) {
         c->timer.begin(NNPS_PHASE_DCOUNT, s);
         HIP_TRY(launch_dense(a, false, s));
         c->timer.end(NNPS_PHASE_DCOUNT, s);
@@ -557,7 +568,7 @@ nnps_status enqueue_fill(nnps_cells* c, hipStream_t s)
     c->timer.begin(NNPS_PHASE_LONGROWS, s);
     HIP_TRY(launch_long_rows(a, c->ctx->tuning.long_rows_grid, s));
     c->timer.end(NNPS_PHASE_LONGROWS, s);
-    if (c->dense) {
+    if (c->dense_active) {
         c->timer.begin(NNPS_PHASE_DFILL, s);
         HIP_TRY(launch_dense(a, true, s));
         c->timer.end(NNPS_PHASE_DFILL, s);
@@ -586,9 +597,11 @@ nnps_status read_nnz(nnps_cells* c, int64_t* h_nnz, hipStream_t s)
         const int k = std::min(63, c->nsets - s0);
         HIP_TRY(hipMemcpyAsync(hp, c->nnz.as<int64_t>() + s0, 8 * k, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(hp + 63, c->err.p, 4, hipMemcpyDeviceToHost, s));
+        if (c->dense) HIP_TRY(hipMemcpyAsync(reinterpret_cast<int*>(hp + 63) + 1, c->dseen.p, 4, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         for (int i = 0; i < k; ++i) h_nnz[s0 + i] = hp[i];
         st = err_status(static_cast<int>(hp[63] & 0xFFFFFFFF));
+        if (c->dense) c->dense_seen = reinterpret_cast<int*>(hp + 63)[1] != 0 ? 1 : 0;
     }
     return st;
 }
@@ -716,7 +729,7 @@ void nnps_cells_destroy(nnps_cells* c)
                      &c->table, &c->partial, &c->stats, &c->blk_stats, &c->cbits, &c->err, &c->heavy,
                      &c->nheavy, &c->rowg, &c->nnz, &c->sink, &c->usz, &c->wdense, &c->uoff, &c->nsl, &c->unit_off,
                      &c->ucell, &c->dn, &c->ecnt, &c->epos, &c->uk0, &c->uk1, &c->uv0, &c->uv1, &c->inv,
-                     &c->ucount, &c->dstats};
+                     &c->ucount, &c->dstats, &c->dseen};
     for (DevBuf* b : all) b->release();
     c->timer.release();
     c->graph.reset();
@@ -866,7 +879,7 @@ nnps_status nnps_batch_step(nnps_ctx* ctx, nnps_cells* c, int32_t nsets, const n
     }
     // the graph depends on the sizes (grids), the device buffers and the tuning; the
     // per-set pointers travel in the uploaded set table
-    std::vector<unsigned char> sig(sizeof(nnps_problem) * nsets + sizeof(uint64_t) + sizeof(nnps_tuning) + 4);
+    std::vector<unsigned char> sig(sizeof(nnps_problem) * nsets + sizeof(uint64_t) + sizeof(nnps_tuning) + 8);
     unsigned char* q = sig.data();
     memcpy(q, probs, sizeof(nnps_problem) * nsets);
     q += sizeof(nnps_problem) * nsets;
@@ -875,6 +888,9 @@ nnps_status nnps_batch_step(nnps_ctx* ctx, nnps_cells* c, int32_t nsets, const n
     memcpy(q, &ctx->tuning, sizeof(nnps_tuning));
     q += sizeof(nnps_tuning);
     memcpy(q, &nsets, 4);
+    q += 4;
+    const int dense_plan = c->dense && c->dense_seen != 0 ? 1 : 0;
+    memcpy(q, &dense_plan, 4);
     (void)gen0;
     if (!c->graph.exec || c->graph.sig != sig) {
         c->graph.reset();
@@ -940,8 +956,10 @@ nnps_status nnps_stats_get(nnps_cells* c, nnps_stats* out, void* stream)
     out->heavy_rows = nh;
     out->dense_rows = static_cast<int64_t>(st[kStDenseRows]);
     if (c->dense) {
-        int dn = 0;
-        HIP_TRY(hipMemcpy(&dn, c->dn.p, 4, hipMemcpyDeviceToHost));
+        int dn = 0, seen = 0;
+        HIP_TRY(hipMemcpy(&seen, c->dseen.p, 4, hipMemcpyDeviceToHost));
+        c->dense_seen = seen != 0 ? 1 : 0;
+        if (c->dense_active) HIP_TRY(hipMemcpy(&dn, c->dn.p, 4, hipMemcpyDeviceToHost));
         out->dense_entries = dn;
     }
     out->dim = c->dim;

@@ -929,7 +929,7 @@ k_fill(SearchArgs a)
         if (got != rlen) atomicOr(a.err, kErrLongRow);
     }
     __syncthreads();
-    // Emission, 64 entries per round. The next round's gathers are issued before this
+    // Emission, 64 entries per round. Later rounds' gathers are issued before this
     // round's stores, and every round issues the same memory instructions on every path:
     // lanes past the list (or past the output capacity) gather particle 0 and store to a
     // per-lane sink slot. Vector-memory counters count loads and stores in issue order,
@@ -956,12 +956,14 @@ k_fill(SearchArgs a)
             s.xj[c] = MODE == 1 ? __builtin_bit_cast(long long, sd.pos[static_cast<size_t>(s.oj - sd.poff) * DIM + c])
                                 : a.X[static_cast<size_t>(s.oj) * x_stride(DIM) + c];
     };
-    Ent cur;
+    // three rounds in flight: a round's gathers are issued three rounds before its use
+    Ent cur, n1, n2;
     fetch(lane, 0, cur);
+    fetch(64 + lane, __shfl(cur.t, 63, 64), n1);
+    fetch(128 + lane, __shfl(n1.t, 63, 64), n2);
     for (int e0 = 0; e0 < E; e0 += 64) {
-        Ent nxt;
-        const int tn = __shfl(cur.t, 63, 64);
-        fetch(e0 + 64 + lane, tn, nxt);
+        Ent n3;
+        fetch(e0 + 192 + lane, __shfl(n2.t, 63, 64), n3);
         float d;
         if constexpr (MODE == 1) {
             double pi2[3], pj2[3];
@@ -986,7 +988,9 @@ k_fill(SearchArgs a)
         NNPS_GLOBAL float* pd = valid ? sd.dist + cur.idx : sink_dist;
         *pc = cur.oj - sd.poff;
         *pd = d;
-        cur = nxt;
+        cur = n1;
+        n1 = n2;
+        n2 = n3;
     }
 }
 
