@@ -792,12 +792,15 @@ __device__ __forceinline__ int wave_max_i32(int v)
     return v;
 }
 
+constexpr int kFillThreads = 256;  // four wavefronts share one block's tables
+
 template <int DIM, int MODE>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(kFillThreads) __attribute__((amdgpu_waves_per_eu(5)))
 k_fill(SearchArgs a)
 {
     using C = FillCfg<DIM>;
     using CB = CandBits<DIM>;
+    constexpr int NW = kFillThreads / 64;
     // LDS: the rank table is dead once the rows are compacted, so the flat entry list
     // reuses its space.
     constexpr int kRankBytes = C::UCAP * 2;
@@ -808,14 +811,17 @@ k_fill(SearchArgs a)
     __shared__ uint32_t masks[64 * (C::MW + 1)];
     __shared__ int soff[65];
     __shared__ long long srow[64];
-    __shared__ int soi[64];
     __shared__ long long sxi[64 * DIM];
+    __shared__ int spart[NW][64];   // per-wave popcounts of each row's mask quarter
+    __shared__ int sred[2][NW];
     uint16_t* rank_of = reinterpret_cast<uint16_t*>(smem);
     uint16_t* flat_rank = reinterpret_cast<uint16_t*>(smem);
 
     const int b = blockIdx.x;
     if (b >= *a.nblk || dense_block(a, b)) return;
-    const int lane = threadIdx.x & 63;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    // every wavefront holds the block's geometry; lane = target
     Geom<DIM> g;
     g.init(a, b);
     const Frame& fr = g.fr;
@@ -838,30 +844,51 @@ k_fill(SearchArgs a)
     const bool fits = !g.active || ctotal <= 32 * CB::CW;
     if (g.U > C::UCAP || E > C::FCAP || __ballot(!fits) != 0) {
         // too big for this path: every row of the block goes to the long-row path
-        if (g.active) a.heavy[atomicAdd(a.nheavy, 1)] = g.p;
+        if (wv == 0 && g.active) a.heavy[atomicAdd(a.nheavy, 1)] = g.p;
         return;
     }
-    // stage the union's original indices and rank them
+    // 1. stage the union's original indices; clear the masks
     const int U = g.U;
     int omin = 0x7FFFFFFF, omax = 0;
-    for (int e = lane; e < U; e += 64) {
+    for (int e = tid; e < U; e += kFillThreads) {
         const int o = a.perm[g.global_of_any(e)];
         sorig[e] = o;
         omin = min(omin, o);
         omax = max(omax, o);
     }
+    for (int i = tid; i < 64 * (C::MW + 1); i += kFillThreads) masks[i] = 0;
     omin = wave_min_i32(omin);
     omax = wave_max_i32(omax);
-    uint32_t* mk = masks + lane * (C::MW + 1);
+    if (lane == 0) {
+        sred[0][wv] = omin;
+        sred[1][wv] = omax;
+    }
+    if (wv == 0) {
+        soff[lane] = off;
+        if (lane == 63) soff[64] = E;
+        srow[lane] = rs;
 #pragma unroll
-    for (int w = 0; w < C::MW; ++w) mk[w] = 0;
+        for (int k = 0; k < DIM; ++k) {
+            // the target's own coordinates for the distance: fixed point, or FP64 bits (baseline)
+            sxi[lane * DIM + k] = MODE == 1 ? __builtin_bit_cast(long long, sd.pos[static_cast<size_t>(li) * DIM + k])
+                                            : a.X[static_cast<size_t>(oi) * x_stride(DIM) + k];
+        }
+    }
     __syncthreads();
-    if (static_cast<uint32_t>(omax - omin) < (1u << (32 - C::SHIFT))) {
-        rank_union_any<C::SHIFT>(U, sorig, rank_of, omin);
-    } else {
-        sort_union_any(U, sorig);
-        __syncthreads();
-        for (int e = lane; e < U; e += 64) {
+    // 2. rank the union by original index (wavefront 0; the others wait)
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        omin = min(omin, sred[0][w]);
+        omax = max(omax, sred[1][w]);
+    }
+    const bool packed = static_cast<uint32_t>(omax - omin) < (1u << (32 - C::SHIFT));
+    if (wv == 0) {
+        if (packed) rank_union_any<C::SHIFT>(U, sorig, rank_of, omin);
+        else sort_union_any(U, sorig);
+    }
+    __syncthreads();
+    if (!packed) {
+        for (int e = tid; e < U; e += kFillThreads) {
             const int o = a.perm[g.global_of_any(e)];
             int l = 0, r = U;
             while (l < r) {
@@ -871,21 +898,19 @@ k_fill(SearchArgs a)
             }
             rank_of[e] = static_cast<uint16_t>(l);
         }
+        __syncthreads();
     }
-    __syncthreads();
-    double pi[3] = {0, 0, 0};
-    if (MODE == 1) {
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) pi[k] = sd.pos[static_cast<size_t>(li) * DIM + k];
-    }
+    // 3. accepted candidates from the count pass, re-indexed by rank into each target's
+    // mask; wavefront wv takes the target's bit words w = wv (mod 4)
+    uint32_t* mk = masks + lane * (C::MW + 1);
     if (g.active) {
-        // accepted candidates from the count pass, re-indexed by rank
 #pragma unroll
         for (int r = 0; r < Geom<DIM>::NSEG; ++r) {
             const int c0 = segoff[r], c1 = c0 + (g.lb[r] - g.la[r]);
             if (c0 >= c1) continue;
             const int pbase = g.la[r] - c0;  // logical position = pbase + candidate index
-            for (int w = c0 >> 5; w <= ((c1 - 1) >> 5); ++w) {
+            const int w0 = c0 >> 5, w1 = (c1 - 1) >> 5;
+            for (int w = w0 + ((wv - w0) & (NW - 1)); w <= w1; w += NW) {
                 uint32_t bits = a.cbits[static_cast<size_t>(w) * a.L.ntot + g.p];
                 const int lo = c0 - 32 * w, hi = c1 - 32 * w;
                 if (lo > 0) bits &= ~0u << lo;
@@ -893,31 +918,29 @@ k_fill(SearchArgs a)
                 while (bits) {
                     const int ci = 32 * w + __builtin_ctz(bits);
                     bits &= bits - 1;
-                    const uint32_t rk = rank_of[pbase + ci];
+                    const int posl = pbase + ci;
+                    if (posl == g.pself) continue;  // the target itself is never its own neighbour
+                    const uint32_t rk = rank_of[posl];
                     atomicOr(&mk[rk >> 5], 1u << (rk & 31));
                 }
             }
         }
-        // the target itself is never its own neighbour
-        const uint32_t rself = rank_of[g.pself];
-        mk[rself >> 5] &= ~(1u << (rself & 31));
     }
-    // compaction: each lane walks its mask in rank order into the block's flat list
-    soff[lane] = off;
-    if (lane == 63) soff[64] = E;
-    srow[lane] = rs;
-    soi[lane] = oi;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-        // the target's own coordinates for the distance: fixed point, or FP64 bits (baseline)
-        sxi[lane * DIM + k] = MODE == 1 ? __builtin_bit_cast(long long, pi[k])
-                                        : a.X[static_cast<size_t>(oi) * x_stride(DIM) + k];
-    }
-    __syncthreads();  // rank table and records are dead from here on
+    __syncthreads();
+    // 4. compaction: each target's mask walked in rank order into the block's flat list;
+    // wavefront wv takes word quarter wv, after the popcounts of the quarters before it
+    const int nw = (U + 31) >> 5;
+    const int qw = (nw + NW - 1) / NW;
+    const int wa = wv * qw, wb = min(nw, wa + qw);
+    int cnt = 0;
+    if (g.active)
+        for (int w = wa; w < wb; ++w) cnt += __builtin_popcount(mk[w]);
+    spart[wv][lane] = cnt;
+    __syncthreads();  // rank table dead from here on: the flat list reuses its space
     if (g.active) {
-        const int nw = (U + 31) >> 5;
         int got = 0;
-        for (int w = 0; w < nw; ++w) {
+        for (int q = 0; q < wv; ++q) got += spart[q][lane];
+        for (int w = wa; w < wb; ++w) {
             uint32_t bits = mk[w];
             while (bits) {
                 const int bi = __builtin_ctz(bits);
@@ -926,15 +949,15 @@ k_fill(SearchArgs a)
                 ++got;
             }
         }
-        if (got != rlen) atomicOr(a.err, kErrLongRow);
+        if (wv == NW - 1 && got != rlen) atomicOr(a.err, kErrLongRow);
     }
     __syncthreads();
-    // Emission, 64 entries per round. Later rounds' gathers are issued before this
-    // round's stores, and every round issues the same memory instructions on every path:
-    // lanes past the list (or past the output capacity) gather particle 0 and store to a
-    // per-lane sink slot. Vector-memory counters count loads and stores in issue order,
-    // so with a fixed instruction count the wait for the prefetch need not include the
-    // previous round's stores.
+    // 5. emission, 64 entries per round, rounds dealt to the wavefronts in turn. Later
+    // rounds' gathers are issued before this round's stores, and every round issues the
+    // same memory instructions on every path: lanes past the list (or past the output
+    // capacity) gather particle 0 and store to a per-lane sink slot. Vector-memory
+    // counters count loads and stores in issue order, so with a fixed instruction count
+    // the wait for the prefetch need not include the previous round's stores.
     struct Ent {
         int t, oj;
         long long idx;
@@ -943,11 +966,18 @@ k_fill(SearchArgs a)
     const int64_t cap = sd.capacity;
     NNPS_GLOBAL int32_t* sink_col = (NNPS_GLOBAL int32_t*)a.sink + 2 * lane;
     NNPS_GLOBAL float* sink_dist = (NNPS_GLOBAL float*)(a.sink + 2 * lane + 1);
-    auto fetch = [&](int e, int tstart, Ent& s) {
+    auto fetch = [&](int e, Ent& s) {
         const bool ok = e < E;
-        int t = tstart;
-        if (ok)
-            while (soff[t + 1] <= e) ++t;  // rows are short: a few steps at most
+        // row of entry e: the last t with soff[t] <= e
+        int t = 0;
+        if (ok) {
+            int hi = 63;
+            while (t < hi) {
+                const int m = (t + hi + 1) >> 1;
+                if (soff[m] <= e) t = m;
+                else hi = m - 1;
+            }
+        }
         s.t = t;
         s.oj = ok ? sorig[flat_rank[e]] : sd.poff;
         s.idx = ok ? srow[t] + (e - soff[t]) : -1;
@@ -956,14 +986,13 @@ k_fill(SearchArgs a)
             s.xj[c] = MODE == 1 ? __builtin_bit_cast(long long, sd.pos[static_cast<size_t>(s.oj - sd.poff) * DIM + c])
                                 : a.X[static_cast<size_t>(s.oj) * x_stride(DIM) + c];
     };
-    // three rounds in flight: a round's gathers are issued three rounds before its use
-    Ent cur, n1, n2;
-    fetch(lane, 0, cur);
-    fetch(64 + lane, __shfl(cur.t, 63, 64), n1);
-    fetch(128 + lane, __shfl(n1.t, 63, 64), n2);
-    for (int e0 = 0; e0 < E; e0 += 64) {
-        Ent n3;
-        fetch(e0 + 192 + lane, __shfl(n2.t, 63, 64), n3);
+    constexpr int R = 64 * NW;  // stride between a wavefront's rounds
+    Ent cur, n1;
+    fetch(wv * 64 + lane, cur);
+    fetch(wv * 64 + R + lane, n1);
+    for (int e0 = wv * 64; e0 < E; e0 += R) {
+        Ent n2;
+        fetch(e0 + 2 * R + lane, n2);
         float d;
         if constexpr (MODE == 1) {
             double pi2[3], pj2[3];
@@ -990,7 +1019,6 @@ k_fill(SearchArgs a)
         *pd = d;
         cur = n1;
         n1 = n2;
-        n2 = n3;
     }
 }
 
@@ -1190,7 +1218,7 @@ hipError_t launch_stats(const SearchArgs& a, hipStream_t st)
 hipError_t launch_fill(const SearchArgs& a, int nblk_max, hipStream_t st)
 {
     if (a.L.ntot == 0 || nblk_max == 0) return hipSuccess;
-    const dim3 g(nblk_max), b(64);
+    const dim3 g(nblk_max), b(kFillThreads);
     const int d = a.L.dim, m = a.L.mode;
     if (d == 2 && m == 0) hipLaunchKernelGGL((k_fill<2, 0>), g, b, 0, st, a);
     else if (d == 3 && m == 0) hipLaunchKernelGGL((k_fill<3, 0>), g, b, 0, st, a);
