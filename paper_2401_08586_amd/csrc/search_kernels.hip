@@ -414,6 +414,21 @@ struct CandBits {
     {
         if (keep) atomicOr(&w[ci >> 5], 1u << (ci & 31));
     }
+    // Bits of up to 4 consecutive candidates starting at ci (bit k = candidate ci + k),
+    // with no branch on the bits: two unconditional ORs, the second into the next word
+    // (the padding word after the lane's last one). ci may be -1 with bit 0 clear (the
+    // first record of a segment starting at an odd position).
+    __device__ __forceinline__ void put(int ci, uint32_t bits)
+    {
+        if (!keep) return;
+        if (ci < 0) {
+            bits >>= 1;
+            ci = 0;
+        }
+        const int wd = ci >> 5, sh = ci & 31;
+        atomicOr(&w[wd], bits << sh);
+        atomicOr(&w[wd + 1], sh ? bits >> (32 - sh) : 0u);
+    }
     // candidate index of a logical position inside the lane's ranges
     __device__ __forceinline__ int index_of(const Geom<DIM>& g, int posl) const
     {
@@ -512,16 +527,13 @@ k_count16(SearchArgs a)
                         }
                     }
                 };
-                auto accept = [&](int m, uint32_t inb) {
-                    cnt += __builtin_popcount(inb);
-                    if (inb & 0x8000u) cb_.set(cbase + 2 * m);
-                    if (inb & 0x80000000u) cb_.set(cbase + 2 * m + 1);
-                };
                 auto one = [&](int m, uint32_t inv) {
                     const uint32_t rb = r2_pair<DIM>(tg, ay, az, rec[m]) | inv;
                     const u16x2 d = as_u16x2(rb) - th.tlo2;
                     const uint32_t inb = u16x2_bits(d) & 0x80008000u;
-                    if (inb) accept(m, inb);
+                    const uint32_t two = ((inb >> 15) & 1u) | ((inb >> 30) & 2u);
+                    cnt += __builtin_popcount(two);
+                    cb_.put(cbase + 2 * m, two);
                     const uint32_t x = u16x2_bits(__builtin_elementwise_add_sat(d, th.bias2));
                     if (x != 0xFFFFFFFFu) band(m, rb, x);
                 };
@@ -540,10 +552,10 @@ k_count16(SearchArgs a)
                     const u16x2 dB = as_u16x2(B) - th.tlo2;
                     const uint32_t inA = u16x2_bits(dA) & 0x80008000u;
                     const uint32_t inB = u16x2_bits(dB) & 0x80008000u;
-                    if (inA | inB) {
-                        accept(m, inA);
-                        accept(m + 1, inB);
-                    }
+                    const uint32_t nib =
+                        ((inA >> 15) & 1u) | ((inA >> 30) & 2u) | ((inB >> 13) & 4u) | ((inB >> 28) & 8u);
+                    cnt += __builtin_popcount(nib);
+                    cb_.put(cbase + 2 * m, nib);
                     const uint32_t xA = u16x2_bits(__builtin_elementwise_add_sat(dA, th.bias2));
                     const uint32_t xB = u16x2_bits(__builtin_elementwise_add_sat(dB, th.bias2));
                     if ((xA & xB) != 0xFFFFFFFFu) {
