@@ -412,7 +412,7 @@ nnps_status prepare(nnps_ctx* ctx, nnps_cells* c, int nsets, const nnps_problem*
         // blocks: full ones, at most one per span of xwin cells and one per row ending
         // early, and around each run of dense cells one marker plus one cut short
         int64_t b = fr.n / kWave + nrows * ((fr.nc[0] + fr.xwin - 1) / fr.xwin + 1);
-        if (c->dense)
+        if (c->dense && c->dense_seen != 0)  // the build will use the dense-cell path
             b += 2 * std::min<int64_t>(fr.ncell, stencil * fr.n / (static_cast<int64_t>(c->dthresh) + 1));
         nblk_bound += std::min<int64_t>(fr.n, b);
         poff += fr.n;

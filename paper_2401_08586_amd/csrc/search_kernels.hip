@@ -723,71 +723,24 @@ __device__ __forceinline__ void wave_bitonic(uint32_t (&v)[EPL])
     }
 }
 
-// Ranks of the staged union by original index: rank_of[pos] and, in place of the
-// per-position original indices, orig[rank]. Fast form: one 32-bit key per entry,
-// (orig - base) << SHIFT | pos, valid when the union's index range is below 2^(32-SHIFT).
-template <int EPL, int SHIFT>
-__device__ __forceinline__ void rank_union(int U, int* sorig, uint16_t* rank_of, int base)
+// One wavefront sorts n <= 64 EPL keys (key_of(e0 + i), i < n) in registers and stores
+// them ascending at out[e0 ..).
+template <int EPL, typename K>
+__device__ __forceinline__ void sort_quarter(int e0, int n, K&& key_of, uint32_t* out)
 {
     const int lane = threadIdx.x & 63;
     uint32_t v[EPL];
 #pragma unroll
     for (int i = 0; i < EPL; ++i) {
-        const int e = lane * EPL + i;
-        v[i] = e < U ? (static_cast<uint32_t>(sorig[e] - base) << SHIFT) | static_cast<uint32_t>(e) : 0xFFFFFFFFu;
+        const int k = lane * EPL + i;
+        v[i] = k < n ? key_of(e0 + k) : 0xFFFFFFFFu;
     }
-    __builtin_amdgcn_wave_barrier();
     wave_bitonic<EPL>(v);
 #pragma unroll
     for (int i = 0; i < EPL; ++i) {
-        const int e = lane * EPL + i;
-        if (e < U) {
-            rank_of[v[i] & ((1u << SHIFT) - 1)] = static_cast<uint16_t>(e);
-            sorig[e] = static_cast<int>(v[i] >> SHIFT) + base;
-        }
+        const int k = lane * EPL + i;
+        if (k < n) out[e0 + k] = v[i];
     }
-    __builtin_amdgcn_wave_barrier();
-}
-
-// Wide form: the (distinct) original indices alone are sorted in place; ranks are then
-// found by binary search (the caller re-reads each position's index).
-template <int EPL>
-__device__ __forceinline__ void sort_union(int U, int* sorig)
-{
-    const int lane = threadIdx.x & 63;
-    uint32_t v[EPL];
-#pragma unroll
-    for (int i = 0; i < EPL; ++i) {
-        const int e = lane * EPL + i;
-        v[i] = e < U ? static_cast<uint32_t>(sorig[e]) : 0xFFFFFFFFu;
-    }
-    __builtin_amdgcn_wave_barrier();
-    wave_bitonic<EPL>(v);
-#pragma unroll
-    for (int i = 0; i < EPL; ++i) {
-        const int e = lane * EPL + i;
-        if (e < U) sorig[e] = static_cast<int>(v[i]);
-    }
-    __builtin_amdgcn_wave_barrier();
-}
-
-template <int SHIFT>
-__device__ __forceinline__ void rank_union_any(int U, int* sorig, uint16_t* rank_of, int base)
-{
-    if (U <= 64) rank_union<1, SHIFT>(U, sorig, rank_of, base);
-    else if (U <= 128) rank_union<2, SHIFT>(U, sorig, rank_of, base);
-    else if (U <= 256) rank_union<4, SHIFT>(U, sorig, rank_of, base);
-    else if (U <= 512) rank_union<8, SHIFT>(U, sorig, rank_of, base);
-    else rank_union<16, SHIFT>(U, sorig, rank_of, base);
-}
-
-__device__ __forceinline__ void sort_union_any(int U, int* sorig)
-{
-    if (U <= 64) sort_union<1>(U, sorig);
-    else if (U <= 128) sort_union<2>(U, sorig);
-    else if (U <= 256) sort_union<4>(U, sorig);
-    else if (U <= 512) sort_union<8>(U, sorig);
-    else sort_union<16>(U, sorig);
 }
 
 __device__ __forceinline__ int wave_min_i32(int v)
@@ -887,54 +840,91 @@ k_fill(SearchArgs a)
         }
     }
     __syncthreads();
-    // 2. rank the union by original index (wavefront 0; the others wait)
+    // 2. rank the union by original index. Keys are (orig - omin) << SHIFT | position when
+    // the union's index range allows, else the original index itself (distinct either
+    // way). Each wavefront sorts a quarter of the keys in registers and stores it; an
+    // element's rank is the number of keys below its own in the four sorted quarters.
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         omin = min(omin, sred[0][w]);
         omax = max(omax, sred[1][w]);
     }
     const bool packed = static_cast<uint32_t>(omax - omin) < (1u << (32 - C::SHIFT));
-    if (wv == 0) {
-        if (packed) rank_union_any<C::SHIFT>(U, sorig, rank_of, omin);
-        else sort_union_any(U, sorig);
+    static_assert(C::UCAP * 2 + C::UCAP * 4 <= kShared, "sorted quarters fit beside the rank table");
+    uint32_t* skeys = reinterpret_cast<uint32_t*>(smem + C::UCAP * 2);
+    const int Q = (U + NW - 1) / NW;
+    auto key_of = [&](int e) -> uint32_t {
+        const int o = sorig[e];
+        return packed ? (static_cast<uint32_t>(o - omin) << C::SHIFT) | static_cast<uint32_t>(e)
+                      : static_cast<uint32_t>(o);
+    };
+    if (Q <= 64) sort_quarter<1>(wv * Q, min(Q, U - wv * Q), key_of, skeys);
+    else if (Q <= 128) sort_quarter<2>(wv * Q, min(Q, U - wv * Q), key_of, skeys);
+    else sort_quarter<4>(wv * Q, min(Q, U - wv * Q), key_of, skeys);
+    __syncthreads();
+    constexpr int EPT = (C::UCAP + kFillThreads - 1) / kFillThreads;  // elements per thread
+    int rk[EPT], og[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * kFillThreads;
+        rk[i] = -1;
+        og[i] = 0;
+        if (e < U) {
+            const uint32_t key = key_of(e);
+            int r = 0;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) {
+                const int lo = q * Q, n = max(0, min(Q, U - lo));
+                int l = lo, h = lo + n;
+                while (l < h) {
+                    const int m = (l + h) >> 1;
+                    if (skeys[m] < key) l = m + 1;
+                    else h = m;
+                }
+                r += l - lo;
+            }
+            rk[i] = r;
+            og[i] = sorig[e];
+        }
     }
     __syncthreads();
-    if (!packed) {
-        for (int e = tid; e < U; e += kFillThreads) {
-            const int o = a.perm[g.global_of_any(e)];
-            int l = 0, r = U;
-            while (l < r) {
-                const int m = (l + r) >> 1;
-                if (sorig[m] < o) l = m + 1;
-                else r = m;
-            }
-            rank_of[e] = static_cast<uint16_t>(l);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * kFillThreads;
+        if (rk[i] >= 0) {
+            rank_of[e] = static_cast<uint16_t>(rk[i]);
+            sorig[rk[i]] = og[i];
         }
-        __syncthreads();
     }
+    __syncthreads();
     // 3. accepted candidates from the count pass, re-indexed by rank into each target's
     // mask; wavefront wv takes the target's bit words w = wv (mod 4)
     uint32_t* mk = masks + lane * (C::MW + 1);
     if (g.active) {
+        // this wavefront's words (w = wv + NW k), all loaded before any is used
+        constexpr int KW = (CB::CW + NW - 1) / NW;
+        const int nwt = (ctotal + 31) >> 5;
+        uint32_t wbits[KW];
 #pragma unroll
-        for (int r = 0; r < Geom<DIM>::NSEG; ++r) {
-            const int c0 = segoff[r], c1 = c0 + (g.lb[r] - g.la[r]);
-            if (c0 >= c1) continue;
-            const int pbase = g.la[r] - c0;  // logical position = pbase + candidate index
-            const int w0 = c0 >> 5, w1 = (c1 - 1) >> 5;
-            for (int w = w0 + ((wv - w0) & (NW - 1)); w <= w1; w += NW) {
-                uint32_t bits = a.cbits[static_cast<size_t>(w) * a.L.ntot + g.p];
-                const int lo = c0 - 32 * w, hi = c1 - 32 * w;
-                if (lo > 0) bits &= ~0u << lo;
-                if (hi < 32) bits &= (1u << hi) - 1u;
-                while (bits) {
-                    const int ci = 32 * w + __builtin_ctz(bits);
-                    bits &= bits - 1;
-                    const int posl = pbase + ci;
-                    if (posl == g.pself) continue;  // the target itself is never its own neighbour
-                    const uint32_t rk = rank_of[posl];
-                    atomicOr(&mk[rk >> 5], 1u << (rk & 31));
-                }
+        for (int k = 0; k < KW; ++k) {
+            const int w = wv + NW * k;
+            wbits[k] = w < nwt ? a.cbits[static_cast<size_t>(w) * a.L.ntot + g.p] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < KW; ++k) {
+            const int w = wv + NW * k;
+            uint32_t bits = wbits[k];
+            while (bits) {
+                const int ci = 32 * w + __builtin_ctz(bits);
+                bits &= bits - 1;
+                // logical position of candidate ci: its row segment's base plus the offset
+                int posl = 0;
+#pragma unroll
+                for (int r = 0; r < Geom<DIM>::NSEG; ++r)
+                    if (ci >= segoff[r]) posl = g.la[r] + (ci - segoff[r]);
+                if (posl == g.pself) continue;  // the target itself is never its own neighbour
+                const uint32_t rk = rank_of[posl];
+                atomicOr(&mk[rk >> 5], 1u << (rk & 31));
             }
         }
     }
