@@ -97,9 +97,9 @@ typedef struct nnps_stats {
 } nnps_stats;
 
 /* Work-shape parameters (nnps_ctx_set_tuning; picked per workload by an autotuner).
- * block_target: mean particles per work block; a block is an x-window of about
- *   block_target / (mean cell occupancy) cells in one row of cells, at most 64 particles.
- *   Default 56. Valid 8..4096.
+ * block_target: sets the largest x-span of a work block to block_target / (mean cell
+ *   occupancy) cells (at least 1); a block is a run of at most 64 consecutive particles of
+ *   one row of cells within that span. Default 80. Valid 8..4096.
  * long_rows_grid: workgroups of the long-row path. Default 1024. Valid 1..2^20.
  * long_rows_keys: row entries the long-row path sorts in LDS at once (longer rows are
  *   sorted in chunks and merged); 0 = as many as the device's LDS allows. Valid 0 or

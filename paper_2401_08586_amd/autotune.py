@@ -18,11 +18,11 @@ import json
 import math
 import os
 
-DEFAULTS = {"block_target": 56, "long_rows_grid": 1024, "long_rows_keys": 0, "dense_min_union": 0,
+DEFAULTS = {"block_target": 80, "long_rows_grid": 1024, "long_rows_keys": 0, "dense_min_union": 0,
             "dense_grid": 0, "dense_max_entries": 0}
 
 SPACE = {
-    "block_target": [24, 32, 40, 48, 56, 64, 80, 96],
+    "block_target": [32, 48, 56, 64, 72, 80, 88, 96],
     "dense_min_union": [1, 128, 256, 384, 512, 768, 1024, -1],
     "dense_grid": [256, 512, 1024, 2048, 4096],
     "long_rows_grid": [256, 1024, 4096],

@@ -14,11 +14,12 @@ struct Launch {
     const SetDesc* sets;       // [nsets] (device)
     const int* poffs;          // [nsets + 1] particle offsets (device)
     const int* coffs;          // [nsets + 1] cell offsets (device)
-    const int* roffs;          // [nsets + 1] offsets of the sets' rows of cells (device)
-    int nrows_tot;             // total rows of cells (x-lines)
+    const int* roffs;          // [nsets + 1] offsets of the sets' row segments (device)
+    int nrows_tot;             // total row segments (x-lines cut into pieces of 64 cells)
 };
 
 hipError_t launch_fill_i32(int* p, int64_t m, int v, hipStream_t st);
+int row_segments(int ncx);  // pieces a row of ncx cells is walked in
 hipError_t launch_assign(const Launch& L, int64_t* X, uint32_t* key, int* cell_count, int* err, hipStream_t st);
 hipError_t launch_scan_i32_i32(const int* in, int64_t m, int* out, int64_t* partial, hipStream_t st);
 hipError_t launch_scan_i32_i64(const int* in, int64_t m, int64_t* out, int64_t* partial, hipStream_t st);

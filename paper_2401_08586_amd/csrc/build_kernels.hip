@@ -335,11 +335,14 @@ k_pack(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nset
 }
 
 // ---------------------------------------------------------------------------
-// Work blocks, one wavefront per row of cells of a set: walking the row in x, a block is
-// a run of at most kWave consecutive sorted particles whose cells span at most fr.xwin
-// cells; it starts where the previous one ended (so blocks are full unless the span or
-// the row ends them). A run of dense cells (the dense-cell path's) is one block that the
-// block kernels skip. flags (zeroed beforehand) receives 1 at every block start.
+// Work blocks, one wavefront per segment of 64 cells of a row of cells of a set: walking
+// the segment in x, a block is a run of at most kWave consecutive sorted particles whose
+// cells span at most fr.xwin cells; it starts where the previous one ended (so blocks are
+// full unless the span, the segment or the row ends them). A run of dense cells (the
+// dense-cell path's) is one block that the block kernels skip. flags (zeroed beforehand)
+// receives 1 at every block start.
+constexpr int kRowSegment = 64;
+
 __global__ void __launch_bounds__(256)
 k_row_blocks(const SetDesc* __restrict__ sets, const int* __restrict__ roffs, int nsets, int nrows_tot,
              const int* __restrict__ cell_start, const int* __restrict__ wdense, int* __restrict__ flags)
@@ -351,11 +354,14 @@ k_row_blocks(const SetDesc* __restrict__ sets, const int* __restrict__ roffs, in
     const SetDesc& sd = sets[s];
     const int ncx = sd.fr.nc[0];
     const int span = sd.fr.xwin;
-    const int g0 = sd.coff + (r - roffs[s]) * ncx;
+    const int nseg = (ncx + kRowSegment - 1) / kRowSegment;
+    const int rs = r - roffs[s];
+    const int g0 = sd.coff + (rs / nseg) * ncx;
+    const int base = (rs % nseg) * kRowSegment;
     // wavefront-uniform walk state
     int bs = -1, xs = 0;
     bool dense_open = false;
-    for (int base = 0; base < ncx; base += 64) {
+    {
         const int x = base + lane;
         int c0 = 0, c1 = 0, dn = 0;
         if (x < ncx) {
@@ -363,7 +369,7 @@ k_row_blocks(const SetDesc* __restrict__ sets, const int* __restrict__ roffs, in
             c1 = cell_start[g0 + x + 1];
             dn = wdense ? wdense[g0 + x] : 0;
         }
-        const int m = min(64, ncx - base);
+        const int m = min(kRowSegment, ncx - base);
         for (int i = 0; i < m; ++i) {
             const int a0 = __builtin_amdgcn_readlane(c0, i);
             const int a1 = __builtin_amdgcn_readlane(c1, i);
@@ -572,6 +578,8 @@ k_union_emit(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, in
 
 // ---------------------------------------------------------------------------
 // Host-side launchers.
+int row_segments(int ncx) { return (ncx + kRowSegment - 1) / kRowSegment; }
+
 hipError_t launch_fill_i32(int* p, int64_t m, int v, hipStream_t st)
 {
     if (m <= 0) return hipSuccess;

@@ -140,7 +140,7 @@ struct nnps_ctx {
     int device = 0;
     int64_t* h_pinned = nullptr;  // pinned staging for synchronous read-backs
     int max_lds = 65536;          // LDS bytes a workgroup may use on this device
-    nnps_tuning tuning{56, 1024, 0, 0, 0, 0, 0};
+    nnps_tuning tuning{80, 1024, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -214,7 +214,7 @@ struct nnps_cells {
     bool built = false, counted = false;
     int nsets = 0, dim = 0, mode = 0, ntot = 0, ncell_tot = 0, nblk_max = 0;
     std::vector<Frame> frames;
-    int nrows_tot = 0;                    // rows of cells (x-lines) of all sets
+    int nrows_tot = 0;                    // row segments of all sets
     std::vector<const double*> pos;
     SetDesc* h_sets = nullptr;            // pinned mirror of the set table
     int* h_offs = nullptr;                // pinned mirror of the offsets
@@ -409,15 +409,16 @@ nnps_status prepare(nnps_ctx* ctx, nnps_cells* c, int nsets, const nnps_problem*
         c->h_offs[2 * (nsets + 1) + s] = roff;
         const Frame& fr = frames[s];
         const int64_t nrows = static_cast<int64_t>(fr.nc[1]) * fr.nc[2];
-        // blocks: full ones, at most one per span of xwin cells and one per row ending
-        // early, and around each run of dense cells one marker plus one cut short
-        int64_t b = fr.n / kWave + nrows * ((fr.nc[0] + fr.xwin - 1) / fr.xwin + 1);
+        const int64_t nseg = nrows * row_segments(fr.nc[0]);
+        // blocks: full ones, at most one per span of xwin cells and one per row segment
+        // ending early, and around each run of dense cells one marker plus one cut short
+        int64_t b = fr.n / kWave + nrows * ((fr.nc[0] + fr.xwin - 1) / fr.xwin) + nseg;
         if (c->dense && c->dense_seen != 0)  // the build will use the dense-cell path
             b += 2 * std::min<int64_t>(fr.ncell, stencil * fr.n / (static_cast<int64_t>(c->dthresh) + 1));
         nblk_bound += std::min<int64_t>(fr.n, b);
         poff += fr.n;
         coff += fr.ncell;
-        roff += static_cast<int>(nrows);
+        roff += static_cast<int>(nseg);
     }
     c->h_offs[nsets] = poff;
     c->h_offs[2 * nsets + 1] = coff;
@@ -647,7 +648,7 @@ nnps_status nnps_validate(const nnps_problem* p)
 nnps_status nnps_grid(const nnps_problem* prob, int32_t ncell[3], int32_t* frac_bits, double* cell_width)
 {
     Frame fr;
-    nnps_status st = frame_of(prob, &fr, 56);
+    nnps_status st = frame_of(prob, &fr, 80);
     if (st != NNPS_OK) return st;
     if (ncell)
         for (int k = 0; k < 3; ++k) ncell[k] = fr.nc[k];

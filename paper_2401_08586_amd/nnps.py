@@ -199,7 +199,7 @@ class Context:
         except Exception:
             pass
 
-    def set_tuning(self, block_target: int = 56, long_rows_grid: int = 1024, long_rows_keys: int = 0,
+    def set_tuning(self, block_target: int = 80, long_rows_grid: int = 1024, long_rows_keys: int = 0,
                    dense_min_union: int = 0, dense_grid: int = 0, dense_max_entries: int = 0):
         t = Tuning(int(block_target), int(long_rows_grid), int(long_rows_keys), int(dense_min_union),
                    int(dense_grid), 0, int(dense_max_entries))
