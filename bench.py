@@ -248,7 +248,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def bench_serving(args, nsims=64, slots=2, load=0.7):
+def bench_serving(args, nsims=64, slots=4, load=0.7):
     """Serving mix: 64 simulations (half 2D, half 3D lattices, 1e3..2e6 particles), each
     request one time step (move, rebuild, search). The saturated request rate is measured
     closed-loop first; then Poisson arrivals at `load` times that rate. Latency = arrival

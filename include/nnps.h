@@ -215,6 +215,13 @@ nnps_status nnps_batch_step(nnps_ctx *ctx, nnps_cells *cells, int32_t nsets, con
 nnps_status nnps_cells_set_graphs(nnps_cells *cells, int on);
 /* Waits for the stream and returns each set's nnz of the last count (nsets entries). */
 nnps_status nnps_batch_nnz(nnps_cells *cells, int64_t *h_nnz, void *stream);
+/* The same without a synchronous round trip: enqueue copies each set's nnz and the
+ * device error flags into the structure's own pinned host memory on `stream` (returns at
+ * once); fetch waits for those copies (normally long finished when the caller has seen
+ * the step complete) and writes nnz[nsets]. fetch returns the device-detected errors like
+ * nnps_batch_nnz, or NNPS_EORDER without a preceding enqueue. */
+nnps_status nnps_batch_nnz_enqueue(nnps_cells *cells, void *stream);
+nnps_status nnps_batch_nnz_fetch(nnps_cells *cells, int64_t *h_nnz);
 
 /* Phases timed when profiling is on, in launch order. */
 enum {

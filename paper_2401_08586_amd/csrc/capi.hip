@@ -221,6 +221,10 @@ struct nnps_cells {
     int h_cap = 0;                        // sets the pinned mirrors can hold
     hipEvent_t upload_done = nullptr;     // last upload from the pinned mirrors
     bool upload_pending = false;
+    int64_t* h_report = nullptr;          // pinned: nnz per set, then error and dense words
+    int h_report_cap = 0;
+    hipEvent_t report_done = nullptr;     // the last enqueued report's copies
+    bool report_pending = false;
     uint64_t buf_gen = 0;                 // bumps whenever a device buffer moves
     uint32_t* skey = nullptr;
     int* perm = nullptr;
@@ -737,6 +741,8 @@ void nnps_cells_destroy(nnps_cells* c)
     if (c->upload_done) (void)hipEventDestroy(c->upload_done);
     if (c->h_sets) (void)hipHostFree(c->h_sets);
     if (c->h_offs) (void)hipHostFree(c->h_offs);
+    if (c->report_done) (void)hipEventDestroy(c->report_done);
+    if (c->h_report) (void)hipHostFree(c->h_report);
     delete c;
 }
 
@@ -927,6 +933,50 @@ nnps_status nnps_batch_nnz(nnps_cells* c, int64_t* h_nnz, void* stream)
     DeviceGuard g(c->ctx->device);
     if (!g.ok) return NNPS_EDEVICE;
     return read_nnz(c, h_nnz, static_cast<hipStream_t>(stream));
+}
+
+nnps_status nnps_batch_nnz_enqueue(nnps_cells* c, void* stream)
+{
+    if (!c) return NNPS_EINVAL;
+    if (!c->counted) return NNPS_EORDER;
+    DeviceGuard g(c->ctx->device);
+    if (!g.ok) return NNPS_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (c->report_pending) HIP_TRY(hipEventSynchronize(c->report_done));  // the buffer is reused
+    c->report_pending = false;
+    if (c->h_report_cap < c->nsets + 2) {
+        if (c->h_report) (void)hipHostFree(c->h_report);
+        c->h_report = nullptr;
+        c->h_report_cap = 0;
+        if (hipHostMalloc(reinterpret_cast<void**>(&c->h_report), sizeof(int64_t) * (c->nsets + 2),
+                          hipHostMallocDefault) != hipSuccess)
+            return NNPS_ENOMEM;
+        c->h_report_cap = c->nsets + 2;
+    }
+    if (!c->report_done && hipEventCreateWithFlags(&c->report_done, hipEventDisableTiming) != hipSuccess)
+        return NNPS_EDEVICE;
+    int64_t* hp = c->h_report;
+    hp[c->nsets] = 0;
+    hp[c->nsets + 1] = 0;
+    HIP_TRY(hipMemcpyAsync(hp, c->nnz.p, 8 * c->nsets, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hp + c->nsets, c->err.p, 4, hipMemcpyDeviceToHost, s));
+    if (c->dense) HIP_TRY(hipMemcpyAsync(hp + c->nsets + 1, c->dseen.p, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(c->report_done, s));
+    c->report_pending = true;
+    return NNPS_OK;
+}
+
+nnps_status nnps_batch_nnz_fetch(nnps_cells* c, int64_t* h_nnz)
+{
+    if (!c || !h_nnz) return NNPS_EINVAL;
+    if (!c->report_pending) return NNPS_EORDER;
+    DeviceGuard g(c->ctx->device);
+    if (!g.ok) return NNPS_EDEVICE;
+    HIP_TRY(hipEventSynchronize(c->report_done));
+    const int64_t* hp = c->h_report;
+    for (int i = 0; i < c->nsets; ++i) h_nnz[i] = hp[i];
+    if (c->dense) c->dense_seen = static_cast<int>(hp[c->nsets + 1] & 0xFFFFFFFF) != 0 ? 1 : 0;
+    return err_status(static_cast<int>(hp[c->nsets] & 0xFFFFFFFF));
 }
 
 nnps_status nnps_stats_get(nnps_cells* c, nnps_stats* out, void* stream)

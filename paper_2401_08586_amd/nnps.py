@@ -71,7 +71,8 @@ EXPORTS = ["nnps_status_str", "nnps_validate", "nnps_grid", "nnps_ctx_create", "
            "nnps_cells_create", "nnps_cells_destroy", "nnps_cells_build", "nnps_count", "nnps_fill",
            "nnps_search", "nnps_stats_get", "nnps_cells_set_profiling", "nnps_phase_times",
            "nnps_batch_build", "nnps_batch_count", "nnps_batch_fill", "nnps_batch_search",
-           "nnps_batch_step", "nnps_cells_set_graphs", "nnps_batch_nnz"]
+           "nnps_batch_step", "nnps_cells_set_graphs", "nnps_batch_nnz", "nnps_batch_nnz_enqueue",
+           "nnps_batch_nnz_fetch"]
 
 PHASES = ["assign", "cellscan", "sort", "pack", "blocks", "unions", "count", "dcount", "rowscan", "fill",
           "longrows", "dfill"]
@@ -299,6 +300,19 @@ class Cells:
         if not check:
             return list(nnz), code
         _check(code, "nnps_batch_nnz")
+        return list(nnz)
+
+    def batch_nnz_enqueue(self, stream=None):
+        """Queue the copies of each set's nnz and the error flags to pinned host memory."""
+        _check(self._lib.nnps_batch_nnz_enqueue(self._h, _stream_ptr(stream)), "nnps_batch_nnz_enqueue")
+
+    def batch_nnz_fetch(self, check: bool = True):
+        """Each set's nnz from the last enqueue (waits only for those copies)."""
+        nnz = (ctypes.c_int64 * self.nsets)()
+        code = self._lib.nnps_batch_nnz_fetch(self._h, nnz)
+        if not check:
+            return list(nnz), code
+        _check(code, "nnps_batch_nnz_fetch")
         return list(nnz)
 
     def set_graphs(self, on: bool = True):

@@ -1,13 +1,17 @@
 """Serving loop: neighbour-search requests from many concurrent simulations on one GPU.
 
-Each simulation keeps its particles resident in HBM between time steps; a request asks
-for one step (the particles move, then a rebuild + search of that simulation). The loop
-does continuous batching: whenever one of its stream slots is free, every queued request
-whose simulation is idle joins the next batch (up to a particle budget per batch), and
-the batch runs as one library batch call (one launch per pass for all its sets) on that
-slot's stream while other slots' batches run beside it. Simulations are admitted into
-HBM by a byte budget: before a batch runs, idle simulations are evicted (positions to
-pinned host memory, outputs freed) in least-recently-used order until the batch fits.
+Each simulation keeps its particles, its CSR outputs and its sorted cell structure
+resident in HBM between time steps; a request asks for one step (the particles move, then
+a rebuild + search of that simulation). Requests are served continuously: whenever one
+of the stream slots is free, the oldest queued request whose simulation is idle starts
+on it, so requests that arrive while others run are admitted as slots and memory free
+up, and their work overlaps on the device. Each step of a simulation replays the HIP
+graph its cell structure captured on the first step (one launch per request). With
+per_sim=False the requests of a slot are instead batched (up to a particle budget) into
+one library batch call on a structure per slot. Simulations are admitted into HBM by a
+byte budget: before a request runs, idle simulations are evicted (positions to pinned
+host memory, outputs and cell structure freed) in least-recently-used order until it
+fits.
 
 The scheduler (`Scheduler`) is host logic only and is tested on the CPU; `Server` drives
 the library through the binding in `nnps.py`. Every search runs in the HIP library; the
@@ -142,8 +146,9 @@ class Server:
     """Runs the request loop on one GPU. `sims` are workloads.ParticleSet; `slots` is the
     number of batches that may be on the device at once (one stream each)."""
 
-    def __init__(self, sims, slots: int = 2, budget_bytes: float = math.inf, max_batch_particles: int = 1 << 23,
-                 seed: int = 4, frac: float = 0.05, headroom: float = 1.1, ctx=None, keep_results: bool = False):
+    def __init__(self, sims, slots: int = 4, budget_bytes: float = math.inf, max_batch_particles: int = 1 << 23,
+                 seed: int = 4, frac: float = 0.05, headroom: float = 1.1, ctx=None, keep_results: bool = False,
+                 per_sim: bool = True):
         import torch
         from . import nnps
         self.torch = torch
@@ -156,6 +161,11 @@ class Server:
         self.headroom = headroom
         self.keep_results = keep_results
         self.results = {}  # (sim, step) -> (pos, row_ptr, col, dist) copies when keep_results
+        # per_sim: every resident simulation keeps its own cell structure, and each step is
+        # one replay of that structure's captured graph; otherwise the requests of a slot
+        # are batched into one library batch call on the slot's structure
+        self.per_sim = per_sim
+        self.cells = [None] * len(sims)
         n = len(sims)
         self.step = [0] * n
         self.pos = [None] * n       # device positions (resident) or None
@@ -165,6 +175,8 @@ class Server:
         self.dist = [None] * n
         self.cap = [0] * n
         self.ready = [None] * n     # event: positions of the next step are in place
+        self.gen = {}               # per-simulation device generator (reseeded every step)
+        self.disp = {}              # per-simulation displacement buffer of the motion
         self.box = [(torch.tensor(ps.lo, dtype=torch.float64, device="cuda"),
                      torch.tensor(ps.hi, dtype=torch.float64, device="cuda")) for ps in sims]
         # initial capacity estimate per simulation from one search of its starting positions
@@ -176,8 +188,8 @@ class Server:
             self.cap[s] = int(col.numel() * headroom) + 4096
             del pos, rp, col
         cells.close()
-        nbytes = [ps.n * ps.dim * 8 + (ps.n + 1) * 8 + self.cap[s] * 8 for s, ps in enumerate(sims)]
-        self.sched = Scheduler([ps.n for ps in sims], nbytes, budget_bytes, max_batch_particles,
+        nbytes = [self._footprint(s) for s in range(len(sims))]
+        self.sched = Scheduler([ps.n for ps in sims], nbytes, budget_bytes, 1 if per_sim else max_batch_particles,
                                groups=[ps.dim for ps in sims])
         self.slots = []
         for _ in range(slots):
@@ -187,6 +199,16 @@ class Server:
         torch.cuda.synchronize()
 
     # -- resident state ------------------------------------------------------------------
+    def _footprint(self, s):
+        """Device bytes a resident simulation holds: positions and the motion's displacement
+        buffer, CSR outputs and, per simulation, its cell structure (about 200 bytes per particle plus the dense-cell
+        lists' 16 bytes per stencil entry, 3^d per particle)."""
+        ps = self.sims[s]
+        b = 2 * ps.n * ps.dim * 8 + (ps.n + 1) * 8 + self.cap[s] * 8
+        if self.per_sim:
+            b += ps.n * (200 + 16 * 3 ** ps.dim)
+        return b
+
     def _admit(self, s, stream):
         torch = self.torch
         ps = self.sims[s]
@@ -196,6 +218,9 @@ class Server:
             self.col[s] = torch.empty(self.cap[s], dtype=torch.int32, device="cuda")
             self.dist[s] = torch.empty(self.cap[s], dtype=torch.float32, device="cuda")
         self.host[s] = None
+        if self.per_sim:
+            self.cells[s] = self.ctx.cells()
+            self.cells[s].set_graphs(True)
 
     def _evict(self, s):
         torch = self.torch
@@ -206,24 +231,32 @@ class Server:
         host.copy_(self.pos[s])
         self.host[s] = host
         self.pos[s] = self.rp[s] = self.col[s] = self.dist[s] = None
+        self.disp.pop(s, None)
         self.ready[s] = None
+        if self.cells[s] is not None:
+            self.cells[s].close()
+            self.cells[s] = None
 
     def _move(self, s, stream):
         """The simulation's time step: every particle moves by U(-frac dx, +frac dx) per
-        component, dx = radius / 2.4, walls reflect (seeded per simulation and step)."""
+        component, dx = radius / 2.4, and is clamped to the box (seeded per simulation and
+        step; three device launches)."""
         torch = self.torch
         ps = self.sims[s]
-        g = torch.Generator(device="cuda")
+        g = self.gen.get(s)
+        if g is None:
+            g = self.gen[s] = torch.Generator(device="cuda")
         g.manual_seed(self.seed * 1_000_003 + s * 65_537 + self.step[s])
-        dx = ps.radius / 2.4
+        a = self.frac * ps.radius / 2.4
         with torch.cuda.stream(stream):
             p = self.pos[s]
-            d = torch.rand(p.shape, dtype=torch.float64, device="cuda", generator=g)
-            p.add_(d.mul_(2 * self.frac * dx).sub_(self.frac * dx))
+            d = self.disp.get(s)
+            if d is None or d.shape != p.shape:
+                d = self.disp[s] = torch.empty_like(p)
+            d.uniform_(-a, a, generator=g)
+            p.add_(d)
             lo, hi = self.box[s]
-            p.copy_(torch.where(p < lo, 2 * lo - p, p))
-            p.copy_(torch.where(p > hi, 2 * hi - p, p))
-            p.copy_(torch.minimum(torch.maximum(p, lo), hi))
+            p.clamp_(lo, hi)
             ev = torch.cuda.Event()
             ev.record(stream)
         self.ready[s] = ev
@@ -243,11 +276,14 @@ class Server:
                 stream.wait_event(self.ready[s])
         sets = [(self.pos[s], self.sims[s].lo, self.sims[s].hi, self.sims[s].cell_size, self.sims[s].radius)
                 for s in sims]
+        cells = self.cells[sims[0]] if self.per_sim else slot["cells"]
         with torch.cuda.stream(stream):
-            slot["cells"].batch_step(sets, [self.rp[s] for s in sims], [self.col[s] for s in sims],
-                                     [self.dist[s] for s in sims], stream=stream)
+            cells.batch_step(sets, [self.rp[s] for s in sims], [self.col[s] for s in sims],
+                             [self.dist[s] for s in sims], stream=stream)
             done = torch.cuda.Event(enable_timing=True)
             done.record(stream)
+            cells.batch_nnz_enqueue(stream=stream)
+        slot["used"] = cells
         now = time.perf_counter() - t0
         for r in reqs:
             r.issued = now
@@ -263,7 +299,7 @@ class Server:
         reqs = slot["batch"]
         stream = slot["stream"]
         done_ms = ref.elapsed_time(slot["done"])
-        nnz, code = slot["cells"].batch_nnz(stream=stream, check=False)
+        nnz, code = slot["used"].batch_nnz_fetch(check=False)
         sims = [r.sim for r in reqs]
         redo = []
         for r, k in zip(reqs, nnz):
@@ -284,7 +320,7 @@ class Server:
         for r in redo:  # outputs too small: grow them and run that step again first
             s = r.sim
             self.cap[s] = int(nnz[sims.index(s)] * self.headroom) + 4096
-            self.sched.nbytes[s] = self.sims[s].n * self.sims[s].dim * 8 + (self.sims[s].n + 1) * 8 + self.cap[s] * 8
+            self.sched.nbytes[s] = self._footprint(s)
             with torch.cuda.stream(stream):
                 self.col[s] = torch.empty(self.cap[s], dtype=torch.int32, device="cuda")
                 self.dist[s] = torch.empty(self.cap[s], dtype=torch.float32, device="cuda")
@@ -341,6 +377,9 @@ class Server:
     def close(self):
         for slot in self.slots:
             slot["cells"].close()
+        for c in self.cells:
+            if c is not None:
+                c.close()
         if self.own_ctx:
             self.ctx.close()
 

@@ -108,8 +108,9 @@ def test_graph_step_replays(ctx):
     for rep in range(4):
         with torch.cuda.stream(stream):
             cells.batch_step(sets, rps, cols, dists, stream=stream)
-        stream.synchronize()
-        nnz = cells.batch_nnz(stream=stream)
+        cells.batch_nnz_enqueue(stream=stream)
+        nnz = cells.batch_nnz_fetch()
+        assert nnz == cells.batch_nnz(stream=stream)
         for s, (r, k) in enumerate(zip(ref, nnz)):
             assert k == r[1].numel()
             assert torch.equal(rps[s], r[0])

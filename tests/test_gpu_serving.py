@@ -24,8 +24,9 @@ def ctx():
     c.close()
 
 
-def serve(ctx, sims, slots, budget, arrivals):
-    srv = S.Server(sims, slots=slots, budget_bytes=budget, max_batch_particles=60000, ctx=ctx, keep_results=True)
+def serve(ctx, sims, slots, budget, arrivals, per_sim=True):
+    srv = S.Server(sims, slots=slots, budget_bytes=budget, max_batch_particles=60000, ctx=ctx, keep_results=True,
+                   per_sim=per_sim)
     done = srv.run(arrivals)
     out = dict(srv.results)
     ev = srv.sched.evictions
@@ -34,15 +35,18 @@ def serve(ctx, sims, slots, budget, arrivals):
     return done, out, ev, nb
 
 
-def test_serving_results_equal_alone_and_in_the_mix(ctx):
+@pytest.mark.parametrize("per_sim", [True, False], ids=["per_sim_graphs", "batched"])
+def test_serving_results_equal_alone_and_in_the_mix(ctx, per_sim):
     sims = W.serving_sims(8, seed=7, lo=1e3, hi=5e4)
-    total = sum(p.n * p.dim * 8 + (p.n + 1) * 8 + p.n * 60 * 8 for p in sims)
+    total = sum(p.n * p.dim * 8 + (p.n + 1) * 8 + p.n * 60 * 8 + (p.n * (200 + 16 * 3 ** p.dim) if per_sim else 0)
+                for p in sims)
     arrivals = S.poisson_arrivals(3000.0, 60, nsims=len(sims), seed=9)
-    print(f"[gpu] serving {len(sims)} sims, {sum(p.n for p in sims)} particles", flush=True)
-    done, res, evictions, batches = serve(ctx, sims, 2, total * 0.4, arrivals)
+    print(f"[gpu] serving {len(sims)} sims, {sum(p.n for p in sims)} particles, per_sim={per_sim}", flush=True)
+    done, res, evictions, batches = serve(ctx, sims, 2, total * 0.4, arrivals, per_sim)
     assert len(done) == 60 and len(res) == 60
     assert evictions > 0, "the budget should force evictions"
-    assert batches < 60, "requests should share batches"
+    if not per_sim:
+        assert batches < 60, "requests should share batches"
     assert all(r.latency_ms > 0 for r in done)
     cells = ctx.cells()
     for (s, step), (pos, rp, col, dist) in sorted(res.items()):
@@ -52,7 +56,7 @@ def test_serving_results_equal_alone_and_in_the_mix(ctx):
     cells.close()
     # a different schedule (one slot, no budget) gives the same (sim, step) results
     print("[gpu] serving again, one slot", flush=True)
-    done2, res2, ev2, _ = serve(ctx, sims, 1, float("inf"), arrivals)
+    done2, res2, ev2, _ = serve(ctx, sims, 1, float("inf"), arrivals, per_sim)
     assert ev2 == 0 and res2.keys() == res.keys()
     for key in res:
         for a, b in zip(res[key], res2[key]):
