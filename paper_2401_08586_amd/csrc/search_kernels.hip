@@ -774,13 +774,14 @@ k_fill(SearchArgs a)
     __shared__ __attribute__((aligned(16))) unsigned char smem[kShared];
     __shared__ int sorig[C::UCAP];
     __shared__ uint32_t masks[64 * (C::MW + 1)];
-    __shared__ int soff[65];
-    __shared__ long long srow[64];
+    __shared__ long long sbase[64];  // row start in the output minus the row's flat offset
     __shared__ long long sxi[64 * DIM];
     __shared__ int spart[NW][64];   // per-wave popcounts of each row's mask quarter
     __shared__ int sred[2][NW];
     uint16_t* rank_of = reinterpret_cast<uint16_t*>(smem);
-    uint16_t* flat_rank = reinterpret_cast<uint16_t*>(smem);
+    // flat list entry: target lane << SHIFT | the candidate's rank in the union
+    uint16_t* flat = reinterpret_cast<uint16_t*>(smem);
+    static_assert(64 << C::SHIFT <= 65536 && (1 << C::SHIFT) == C::UCAP, "flat entries fit 16 bits");
 
     const int b = blockIdx.x;
     if (b >= *a.nblk || dense_block(a, b)) return;
@@ -829,9 +830,7 @@ k_fill(SearchArgs a)
         sred[1][wv] = omax;
     }
     if (wv == 0) {
-        soff[lane] = off;
-        if (lane == 63) soff[64] = E;
-        srow[lane] = rs;
+        sbase[lane] = rs - off;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
             // the target's own coordinates for the distance: fixed point, or FP64 bits (baseline)
@@ -910,44 +909,63 @@ k_fill(SearchArgs a)
             const int w = wv + NW * k;
             wbits[k] = w < nwt ? a.cbits[static_cast<size_t>(w) * a.L.ntot + g.p] : 0u;
         }
+        // union position of candidate ci: ci plus its row segment's shift
+        int dseg[Geom<DIM>::NSEG];
+#pragma unroll
+        for (int r = 0; r < Geom<DIM>::NSEG; ++r) dseg[r] = g.la[r] - segoff[r];
 #pragma unroll
         for (int k = 0; k < KW; ++k) {
             const int w = wv + NW * k;
             uint32_t bits = wbits[k];
+            // four bits per round: their rank lookups are issued together, and bits past
+            // the word's last read entry 0 and OR nothing
             while (bits) {
-                const int ci = 32 * w + __builtin_ctz(bits);
-                bits &= bits - 1;
-                // logical position of candidate ci: its row segment's base plus the offset
-                int posl = 0;
+                int posl[4];
+                uint32_t on[4];
 #pragma unroll
-                for (int r = 0; r < Geom<DIM>::NSEG; ++r)
-                    if (ci >= segoff[r]) posl = g.la[r] + (ci - segoff[r]);
-                if (posl == g.pself) continue;  // the target itself is never its own neighbour
-                const uint32_t rk = rank_of[posl];
-                atomicOr(&mk[rk >> 5], 1u << (rk & 31));
+                for (int j = 0; j < 4; ++j) {
+                    on[j] = bits != 0u ? 1u : 0u;
+                    const int ci = 32 * w + __builtin_ctz(bits | (on[j] ? 0u : 1u));
+                    bits &= bits - 1u;
+                    int d = dseg[0];
+#pragma unroll
+                    for (int r = 1; r < Geom<DIM>::NSEG; ++r) d = ci >= segoff[r] ? dseg[r] : d;
+                    posl[j] = on[j] ? ci + d : 0;
+                }
+                uint32_t rk[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) rk[j] = rank_of[posl[j]];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) atomicOr(&mk[rk[j] >> 5], on[j] << (rk[j] & 31));
             }
         }
     }
+    // the target's own bit (set by the count pass when it accepted the target itself) is
+    // masked out below
+    const int rself = g.active ? rank_of[g.pself] : -1;
     __syncthreads();
     // 4. compaction: each target's mask walked in rank order into the block's flat list;
     // wavefront wv takes word quarter wv, after the popcounts of the quarters before it
     const int nw = (U + 31) >> 5;
     const int qw = (nw + NW - 1) / NW;
     const int wa = wv * qw, wb = min(nw, wa + qw);
+    const int wself = rself >> 5;
+    const uint32_t keep_self = ~(1u << (rself & 31));
+    auto word = [&](int w) { return mk[w] & (w == wself ? keep_self : ~0u); };
     int cnt = 0;
     if (g.active)
-        for (int w = wa; w < wb; ++w) cnt += __builtin_popcount(mk[w]);
+        for (int w = wa; w < wb; ++w) cnt += __builtin_popcount(word(w));
     spart[wv][lane] = cnt;
     __syncthreads();  // rank table dead from here on: the flat list reuses its space
     if (g.active) {
         int got = 0;
         for (int q = 0; q < wv; ++q) got += spart[q][lane];
         for (int w = wa; w < wb; ++w) {
-            uint32_t bits = mk[w];
+            uint32_t bits = word(w);
             while (bits) {
                 const int bi = __builtin_ctz(bits);
                 bits &= bits - 1;
-                if (got < rlen) flat_rank[off + got] = static_cast<uint16_t>(w * 32 + bi);
+                if (got < rlen) flat[off + got] = static_cast<uint16_t>((lane << C::SHIFT) | (w * 32 + bi));
                 ++got;
             }
         }
@@ -969,20 +987,16 @@ k_fill(SearchArgs a)
     NNPS_GLOBAL int32_t* sink_col = (NNPS_GLOBAL int32_t*)a.sink + 2 * lane;
     NNPS_GLOBAL float* sink_dist = (NNPS_GLOBAL float*)(a.sink + 2 * lane + 1);
     auto fetch = [&](int e, Ent& s) {
+        // every read stays inside its table whatever e is, so no branch is needed: entries
+        // past the list read stale values that the selects below discard
         const bool ok = e < E;
-        // row of entry e: the last t with soff[t] <= e
-        int t = 0;
-        if (ok) {
-            int hi = 63;
-            while (t < hi) {
-                const int m = (t + hi + 1) >> 1;
-                if (soff[m] <= e) t = m;
-                else hi = m - 1;
-            }
-        }
+        const uint32_t f = flat[min(e, C::FCAP - 1)];
+        const int t = static_cast<int>(f >> C::SHIFT) & 63;
+        const int o = sorig[f & (C::UCAP - 1)];
+        const long long base = sbase[t];
         s.t = t;
-        s.oj = ok ? sorig[flat_rank[e]] : sd.poff;
-        s.idx = ok ? srow[t] + (e - soff[t]) : -1;
+        s.oj = ok ? o : sd.poff;
+        s.idx = ok ? base + e : -1;
 #pragma unroll
         for (int c = 0; c < DIM; ++c)
             s.xj[c] = MODE == 1 ? __builtin_bit_cast(long long, sd.pos[static_cast<size_t>(s.oj - sd.poff) * DIM + c])
