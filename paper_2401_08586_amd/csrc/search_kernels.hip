@@ -723,12 +723,30 @@ __device__ __forceinline__ void wave_bitonic(uint32_t (&v)[EPL])
     }
 }
 
-// One wavefront sorts n <= 64 EPL keys (key_of(e0 + i), i < n) in registers and stores
-// them ascending at out[e0 ..).
-template <int EPL, typename K>
-__device__ __forceinline__ void sort_quarter(int e0, int n, K&& key_of, uint32_t* out)
+// Number of keys below `key` in a sorted run of P keys (P a power of two, the run padded
+// with all-ones keys): fixed-step binary lifting, every read inside the run.
+template <int P>
+__device__ __forceinline__ int count_below(const uint32_t* run, uint32_t key)
 {
-    const int lane = threadIdx.x & 63;
+    int c = 0;
+#pragma unroll
+    for (int s = P >> 1; s > 0; s >>= 1) c += run[c + s - 1] < key ? s : 0;
+    return c + (run[c] < key ? 1 : 0);
+}
+
+// Ranks of the U union keys (key_of(e), e < U) across NW wavefronts: wavefront wv sorts
+// keys [wv Q, wv Q + Q) in registers and stores them padded to 64 EPL entries; a key's
+// rank is the number of keys below it in the NW sorted quarters. Writes rank_of[e] and
+// moves the original indices into rank order (sorig[rank]). Keys that carry their
+// position (packed) are ranked straight from the registers; otherwise every element
+// looks its own key up in all quarters.
+template <int UCAP, int SHIFT, int NW, int EPL, typename K>
+__device__ __forceinline__ void rank_union(int U, int Q, bool packed, int omin, K&& key_of, uint32_t* skeys,
+                                           uint16_t* rank_of, int* sorig)
+{
+    constexpr int QP = 64 * EPL;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int e0 = wv * Q, n = max(0, min(Q, U - e0));
     uint32_t v[EPL];
 #pragma unroll
     for (int i = 0; i < EPL; ++i) {
@@ -737,9 +755,48 @@ __device__ __forceinline__ void sort_quarter(int e0, int n, K&& key_of, uint32_t
     }
     wave_bitonic<EPL>(v);
 #pragma unroll
-    for (int i = 0; i < EPL; ++i) {
-        const int k = lane * EPL + i;
-        if (k < n) out[e0 + k] = v[i];
+    for (int i = 0; i < EPL; ++i) skeys[wv * QP + lane * EPL + i] = v[i];
+    __syncthreads();
+    if (packed) {
+        int rk[EPL];
+#pragma unroll
+        for (int i = 0; i < EPL; ++i) rk[i] = lane * EPL + i;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            if (q == wv) continue;
+#pragma unroll
+            for (int i = 0; i < EPL; ++i) rk[i] += count_below<QP>(skeys + q * QP, v[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < EPL; ++i) {
+            if (v[i] == 0xFFFFFFFFu) continue;
+            rank_of[v[i] & (UCAP - 1)] = static_cast<uint16_t>(rk[i]);
+            sorig[rk[i]] = static_cast<int>(v[i] >> SHIFT) + omin;
+        }
+    } else {
+        constexpr int EPT = UCAP / (64 * NW);
+        int rk[EPT], og[EPT];
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = tid + i * 64 * NW;
+            rk[i] = -1;
+            og[i] = 0;
+            if (e < U) {
+                const uint32_t key = static_cast<uint32_t>(sorig[e]);
+                int r = 0;
+#pragma unroll
+                for (int q = 0; q < NW; ++q) r += count_below<QP>(skeys + q * QP, key);
+                rk[i] = r;
+                og[i] = static_cast<int>(key);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            if (rk[i] < 0) continue;
+            rank_of[tid + i * 64 * NW] = static_cast<uint16_t>(rk[i]);
+            sorig[rk[i]] = og[i];
+        }
     }
 }
 
@@ -813,6 +870,18 @@ k_fill(SearchArgs a)
         if (wv == 0 && g.active) a.heavy[atomicAdd(a.nheavy, 1)] = g.p;
         return;
     }
+    // the count pass's accepted-candidate bits, this wavefront's words w = wv + NW k, are
+    // loaded first: their latency is hidden behind the staging and ranking
+    constexpr int KW = (CB::CW + NW - 1) / NW;
+    uint32_t wbits[KW];
+    {
+        const int nwt = g.active ? (ctotal + 31) >> 5 : 0;
+#pragma unroll
+        for (int k = 0; k < KW; ++k) {
+            const int w = wv + NW * k;
+            wbits[k] = w < nwt ? a.cbits[static_cast<size_t>(w) * a.L.ntot + g.p] : 0u;
+        }
+    }
     // 1. stage the union's original indices; clear the masks
     const int U = g.U;
     int omin = 0x7FFFFFFF, omax = 0;
@@ -840,15 +909,14 @@ k_fill(SearchArgs a)
     }
     __syncthreads();
     // 2. rank the union by original index. Keys are (orig - omin) << SHIFT | position when
-    // the union's index range allows, else the original index itself (distinct either
-    // way). Each wavefront sorts a quarter of the keys in registers and stores it; an
-    // element's rank is the number of keys below its own in the four sorted quarters.
+    // the union's index range allows, else the original index itself: distinct either way,
+    // and below the all-ones key that pads the sorted quarters.
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         omin = min(omin, sred[0][w]);
         omax = max(omax, sred[1][w]);
     }
-    const bool packed = static_cast<uint32_t>(omax - omin) < (1u << (32 - C::SHIFT));
+    const bool packed = static_cast<uint32_t>(omax - omin) < (1u << (32 - C::SHIFT)) - 1u;
     static_assert(C::UCAP * 2 + C::UCAP * 4 <= kShared, "sorted quarters fit beside the rank table");
     uint32_t* skeys = reinterpret_cast<uint32_t*>(smem + C::UCAP * 2);
     const int Q = (U + NW - 1) / NW;
@@ -857,58 +925,14 @@ k_fill(SearchArgs a)
         return packed ? (static_cast<uint32_t>(o - omin) << C::SHIFT) | static_cast<uint32_t>(e)
                       : static_cast<uint32_t>(o);
     };
-    if (Q <= 64) sort_quarter<1>(wv * Q, min(Q, U - wv * Q), key_of, skeys);
-    else if (Q <= 128) sort_quarter<2>(wv * Q, min(Q, U - wv * Q), key_of, skeys);
-    else sort_quarter<4>(wv * Q, min(Q, U - wv * Q), key_of, skeys);
-    __syncthreads();
-    constexpr int EPT = (C::UCAP + kFillThreads - 1) / kFillThreads;  // elements per thread
-    int rk[EPT], og[EPT];
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-        const int e = tid + i * kFillThreads;
-        rk[i] = -1;
-        og[i] = 0;
-        if (e < U) {
-            const uint32_t key = key_of(e);
-            int r = 0;
-#pragma unroll
-            for (int q = 0; q < NW; ++q) {
-                const int lo = q * Q, n = max(0, min(Q, U - lo));
-                int l = lo, h = lo + n;
-                while (l < h) {
-                    const int m = (l + h) >> 1;
-                    if (skeys[m] < key) l = m + 1;
-                    else h = m;
-                }
-                r += l - lo;
-            }
-            rk[i] = r;
-            og[i] = sorig[e];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-        const int e = tid + i * kFillThreads;
-        if (rk[i] >= 0) {
-            rank_of[e] = static_cast<uint16_t>(rk[i]);
-            sorig[rk[i]] = og[i];
-        }
-    }
+    if (Q <= 64) rank_union<C::UCAP, C::SHIFT, NW, 1>(U, Q, packed, omin, key_of, skeys, rank_of, sorig);
+    else if (Q <= 128) rank_union<C::UCAP, C::SHIFT, NW, 2>(U, Q, packed, omin, key_of, skeys, rank_of, sorig);
+    else rank_union<C::UCAP, C::SHIFT, NW, 4>(U, Q, packed, omin, key_of, skeys, rank_of, sorig);
     __syncthreads();
     // 3. accepted candidates from the count pass, re-indexed by rank into each target's
     // mask; wavefront wv takes the target's bit words w = wv (mod 4)
     uint32_t* mk = masks + lane * (C::MW + 1);
     if (g.active) {
-        // this wavefront's words (w = wv + NW k), all loaded before any is used
-        constexpr int KW = (CB::CW + NW - 1) / NW;
-        const int nwt = (ctotal + 31) >> 5;
-        uint32_t wbits[KW];
-#pragma unroll
-        for (int k = 0; k < KW; ++k) {
-            const int w = wv + NW * k;
-            wbits[k] = w < nwt ? a.cbits[static_cast<size_t>(w) * a.L.ntot + g.p] : 0u;
-        }
         // union position of candidate ci: ci plus its row segment's shift
         int dseg[Geom<DIM>::NSEG];
 #pragma unroll
