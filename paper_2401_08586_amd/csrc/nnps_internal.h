@@ -17,11 +17,11 @@ constexpr int kUnion2 = 512;
 constexpr int kUnion3 = 1024;
 constexpr int kFlat2 = 2048;
 constexpr int kFlat3 = 4608;
-// Accepted-candidate bits the count pass keeps per target (32 candidates per word),
-// stored word-major so a wavefront's stores coalesce. Targets with more candidates
-// take the long-row path in the fill.
-constexpr int kCandWords2 = 8;
-constexpr int kCandWords3 = 24;
+// Accepted-candidate bits the count pass keeps per target, indexed by the candidate's
+// position in the block's union (32 positions per word), stored word-major so a
+// wavefront's stores coalesce. Blocks with a larger union take the long-row path.
+constexpr int kCandWords2 = kUnion2 / 32;
+constexpr int kCandWords3 = kUnion3 / 32;
 // Fixed-point positions are stored per particle, padded to a power of two of int64.
 __host__ __device__ constexpr int x_stride(int dim) { return dim == 3 ? 4 : 2; }
 // Largest x-span (cells) of a work block; keeps staged cell offsets exact in FP16.

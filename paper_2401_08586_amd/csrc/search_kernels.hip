@@ -393,55 +393,41 @@ struct CandBits {
     static constexpr int CW = DIM == 3 ? kCandWords3 : kCandWords2;
     static constexpr int NSEG = Geom<DIM>::NSEG;
     uint32_t* w;
-    int segoff[NSEG];
-    int total;
+    int total;  // the lane's candidates (its own stencil ranges)
+    int nw;     // words of the block's union
     bool keep;
+    // Bits are indexed by union position; the block's tables (CW + 1 words per lane, the
+    // last one padding) are cleared by the whole wavefront.
     __device__ __forceinline__ void init(const Geom<DIM>& g, uint32_t* lds)
     {
         const int lane = threadIdx.x & 63;
         w = lds + lane * (CW + 1);
         total = 0;
 #pragma unroll
-        for (int r = 0; r < NSEG; ++r) {
-            segoff[r] = total;
-            total += g.lb[r] - g.la[r];
-        }
-        keep = g.active && total <= 32 * CW;
-#pragma unroll
-        for (int k = 0; k < CW; ++k) w[k] = 0;
+        for (int r = 0; r < NSEG; ++r) total += g.lb[r] - g.la[r];
+        keep = g.active && g.U <= 32 * CW;
+        nw = (g.U + 31) >> 5;
+        static_assert((64 * (CW + 1)) % 4 == 0, "the tables clear as 16-byte words");
+        uint4* z = reinterpret_cast<uint4*>(lds);
+        for (int k = lane; k < 64 * (CW + 1) / 4; k += 64) z[k] = make_uint4(0, 0, 0, 0);
     }
-    __device__ __forceinline__ void set(int ci)
+    __device__ __forceinline__ void set(int posl)
     {
-        if (keep) atomicOr(&w[ci >> 5], 1u << (ci & 31));
+        if (keep) atomicOr(&w[posl >> 5], 1u << (posl & 31));
     }
-    // Bits of up to 4 consecutive candidates starting at ci (bit k = candidate ci + k),
+    // Bits of up to 4 consecutive positions starting at posl (bit k = position posl + k),
     // with no branch on the bits: two unconditional ORs, the second into the next word
-    // (the padding word after the lane's last one). ci may be -1 with bit 0 clear (the
-    // first record of a segment starting at an odd position).
-    __device__ __forceinline__ void put(int ci, uint32_t bits)
+    // (the padding word after the union's last one).
+    __device__ __forceinline__ void put(int posl, uint32_t bits)
     {
         if (!keep) return;
-        if (ci < 0) {
-            bits >>= 1;
-            ci = 0;
-        }
-        const int wd = ci >> 5, sh = ci & 31;
+        const int wd = posl >> 5, sh = posl & 31;
         atomicOr(&w[wd], bits << sh);
         atomicOr(&w[wd + 1], sh ? bits >> (32 - sh) : 0u);
-    }
-    // candidate index of a logical position inside the lane's ranges
-    __device__ __forceinline__ int index_of(const Geom<DIM>& g, int posl) const
-    {
-        int ci = 0;
-#pragma unroll
-        for (int r = 0; r < NSEG; ++r)
-            if (posl >= g.la[r] && posl < g.lb[r]) ci = segoff[r] + posl - g.la[r];
-        return ci;
     }
     __device__ __forceinline__ void store(const SearchArgs& a, int p) const
     {
         if (!keep) return;
-        const int nw = (total + 31) >> 5;
         for (int k = 0; k < nw; ++k) a.cbits[static_cast<size_t>(k) * a.L.ntot + p] = w[k];
     }
 };
@@ -493,7 +479,6 @@ k_count16(SearchArgs a)
             const int dy = r % 3 - 1, dz = DIM == 3 ? r / 3 - 1 : 0;
             const h2 ay = splat(tg.qiy + static_cast<_Float16>(-2 * dy));
             const h2 az = splat(tg.qiz + static_cast<_Float16>(-2 * dz));
-            const int cbase = cb_.segoff[r] - g.la[r];  // candidate index = cbase + posl
             if constexpr (MODE == 2) {
                 const int selfp = (r == Geom<DIM>::SELF) ? g.pself : -1;
                 for_pairs(lo, hi, [&](int m, uint32_t inv) {
@@ -506,7 +491,7 @@ k_count16(SearchArgs a)
                         if (classify<DIM, MODE>(a, g, pi, r, posl, (rb >> (16 * h)) & 0xFFFF, t, nullptr, cb,
                                                 &oj)) {
                             ++cnt;
-                            cb_.set(cbase + posl);
+                            cb_.set(posl);
                         }
                     }
                 });
@@ -522,7 +507,7 @@ k_count16(SearchArgs a)
                             int oj;
                             if (classify<DIM, 0>(a, g, pi, r, posl, r2h, t, nullptr, cb, &oj)) {
                                 ++cnt;
-                                cb_.set(cbase + posl);
+                                cb_.set(posl);
                             }
                         }
                     }
@@ -533,7 +518,7 @@ k_count16(SearchArgs a)
                     const uint32_t inb = u16x2_bits(d) & 0x80008000u;
                     const uint32_t two = ((inb >> 15) & 1u) | ((inb >> 30) & 2u);
                     cnt += __builtin_popcount(two);
-                    cb_.put(cbase + 2 * m, two);
+                    cb_.put(2 * m, two);
                     const uint32_t x = u16x2_bits(__builtin_elementwise_add_sat(d, th.bias2));
                     if (x != 0xFFFFFFFFu) band(m, rb, x);
                 };
@@ -555,7 +540,7 @@ k_count16(SearchArgs a)
                     const uint32_t nib =
                         ((inA >> 15) & 1u) | ((inA >> 30) & 2u) | ((inB >> 13) & 4u) | ((inB >> 28) & 8u);
                     cnt += __builtin_popcount(nib);
-                    cb_.put(cbase + 2 * m, nib);
+                    cb_.put(2 * m, nib);
                     const uint32_t xA = u16x2_bits(__builtin_elementwise_add_sat(dA, th.bias2));
                     const uint32_t xB = u16x2_bits(__builtin_elementwise_add_sat(dB, th.bias2));
                     if ((xA & xB) != 0xFFFFFFFFu) {
@@ -583,7 +568,7 @@ k_count16(SearchArgs a)
             t.fpos += naive && !truth;
             t.fneg += !naive && truth;
             cnt += truth;
-            if (truth) cb_.set(cb_.index_of(g, posl));
+            if (truth) cb_.set(posl);
         });
         // candidates: the lane's ranges minus itself
         if (g.active) t.cand += cb_.total - 1;
@@ -624,13 +609,23 @@ k_count64(SearchArgs a)
 #pragma unroll
         for (int r = 0; r < Geom<DIM>::NSEG; ++r) {
             const int ga = g.global_of(r, g.la[r]), gb = g.global_of(r, g.lb[r]);
-            const int cbase = cb_.segoff[r] - ga;
+            const int pbase = g.la[r] - ga;  // union position = pbase + j
             cand += gb - ga;
-            for (int j = ga; j < gb; ++j) {
-                const double* pj = a.spos + static_cast<size_t>(j) * 4;
-                if (r2_fp64<DIM>(pix, pj) <= fr.R2) {
-                    ++cnt;
-                    cb_.set(cbase + j);
+            // four candidates per step, their loads issued together (the last index is
+            // repeated past the range end and its result dropped)
+            for (int j = ga; j < gb; j += 4) {
+                double d2[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double* pj = a.spos + static_cast<size_t>(min(j + u, gb - 1)) * 4;
+                    d2[u] = r2_fp64<DIM>(pix, pj);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (j + u < gb && d2[u] <= fr.R2) {
+                        ++cnt;
+                        cb_.set(pbase + j + u);
+                    }
                 }
             }
         }
@@ -856,26 +851,18 @@ k_fill(SearchArgs a)
     const int rlen = g.active ? static_cast<int>(sd.row_ptr[li + 1] - rs) : 0;
     int E;
     const int off = wave_excl_scan_i32(rlen, &E);
-    // the lane's candidate order (row segment by row segment), as in the count pass
-    int segoff[Geom<DIM>::NSEG];
-    int ctotal = 0;
-#pragma unroll
-    for (int r = 0; r < Geom<DIM>::NSEG; ++r) {
-        segoff[r] = ctotal;
-        ctotal += g.lb[r] - g.la[r];
-    }
-    const bool fits = !g.active || ctotal <= 32 * CB::CW;
-    if (g.U > C::UCAP || E > C::FCAP || __ballot(!fits) != 0) {
+    static_assert(32 * CB::CW == C::UCAP, "the count pass keeps a bit per union position");
+    if (g.U > C::UCAP || E > C::FCAP) {
         // too big for this path: every row of the block goes to the long-row path
         if (wv == 0 && g.active) a.heavy[atomicAdd(a.nheavy, 1)] = g.p;
         return;
     }
-    // the count pass's accepted-candidate bits, this wavefront's words w = wv + NW k, are
-    // loaded first: their latency is hidden behind the staging and ranking
+    // the count pass's accepted-candidate bits (by union position), this wavefront's words
+    // w = wv + NW k, are loaded first: their latency is hidden behind staging and ranking
     constexpr int KW = (CB::CW + NW - 1) / NW;
     uint32_t wbits[KW];
     {
-        const int nwt = g.active ? (ctotal + 31) >> 5 : 0;
+        const int nwt = g.active ? (g.U + 31) >> 5 : 0;
 #pragma unroll
         for (int k = 0; k < KW; ++k) {
             const int w = wv + NW * k;
@@ -933,10 +920,6 @@ k_fill(SearchArgs a)
     // mask; wavefront wv takes the target's bit words w = wv (mod 4)
     uint32_t* mk = masks + lane * (C::MW + 1);
     if (g.active) {
-        // union position of candidate ci: ci plus its row segment's shift
-        int dseg[Geom<DIM>::NSEG];
-#pragma unroll
-        for (int r = 0; r < Geom<DIM>::NSEG; ++r) dseg[r] = g.la[r] - segoff[r];
 #pragma unroll
         for (int k = 0; k < KW; ++k) {
             const int w = wv + NW * k;
@@ -944,21 +927,14 @@ k_fill(SearchArgs a)
             // four bits per round: their rank lookups are issued together, and bits past
             // the word's last read entry 0 and OR nothing
             while (bits) {
-                int posl[4];
-                uint32_t on[4];
+                uint32_t rk[4], on[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     on[j] = bits != 0u ? 1u : 0u;
-                    const int ci = 32 * w + __builtin_ctz(bits | (on[j] ? 0u : 1u));
+                    const int posl = 32 * w + __builtin_ctz(bits | (on[j] ? 0u : 1u));
                     bits &= bits - 1u;
-                    int d = dseg[0];
-#pragma unroll
-                    for (int r = 1; r < Geom<DIM>::NSEG; ++r) d = ci >= segoff[r] ? dseg[r] : d;
-                    posl[j] = on[j] ? ci + d : 0;
+                    rk[j] = rank_of[on[j] ? posl : 0];
                 }
-                uint32_t rk[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) rk[j] = rank_of[posl[j]];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) atomicOr(&mk[rk[j] >> 5], on[j] << (rk[j] & 31));
             }
