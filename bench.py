@@ -55,53 +55,22 @@ def describe(ps):
 
 
 def time_mode(ctx, pos, ps, mode, steps, warmup):
-    """Returns (ms per step, nnz, stats, per-phase mean ms) for one mode."""
-    import torch
-    from paper_2401_08586_amd import nnps
-    cells = ctx.cells()
-    n = ps.n
-    rp = torch.empty(n + 1, dtype=torch.int64, device="cuda")
-    cells.build(pos, ps.lo, ps.hi, ps.cell_size, ps.radius, mode)
-    nnz = cells.count(rp, sync=True)
-    col = torch.empty(nnz, dtype=torch.int32, device="cuda")
-    dist = torch.empty(nnz, dtype=torch.float32, device="cuda")
-    cells.fill(rp, col, dist)
-    st = cells.stats()
-
-    def step():
-        cells.build(pos, ps.lo, ps.hi, ps.cell_size, ps.radius, mode)
-        cells.count(rp, sync=False)
-        cells.fill(rp, col, dist)
-
-    for _ in range(warmup):
-        step()
-    cells.set_profiling(True)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record()
-    for _ in range(steps):
-        step()
-    e1.record()
-    torch.cuda.synchronize()
-    wall_ms = (time.perf_counter() - t0) * 1e3
-    ev_ms = e0.elapsed_time(e1)
-    ph = cells.phase_times()
-    cells.set_profiling(False)
-    st2 = cells.stats()  # surfaces any device-side error of the timed steps
-    assert st2["nnz"] == nnz
-    phases = {k: (v[0] / v[1] if v[1] else None) for k, v in ph.items()}
-    cells.close()
-    return max(wall_ms, ev_ms) / steps, nnz, st, phases
+    """Returns (ms per step, nnz, stats, per-phase mean ms) for one mode: the timed steps
+    replay the captured build + count + fill of the set (no events inside), and the
+    per-phase means come from as many eager steps with an event pair around each phase."""
+    ms, nnz, st, phases = time_batch(ctx, [ps], mode, steps, warmup, pos=[pos], phase_steps=steps)
+    return ms, nnz, st, phases
 
 
-def time_batch(ctx, pss, mode, steps, warmup, graphs=True):
+def time_batch(ctx, pss, mode, steps, warmup, graphs=True, pos=None, phase_steps=1):
     """Batch of particle sets: one graph-captured step (build + count + fill) per timed
-    step. Returns (ms per step, total nnz, stats, per-phase mean ms)."""
+    step. Returns (ms per step, total nnz, stats, per-phase mean ms over `phase_steps`
+    further eager steps)."""
     import torch
     from paper_2401_08586_amd import nnps
-    sets = [(torch.from_numpy(p.pos).cuda(), p.lo, p.hi, p.cell_size, p.radius) for p in pss]
+    if pos is None:
+        pos = [torch.from_numpy(p.pos).cuda() for p in pss]
+    sets = [(x, p.lo, p.hi, p.cell_size, p.radius) for x, p in zip(pos, pss)]
     cells = ctx.cells()
     cells.batch_build(sets, mode)
     rps = [torch.empty(p.n + 1, dtype=torch.int64, device="cuda") for p in pss]
@@ -126,11 +95,12 @@ def time_batch(ctx, pss, mode, steps, warmup, graphs=True):
         stream.synchronize()
     wall = (time.perf_counter() - t0) * 1e3
     assert cells.batch_nnz(stream=stream) == nnz
-    # per-phase times of one more (eager) step
+    # per-phase times of further eager steps
     cells.set_graphs(False)
     cells.set_profiling(True)
     with torch.cuda.stream(stream):
-        cells.batch_step(sets, rps, cols, dists, mode, stream=stream)
+        for _ in range(max(1, phase_steps)):
+            cells.batch_step(sets, rps, cols, dists, mode, stream=stream)
     ph = cells.phase_times(stream=stream)
     cells.set_profiling(False)
     cells.close()

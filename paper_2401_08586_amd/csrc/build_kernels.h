@@ -20,15 +20,15 @@ struct Launch {
 
 hipError_t launch_fill_i32(int* p, int64_t m, int v, hipStream_t st);
 int row_segments(int ncx);  // pieces a row of ncx cells is walked in
-hipError_t launch_assign(const Launch& L, int64_t* X, uint32_t* key, int* cell_count, int* err, hipStream_t st);
+hipError_t launch_assign(const Launch& L, int64_t* X, uint32_t* key, int* slot, int* cell_count, int* err,
+                         hipStream_t st);
+hipError_t launch_place(int ntot, const uint32_t* key, const int* slot, const int* cell_start, uint32_t* skey,
+                        int* perm, hipStream_t st);
 hipError_t launch_scan_i32_i32(const int* in, int64_t m, int* out, int64_t* partial, hipStream_t st);
 hipError_t launch_scan_i32_i64(const int* in, int64_t m, int64_t* out, int64_t* partial, hipStream_t st);
 int64_t scan_partials_needed(int64_t m);
 int radix_tiles(int n);
 size_t radix_table_entries(int n);
-hipError_t launch_radix_sort(int n, int keybits, uint32_t* k0, int* v0, uint32_t* k1, int* v1,
-                             uint32_t* table, int64_t* partial, hipStream_t st, uint32_t** kfinal,
-                             int** vfinal);
 hipError_t launch_pack(const Launch& L, const uint32_t* skey, const int* perm, const int64_t* X, ushort4* q4,
                        double* spos, int* inv, hipStream_t st);
 hipError_t launch_blocks(const Launch& L, const uint32_t* skey, const int* cell_start, const int* wdense, int* flags,

@@ -1,5 +1,6 @@
-// Cell build: FP64 cell assignment, a stable LDS radix sort by cell, cell starts by
-// a device-wide scan, the FP16 relative-coordinate pack and the work-block table.
+// Cell build: FP64 cell assignment with a slot per particle in its cell, cell starts by a
+// device-wide scan, a counting sort by cell, the FP16 relative-coordinate pack and the
+// work-block table (the LDS radix sort serves the dense-cell lists).
 //
 // Paper: cell link list with cell size equal to the search radius (SPH method
 // section, Fig. 3b); cell-relative coordinates (Eq. 5-6, Fig. 5); spatial sorting
@@ -26,11 +27,13 @@ __device__ __forceinline__ float exact_i64_to_f32(int64_t v)
 // A1: cell assignment in FP64. X = rint((p - lo) * 2^F / w) (round half to even, stored
 // per particle with stride x_stride), cell = X >> F, global key = coff + cx + ncx (cy +
 // ncy cz). Positions outside [lo, hi] (or NaN) raise the domain flag and are treated as
-// lo so every index stays in range.
+// lo so every index stays in range. Each particle also takes a slot in its cell (the
+// cell's count before it), which places it in the sort by cell: runs of consecutive
+// lanes with the same cell take their slots with one atomic, in lane order.
 template <int DIM>
 __global__ void __launch_bounds__(256)
 k_assign(const SetDesc* __restrict__ sets, const int* __restrict__ poffs, int nsets, int ntot,
-         int64_t* __restrict__ X, uint32_t* __restrict__ key, int* __restrict__ cell_count,
+         int64_t* __restrict__ X, uint32_t* __restrict__ key, int* __restrict__ slot, int* __restrict__ cell_count,
          int* __restrict__ err)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -55,8 +58,32 @@ k_assign(const SetDesc* __restrict__ sets, const int* __restrict__ poffs, int ns
     }
     const uint32_t kk = static_cast<uint32_t>(sd.coff + c[0] + fr.nc[0] * (c[1] + fr.nc[1] * c[2]));
     key[i] = kk;
-    atomicAdd(&cell_count[kk], 1);
+    // the active lanes are a prefix of the wavefront (i = base + lane, tail lanes returned)
+    const int lane = threadIdx.x & 63;
+    const int prev = __shfl_up(static_cast<int>(kk), 1, 64);
+    const uint64_t heads = __ballot(lane == 0 || static_cast<uint32_t>(prev) != kk);
+    const int nact = __popcll(__ballot(1));
+    const uint64_t upto = lane == 63 ? ~0ull : (2ull << lane) - 1ull;
+    const int head = 63 - __clzll(heads & upto);  // first lane of this lane's run
+    const uint64_t after = heads & ~upto;
+    const int next = after ? __ffsll(static_cast<long long>(after)) - 1 : nact;
+    int base = 0;
+    if (head == lane) base = atomicAdd(&cell_count[kk], next - lane);
+    slot[i] = __shfl(base, head, 64) + (lane - head);
     if (bad) atomicOr(err, kErrDomain);
+}
+
+// Counting sort by cell: particle i goes to cell_start[key] + slot.
+__global__ void __launch_bounds__(256)
+k_place(const uint32_t* __restrict__ key, const int* __restrict__ slot, const int* __restrict__ cell_start,
+        int ntot, uint32_t* __restrict__ skey, int* __restrict__ perm)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ntot) return;
+    const uint32_t kk = key[i];
+    const int at = cell_start[kk] + slot[i];
+    skey[at] = kk;
+    perm[at] = i;
 }
 
 // Fill an int32 array with a value (a kernel rather than a memset node, so the sequence
@@ -588,14 +615,23 @@ hipError_t launch_fill_i32(int* p, int64_t m, int v, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_assign(const Launch& L, int64_t* X, uint32_t* key, int* cell_count, int* err, hipStream_t st)
+hipError_t launch_place(int ntot, const uint32_t* key, const int* slot, const int* cell_start, uint32_t* skey,
+                        int* perm, hipStream_t st)
+{
+    if (ntot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_place, dim3((ntot + 255) / 256), dim3(256), 0, st, key, slot, cell_start, ntot, skey, perm);
+    return hipGetLastError();
+}
+
+hipError_t launch_assign(const Launch& L, int64_t* X, uint32_t* key, int* slot, int* cell_count, int* err,
+                         hipStream_t st)
 {
     if (L.ntot == 0) return hipSuccess;
     const dim3 g((L.ntot + 255) / 256), b(256);
     if (L.dim == 2)
-        hipLaunchKernelGGL(k_assign<2>, g, b, 0, st, L.sets, L.poffs, L.nsets, L.ntot, X, key, cell_count, err);
+        hipLaunchKernelGGL(k_assign<2>, g, b, 0, st, L.sets, L.poffs, L.nsets, L.ntot, X, key, slot, cell_count, err);
     else
-        hipLaunchKernelGGL(k_assign<3>, g, b, 0, st, L.sets, L.poffs, L.nsets, L.ntot, X, key, cell_count, err);
+        hipLaunchKernelGGL(k_assign<3>, g, b, 0, st, L.sets, L.poffs, L.nsets, L.ntot, X, key, slot, cell_count, err);
     return hipGetLastError();
 }
 
@@ -632,42 +668,6 @@ hipError_t radix_sort_kv_dev(int n, const int* ndev, int keybits, uint32_t* k0, 
                            vout, n, shift, bits, table, ntiles, ndev);
         std::swap(kin, kout);
         std::swap(vin, vout);
-    }
-    *kfinal = kin;
-    *vfinal = vin;
-    return hipGetLastError();
-}
-
-hipError_t launch_radix_sort(int n, int keybits, uint32_t* k0, int* v0, uint32_t* k1, int* v1,
-                             uint32_t* table, int64_t* partial, hipStream_t st, uint32_t** kfinal,
-                             int** vfinal)
-{
-    // the first pass reads the identity permutation implicitly; v0 is the second value buffer
-    const int ntiles = radix_tiles(n);
-    const int passes = keybits <= 0 ? 1 : (keybits + kRsMaxBits - 1) / kRsMaxBits;
-    const int bits = keybits <= 0 ? 1 : (keybits + passes - 1) / passes;
-    uint32_t* kin = k0;
-    int* vin = nullptr;
-    uint32_t* kout = k1;
-    int* vout = v1;
-    for (int p = 0; p < passes; ++p) {
-        const int shift = p * bits;
-        hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kRsThreads), 0, st, kin, n, shift, bits,
-                           table, ntiles, static_cast<const int*>(nullptr));
-        hipError_t e = scan_exclusive<uint32_t, uint32_t>(table, static_cast<int64_t>(ntiles) << bits,
-                                                          table, partial, st);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(kRsThreads), 0, st, kin, vin, kout,
-                           vout, n, shift, bits, table, ntiles, static_cast<const int*>(nullptr));
-        if (p == 0) {
-            kin = k1;
-            vin = v1;
-            kout = k0;
-            vout = v0;
-        } else {
-            std::swap(kin, kout);
-            std::swap(vin, vout);
-        }
     }
     *kfinal = kin;
     *vfinal = vin;

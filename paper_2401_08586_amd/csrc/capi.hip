@@ -439,8 +439,7 @@ nnps_status prepare(nnps_ctx* ctx, nnps_cells* c, int nsets, const nnps_problem*
     c->dcap = c->dense ? std::max<int64_t>(1, std::min<int64_t>((c->dim == 3 ? 27 : 9) * static_cast<int64_t>(nn), dmax))
                        : 0;
     const size_t dcap = static_cast<size_t>(c->dcap);
-    const size_t table_n = std::max(radix_table_entries(static_cast<int>(nn)),
-                                    c->dense ? radix_table_entries(static_cast<int>(dcap)) : size_t(0)) + 1;
+    const size_t table_n = (c->dense ? radix_table_entries(static_cast<int>(dcap)) : size_t(0)) + 1;
     const int64_t scan_m = std::max<int64_t>({static_cast<int64_t>(nn) + 1, static_cast<int64_t>(nc) + 1,
                                               static_cast<int64_t>(table_n)});
     const bool base = c->mode == NNPS_MODE_FP64_BASELINE;
@@ -495,21 +494,19 @@ nnps_status enqueue_build(nnps_cells* c, hipStream_t s)
     HIP_TRY(launch_fill_i32(c->cell_count.as<int>(), static_cast<int64_t>(c->ncell_tot) + 1, 0, s));
     HIP_TRY(launch_fill_i32(c->err.as<int>(), 1, 0, s));
     tm.begin(NNPS_PHASE_ASSIGN, s);
-    HIP_TRY(launch_assign(L, c->X.as<int64_t>(), c->k0.as<uint32_t>(), c->cell_count.as<int>(), c->err.as<int>(), s));
+    HIP_TRY(launch_assign(L, c->X.as<int64_t>(), c->k0.as<uint32_t>(), c->v1.as<int>(), c->cell_count.as<int>(),
+                          c->err.as<int>(), s));
     tm.end(NNPS_PHASE_ASSIGN, s);
     tm.begin(NNPS_PHASE_CELLSCAN, s);
     HIP_TRY(launch_scan_i32_i32(c->cell_count.as<int>(), c->ncell_tot, c->cell_start.as<int>(),
                                 c->partial.as<int64_t>(), s));
     tm.end(NNPS_PHASE_CELLSCAN, s);
-    uint32_t* kf = c->k0.as<uint32_t>();
-    int* vf = c->v0.as<int>();
     tm.begin(NNPS_PHASE_SORT, s);
-    if (c->ntot > 0) {
-        const int keybits = bitlen(static_cast<int64_t>(c->ncell_tot) - 1);
-        HIP_TRY(launch_radix_sort(c->ntot, keybits, c->k0.as<uint32_t>(), c->v0.as<int>(), c->k1.as<uint32_t>(),
-                                  c->v1.as<int>(), c->table.as<uint32_t>(), c->partial.as<int64_t>(), s, &kf, &vf));
-    }
+    HIP_TRY(launch_place(c->ntot, c->k0.as<uint32_t>(), c->v1.as<int>(), c->cell_start.as<int>(),
+                         c->k1.as<uint32_t>(), c->v0.as<int>(), s));
     tm.end(NNPS_PHASE_SORT, s);
+    uint32_t* kf = c->k1.as<uint32_t>();
+    int* vf = c->v0.as<int>();
     c->skey = kf;
     c->perm = vf;
     tm.begin(NNPS_PHASE_PACK, s);
