@@ -31,8 +31,8 @@ int radix_tiles(int n);
 size_t radix_table_entries(int n);
 hipError_t launch_pack(const Launch& L, const uint32_t* skey, const int* perm, const int64_t* X, ushort4* q4,
                        double* spos, int* inv, hipStream_t st);
-hipError_t launch_blocks(const Launch& L, const uint32_t* skey, const int* cell_start, const int* wdense, int* flags,
-                         int* bidx, int* bstart, int* bset, int64_t* partial, hipStream_t st);
+hipError_t launch_blocks(const Launch& L, const int* cell_start, const int* wdense, int* boff, int* bstart, int* bset,
+                         int64_t* partial, hipStream_t st);
 
 // Dense-cell path: device tables of one build. A cell is "dense" when its stencil holds
 // more than `thresh` particles; runs of dense cells get no work blocks. Each dense cell g owns the list ulist[uoff[g] ..

@@ -38,25 +38,30 @@ k_assign(const SetDesc* __restrict__ sets, const int* __restrict__ poffs, int ns
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ntot) return;
-    const SetDesc& sd = sets[find_set(poffs, nsets, i)];
-    const Frame& fr = sd.fr;
-    const int li = i - sd.poff;
     bool bad = false;
-    int64_t c[3] = {0, 0, 0};
+    auto cell_of = [&](const SetDesc& sd) -> uint32_t {
+        const Frame& fr = sd.fr;
+        const int li = i - sd.poff;
+        int64_t c[3] = {0, 0, 0};
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-        double p = sd.pos[static_cast<size_t>(li) * DIM + k];
-        if (!(p >= fr.lo[k] && p <= fr.hi[k])) {
-            bad = true;
-            p = fr.lo[k];
+        for (int k = 0; k < DIM; ++k) {
+            double p = sd.pos[static_cast<size_t>(li) * DIM + k];
+            if (!(p >= fr.lo[k] && p <= fr.hi[k])) {
+                bad = true;
+                p = fr.lo[k];
+            }
+            const double d = __dsub_rn(p, fr.lo[k]);
+            const double t = __dmul_rn(d, fr.s);
+            const int64_t x = static_cast<int64_t>(rint(t));
+            X[static_cast<size_t>(i) * x_stride(DIM) + k] = x;
+            c[k] = x >> fr.F;
         }
-        const double d = __dsub_rn(p, fr.lo[k]);
-        const double t = __dmul_rn(d, fr.s);
-        const int64_t x = static_cast<int64_t>(rint(t));
-        X[static_cast<size_t>(i) * x_stride(DIM) + k] = x;
-        c[k] = x >> fr.F;
-    }
-    const uint32_t kk = static_cast<uint32_t>(sd.coff + c[0] + fr.nc[0] * (c[1] + fr.nc[1] * c[2]));
+        return static_cast<uint32_t>(sd.coff + c[0] + fr.nc[0] * (c[1] + fr.nc[1] * c[2]));
+    };
+    // a wavefront inside one set reads the set's fields with scalar loads
+    const int s = find_set(poffs, nsets, i);
+    const int s0 = __builtin_amdgcn_readfirstlane(s);
+    const uint32_t kk = __all(s == s0) ? cell_of(sets[s0]) : cell_of(sets[s]);
     key[i] = kk;
     // the active lanes are a prefix of the wavefront (i = base + lane, tail lanes returned)
     const int lane = threadIdx.x & 63;
@@ -204,6 +209,41 @@ k_scan_down(const TIn* __restrict__ in, int64_t m, const int64_t* __restrict__ p
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[m] = static_cast<TOut>(partial[nt]);
 }
 
+// The same final phase for up to kScanFold tiles, each workgroup summing the tile sums
+// before its own (no separate scan of the tile sums; a single tile needs no tile sums).
+constexpr int64_t kScanFold = 1024;
+
+template <typename TIn, typename TOut>
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_down_fold(const TIn* __restrict__ in, int64_t m, const int64_t* __restrict__ partial,
+                 TOut* __restrict__ out, const int* gate)
+{
+    if (gate && *gate == 0) return;
+    __shared__ int64_t sh[4];
+    int64_t before = 0;
+    for (int64_t t = threadIdx.x; t < blockIdx.x; t += kScanThreads) before += partial[t];
+    int64_t offset;
+    block_excl_scan(before, &offset, sh);
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
+    TIn v[kScanItems];
+    int64_t s = 0;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        const int64_t idx = base + r;
+        v[r] = idx < m ? in[idx] : TIn(0);
+        s += static_cast<int64_t>(v[r]);
+    }
+    int64_t tot;
+    int64_t run = block_excl_scan(s, &tot, sh) + offset;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        const int64_t idx = base + r;
+        if (idx < m) out[idx] = static_cast<TOut>(run);
+        run += static_cast<int64_t>(v[r]);
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[m] = static_cast<TOut>(offset + tot);
+}
+
 template <typename T>
 __global__ void k_zero_one(T* p) { *p = T(0); }
 
@@ -215,6 +255,13 @@ hipError_t scan_exclusive(const TIn* in, int64_t m, TOut* out, int64_t* partial,
     if (nt == 0) {
         // m == 0: out[0] = 0
         hipLaunchKernelGGL(k_zero_one<TOut>, dim3(1), dim3(1), 0, st, out);
+        return hipGetLastError();
+    }
+    if (nt <= kScanFold) {
+        if (nt > 1)
+            hipLaunchKernelGGL(k_scan_reduce<TIn>, dim3(nt), dim3(kScanThreads), 0, st, in, m, partial, gate);
+        hipLaunchKernelGGL((k_scan_down_fold<TIn, TOut>), dim3(nt), dim3(kScanThreads), 0, st, in, m, partial, out,
+                           gate);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_scan_reduce<TIn>, dim3(nt), dim3(kScanThreads), 0, st, in, m, partial, gate);
@@ -338,27 +385,33 @@ k_pack(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nset
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= ntot) return;
-    const SetDesc& sd = sets[find_set(coffs, nsets, static_cast<int>(skey[p]))];
-    const Frame& fr = sd.fr;
     const int o = perm[p];
     if (inv) inv[o] = p;
-    if (spos) {
+    auto pack = [&](const SetDesc& sd) {
+        const Frame& fr = sd.fr;
+        if (spos) {
 #pragma unroll
-        for (int k = 0; k < DIM; ++k)
-            spos[static_cast<size_t>(p) * 4 + k] = sd.pos[static_cast<size_t>(o - sd.poff) * DIM + k];
-    }
-    uint16_t h[4] = {0, 0, 0, 0};
-    const float scale = __builtin_ldexpf(1.0f, 1 - fr.F);
+            for (int k = 0; k < DIM; ++k)
+                spos[static_cast<size_t>(p) * 4 + k] = sd.pos[static_cast<size_t>(o - sd.poff) * DIM + k];
+        }
+        uint16_t h[4] = {0, 0, 0, 0};
+        const float scale = __builtin_ldexpf(1.0f, 1 - fr.F);
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-        const int64_t x = X[static_cast<size_t>(o) * x_stride(DIM) + k];
-        const int64_t c = x >> fr.F;
-        const int64_t D = x - (c << fr.F) - (int64_t(1) << (fr.F - 1));
-        const _Float16 q = static_cast<_Float16>(exact_i64_to_f32(D) * scale);
-        h[k] = __builtin_bit_cast(uint16_t, q);
-        if (k == 0) h[3] = static_cast<uint16_t>(c & 0xFFFF);
-    }
-    q4[p] = make_ushort4(h[0], h[1], h[2], h[3]);
+        for (int k = 0; k < DIM; ++k) {
+            const int64_t x = X[static_cast<size_t>(o) * x_stride(DIM) + k];
+            const int64_t c = x >> fr.F;
+            const int64_t D = x - (c << fr.F) - (int64_t(1) << (fr.F - 1));
+            const _Float16 q = static_cast<_Float16>(exact_i64_to_f32(D) * scale);
+            h[k] = __builtin_bit_cast(uint16_t, q);
+            if (k == 0) h[3] = static_cast<uint16_t>(c & 0xFFFF);
+        }
+        q4[p] = make_ushort4(h[0], h[1], h[2], h[3]);
+    };
+    // a wavefront inside one set reads the set's fields with scalar loads
+    const int s = find_set(coffs, nsets, static_cast<int>(skey[p]));
+    const int s0 = __builtin_amdgcn_readfirstlane(s);
+    if (__all(s == s0)) pack(sets[s0]);
+    else pack(sets[s]);
 }
 
 // ---------------------------------------------------------------------------
@@ -366,13 +419,17 @@ k_pack(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nset
 // the segment in x, a block is a run of at most kWave consecutive sorted particles whose
 // cells span at most fr.xwin cells; it starts where the previous one ended (so blocks are
 // full unless the span, the segment or the row ends them). A run of dense cells (the
-// dense-cell path's) is one block that the block kernels skip. flags (zeroed beforehand)
-// receives 1 at every block start.
+// dense-cell path's) is one block that the block kernels skip. The walk runs twice: the
+// first counts each segment's blocks (nb[r]), the second, after an exclusive scan of the
+// counts into boff, writes block boff[r] + j's first particle and set. Blocks come out in
+// particle order, so block b ends where block b + 1 starts; bstart[total] = ntot.
 constexpr int kRowSegment = 64;
 
+template <bool WRITE>
 __global__ void __launch_bounds__(256)
-k_row_blocks(const SetDesc* __restrict__ sets, const int* __restrict__ roffs, int nsets, int nrows_tot,
-             const int* __restrict__ cell_start, const int* __restrict__ wdense, int* __restrict__ flags)
+k_row_blocks(const SetDesc* __restrict__ sets, const int* __restrict__ roffs, int nsets, int nrows_tot, int ntot,
+             const int* __restrict__ cell_start, const int* __restrict__ wdense, int* __restrict__ nb_or_boff,
+             int* __restrict__ bstart, int* __restrict__ bset)
 {
     const int r = blockIdx.x * (blockDim.x >> 6) + static_cast<int>(threadIdx.x >> 6);
     if (r >= nrows_tot) return;
@@ -385,9 +442,18 @@ k_row_blocks(const SetDesc* __restrict__ sets, const int* __restrict__ roffs, in
     const int rs = r - roffs[s];
     const int g0 = sd.coff + (rs / nseg) * ncx;
     const int base = (rs % nseg) * kRowSegment;
+    const int b0 = WRITE ? nb_or_boff[r] : 0;
+    if (WRITE && r == nrows_tot - 1 && lane == 0) bstart[nb_or_boff[nrows_tot]] = ntot;
     // wavefront-uniform walk state
-    int bs = -1, xs = 0;
+    int bs = -1, xs = 0, nb = 0;
     bool dense_open = false;
+    auto start = [&](int a) {
+        if (WRITE && lane == 0) {
+            bstart[b0 + nb] = a;
+            bset[b0 + nb] = s;
+        }
+        ++nb;
+    };
     {
         const int x = base + lane;
         int c0 = 0, c1 = 0, dn = 0;
@@ -405,38 +471,26 @@ k_row_blocks(const SetDesc* __restrict__ sets, const int* __restrict__ roffs, in
             const int xx = base + i;
             if (ad) {
                 if (bs < 0 || !dense_open) {
-                    if (lane == i) flags[a0] = 1;
+                    start(a0);
                     bs = a0;
                     dense_open = true;
                 }
                 continue;
             }
             if (bs < 0 || dense_open || xx - xs >= span) {
-                if (lane == i) flags[a0] = 1;
+                start(a0);
                 bs = a0;
                 xs = xx;
                 dense_open = false;
             }
             while (a1 - bs > kWave) {
                 bs += kWave;
-                if (lane == i) flags[bs] = 1;
+                start(bs);
                 xs = xx;
             }
         }
     }
-}
-
-__global__ void __launch_bounds__(256)
-k_block_write(const int* __restrict__ coffs, int nsets, int ntot, const uint32_t* __restrict__ skey,
-              const int* __restrict__ flags, const int* __restrict__ bidx, int* __restrict__ bstart,
-              int* __restrict__ bset)
-{
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < ntot && flags[p]) {
-        bstart[bidx[p]] = p;
-        bset[bidx[p]] = find_set(coffs, nsets, static_cast<int>(skey[p]));
-    }
-    if (p == 0) bstart[bidx[ntot]] = ntot;
+    if (!WRITE && lane == 0) nb_or_boff[r] = nb;
 }
 
 // Per-set CSR row pointers from the global exclusive scan of the counts (one thread per
@@ -688,18 +742,17 @@ hipError_t launch_pack(const Launch& L, const uint32_t* skey, const int* perm, c
     return hipGetLastError();
 }
 
-hipError_t launch_blocks(const Launch& L, const uint32_t* skey, const int* cell_start, const int* wdense, int* flags,
-                         int* bidx, int* bstart, int* bset, int64_t* partial, hipStream_t st)
+hipError_t launch_blocks(const Launch& L, const int* cell_start, const int* wdense, int* boff, int* bstart, int* bset,
+                         int64_t* partial, hipStream_t st)
 {
-    if (L.ntot == 0) return launch_fill_i32(bidx, 1, 0, st);
-    hipError_t e = launch_fill_i32(flags, L.ntot, 0, st);
+    if (L.ntot == 0) return launch_fill_i32(boff, static_cast<int64_t>(L.nrows_tot) + 1, 0, st);
+    const dim3 g((L.nrows_tot + 3) / 4), b(256);
+    hipLaunchKernelGGL(k_row_blocks<false>, g, b, 0, st, L.sets, L.roffs, L.nsets, L.nrows_tot, L.ntot, cell_start,
+                       wdense, boff, bstart, bset);
+    hipError_t e = scan_exclusive<int, int>(boff, L.nrows_tot, boff, partial, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_row_blocks, dim3((L.nrows_tot + 3) / 4), dim3(256), 0, st, L.sets, L.roffs, L.nsets,
-                       L.nrows_tot, cell_start, wdense, flags);
-    e = scan_exclusive<int, int>(flags, L.ntot, bidx, partial, st);
-    if (e != hipSuccess) return e;
-    const dim3 g((L.ntot + 255) / 256), b(256);
-    hipLaunchKernelGGL(k_block_write, g, b, 0, st, L.coffs, L.nsets, L.ntot, skey, flags, bidx, bstart, bset);
+    hipLaunchKernelGGL(k_row_blocks<true>, g, b, 0, st, L.sets, L.roffs, L.nsets, L.nrows_tot, L.ntot, cell_start,
+                       wdense, boff, bstart, bset);
     return hipGetLastError();
 }
 

@@ -228,7 +228,7 @@ struct nnps_cells {
     uint64_t buf_gen = 0;                 // bumps whenever a device buffer moves
     uint32_t* skey = nullptr;
     int* perm = nullptr;
-    DevBuf d_sets, d_offs, X, k0, k1, v0, v1, cell_count, cell_start, q4, spos, flags, bidx, bstart, bset,
+    DevBuf d_sets, d_offs, X, k0, k1, v0, v1, cell_count, cell_start, q4, spos, boff, bstart, bset,
         counts, table, partial, stats, blk_stats, cbits, err, heavy, nheavy, rowg, nnz, sink;
     // dense-cell path (see DenseBuild)
     bool dense = false;         // the tuning allows the dense-cell path
@@ -303,7 +303,7 @@ SearchArgs args_of(const nnps_cells* c)
     a.X = c->X.as<int64_t>();
     a.bstart = c->bstart.as<int>();
     a.bset = c->bset.as<int>();
-    a.nblk = c->bidx.as<int>() + c->ntot;
+    a.nblk = c->boff.as<int>() + c->nrows_tot;
     a.counts = c->counts.as<int>();
     a.heavy = c->heavy.as<int>();
     a.nheavy = c->nheavy.as<int>();
@@ -441,7 +441,8 @@ nnps_status prepare(nnps_ctx* ctx, nnps_cells* c, int nsets, const nnps_problem*
     const size_t dcap = static_cast<size_t>(c->dcap);
     const size_t table_n = (c->dense ? radix_table_entries(static_cast<int>(dcap)) : size_t(0)) + 1;
     const int64_t scan_m = std::max<int64_t>({static_cast<int64_t>(nn) + 1, static_cast<int64_t>(nc) + 1,
-                                              static_cast<int64_t>(table_n)});
+                                              static_cast<int64_t>(table_n),
+                                              static_cast<int64_t>(c->nrows_tot) + 1});
     const bool base = c->mode == NNPS_MODE_FP64_BASELINE;
     const int cw = c->dim == 3 ? kCandWords3 : kCandWords2;
     struct Need {
@@ -455,7 +456,7 @@ nnps_status prepare(nnps_ctx* ctx, nnps_cells* c, int nsets, const nnps_problem*
         {&c->cell_count, (nc + 1) * 4}, {&c->cell_start, (nc + 1) * 4},
         {&c->q4, nn * sizeof(ushort4)},
         {&c->spos, base ? nn * 4 * sizeof(double) : 0},
-        {&c->flags, nn * 4}, {&c->bidx, (nn + 1) * 4}, {&c->bstart, (nn + 2) * 4}, {&c->bset, (nn + 1) * 4},
+        {&c->boff, (static_cast<size_t>(c->nrows_tot) + 1) * 4}, {&c->bstart, (nn + 2) * 4}, {&c->bset, (nn + 1) * 4},
         {&c->counts, nn * 4},
         {&c->table, table_n * 4},
         {&c->partial, static_cast<size_t>(scan_partials_needed(scan_m) + 1) * 8},
@@ -529,9 +530,8 @@ nnps_status enqueue_build(nnps_cells* c, hipStream_t s)
         tm.end(NNPS_PHASE_UNIONS, s);
     }
     tm.begin(NNPS_PHASE_BLOCKS, s);
-    HIP_TRY(launch_blocks(L, c->skey, c->cell_start.as<int>(), c->dense_active ? c->wdense.as<int>() : nullptr,
-                          c->flags.as<int>(), c->bidx.as<int>(), c->bstart.as<int>(), c->bset.as<int>(),
-                          c->partial.as<int64_t>(), s));
+    HIP_TRY(launch_blocks(L, c->cell_start.as<int>(), c->dense_active ? c->wdense.as<int>() : nullptr,
+                          c->boff.as<int>(), c->bstart.as<int>(), c->bset.as<int>(), c->partial.as<int64_t>(), s));
     tm.end(NNPS_PHASE_BLOCKS, s);
     c->built = true;
     c->counted = false;
@@ -727,7 +727,7 @@ void nnps_cells_destroy(nnps_cells* c)
     DeviceGuard g(c->ctx->device);
     if (c->upload_pending) (void)hipEventSynchronize(c->upload_done);
     DevBuf* all[] = {&c->d_sets, &c->d_offs, &c->X, &c->k0, &c->k1, &c->v0, &c->v1, &c->cell_count,
-                     &c->cell_start, &c->q4, &c->spos, &c->flags, &c->bidx, &c->bstart, &c->bset, &c->counts,
+                     &c->cell_start, &c->q4, &c->spos, &c->boff, &c->bstart, &c->bset, &c->counts,
                      &c->table, &c->partial, &c->stats, &c->blk_stats, &c->cbits, &c->err, &c->heavy,
                      &c->nheavy, &c->rowg, &c->nnz, &c->sink, &c->usz, &c->wdense, &c->uoff, &c->nsl, &c->unit_off,
                      &c->ucell, &c->dn, &c->ecnt, &c->epos, &c->uk0, &c->uk1, &c->uv0, &c->uv1, &c->inv,
