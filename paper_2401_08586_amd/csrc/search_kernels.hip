@@ -328,16 +328,37 @@ __device__ __forceinline__ u16x2 as_u16x2(uint32_t u) { return __builtin_bit_cas
 __device__ __forceinline__ uint32_t u16x2_bits(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
 
 struct Thresh {
-    u16x2 tlo2, bias2;
+    u16x2 tlo2, bias2, w12;
     __device__ __forceinline__ void init(const Frame& fr)
     {
         tlo2 = u16x2{fr.t_lo, fr.t_lo};
         const uint16_t b = static_cast<uint16_t>(0xFFFE - (fr.t_hi - fr.t_lo));
         bias2 = u16x2{b, b};
+        const uint16_t w1 = static_cast<uint16_t>(fr.t_hi - fr.t_lo + 1);
+        w12 = u16x2{w1, w1};
     }
 };
 
+// Bits j (j < 8) and 16 + j of x moved to bits 2j and 2j + 1.
+__device__ __forceinline__ uint32_t interleave8(uint32_t x)
+{
+    x &= 0x00FF00FFu;
+    x = (x | (x << 4)) & 0x0F0F0F0Fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+    return (x & 0xFFFFu) | ((x >> 15) & 0x1FFFEu);
+}
+
+// Bits [a, b) of an 8-bit field (a, b clamped to [0, 8]).
+__device__ __forceinline__ uint32_t span8(int a, int b)
+{
+    a = min(max(a, 0), 8);
+    b = min(max(b, 0), 8);
+    return ((1u << b) - 1u) & ~((1u << a) - 1u);
+}
+
 constexpr uint32_t kInvLo = 0x7C00u, kInvHi = 0x7C000000u;
+constexpr int kGroup = 8;  // pair records per group in the FP16 count loop
 
 // Per-lane queue of band pairs (logical position and FP16 r2 bits), held in registers
 // and rechecked after the loop so the FP64 work runs with the lanes converged. Band
@@ -425,6 +446,14 @@ struct CandBits {
         atomicOr(&w[wd], bits << sh);
         atomicOr(&w[wd + 1], sh ? bits >> (32 - sh) : 0u);
     }
+    // Bits of 16 consecutive positions starting at posl (bit k = position posl + k).
+    __device__ __forceinline__ void put16(int posl, uint32_t bits)
+    {
+        if (!keep) return;
+        const int wd = posl >> 5, sh = posl & 31;
+        atomicOr(&w[wd], bits << sh);
+        atomicOr(&w[wd + 1], sh ? bits >> (32 - sh) : 0u);
+    }
     __device__ __forceinline__ void store(const SearchArgs& a, int p) const
     {
         if (!keep) return;
@@ -438,7 +467,9 @@ __global__ void __launch_bounds__(64)
 k_count16(SearchArgs a)
 {
     using CB = CandBits<DIM>;
-    __shared__ uint4 srec[kStage / 2];
+    // pair records of the staged chunk, and kGroup more that the last group of a range may
+    // read past the chunk (their bits are masked)
+    __shared__ uint4 srec[kStage / 2 + kGroup];
     __shared__ uint32_t lbits[64 * (CB::CW + 1)];
     const int b = blockIdx.x;
     if (b >= *a.nblk) return;
@@ -496,63 +527,48 @@ k_count16(SearchArgs a)
                     }
                 });
             } else {
+                // kGroup pair records (2 kGroup positions) at a time: the bits of the
+                // accepted and of the band candidates gather in registers (bit j: position
+                // 2(mg + j), bit 16 + j: position 2(mg + j) + 1) and go to the candidate
+                // bits once per group; band candidates are queued for the FP64 recheck.
                 const uint4* rec = srec - (cb >> 1);
-                auto band = [&](int m, uint32_t rb, uint32_t x) {
+                const int m0 = lo >> 1, mend = (hi + 1) >> 1;
+                for (int mg = m0; mg < mend; mg += kGroup) {
+                    uint32_t acc = 0, ebits = 0;
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        if (((x >> (16 * h)) & 0xFFFF) == 0xFFFF) continue;
-                        const int posl = 2 * m + h;
-                        const uint32_t r2h = (rb >> (16 * h)) & 0xFFFF;
-                        if (!bq.push(posl, r2h) && posl != g.pself) {
-                            int oj;
-                            if (classify<DIM, 0>(a, g, pi, r, posl, r2h, t, nullptr, cb, &oj)) {
-                                ++cnt;
-                                cb_.set(posl);
+                    for (int j = 0; j < kGroup; ++j) {
+                        const uint32_t rb = r2_pair<DIM>(tg, ay, az, rec[mg + j]);
+                        const u16x2 d = as_u16x2(rb) - th.tlo2;
+                        const u16x2 e = d - th.w12;
+                        acc |= (u16x2_bits(d) >> (15 - j)) & (0x10001u << j);
+                        ebits |= (u16x2_bits(e) >> (15 - j)) & (0x10001u << j);
+                    }
+                    // the group's positions inside [lo, hi)
+                    const int a0 = lo - 2 * mg, b0 = hi - 2 * mg;
+                    const uint32_t valid = span8((a0 + 1) >> 1, (b0 + 1) >> 1) |
+                                           (span8(a0 >> 1, b0 >> 1) << 16);
+                    acc &= valid;
+                    const uint32_t bnd = ebits & ~acc & valid;
+                    cnt += __builtin_popcount(acc);
+                    cb_.put16(2 * mg, interleave8(acc));
+                    if (bnd) {
+                        uint32_t bb = interleave8(bnd);
+                        while (bb) {
+                            const int k = __builtin_ctz(bb);
+                            bb &= bb - 1u;
+                            const int posl = 2 * mg + k;
+                            const uint32_t rb = r2_pair<DIM>(tg, ay, az, rec[posl >> 1]);
+                            const uint32_t r2h = (rb >> (16 * (posl & 1))) & 0xFFFFu;
+                            if (!bq.push(posl, r2h) && posl != g.pself) {
+                                int oj;
+                                if (classify<DIM, 0>(a, g, pi, r, posl, r2h, t, nullptr, cb, &oj)) {
+                                    ++cnt;
+                                    cb_.set(posl);
+                                }
                             }
                         }
                     }
-                };
-                auto one = [&](int m, uint32_t inv) {
-                    const uint32_t rb = r2_pair<DIM>(tg, ay, az, rec[m]) | inv;
-                    const u16x2 d = as_u16x2(rb) - th.tlo2;
-                    const uint32_t inb = u16x2_bits(d) & 0x80008000u;
-                    const uint32_t two = ((inb >> 15) & 1u) | ((inb >> 30) & 2u);
-                    cnt += __builtin_popcount(two);
-                    cb_.put(2 * m, two);
-                    const uint32_t x = u16x2_bits(__builtin_elementwise_add_sat(d, th.bias2));
-                    if (x != 0xFFFFFFFFu) band(m, rb, x);
-                };
-                int m = lo >> 1;
-                const int mend = (hi + 1) >> 1;
-                if (m < mend) {
-                    one(m, ((lo & 1) ? kInvLo : 0u) | ((2 * m + 1 >= hi) ? kInvHi : 0u));
-                    ++m;
                 }
-                const int mlast = (hi & 1) ? mend - 1 : mend;
-                for (; m + 1 < mlast; m += 2) {
-                    const uint4 ra = rec[m], rc = rec[m + 1];
-                    const uint32_t A = r2_pair<DIM>(tg, ay, az, ra);
-                    const uint32_t B = r2_pair<DIM>(tg, ay, az, rc);
-                    const u16x2 dA = as_u16x2(A) - th.tlo2;
-                    const u16x2 dB = as_u16x2(B) - th.tlo2;
-                    const uint32_t inA = u16x2_bits(dA) & 0x80008000u;
-                    const uint32_t inB = u16x2_bits(dB) & 0x80008000u;
-                    const uint32_t nib =
-                        ((inA >> 15) & 1u) | ((inA >> 30) & 2u) | ((inB >> 13) & 4u) | ((inB >> 28) & 8u);
-                    cnt += __builtin_popcount(nib);
-                    cb_.put(2 * m, nib);
-                    const uint32_t xA = u16x2_bits(__builtin_elementwise_add_sat(dA, th.bias2));
-                    const uint32_t xB = u16x2_bits(__builtin_elementwise_add_sat(dB, th.bias2));
-                    if ((xA & xB) != 0xFFFFFFFFu) {
-                        if (xA != 0xFFFFFFFFu) band(m, A, xA);
-                        if (xB != 0xFFFFFFFFu) band(m + 1, B, xB);
-                    }
-                }
-                if (m < mlast) {
-                    one(m, 0u);
-                    ++m;
-                }
-                if (m < mend) one(m, kInvHi);
             }
         }
     }
