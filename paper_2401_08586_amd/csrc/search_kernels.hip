@@ -285,12 +285,12 @@ struct Tally {
     unsigned long long cand = 0, band = 0, fpos = 0, fneg = 0, odis = 0;
 };
 
-// Classify one candidate (FP16 bits r2h at staged position posl of segment r);
+// Classify one candidate (FP16 bits r2h at union position posl);
 // returns whether j is a neighbour. MODE 0: three-way test with FP64 recheck in the
 // band; MODE 2: FP64 decides every candidate.
 template <int DIM, int MODE>
 __device__ __forceinline__ bool classify(const SearchArgs& a, const Geom<DIM>& g, const double* pi,
-                                         int r, int posl, uint32_t r2h, Tally& t, const int* sorig,
+                                         int posl, uint32_t r2h, Tally& t, const int* sorig,
                                          int cb, int* oj_out)
 {
     const Frame& fr = g.fr;
@@ -300,7 +300,7 @@ __device__ __forceinline__ bool classify(const SearchArgs& a, const Geom<DIM>& g
     bool nb;
     int oj = -1;
     if (MODE == 2 || band) {
-        oj = sorig ? sorig[posl - cb] : a.perm[g.global_of(r, posl)];
+        oj = sorig ? sorig[posl - cb] : a.perm[g.global_of_any(posl)];
         const bool truth = recheck<DIM>(g.sd->pos, pi, oj - g.sd->poff, fr.R2);
         const bool naive = r2h <= fr.t_mid;
         t.band += band;
@@ -385,6 +385,33 @@ struct BandQueue {
         if (n > 1) f(p1, r1);
         if (n > 2) f(p2, r2);
         if (n > 3) f(p3, r3);
+    }
+};
+
+// Per-lane queue of groups holding band candidates: the group's row segment and first
+// pair (r << 27 | pair) and its 16 band bits in position order; a shift register in
+// registers, drained once per staged chunk.
+struct BandGroups {
+    static constexpr int kCap = 4;
+    uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    uint32_t b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+    int n = 0;
+    __device__ __forceinline__ bool push(uint32_t where, uint32_t bits)
+    {
+        if (n >= kCap) return false;
+        a3 = a2; a2 = a1; a1 = a0; a0 = where;
+        b3 = b2; b2 = b1; b1 = b0; b0 = bits;
+        ++n;
+        return true;
+    }
+    template <typename F>
+    __device__ __forceinline__ void drain(F&& f)
+    {
+        if (n > 0) f(a0, b0);
+        if (n > 1) f(a1, b1);
+        if (n > 2) f(a2, b2);
+        if (n > 3) f(a3, b3);
+        n = 0;
     }
 };
 
@@ -497,8 +524,35 @@ k_count16(SearchArgs a)
     BandQueue bq;
     uint32_t cnt = 0;
     Tally t;
+    // band candidates of a queued group (staged in the current chunk): FP16 r2 bits into the
+    // position queue, or, when that is full, the FP64 recheck on the spot
+    BandGroups bg;
+    int cbase = 0;  // first position of the staged chunk
+    auto band_group = [&](uint32_t where, uint32_t bits) {
+        const int r = static_cast<int>(where >> 27);
+        const int mg = static_cast<int>(where & 0x7FFFFFFu);
+        const int dy = r % 3 - 1, dz = DIM == 3 ? r / 3 - 1 : 0;
+        const h2 ay = splat(tg.qiy + static_cast<_Float16>(-2 * dy));
+        const h2 az = splat(tg.qiz + static_cast<_Float16>(-2 * dz));
+        uint32_t bb = bits;
+        while (bb) {
+            const int k = __builtin_ctz(bb);
+            bb &= bb - 1u;
+            const int posl = 2 * mg + k;
+            const uint32_t rb = r2_pair<DIM>(tg, ay, az, srec[(posl >> 1) - (cbase >> 1)]);
+            const uint32_t r2h = (rb >> (16 * (posl & 1))) & 0xFFFFu;
+            if (!bq.push(posl, r2h) && posl != g.pself) {
+                int oj;
+                if (classify<DIM, 0>(a, g, pi, posl, r2h, t, nullptr, cbase, &oj)) {
+                    ++cnt;
+                    cb_.set(posl);
+                }
+            }
+        }
+    };
     for (int cb = 0; cb < g.U; cb += kStage) {
         const int ce = min(g.U, cb + kStage);
+        cbase = cb;
         __syncthreads();
         stage<DIM, false>(a, g, cb, ce, srec, nullptr);
         __syncthreads();
@@ -519,7 +573,7 @@ k_count16(SearchArgs a)
                         const int posl = 2 * m + h;
                         if (((inv >> (16 * h)) & 0xFFFF) || posl == selfp) continue;
                         int oj;
-                        if (classify<DIM, MODE>(a, g, pi, r, posl, (rb >> (16 * h)) & 0xFFFF, t, nullptr, cb,
+                        if (classify<DIM, MODE>(a, g, pi, posl, (rb >> (16 * h)) & 0xFFFF, t, nullptr, cb,
                                                 &oj)) {
                             ++cnt;
                             cb_.set(posl);
@@ -552,25 +606,14 @@ k_count16(SearchArgs a)
                     cnt += __builtin_popcount(acc);
                     cb_.put16(2 * mg, interleave8(acc));
                     if (bnd) {
-                        uint32_t bb = interleave8(bnd);
-                        while (bb) {
-                            const int k = __builtin_ctz(bb);
-                            bb &= bb - 1u;
-                            const int posl = 2 * mg + k;
-                            const uint32_t rb = r2_pair<DIM>(tg, ay, az, rec[posl >> 1]);
-                            const uint32_t r2h = (rb >> (16 * (posl & 1))) & 0xFFFFu;
-                            if (!bq.push(posl, r2h) && posl != g.pself) {
-                                int oj;
-                                if (classify<DIM, 0>(a, g, pi, r, posl, r2h, t, nullptr, cb, &oj)) {
-                                    ++cnt;
-                                    cb_.set(posl);
-                                }
-                            }
-                        }
+                        const uint32_t where = (static_cast<uint32_t>(r) << 27) | static_cast<uint32_t>(mg);
+                        const uint32_t bits = interleave8(bnd);
+                        if (!bg.push(where, bits)) band_group(where, bits);
                     }
                 }
             }
         }
+        if constexpr (MODE == 0) bg.drain(band_group);
     }
     if constexpr (MODE == 0) {
         // self (r2 = 0) was counted as "in" when T_lo > 0, or queued as a band pair
