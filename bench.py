@@ -26,8 +26,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of one fill launch at the default workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE per dispatch scaled by what they read for a 512 MiB device copy (x2.000 and
 # x1.000); valid only for the kernel source it was measured on (see profiles/).
-FILL_TRAFFIC = {"source_sha256_16": "8372743ce5bae059", "bytes": (226970 * 2.0 + 512858 * 1.0) * 1024,
-                "fetch_kib": 226970, "write_kib": 512858, "fetch_scale": 2.0, "write_scale": 1.0}
+FILL_TRAFFIC = {"source_sha256_16": "2a763eca0a2034dd", "bytes": (229313 * 2.0 + 477314 * 1.0) * 1024,
+                "fetch_kib": 229313, "write_kib": 477314, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def fill_traffic():
