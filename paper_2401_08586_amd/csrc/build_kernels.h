@@ -20,7 +20,7 @@ struct Launch {
 
 hipError_t launch_fill_i32(int* p, int64_t m, int v, hipStream_t st);
 int row_segments(int ncx);  // pieces a row of ncx cells is walked in
-hipError_t launch_assign(const Launch& L, int64_t* X, uint32_t* key, int* slot, int* cell_count, int* err,
+hipError_t launch_assign(const Launch& L, double* X, uint32_t* key, int* slot, int* cell_count, int* err,
                          hipStream_t st);
 hipError_t launch_place(int ntot, const uint32_t* key, const int* slot, const int* cell_start, uint32_t* skey,
                         int* perm, hipStream_t st);
@@ -29,7 +29,7 @@ hipError_t launch_scan_i32_i64(const int* in, int64_t m, int64_t* out, int64_t* 
 int64_t scan_partials_needed(int64_t m);
 int radix_tiles(int n);
 size_t radix_table_entries(int n);
-hipError_t launch_pack(const Launch& L, const uint32_t* skey, const int* perm, const int64_t* X, ushort4* q4,
+hipError_t launch_pack(const Launch& L, const uint32_t* skey, const int* perm, const double* X, ushort4* q4,
                        double* spos, int* inv, hipStream_t st);
 hipError_t launch_blocks(const Launch& L, const int* cell_start, const int* wdense, int* boff, int* bstart, int* bset,
                          int64_t* partial, hipStream_t st);
@@ -75,7 +75,7 @@ struct SearchArgs {
     const int* cell_start;    // [ncell_tot + 1]
     const ushort4* q4;        // sorted FP16 relative coordinates (+ c_x mod 2^16)
     const double* spos;       // sorted FP64 positions [ntot][4] (baseline only)
-    const int64_t* X;         // fixed-point positions, global index, stride x_stride(dim)
+    const double* X;          // fixed-point positions (exact integers), global index, stride x_stride(dim)
     const int* bstart;        // block starts [nblk + 1]
     const int* bset;          // set of each block [nblk]
     const int* nblk;          // device pointer to the block count

@@ -24,8 +24,9 @@ __device__ __forceinline__ float exact_i64_to_f32(int64_t v)
 }
 
 // ---------------------------------------------------------------------------
-// A1: cell assignment in FP64. X = rint((p - lo) * 2^F / w) (round half to even, stored
-// per particle with stride x_stride), cell = X >> F, global key = coff + cx + ncx (cy +
+// A1: cell assignment in FP64. X = rint((p - lo) * 2^F / w) (round half to even; an
+// integer below 2^52, stored exactly as a double per particle with stride x_stride, so
+// differences of two X are exact in binary64), cell = X >> F, global key = coff + cx + ncx (cy +
 // ncy cz). Positions outside [lo, hi] (or NaN) raise the domain flag and are treated as
 // lo so every index stays in range. Each particle also takes a slot in its cell (the
 // cell's count before it), which places it in the sort by cell: runs of consecutive
@@ -33,7 +34,7 @@ __device__ __forceinline__ float exact_i64_to_f32(int64_t v)
 template <int DIM>
 __global__ void __launch_bounds__(256)
 k_assign(const SetDesc* __restrict__ sets, const int* __restrict__ poffs, int nsets, int ntot,
-         int64_t* __restrict__ X, uint32_t* __restrict__ key, int* __restrict__ slot, int* __restrict__ cell_count,
+         double* __restrict__ X, uint32_t* __restrict__ key, int* __restrict__ slot, int* __restrict__ cell_count,
          int* __restrict__ err)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -51,10 +52,9 @@ k_assign(const SetDesc* __restrict__ sets, const int* __restrict__ poffs, int ns
                 p = fr.lo[k];
             }
             const double d = __dsub_rn(p, fr.lo[k]);
-            const double t = __dmul_rn(d, fr.s);
-            const int64_t x = static_cast<int64_t>(rint(t));
-            X[static_cast<size_t>(i) * x_stride(DIM) + k] = x;
-            c[k] = x >> fr.F;
+            const double t = rint(__dmul_rn(d, fr.s));  // an integer below 2^52
+            X[static_cast<size_t>(i) * x_stride(DIM) + k] = t;
+            c[k] = static_cast<int64_t>(t) >> fr.F;
         }
         return static_cast<uint32_t>(sd.coff + c[0] + fr.nc[0] * (c[1] + fr.nc[1] * c[2]));
     };
@@ -380,7 +380,7 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const int* __restrict__ vin,
 template <int DIM>
 __global__ void __launch_bounds__(256)
 k_pack(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nsets, int ntot,
-       const uint32_t* __restrict__ skey, const int* __restrict__ perm, const int64_t* __restrict__ X,
+       const uint32_t* __restrict__ skey, const int* __restrict__ perm, const double* __restrict__ X,
        ushort4* __restrict__ q4, double* __restrict__ spos, int* __restrict__ inv)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -398,7 +398,7 @@ k_pack(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nset
         const float scale = __builtin_ldexpf(1.0f, 1 - fr.F);
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
-            const int64_t x = X[static_cast<size_t>(o) * x_stride(DIM) + k];
+            const int64_t x = static_cast<int64_t>(X[static_cast<size_t>(o) * x_stride(DIM) + k]);
             const int64_t c = x >> fr.F;
             const int64_t D = x - (c << fr.F) - (int64_t(1) << (fr.F - 1));
             const _Float16 q = static_cast<_Float16>(exact_i64_to_f32(D) * scale);
@@ -677,7 +677,7 @@ hipError_t launch_place(int ntot, const uint32_t* key, const int* slot, const in
     return hipGetLastError();
 }
 
-hipError_t launch_assign(const Launch& L, int64_t* X, uint32_t* key, int* slot, int* cell_count, int* err,
+hipError_t launch_assign(const Launch& L, double* X, uint32_t* key, int* slot, int* cell_count, int* err,
                          hipStream_t st)
 {
     if (L.ntot == 0) return hipSuccess;
@@ -730,7 +730,7 @@ hipError_t radix_sort_kv_dev(int n, const int* ndev, int keybits, uint32_t* k0, 
 
 size_t radix_table_entries(int n) { return static_cast<size_t>(radix_tiles(n)) << kRsMaxBits; }
 
-hipError_t launch_pack(const Launch& L, const uint32_t* skey, const int* perm, const int64_t* X, ushort4* q4,
+hipError_t launch_pack(const Launch& L, const uint32_t* skey, const int* perm, const double* X, ushort4* q4,
                        double* spos, int* inv, hipStream_t st)
 {
     if (L.ntot == 0) return hipSuccess;

@@ -300,7 +300,7 @@ SearchArgs args_of(const nnps_cells* c)
     a.cell_start = c->cell_start.as<int>();
     a.q4 = c->q4.as<ushort4>();
     a.spos = c->mode == NNPS_MODE_FP64_BASELINE ? c->spos.as<double>() : nullptr;
-    a.X = c->X.as<int64_t>();
+    a.X = c->X.as<double>();
     a.bstart = c->bstart.as<int>();
     a.bset = c->bset.as<int>();
     a.nblk = c->boff.as<int>() + c->nrows_tot;
@@ -495,7 +495,7 @@ nnps_status enqueue_build(nnps_cells* c, hipStream_t s)
     HIP_TRY(launch_fill_i32(c->cell_count.as<int>(), static_cast<int64_t>(c->ncell_tot) + 1, 0, s));
     HIP_TRY(launch_fill_i32(c->err.as<int>(), 1, 0, s));
     tm.begin(NNPS_PHASE_ASSIGN, s);
-    HIP_TRY(launch_assign(L, c->X.as<int64_t>(), c->k0.as<uint32_t>(), c->v1.as<int>(), c->cell_count.as<int>(),
+    HIP_TRY(launch_assign(L, c->X.as<double>(), c->k0.as<uint32_t>(), c->v1.as<int>(), c->cell_count.as<int>(),
                           c->err.as<int>(), s));
     tm.end(NNPS_PHASE_ASSIGN, s);
     tm.begin(NNPS_PHASE_CELLSCAN, s);
@@ -511,7 +511,7 @@ nnps_status enqueue_build(nnps_cells* c, hipStream_t s)
     c->skey = kf;
     c->perm = vf;
     tm.begin(NNPS_PHASE_PACK, s);
-    HIP_TRY(launch_pack(L, c->skey, c->perm, c->X.as<int64_t>(), c->q4.as<ushort4>(),
+    HIP_TRY(launch_pack(L, c->skey, c->perm, c->X.as<double>(), c->q4.as<ushort4>(),
                         c->mode == NNPS_MODE_FP64_BASELINE ? c->spos.as<double>() : nullptr,
                         c->dense ? c->inv.as<int>() : nullptr, s));
     tm.end(NNPS_PHASE_PACK, s);

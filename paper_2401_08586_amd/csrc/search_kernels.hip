@@ -20,13 +20,6 @@ __device__ __forceinline__ uint32_t as_u32(h2 v) { return __builtin_bit_cast(uin
 __device__ __forceinline__ _Float16 as_f16(uint16_t u) { return __builtin_bit_cast(_Float16, u); }
 __device__ __forceinline__ h2 splat(_Float16 v) { return h2{v, v}; }
 
-__device__ __forceinline__ float exact_i64_to_f32_s(int64_t v)
-{
-    const int32_t hi = static_cast<int32_t>(v >> 20);
-    const int32_t lo = static_cast<int32_t>(v & 0xFFFFF);
-    return __builtin_fmaf(static_cast<float>(hi), 1048576.0f, static_cast<float>(lo));
-}
-
 // The binary64 predicate, in the fixed order and with no contraction.
 template <int DIM>
 __device__ __forceinline__ double r2_fp64(const double* pi, const double* pj)
@@ -52,16 +45,16 @@ __device__ __forceinline__ bool recheck(const double* __restrict__ pos, const do
     return r2_fp64<DIM>(pi, pj) <= R2;
 }
 
-// FP32 distance from the fixed-point positions: the int64 displacement is exact and
-// is rounded once to FP32 (|dX| < 2^41 for any pair within the radius).
+// FP32 distance from the fixed-point positions: the displacement of two exact integers
+// below 2^52 is exact in binary64 and is rounded once to FP32.
 template <int DIM>
-__device__ __forceinline__ float dist_fixed(const int64_t* __restrict__ X, int oi, int oj, float scale)
+__device__ __forceinline__ float dist_fixed(const double* __restrict__ X, int oi, int oj, float scale)
 {
     float s2 = 0.0f;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-        const int64_t d = X[static_cast<size_t>(oj) * x_stride(DIM) + k] - X[static_cast<size_t>(oi) * x_stride(DIM) + k];
-        const float f = exact_i64_to_f32_s(d);
+        const double d = X[static_cast<size_t>(oj) * x_stride(DIM) + k] - X[static_cast<size_t>(oi) * x_stride(DIM) + k];
+        const float f = static_cast<float>(d);
         s2 = s2 + f * f;
     }
     return __builtin_amdgcn_sqrtf(s2) * scale;  // <= 1 ulp; s2 >= 1 or 0
@@ -861,6 +854,13 @@ __device__ __forceinline__ int wave_min_i32(int v)
     return v;
 }
 
+__device__ __forceinline__ long long wave_max_i64(long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, static_cast<long long>(__shfl_xor(v, o, 64)));
+    return v;
+}
+
 __device__ __forceinline__ int wave_max_i32(int v)
 {
 #pragma unroll
@@ -886,7 +886,7 @@ k_fill(SearchArgs a)
     __shared__ int sorig[C::UCAP];
     __shared__ uint32_t masks[64 * (C::MW + 1)];
     __shared__ long long sbase[64];  // row start in the output minus the row's flat offset
-    __shared__ long long sxi[64 * DIM];
+    __shared__ double sxi[64 * DIM];  // targets' positions: fixed point, or FP64 (baseline)
     __shared__ int spart[NW][64];   // per-wave popcounts of each row's mask quarter
     __shared__ int sred[2][NW];
     uint16_t* rank_of = reinterpret_cast<uint16_t*>(smem);
@@ -897,7 +897,7 @@ k_fill(SearchArgs a)
     const int b = blockIdx.x;
     if (b >= *a.nblk || dense_block(a, b)) return;
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wv = tid >> 6;
+    const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront index, uniform
     // every wavefront holds the block's geometry; lane = target
     Geom<DIM> g;
     g.init(a, b);
@@ -910,6 +910,7 @@ k_fill(SearchArgs a)
     const int rlen = g.active ? static_cast<int>(sd.row_ptr[li + 1] - rs) : 0;
     int E;
     const int off = wave_excl_scan_i32(rlen, &E);
+    E = __builtin_amdgcn_readfirstlane(E);  // the block's entry count, wave-uniform
     static_assert(32 * CB::CW == C::UCAP, "the count pass keeps a bit per union position");
     if (g.U > C::UCAP || E > C::FCAP) {
         // too big for this path: every row of the block goes to the long-row path
@@ -949,7 +950,7 @@ k_fill(SearchArgs a)
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
             // the target's own coordinates for the distance: fixed point, or FP64 bits (baseline)
-            sxi[lane * DIM + k] = MODE == 1 ? __builtin_bit_cast(long long, sd.pos[static_cast<size_t>(li) * DIM + k])
+            sxi[lane * DIM + k] = MODE == 1 ? sd.pos[static_cast<size_t>(li) * DIM + k]
                                             : a.X[static_cast<size_t>(oi) * x_stride(DIM) + k];
         }
     }
@@ -1033,16 +1034,79 @@ k_fill(SearchArgs a)
     __syncthreads();
     // 5. emission, 64 entries per round, rounds dealt to the wavefronts in turn. Later
     // rounds' gathers are issued before this round's stores, and every round issues the
-    // same memory instructions on every path: lanes past the list (or past the output
-    // capacity) gather particle 0 and store to a per-lane sink slot. Vector-memory
-    // counters count loads and stores in issue order, so with a fixed instruction count
-    // the wait for the prefetch need not include the previous round's stores.
+    // same memory instructions on every path. Vector-memory counters count loads and
+    // stores in issue order, so with a fixed instruction count the wait for the prefetch
+    // need not include the previous round's stores.
     struct Ent {
         int t, oj;
         long long idx;
-        long long xj[DIM];
+        double xj[DIM];
     };
+    auto gather = [&](Ent& s) {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+            s.xj[c] = MODE == 1 ? sd.pos[static_cast<size_t>(s.oj - sd.poff) * DIM + c]
+                                : a.X[static_cast<size_t>(s.oj) * x_stride(DIM) + c];
+    };
+    auto distance = [&](const Ent& s) -> float {
+        if constexpr (MODE == 1) {
+            double pi2[3], pj2[3];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                pi2[c] = sxi[s.t * DIM + c];
+                pj2[c] = s.xj[c];
+            }
+            return static_cast<float>(__dsqrt_rn(r2_fp64<DIM>(pi2, pj2)));
+        } else {
+            float s2 = 0.0f;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                const float f = static_cast<float>(s.xj[c] - sxi[s.t * DIM + c]);  // exact difference, one rounding
+                s2 = s2 + f * f;
+            }
+            return __builtin_amdgcn_sqrtf(s2) * fr.dist_scale;  // <= 1 ulp; s2 >= 1 or 0
+        }
+    };
+    constexpr int R = 64 * NW;  // stride between a wavefront's rounds
     const int64_t cap = sd.capacity;
+    const long long rend = g.active ? rs + rlen : 0;  // the row's end in the output
+    if (wave_max_i64(rend) <= cap) {
+        // every row fits the output: lanes past the list repeat the list's last entry (the
+        // same values to the same place), so no address is ever switched
+        auto fetch = [&](int e, Ent& s) {
+            const uint32_t f = flat[min(e, E - 1)];
+            s.t = static_cast<int>(f >> C::SHIFT);
+            s.oj = sorig[f & (C::UCAP - 1)];
+            s.idx = sbase[s.t] + min(e, E - 1);
+            gather(s);
+        };
+        auto emit = [&](const Ent& s) {
+            const float d = distance(s);
+            sd.col[s.idx] = s.oj - sd.poff;
+            sd.dist[s.idx] = d;
+        };
+        // three entry sets in rotation: the fetch two rounds ahead never waits for a copy
+        Ent A, B, Cn;
+        int e0 = wv * 64;
+        if (e0 < E) {
+            fetch(e0 + lane, A);
+            fetch(e0 + R + lane, B);
+            for (;;) {
+                fetch(e0 + 2 * R + lane, Cn);
+                emit(A);
+                if ((e0 += R) >= E) break;
+                fetch(e0 + 2 * R + lane, A);
+                emit(B);
+                if ((e0 += R) >= E) break;
+                fetch(e0 + 2 * R + lane, B);
+                emit(Cn);
+                if ((e0 += R) >= E) break;
+            }
+        }
+        return;
+    }
+    // some row ends past the output capacity: entries there (and lanes past the list)
+    // store to a per-lane sink slot, and the capacity error is raised
     NNPS_GLOBAL int32_t* sink_col = (NNPS_GLOBAL int32_t*)a.sink + 2 * lane;
     NNPS_GLOBAL float* sink_dist = (NNPS_GLOBAL float*)(a.sink + 2 * lane + 1);
     auto fetch = [&](int e, Ent& s) {
@@ -1056,36 +1120,15 @@ k_fill(SearchArgs a)
         s.t = t;
         s.oj = ok ? o : sd.poff;
         s.idx = ok ? base + e : -1;
-#pragma unroll
-        for (int c = 0; c < DIM; ++c)
-            s.xj[c] = MODE == 1 ? __builtin_bit_cast(long long, sd.pos[static_cast<size_t>(s.oj - sd.poff) * DIM + c])
-                                : a.X[static_cast<size_t>(s.oj) * x_stride(DIM) + c];
+        gather(s);
     };
-    constexpr int R = 64 * NW;  // stride between a wavefront's rounds
     Ent cur, n1;
     fetch(wv * 64 + lane, cur);
     fetch(wv * 64 + R + lane, n1);
     for (int e0 = wv * 64; e0 < E; e0 += R) {
         Ent n2;
         fetch(e0 + 2 * R + lane, n2);
-        float d;
-        if constexpr (MODE == 1) {
-            double pi2[3], pj2[3];
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) {
-                pi2[c] = __builtin_bit_cast(double, sxi[cur.t * DIM + c]);
-                pj2[c] = __builtin_bit_cast(double, cur.xj[c]);
-            }
-            d = static_cast<float>(__dsqrt_rn(r2_fp64<DIM>(pi2, pj2)));
-        } else {
-            float s2 = 0.0f;
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) {
-                const float f = exact_i64_to_f32_s(cur.xj[c] - sxi[cur.t * DIM + c]);
-                s2 = s2 + f * f;
-            }
-            d = __builtin_amdgcn_sqrtf(s2) * fr.dist_scale;  // <= 1 ulp; s2 >= 1 or 0
-        }
+        const float d = distance(cur);
         const bool valid = cur.idx >= 0 && cur.idx < cap;
         if (cur.idx >= cap) atomicOr(a.err, kErrCapacity);
         NNPS_GLOBAL int32_t* pc = valid ? sd.col + cur.idx : sink_col;
@@ -1353,7 +1396,7 @@ k_dense(SearchArgs a)
     __shared__ uint2 recB[F16 ? K / 2 : 1];               // 2(c_y - c_jy), 2(c_z - c_jz) pairs
     __shared__ double spj[F16 ? 1 : K * DIM];             // baseline: candidate positions
     __shared__ int sorig[K];
-    __shared__ long long sX[(FILL && F16) ? K * DIM : 1];  // fixed-point positions (distances)
+    __shared__ double sX[(FILL && F16) ? K * DIM : 1];  // fixed-point positions (distances)
     __shared__ int s_unit;
     __shared__ unsigned long long s_red[kDenseThreads / 64][kDenseStats];
     __shared__ uint16_t squeue[FILL ? kDenseThreads / 64 : 1][FILL ? 192 : 1];  // per-wave emission queue
@@ -1391,7 +1434,8 @@ k_dense(SearchArgs a)
         const bool vk = pk < t1;
         const int nt = (t1 - t0 > wv) ? (t1 - t0 - wv + 3) / 4 : 0;
         int oi_k = 0, q01_k = 0, q2_k = 0, acc_k = 0, rl_k = 0;
-        long long rs_k = 0, xi_k[3] = {0, 0, 0};
+        long long rs_k = 0;
+        double xi_k[3] = {0, 0, 0};
         double pi_k[3] = {0, 0, 0};
         if (vk) {
             oi_k = a.perm[pk];
@@ -1611,9 +1655,9 @@ k_dense(SearchArgs a)
                     const int rl = rl32(rl_k, k);
                     const int done = rl32(acc_k, k);
                     const bool room = rs + rl <= sd.capacity;
-                    long long xi[3];
+                    double xi[3];
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) xi[d] = rl64(xi_k[d], k);
+                    for (int d = 0; d < 3; ++d) xi[d] = rlf64(xi_k[d], k);
                     const double* pis = pi;
                     uint16_t* q = squeue[wv];
                     int w = done;  // CSR entries of this row written so far
@@ -1629,7 +1673,7 @@ k_dense(SearchArgs a)
                                     float s2 = 0.0f;
 #pragma unroll
                                     for (int d = 0; d < DIM; ++d) {
-                                        const float f = exact_i64_to_f32_s(sX[e * DIM + d] - xi[d]);
+                                        const float f = static_cast<float>(sX[e * DIM + d] - xi[d]);
                                         s2 = s2 + f * f;
                                     }
                                     dv = __builtin_amdgcn_sqrtf(s2) * dscale;
