@@ -210,12 +210,48 @@ def main():
                                               "fp16_false_neg", "heavy_rows", "dense_rows")},
         "fp64_baseline": res64,
     }
+    if args.workload in ("c1", "c2"):
+        out["sph_gradient"] = bench_gradient(ctx_grad_ps=ps, pos=pos, steps=max(args.steps, 5))
     if not args.no_serving:
         out["serving"] = bench_serving(args)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(ps)
     print(json.dumps(out), flush=True)
+
+
+def bench_gradient(ctx_grad_ps, pos, steps):
+    """The SPH gradient (Eq. 2 and Eq. A5) of f = x^3 over this workload's neighbour list:
+    mean kernel time over `steps` launches (HIP events on the launch stream) and its HBM
+    roofline with algorithmic bytes 4 per pair (column index) plus, per particle, position
+    8d, field 8, row bounds 8 and both outputs 16d."""
+    import torch
+    from paper_2401_08586_amd import nnps
+    ps = ctx_grad_ps
+    ctx = nnps.Context(0)
+    rp, col, _, cells = nnps.search(pos, ps.lo, ps.hi, ps.cell_size, ps.radius, ctx=ctx)
+    nnz = int(col.numel())
+    f = (pos[:, 0] ** 3).contiguous()
+    h = ps.radius / 2.0
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        nnps.sph_gradient(pos, f, h, rp, col, ctx=ctx, stream=stream)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            nnps.sph_gradient(pos, f, h, rp, col, ctx=ctx, stream=stream)
+        e1.record(stream)
+    stream.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    d = ps.dim
+    nbytes = 4 * nnz + ps.n * (8 * d + 8 + 8 + 16 * d)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    ctx.close()
+    log(f"[bench] sph gradient {ms:.3f} ms ({nnz / (ms * 1e-3) / 1e9:.1f} Gpairs/s)")
+    return {"ms": ms, "gpairs_per_s": nnz / (ms * 1e-3) / 1e9, "dtype": "f64",
+            "roofline": {"bound": "hbm", "kernel": "k_sph_gradient", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": nbytes}}
 
 
 def bench_serving(args, nsims=64, slots=4, load=0.7):

@@ -223,6 +223,25 @@ nnps_status nnps_batch_nnz(nnps_cells *cells, int64_t *h_nnz, void *stream);
 nnps_status nnps_batch_nnz_enqueue(nnps_cells *cells, void *stream);
 nnps_status nnps_batch_nnz_fetch(nnps_cells *cells, int64_t *h_nnz);
 
+/* ---- SPH gradient over a neighbour list ------------------------------------------
+ * The SPH approximation of the gradient of a scalar field f (SPH method section, Eq. 2,
+ * with the cubic B-spline kernel of Eq. 3, support 2h) and the normalised, volume-free
+ * first-order operator of the appendix (Eq. A5), in binary64, for one set of n particles
+ * in dim (2 or 3) dimensions. d_pos [n][dim], d_f [n] and d_vol [n] (particle volumes V_j;
+ * NULL means V_j = 1) are device arrays; d_row_ptr [n+1] and d_col [nnz] are a CSR
+ * neighbour list such as nnps_search writes (a row may hold any neighbours; those at
+ * r >= 2h add nothing). Outputs, each NULL or a device array [n][dim]:
+ *   d_grad[i][a]      = sum_j V_j f_j dW_ij/dx_i,a
+ *   d_grad_norm[i][a] = sum_j (f_j - f_i) dW_ij/dx_i,a / sum_j (x_j,a - x_i,a) dW_ij/dx_i,a
+ *                       (0 where the denominator is 0, e.g. an empty row),
+ * with dW_ij/dx_i,a = alpha_d / h * dW/dq (q = r_ij / h) * (x_i,a - x_j,a) / r_ij (0 when
+ * r_ij = 0), alpha_d = 15 / (7 pi h^2) in 2D and 3 / (2 pi h^3) in 3D. Every input pointer
+ * but d_vol must be non-NULL when n > 0. Asynchronous on `stream`; NNPS_EINVAL for bad
+ * arguments (h <= 0 or not finite, dim not 2 or 3, n outside [0, 2^31)). */
+nnps_status nnps_sph_gradient(nnps_ctx *ctx, int32_t dim, int64_t n, double h, const double *d_pos,
+                              const double *d_f, const double *d_vol, const int64_t *d_row_ptr,
+                              const int32_t *d_col, double *d_grad, double *d_grad_norm, void *stream);
+
 /* Phases timed when profiling is on, in launch order. */
 enum {
     NNPS_PHASE_ASSIGN = 0,   /* FP64 cell assignment + cell histogram */

@@ -12,6 +12,7 @@
 
 #include "../../include/nnps.h"
 #include "build_kernels.h"
+#include "sph_kernels.h"
 
 using namespace nnps;
 
@@ -790,6 +791,19 @@ nnps_status nnps_count(nnps_ctx* ctx, nnps_cells* c, int64_t* d_row_ptr, int64_t
     if (!c || c->nsets != 1) return c ? NNPS_EORDER : NNPS_EINVAL;
     int64_t* rp[1] = {d_row_ptr};
     return nnps_batch_count(ctx, c, rp, h_nnz, stream);
+}
+
+nnps_status nnps_sph_gradient(nnps_ctx* ctx, int32_t dim, int64_t n, double h, const double* d_pos, const double* d_f,
+                              const double* d_vol, const int64_t* d_row_ptr, const int32_t* d_col, double* d_grad,
+                              double* d_grad_norm, void* stream)
+{
+    if (!ctx || (dim != 2 && dim != 3) || n < 0 || n > INT32_MAX || !(h > 0.0) || !isfinite(h)) return NNPS_EINVAL;
+    if (n > 0 && (!d_pos || !d_f || !d_row_ptr || !d_col)) return NNPS_EINVAL;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return NNPS_EDEVICE;
+    HIP_TRY(launch_sph_gradient(dim, n, h, d_pos, d_f, d_vol, d_row_ptr, d_col, d_grad, d_grad_norm,
+                                static_cast<hipStream_t>(stream)));
+    return NNPS_OK;
 }
 
 nnps_status nnps_batch_fill(nnps_ctx* ctx, nnps_cells* c, int64_t* const* d_row_ptr, int32_t* const* d_col,

@@ -72,7 +72,7 @@ EXPORTS = ["nnps_status_str", "nnps_validate", "nnps_grid", "nnps_ctx_create", "
            "nnps_search", "nnps_stats_get", "nnps_cells_set_profiling", "nnps_phase_times",
            "nnps_batch_build", "nnps_batch_count", "nnps_batch_fill", "nnps_batch_search",
            "nnps_batch_step", "nnps_cells_set_graphs", "nnps_batch_nnz", "nnps_batch_nnz_enqueue",
-           "nnps_batch_nnz_fetch"]
+           "nnps_batch_nnz_fetch", "nnps_sph_gradient"]
 
 PHASES = ["assign", "cellscan", "sort", "pack", "blocks", "unions", "count", "dcount", "rowscan", "fill",
           "longrows", "dfill"]
@@ -118,6 +118,7 @@ def load():
     lib.nnps_cells_set_graphs.argtypes = [P, ctypes.c_int]
     lib.nnps_batch_nnz.argtypes = [P, P, P]
     lib.nnps_phase_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), P]
+    lib.nnps_sph_gradient.argtypes = [P, ctypes.c_int32, I64, ctypes.c_double, P, P, P, P, P, P, P, P]
     for name in EXPORTS:
         fn = getattr(lib, name)
         if name not in ("nnps_status_str", "nnps_ctx_destroy", "nnps_cells_destroy"):
@@ -369,6 +370,35 @@ def search_batch(sets, mode=MODE_FP16_RCLL, ctx: Context | None = None, cells: C
     dists = [torch.empty(max(k, 0), dtype=torch.float32, device=dev) for k in nnz]
     cells.batch_fill(rps, cols, dists, stream)
     return list(zip(rps, cols, dists)), cells
+
+
+def sph_gradient(pos, f, h, row_ptr, col, vol=None, ctx: Context | None = None, want=("grad", "grad_norm"),
+                 stream=None):
+    """SPH gradient of the scalar field f over a CSR neighbour list (nnps_sph_gradient):
+    returns (grad, grad_norm), float64 CUDA tensors [n, dim] (None where not in `want`)."""
+    import torch
+    n, dim = pos.shape
+    for t, dt in ((pos, torch.float64), (f, torch.float64), (row_ptr, torch.int64), (col, torch.int32)):
+        assert t.is_cuda and t.dtype == dt and t.is_contiguous()
+    assert f.numel() == n and row_ptr.numel() == n + 1
+    if vol is not None:
+        assert vol.is_cuda and vol.dtype == torch.float64 and vol.numel() == n and vol.is_contiguous()
+    own = ctx is None
+    ctx = ctx or Context(pos.device.index or 0)
+    try:
+        grad = torch.empty((n, dim), dtype=torch.float64, device=pos.device) if "grad" in want else None
+        gnorm = torch.empty((n, dim), dtype=torch.float64, device=pos.device) if "grad_norm" in want else None
+        colp = col if col.numel() > 0 else torch.zeros(1, dtype=torch.int32, device=pos.device)
+        _check(ctx._lib.nnps_sph_gradient(ctx._ctx, int(dim), int(n), float(h), _ptr(pos), _ptr(f),
+                                          _ptr(vol) if vol is not None else None, _ptr(row_ptr), _ptr(colp),
+                                          _ptr(grad) if grad is not None else None,
+                                          _ptr(gnorm) if gnorm is not None else None, _stream_ptr(stream)),
+               "nnps_sph_gradient")
+    finally:
+        if own:
+            torch.cuda.synchronize()
+            ctx.close()
+    return grad, gnorm
 
 
 def search(pos, lo, hi, cell_size, radius, mode=MODE_FP16_RCLL, ctx: Context | None = None,
