@@ -210,6 +210,14 @@ def main():
                                               "fp16_false_neg", "heavy_rows", "dense_rows")},
         "fp64_baseline": res64,
     }
+    if res64 is not None:
+        # build + count only (no CSR written), from the per-phase means: isolates the test
+        build_count = ("assign", "cellscan", "sort", "pack", "blocks", "unions", "count", "dcount", "rowscan")
+        c16 = sum(ph16[k] or 0.0 for k in build_count)
+        c64 = sum(ph64[k] or 0.0 for k in build_count)
+        out["count_only"] = {"fp16_ms": c16, "fp64_ms": c64, "speedup_fp16_over_fp64": c64 / c16,
+                             "count_kernel_speedup": ph64["count"] / ph16["count"],
+                             "note": "sum of per-phase means of build + count + row scan; not the headline"}
     if args.workload in ("c1", "c2"):
         out["sph_gradient"] = bench_gradient(ctx_grad_ps=ps, pos=pos, steps=max(args.steps, 5))
     if not args.no_serving:
