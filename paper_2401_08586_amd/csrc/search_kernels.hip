@@ -1387,28 +1387,33 @@ __device__ __forceinline__ double rlf64(double v, int k)
 }
 
 template <int DIM, int MODE, bool FILL>
-__global__ void __launch_bounds__(kDenseThreads)
+__global__ void __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_dense(SearchArgs a)
 {
     constexpr int K = kDenseChunk;
     constexpr bool F16 = MODE != 1;
     __shared__ uint4 recA[F16 ? K / 2 : 1];               // qx, qy, qz, 2(c_x - c_jx) pairs
     __shared__ uint2 recB[F16 ? K / 2 : 1];               // 2(c_y - c_jy), 2(c_z - c_jz) pairs
-    __shared__ double spj[F16 ? 1 : K * DIM];             // baseline: candidate positions
-    __shared__ int sorig[K];
-    __shared__ double sX[(FILL && F16) ? K * DIM : 1];  // fixed-point positions (distances)
-    __shared__ int s_unit;
-    __shared__ unsigned long long s_red[kDenseThreads / 64][kDenseStats];
-    __shared__ uint16_t squeue[FILL ? kDenseThreads / 64 : 1][FILL ? 192 : 1];  // per-wave emission queue
+    __shared__ __attribute__((aligned(16))) int sorig[K];
+    // candidate positions: FP64 (baseline) or fixed point, axis-major [DIM][K] (FP16 fill);
+    // one array serves both so that the FP16 fill's tables are exactly 40 KiB (four
+    // workgroups per CU)
+    __shared__ double sdbl[(!F16 || FILL) ? K * DIM : 1];
+    double* const spj = sdbl;
+    double* const sX = sdbl;
+    __shared__ unsigned long long s_red[FILL ? 1 : kDenseThreads / 64][kDenseStats];  // count pass only
+    // the unit counter's broadcast slot: the first record word, free between the last use of
+    // one unit's staged chunk and the staging of the next unit's first chunk
+    int* const s_unit = reinterpret_cast<int*>(recA);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const int nunits = *a.dn > 0 ? a.unit_off[a.L.ncell_tot] : 0;
     unsigned long long tc[kDenseStats] = {0, 0, 0, 0, 0, 0};
     for (;;) {
         __syncthreads();  // the previous unit is done with s_unit and the staged chunk
-        if (threadIdx.x == 0) s_unit = atomicAdd(a.ucount, 1);
+        if (threadIdx.x == 0) *s_unit = atomicAdd(a.ucount, 1);
         __syncthreads();
-        const int u = s_unit;
+        const int u = *s_unit;
         if (u >= nunits) break;
         const int g = a.ucell[u];
         const int slice = u - a.unit_off[g];
@@ -1492,7 +1497,7 @@ k_dense(SearchArgs a)
                             if (FILL) {
 #pragma unroll
                                 for (int k = 0; k < DIM; ++k)
-                                    sX[e * DIM + k] = a.X[static_cast<size_t>(oj) * x_stride(DIM) + k];
+                                    sX[k * K + e] = a.X[static_cast<size_t>(oj) * x_stride(DIM) + k];
                             }
                         } else {
                             w0 |= 0x7C00u << sh;  // qx = +inf: r2 = +inf
@@ -1647,10 +1652,11 @@ k_dense(SearchArgs a)
                     const int tot = static_cast<int>(wave_sum_u64(static_cast<unsigned long long>(__builtin_popcount(inb))));
                     if (lane == k) acc_k += tot;
                 } else {
-                    // ascending emission: candidate order is original-index order. The
-                    // accepted candidates are queued in LDS in that order and written 64 at
-                    // a time, one per lane: every lane computes a distance and the stores
-                    // cover consecutive CSR slots.
+                    // ascending emission: candidate order is original-index order. Each
+                    // group of 128 candidates (two per lane) writes its accepted ones straight
+                    // to the next CSR slots, a lane's slot being the row's count so far plus
+                    // the accepted candidates of lower lanes (ballot prefix); the stores of a
+                    // group cover at most 128 consecutive slots.
                     const long long rs = rl64(rs_k, k);
                     const int rl = rl32(rl_k, k);
                     const int done = rl32(acc_k, k);
@@ -1659,58 +1665,39 @@ k_dense(SearchArgs a)
 #pragma unroll
                     for (int d = 0; d < 3; ++d) xi[d] = rlf64(xi_k[d], k);
                     const double* pis = pi;
-                    uint16_t* q = squeue[wv];
                     int w = done;  // CSR entries of this row written so far
-                    int qn = 0;    // queued entries (wave-uniform)
-                    auto flush = [&](int cnt) {
-                        __builtin_amdgcn_wave_barrier();
-                        if (lane < cnt) {
-                            const int e = q[lane];
-                            const int slot = w + lane;
-                            if (slot < rl && room) {
-                                float dv;
-                                if (F16) {
-                                    float s2 = 0.0f;
+                    auto emit = [&](int e, int slot) {
+                        if (slot < rl && room) {
+                            float dv;
+                            if (F16) {
+                                float s2 = 0.0f;
 #pragma unroll
-                                    for (int d = 0; d < DIM; ++d) {
-                                        const float f = static_cast<float>(sX[e * DIM + d] - xi[d]);
-                                        s2 = s2 + f * f;
-                                    }
-                                    dv = __builtin_amdgcn_sqrtf(s2) * dscale;
-                                } else {
-                                    dv = static_cast<float>(__dsqrt_rn(r2_fp64<DIM>(pis, spj + e * DIM)));
+                                for (int d = 0; d < DIM; ++d) {
+                                    const float f = static_cast<float>(sX[d * K + e] - xi[d]);
+                                    s2 = s2 + f * f;
                                 }
-                                sd.col[rs + slot] = sorig[e] - poff;
-                                sd.dist[rs + slot] = dv;
+                                dv = __builtin_amdgcn_sqrtf(s2) * dscale;
+                            } else {
+                                dv = static_cast<float>(__dsqrt_rn(r2_fp64<DIM>(pis, spj + e * DIM)));
                             }
+                            sd.col[rs + slot] = sorig[e] - poff;
+                            sd.dist[rs + slot] = dv;
                         }
-                        w += cnt;
                     };
                     for (int it = 0; it < nit; ++it) {
                         uint32_t b2 = (inb >> (2 * it)) & 3u;
                         const int e0 = it * 128 + 2 * lane;
-                        if ((b2 & 1u) && sorig[e0] == oi) b2 &= ~1u;
-                        if ((b2 & 2u) && sorig[e0 + 1] == oi) b2 &= ~2u;
+                        const int2 oo = *reinterpret_cast<const int2*>(&sorig[e0]);
+                        if (oo.x == oi) b2 &= ~1u;  // the target itself is never its own neighbour
+                        if (oo.y == oi) b2 &= ~2u;
                         const uint64_t B0 = __ballot(b2 & 1u);
                         const uint64_t B1 = __ballot((b2 >> 1) & 1u);
                         if ((B0 | B1) == 0) continue;
-                        const int pre = qn + __popcll(B0 & lt) + __popcll(B1 & lt);
-                        if (b2 & 1u) q[pre] = static_cast<uint16_t>(e0);
-                        if (b2 & 2u) q[pre + (b2 & 1u)] = static_cast<uint16_t>(e0 + 1);
-                        qn += __popcll(B0) + __popcll(B1);
-                        while (qn >= 64) {
-                            flush(64);
-                            qn -= 64;
-                            __builtin_amdgcn_wave_barrier();
-                            const int mv = lane < qn ? q[64 + lane] : 0;
-                            const int mv2 = lane + 64 < qn ? q[128 + lane] : 0;
-                            __builtin_amdgcn_wave_barrier();
-                            if (lane < qn) q[lane] = static_cast<uint16_t>(mv);
-                            if (lane + 64 < qn) q[64 + lane] = static_cast<uint16_t>(mv2);
-                        }
+                        const int pre = w + __popcll(B0 & lt) + __popcll(B1 & lt);
+                        if (b2 & 1u) emit(e0, pre);
+                        if (b2 & 2u) emit(e0 + 1, pre + static_cast<int>(b2 & 1u));
+                        w += __popcll(B0) + __popcll(B1);
                     }
-                    if (qn > 0) flush(qn);
-                    __builtin_amdgcn_wave_barrier();
                     if (!room && lane == 0 && w > done) atomicOr(a.err, kErrCapacity);
                     if (lane == k) acc_k = w;
                 }
