@@ -1537,9 +1537,13 @@ k_dense(SearchArgs a)
                     qiy2 = splat(as_f16(static_cast<uint16_t>(q01 >> 16)));
                     qiz2 = splat(as_f16(static_cast<uint16_t>(q2 & 0xFFFF)));
                 }
-                for (int it = 0; it < nit; ++it) {
+                // candidate bits: bit it for candidate it*128 + 2 lane, bit 16 + it for the one
+                // after it; "in" and "in or band" from the sign bits of two 16-bit subtractions
+                uint32_t ebits = 0;
+#pragma unroll
+                for (int it = 0; it < K / 128; ++it) {
+                    if (it >= nit) break;
                     const int m = it * 64 + lane;
-                    uint32_t in2, bd2;
                     if (F16) {
                         const uint4 A = recA[m];
                         const uint2 B = recB[m];
@@ -1558,32 +1562,28 @@ k_dense(SearchArgs a)
                         }
                         r2 = __builtin_elementwise_fma(tx, tx, r2);
                         const u16x2 dd = as_u16x2(as_u32(r2)) - th.tlo2;
-                        const uint32_t ib = u16x2_bits(dd) & 0x80008000u;
-                        const uint32_t xb = u16x2_bits(__builtin_elementwise_add_sat(dd, th.bias2));
-                        in2 = ((ib >> 15) & 1u) | ((ib >> 30) & 2u);
-                        bd2 = ((xb & 0xFFFFu) != 0xFFFFu ? 1u : 0u) | ((xb >> 16) != 0xFFFFu ? 2u : 0u);
+                        const u16x2 ee = dd - th.w12;
+                        inb |= (u16x2_bits(dd) >> (15 - it)) & (0x10001u << it);
+                        ebits |= (u16x2_bits(ee) >> (15 - it)) & (0x10001u << it);
                     } else {
-                        in2 = 0;
-                        bd2 = 0;
 #pragma unroll
                         for (int h = 0; h < 2; ++h)
-                            if (r2_fp64<DIM>(pi, spj + (2 * m + h) * DIM) <= R2) in2 |= 1u << h;
+                            if (r2_fp64<DIM>(pi, spj + (2 * m + h) * DIM) <= R2) inb |= 1u << (it + 16 * h);
                     }
-                    inb |= in2 << (2 * it);
-                    bnd |= bd2 << (2 * it);
                 }
+                bnd = ebits & ~inb;
                 if (MODE == 2) {
                     // every candidate decided in FP64; the FP16 classes are only compared
                     uint32_t all = 0;
                     for (int it = 0; it < nit; ++it) {
                         const int e0 = it * 128 + 2 * lane;
-                        all |= ((e0 < nc ? 1u : 0u) | (e0 + 1 < nc ? 2u : 0u)) << (2 * it);
+                        all |= (e0 < nc ? 1u << it : 0u) | (e0 + 1 < nc ? 1u << (16 + it) : 0u);
                     }
                     uint32_t dec = 0;
                     while (all) {
                         const int bb = __builtin_ctz(all);
                         all &= all - 1;
-                        const int e = (bb >> 1) * 128 + 2 * lane + (bb & 1);
+                        const int e = (bb & 15) * 128 + 2 * lane + (bb >> 4);
                         const int oj = sorig[e];
                         if (oj == oi) continue;
                         const bool truth = recheck_g<DIM>(sd.pos, pi, oj - poff, R2);
@@ -1620,7 +1620,7 @@ k_dense(SearchArgs a)
                     while (bb_all) {
                         const int bb = __builtin_ctz(bb_all);
                         bb_all &= bb_all - 1;
-                        const int e = (bb >> 1) * 128 + 2 * lane + (bb & 1);
+                        const int e = (bb & 15) * 128 + 2 * lane + (bb >> 4);
                         const int oj = sorig[e];
                         if (oj == oi) continue;  // itself (a band pair only when T_lo = 0)
                         const bool truth = recheck_g<DIM>(sd.pos, pi, oj - poff, R2);
@@ -1685,7 +1685,7 @@ k_dense(SearchArgs a)
                         }
                     };
                     for (int it = 0; it < nit; ++it) {
-                        uint32_t b2 = (inb >> (2 * it)) & 3u;
+                        uint32_t b2 = ((inb >> it) & 1u) | (((inb >> (16 + it)) & 1u) << 1);
                         const int e0 = it * 128 + 2 * lane;
                         const int2 oo = *reinterpret_cast<const int2*>(&sorig[e0]);
                         if (oo.x == oi) b2 &= ~1u;  // the target itself is never its own neighbour
