@@ -1375,6 +1375,16 @@ hipError_t launch_long_rows(const SearchArgs& a, int grid, hipStream_t st)
 // Wavefront w of a unit holds targets w, w + 4, ...: lane k keeps target w + 4k's data
 // in registers, read by the whole wavefront with readlane when its turn comes.
 __device__ __forceinline__ int rl32(int v, int k) { return __builtin_amdgcn_readlane(v, k); }
+// A pointer every lane holds, marked wave-uniform (scalar registers), so that stores through
+// it can take a 32-bit per-lane offset.
+template <typename T>
+__device__ __forceinline__ NNPS_GLOBAL T* uniform_ptr(NNPS_GLOBAL T* p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+    return (NNPS_GLOBAL T*)((static_cast<uint64_t>(hi) << 32) | lo);
+}
 __device__ __forceinline__ long long rl64(long long v, int k)
 {
     const int lo = __builtin_amdgcn_readlane(static_cast<int>(v & 0xFFFFFFFF), k);
@@ -1666,7 +1676,10 @@ k_dense(SearchArgs a)
                     for (int d = 0; d < 3; ++d) xi[d] = rlf64(xi_k[d], k);
                     const double* pis = pi;
                     int w = done;  // CSR entries of this row written so far
-                    auto emit = [&](int e, int slot) {
+                    // the row's output, wave-uniform: entries are addressed by a 32-bit slot
+                    NNPS_GLOBAL int32_t* const rcol = uniform_ptr(sd.col + rs);
+                    NNPS_GLOBAL float* const rdist = uniform_ptr(sd.dist + rs);
+                    auto emit = [&](int e, int slot, int oj) {
                         if (slot < rl && room) {
                             float dv;
                             if (F16) {
@@ -1680,8 +1693,14 @@ k_dense(SearchArgs a)
                             } else {
                                 dv = static_cast<float>(__dsqrt_rn(r2_fp64<DIM>(pis, spj + e * DIM)));
                             }
-                            sd.col[rs + slot] = sorig[e] - poff;
-                            sd.dist[rs + slot] = dv;
+                            if (rl <= (1 << 30)) {  // byte offsets within the row fit 32 bits
+                                const uint32_t off = static_cast<uint32_t>(slot) * 4u;
+                                *(NNPS_GLOBAL int32_t*)((NNPS_GLOBAL char*)rcol + off) = oj - poff;
+                                *(NNPS_GLOBAL float*)((NNPS_GLOBAL char*)rdist + off) = dv;
+                            } else {
+                                rcol[slot] = oj - poff;
+                                rdist[slot] = dv;
+                            }
                         }
                     };
                     for (int it = 0; it < nit; ++it) {
@@ -1694,8 +1713,8 @@ k_dense(SearchArgs a)
                         const uint64_t B1 = __ballot((b2 >> 1) & 1u);
                         if ((B0 | B1) == 0) continue;
                         const int pre = w + __popcll(B0 & lt) + __popcll(B1 & lt);
-                        if (b2 & 1u) emit(e0, pre);
-                        if (b2 & 2u) emit(e0 + 1, pre + static_cast<int>(b2 & 1u));
+                        if (b2 & 1u) emit(e0, pre, oo.x);
+                        if (b2 & 2u) emit(e0 + 1, pre + static_cast<int>(b2 & 1u), oo.y);
                         w += __popcll(B0) + __popcll(B1);
                     }
                     if (!room && lane == 0 && w > done) atomicOr(a.err, kErrCapacity);
