@@ -416,7 +416,7 @@ k_pack(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nset
 
 // ---------------------------------------------------------------------------
 // Work blocks, one wavefront per segment of 64 cells of a row of cells of a set: walking
-// the segment in x, a block is a run of at most kWave consecutive sorted particles whose
+// the segment in x, a block is a run of at most fr.bmax consecutive sorted particles whose
 // cells span at most fr.xwin cells; it starts where the previous one ended (so blocks are
 // full unless the span, the segment or the row ends them). A run of dense cells (the
 // dense-cell path's) is one block that the block kernels skip. The walk runs twice: the
@@ -438,6 +438,7 @@ k_row_blocks(const SetDesc* __restrict__ sets, const int* __restrict__ roffs, in
     const SetDesc& sd = sets[s];
     const int ncx = sd.fr.nc[0];
     const int span = sd.fr.xwin;
+    const int bmax = sd.fr.bmax;
     const int nseg = (ncx + kRowSegment - 1) / kRowSegment;
     const int rs = r - roffs[s];
     const int g0 = sd.coff + (rs / nseg) * ncx;
@@ -483,8 +484,8 @@ k_row_blocks(const SetDesc* __restrict__ sets, const int* __restrict__ roffs, in
                 xs = xx;
                 dense_open = false;
             }
-            while (a1 - bs > kWave) {
-                bs += kWave;
+            while (a1 - bs > bmax) {
+                bs += bmax;
                 start(bs);
                 xs = xx;
             }

@@ -128,10 +128,24 @@ nnps_status frame_of(const nnps_problem* p, Frame* fr, int block_target)
     fr->t_hi = f16_bits(4.0 * (rho2 + band), +1);
     fr->t_mid = f16_bits(4.0 * rho2, 0);
     // x-window of a work block: about block_target particles on average, so most windows
-    // fill one wavefront and the candidate union stays small
+    // fill one wavefront and the candidate union stays small; and at most what keeps the
+    // union of 3^(d-1) rows of xwin + 2 cells at 85 % of the fill's union limit on average
     const double occ = static_cast<double>(p->n) / static_cast<double>(ncell);
     int xwin = occ > 0.0 ? static_cast<int>(block_target / occ) : kMaxXWin;
+    if (occ > 0.0) {
+        const double rows = p->dim == 3 ? 9.0 : 3.0;
+        const double ucap = p->dim == 3 ? kUnion3 : kUnion2;
+        xwin = std::min(xwin, static_cast<int>(0.85 * ucap / (rows * occ)) - 2);
+    }
     fr->xwin = std::max(1, std::min(kMaxXWin, xwin));
+    // targets per block: at most what keeps the block's CSR entries (targets times the
+    // expected neighbours, occupancy times the radius ball in cell units) at 85 % of the
+    // fill's entry limit
+    const double ball = p->dim == 3 ? 4.18879020478639 * rho * rho * rho : 3.14159265358979 * rho * rho;
+    const double nb = occ * ball;
+    const double fcap = p->dim == 3 ? kFlat3 : kFlat2;
+    const int bm = nb > 0.0 ? static_cast<int>(0.85 * fcap / nb) : kWave;
+    fr->bmax = std::max(8, std::min(kWave, bm));
     return NNPS_OK;
 }
 
@@ -417,7 +431,7 @@ nnps_status prepare(nnps_ctx* ctx, nnps_cells* c, int nsets, const nnps_problem*
         const int64_t nseg = nrows * row_segments(fr.nc[0]);
         // blocks: full ones, at most one per span of xwin cells and one per row segment
         // ending early, and around each run of dense cells one marker plus one cut short
-        int64_t b = fr.n / kWave + nrows * ((fr.nc[0] + fr.xwin - 1) / fr.xwin) + nseg;
+        int64_t b = fr.n / fr.bmax + nrows * ((fr.nc[0] + fr.xwin - 1) / fr.xwin) + nseg;
         if (c->dense && c->dense_seen != 0)  // the build will use the dense-cell path
             b += 2 * std::min<int64_t>(fr.ncell, stencil * fr.n / (static_cast<int64_t>(c->dthresh) + 1));
         nblk_bound += std::min<int64_t>(fr.n, b);

@@ -68,6 +68,7 @@ struct Frame {
     double R2;          // fl(R*R)
     float dist_scale;   // (float)(w * 2^-F)
     int xwin;           // largest x-span of a work block, in cells
+    int bmax;           // most targets of a work block (<= 64)
     uint16_t t_lo, t_hi, t_mid;  // FP16 thresholds on r2 = 4|delta|^2 (bit patterns)
 };
 

@@ -165,6 +165,24 @@ def test_long_rows(ctx):
         assert got[3]["dense_rows"] > 0
 
 
+@pytest.mark.parametrize("radius_factor,block_target", [(2.6, 80), (2.6, 128), (2.4, 128), (2.9, 64)])
+def test_block_shape_stays_within_the_fill_limits(ctx, radius_factor, block_target):
+    """More neighbours per particle than the default workloads, and large block targets:
+    the host caps a block's x-span (union) and target count (entries) so blocks stay on the
+    block path (no long rows), and the result is the oracle's."""
+    ps = W.lattice(3, 26, 1 / 26, 0.1, seed=4, radius_factor=radius_factor,
+                   name=f"lat3d_R{radius_factor}_bt{block_target}")
+    print(f"[gpu] block limits {ps.name}", flush=True)
+    want = oracle.search_ps(ps)
+    ctx.set_tuning(block_target=block_target, dense_min_union=-1)
+    try:
+        got = gpu_search(ctx, ps, nnps.MODE_FP16_RCLL)
+    finally:
+        ctx.set_tuning()
+    check_against_oracle(got, want, nnps.MODE_FP16_RCLL, ps.name)
+    assert got[3]["heavy_rows"] == 0, ps.name
+
+
 def test_deterministic(ctx):
     ps = W.clustered(20000, 12, dim=3)
     a = gpu_search(ctx, ps, nnps.MODE_FP16_RCLL)
