@@ -770,6 +770,26 @@ __device__ __forceinline__ void wave_bitonic(uint32_t (&v)[EPL])
     }
 }
 
+// One wavefront sorts n <= 64 EPL column indices of a row in place (registers, element
+// e = lane EPL + i; padding sorts last and is not written back).
+template <int EPL>
+__device__ __forceinline__ void wave_sort_row(NNPS_GLOBAL int32_t* col, int n)
+{
+    const int lane = threadIdx.x & 63;
+    uint32_t v[EPL];
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) {
+        const int e = lane * EPL + i;
+        v[i] = e < n ? static_cast<uint32_t>(col[e]) : 0xFFFFFFFFu;
+    }
+    wave_bitonic<EPL>(v);
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) {
+        const int e = lane * EPL + i;
+        if (e < n) col[e] = static_cast<int32_t>(v[i]);
+    }
+}
+
 // Number of keys below `key` in a sorted run of P keys (P a power of two, the run padded
 // with all-ones keys): fixed-step binary lifting, every read inside the run.
 template <int P>
@@ -1237,9 +1257,20 @@ k_long(SearchArgs a)
             __syncthreads();
             continue;
         }
-        // 2. sort the row's column indices (distinct keys)
-        const int K = a.lr_keys;
-        for (int c0 = 0; c0 < L; c0 += K) {
+        // 2. sort the row's column indices (distinct keys): rows of up to 512 entries in the
+        // registers of the first wavefront (no workgroup barrier inside the network), longer
+        // ones in LDS chunks merged pairwise below
+        const int K = L <= 512 ? 512 : a.lr_keys;
+        if (L <= 512) {
+            if (threadIdx.x < 64) {
+                if (L <= 64) wave_sort_row<1>(col, L);
+                else if (L <= 128) wave_sort_row<2>(col, L);
+                else if (L <= 256) wave_sort_row<4>(col, L);
+                else wave_sort_row<8>(col, L);
+            }
+            __syncthreads();
+        }
+        for (int c0 = 0; L > 512 && c0 < L; c0 += K) {
             const int len = min(K, L - c0);
             int P = 1;
             while (P < len) P <<= 1;
