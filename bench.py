@@ -62,7 +62,7 @@ def time_mode(ctx, pos, ps, mode, steps, warmup):
     return ms, nnz, st, phases
 
 
-def time_batch(ctx, pss, mode, steps, warmup, graphs=True, pos=None, phase_steps=1):
+def time_batch(ctx, pss, mode, steps, warmup, graphs=True, pos=None, phase_steps=1, half=False):
     """Batch of particle sets: one graph-captured step (build + count + fill) per timed
     step. Returns (ms per step, total nnz, stats, per-phase mean ms over `phase_steps`
     further eager steps)."""
@@ -72,6 +72,7 @@ def time_batch(ctx, pss, mode, steps, warmup, graphs=True, pos=None, phase_steps
         pos = [torch.from_numpy(p.pos).cuda() for p in pss]
     sets = [(x, p.lo, p.hi, p.cell_size, p.radius) for x, p in zip(pos, pss)]
     cells = ctx.cells()
+    cells.set_half(half)
     cells.batch_build(sets, mode)
     rps = [torch.empty(p.n + 1, dtype=torch.int64, device="cuda") for p in pss]
     nnz = cells.batch_count(rps, sync=True)
@@ -220,6 +221,15 @@ def main():
                              "note": "sum of per-phase means of build + count + row scan; not the headline"}
     if args.workload in ("c1", "c2"):
         out["sph_gradient"] = bench_gradient(ctx_grad_ps=ps, pos=pos, steps=max(args.steps, 5))
+        # half lists (each unordered pair once): the same step with nnps_cells_set_half
+        ctx_h = nnps.Context(0)
+        msh, nnzh, _, phh = time_batch(ctx_h, [ps], nnps.MODE_FP16_RCLL, args.steps, args.warmup, pos=[pos],
+                                       phase_steps=args.steps, half=True)
+        ctx_h.close()
+        log(f"[bench] half lists {msh:.3f} ms/step nnz={nnzh}")
+        out["half_list"] = {"ms_per_step": msh, "nnz": nnzh, "pairs_per_s": nnzh / (msh * 1e-3),
+                            "directed_gpairs_per_s": 2 * nnzh / (msh * 1e-3) / 1e9,
+                            "count_ms": phh["count"], "fill_ms": phh["fill"]}
     if not args.no_serving:
         out["serving"] = bench_serving(args)
     if not args.no_cpu_baseline:

@@ -213,6 +213,13 @@ nnps_status nnps_batch_step(nnps_ctx *ctx, nnps_cells *cells, int32_t nsets, con
                             const double *const *d_pos, int64_t *const *d_row_ptr, int32_t *const *d_col,
                             float *const *d_dist, const int64_t *capacity, void *stream);
 nnps_status nnps_cells_set_graphs(nnps_cells *cells, int on);
+/* Half lists (on != 0): from the next count on, row i keeps only the neighbours j with
+ * j > i (original indices), so every unordered pair appears once, in the row of its
+ * smaller index; the CSR and its nnz halve. Distances and statistics are unchanged
+ * otherwise (candidates, band pairs and FP16 misclassifications still count every
+ * directed pair tested). Default off. Applies to every path of the structure; a
+ * following nnps_fill needs a count made in the same setting (else NNPS_EORDER). */
+nnps_status nnps_cells_set_half(nnps_cells *cells, int on);
 /* Waits for the stream and returns each set's nnz of the last count (nsets entries). */
 nnps_status nnps_batch_nnz(nnps_cells *cells, int64_t *h_nnz, void *stream);
 /* The same without a synchronous round trip: enqueue copies each set's nnz and the

@@ -90,6 +90,7 @@ struct SearchArgs {
     int lr_keys;                    // keys a long-row workgroup sorts in LDS
     int* err;
     int* sink;                      // [2 * 64] per-lane dummy output slots
+    int half;                       // 1: rows keep only neighbours of larger original index
     // dense-cell path (wdense == nullptr: off)
     const int* wdense;
     const int* usz;

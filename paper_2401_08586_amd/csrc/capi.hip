@@ -226,6 +226,7 @@ struct nnps_cells {
     PhaseTimer timer;
     GraphCache graph;
     bool use_graphs = false;
+    bool half = false;                    // rows keep only neighbours of larger original index
     bool built = false, counted = false;
     int nsets = 0, dim = 0, mode = 0, ntot = 0, ncell_tot = 0, nblk_max = 0;
     std::vector<Frame> frames;
@@ -330,6 +331,7 @@ SearchArgs args_of(const nnps_cells* c)
     a.lr_keys = c->ctx->tuning.long_rows_keys > 0 ? std::min(c->ctx->tuning.long_rows_keys, keys) : keys;
     a.err = c->err.as<int>();
     a.sink = c->sink.as<int>();
+    a.half = c->half ? 1 : 0;
     if (c->dense_active) {
         a.wdense = c->wdense.as<int>();
         a.usz = c->usz.as<int>();
@@ -807,6 +809,14 @@ nnps_status nnps_count(nnps_ctx* ctx, nnps_cells* c, int64_t* d_row_ptr, int64_t
     return nnps_batch_count(ctx, c, rp, h_nnz, stream);
 }
 
+nnps_status nnps_cells_set_half(nnps_cells* c, int on)
+{
+    if (!c) return NNPS_EINVAL;
+    c->half = on != 0;
+    c->counted = false;  // row pointers of the other kind must be recounted
+    return NNPS_OK;
+}
+
 nnps_status nnps_sph_gradient(nnps_ctx* ctx, int32_t dim, int64_t n, double h, const double* d_pos, const double* d_f,
                               const double* d_vol, const int64_t* d_row_ptr, const int32_t* d_col, double* d_grad,
                               double* d_grad_norm, void* stream)
@@ -921,8 +931,8 @@ nnps_status nnps_batch_step(nnps_ctx* ctx, nnps_cells* c, int32_t nsets, const n
     q += sizeof(nnps_tuning);
     memcpy(q, &nsets, 4);
     q += 4;
-    const int dense_plan = c->dense && c->dense_seen != 0 ? 1 : 0;
-    memcpy(q, &dense_plan, 4);
+    const int plan = (c->dense && c->dense_seen != 0 ? 1 : 0) | (c->half ? 2 : 0);
+    memcpy(q, &plan, 4);
     (void)gen0;
     if (!c->graph.exec || c->graph.sig != sig) {
         c->graph.reset();

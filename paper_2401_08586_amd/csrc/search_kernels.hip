@@ -482,7 +482,7 @@ struct CandBits {
 };
 
 // Count pass, FP16 relative coordinates (MODE 0; MODE 2 decides every candidate in FP64).
-template <int DIM, int MODE>
+template <int DIM, int MODE, bool HALF>
 __global__ void __launch_bounds__(64)
 k_count16(SearchArgs a)
 {
@@ -490,6 +490,8 @@ k_count16(SearchArgs a)
     // pair records of the staged chunk, and kGroup more that the last group of a range may
     // read past the chunk (their bits are masked)
     __shared__ uint4 srec[kStage / 2 + kGroup];
+    // half lists: the staged candidates' original indices (same padding)
+    __shared__ __attribute__((aligned(16))) int corig[HALF ? kStage + 2 * kGroup : 1];
     __shared__ uint32_t lbits[64 * (CB::CW + 1)];
     const int b = blockIdx.x;
     if (b >= *a.nblk) return;
@@ -536,7 +538,7 @@ k_count16(SearchArgs a)
             const uint32_t r2h = (rb >> (16 * (posl & 1))) & 0xFFFFu;
             if (!bq.push(posl, r2h) && posl != g.pself) {
                 int oj;
-                if (classify<DIM, 0>(a, g, pi, posl, r2h, t, nullptr, cbase, &oj)) {
+                if (classify<DIM, 0>(a, g, pi, posl, r2h, t, nullptr, cbase, &oj) && (!HALF || oj > oi)) {
                     ++cnt;
                     cb_.set(posl);
                 }
@@ -547,7 +549,7 @@ k_count16(SearchArgs a)
         const int ce = min(g.U, cb + kStage);
         cbase = cb;
         __syncthreads();
-        stage<DIM, false>(a, g, cb, ce, srec, nullptr);
+        stage<DIM, HALF>(a, g, cb, ce, srec, corig);
         __syncthreads();
         if (!g.active) continue;
 #pragma unroll
@@ -567,7 +569,8 @@ k_count16(SearchArgs a)
                         if (((inv >> (16 * h)) & 0xFFFF) || posl == selfp) continue;
                         int oj;
                         if (classify<DIM, MODE>(a, g, pi, posl, (rb >> (16 * h)) & 0xFFFF, t, nullptr, cb,
-                                                &oj)) {
+                                                &oj) &&
+                            (!HALF || oj > oi)) {
                             ++cnt;
                             cb_.set(posl);
                         }
@@ -581,7 +584,7 @@ k_count16(SearchArgs a)
                 const uint4* rec = srec - (cb >> 1);
                 const int m0 = lo >> 1, mend = (hi + 1) >> 1;
                 for (int mg = m0; mg < mend; mg += kGroup) {
-                    uint32_t acc = 0, ebits = 0;
+                    uint32_t acc = 0, ebits = 0, gt = 0;
 #pragma unroll
                     for (int j = 0; j < kGroup; ++j) {
                         const uint32_t rb = r2_pair<DIM>(tg, ay, az, rec[mg + j]);
@@ -589,6 +592,10 @@ k_count16(SearchArgs a)
                         const u16x2 e = d - th.w12;
                         acc |= (u16x2_bits(d) >> (15 - j)) & (0x10001u << j);
                         ebits |= (u16x2_bits(e) >> (15 - j)) & (0x10001u << j);
+                        if (HALF) {
+                            const int2 oo = *reinterpret_cast<const int2*>(&corig[2 * (mg + j) - cb]);
+                            gt |= (oo.x > oi ? 1u << j : 0u) | (oo.y > oi ? 1u << (16 + j) : 0u);
+                        }
                     }
                     // the group's positions inside [lo, hi)
                     const int a0 = lo - 2 * mg, b0 = hi - 2 * mg;
@@ -596,6 +603,7 @@ k_count16(SearchArgs a)
                                            (span8(a0 >> 1, b0 >> 1) << 16);
                     acc &= valid;
                     const uint32_t bnd = ebits & ~acc & valid;
+                    if (HALF) acc &= gt;  // half list: only candidates of larger original index
                     cnt += __builtin_popcount(acc);
                     cb_.put16(2 * mg, interleave8(acc));
                     if (bnd) {
@@ -609,8 +617,9 @@ k_count16(SearchArgs a)
         if constexpr (MODE == 0) bg.drain(band_group);
     }
     if constexpr (MODE == 0) {
-        // self (r2 = 0) was counted as "in" when T_lo > 0, or queued as a band pair
-        if (g.active && fr.t_lo > 0) cnt -= 1;
+        // self (r2 = 0) was counted as "in" when T_lo > 0, or queued as a band pair; half
+        // lists never count it (its index is not larger than its own)
+        if (!HALF && g.active && fr.t_lo > 0) cnt -= 1;
         bq.drain([&](int posl, uint32_t r2h) {
             if (posl == g.pself) return;
             const int oj = a.perm[g.global_of_any(posl)];
@@ -619,8 +628,9 @@ k_count16(SearchArgs a)
             t.band++;
             t.fpos += naive && !truth;
             t.fneg += !naive && truth;
-            cnt += truth;
-            if (truth) cb_.set(posl);
+            const bool keep = truth && (!HALF || oj > oi);
+            cnt += keep;
+            if (keep) cb_.set(posl);
         });
         // candidates: the lane's ranges minus itself
         if (g.active) t.cand += cb_.total - 1;
@@ -636,7 +646,7 @@ k_count16(SearchArgs a)
 }
 
 // Count pass, plain FP64 baseline: one lane per target, global FP64 loads.
-template <int DIM>
+template <int DIM, bool HALF>
 __global__ void __launch_bounds__(64)
 k_count64(SearchArgs a)
 {
@@ -656,6 +666,7 @@ k_count64(SearchArgs a)
     int cnt = 0;
     unsigned long long cand = 0;
     if (g.active) {
+        const int oi = a.perm[g.p];
         const double* pi = a.spos + static_cast<size_t>(g.p) * 4;
         const double pix[3] = {pi[0], pi[1], DIM == 3 ? pi[2] : 0.0};
 #pragma unroll
@@ -674,16 +685,16 @@ k_count64(SearchArgs a)
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    if (j + u < gb && d2[u] <= fr.R2) {
+                    if (j + u < gb && d2[u] <= fr.R2 && (!HALF || a.perm[j + u] > oi)) {
                         ++cnt;
                         cb_.set(pbase + j + u);
                     }
                 }
             }
         }
-        cnt -= 1;  // itself (r2 = 0)
+        if (!HALF) cnt -= 1;  // itself (r2 = 0)
         cand -= 1;
-        a.counts[a.perm[g.p]] = cnt;
+        a.counts[oi] = cnt;
     }
     cb_.store(a, g.p);
     const unsigned long long s = wave_sum_u64(cand);
@@ -1244,7 +1255,7 @@ k_long(SearchArgs a)
                     const bool band = !in16 && r2h <= fr.t_hi;
                     nb = (MODE == 2 || band) ? recheck_g<DIM>(sd.pos, pi, oj - sd.poff, fr.R2) : in16;
                 }
-                if (nb) {
+                if (nb && (!a.half || oj > oi)) {
                     const int slot = atomicAdd(&fill, 1);
                     if (slot < rlen && room) col[slot] = oj - sd.poff;
                 }
@@ -1347,12 +1358,21 @@ hipError_t launch_count(const SearchArgs& a, int nblk_max, hipStream_t st)
     if (a.L.ntot == 0 || nblk_max == 0) return hipSuccess;
     const dim3 g(nblk_max), b(64);
     const int d = a.L.dim, m = a.L.mode;
-    if (d == 2 && m == 0) hipLaunchKernelGGL((k_count16<2, 0>), g, b, 0, st, a);
-    else if (d == 3 && m == 0) hipLaunchKernelGGL((k_count16<3, 0>), g, b, 0, st, a);
-    else if (d == 2 && m == 2) hipLaunchKernelGGL((k_count16<2, 2>), g, b, 0, st, a);
-    else if (d == 3 && m == 2) hipLaunchKernelGGL((k_count16<3, 2>), g, b, 0, st, a);
-    else if (d == 2) hipLaunchKernelGGL(k_count64<2>, g, b, 0, st, a);
-    else hipLaunchKernelGGL(k_count64<3>, g, b, 0, st, a);
+    if (a.half) {
+        if (d == 2 && m == 0) hipLaunchKernelGGL((k_count16<2, 0, true>), g, b, 0, st, a);
+        else if (d == 3 && m == 0) hipLaunchKernelGGL((k_count16<3, 0, true>), g, b, 0, st, a);
+        else if (d == 2 && m == 2) hipLaunchKernelGGL((k_count16<2, 2, true>), g, b, 0, st, a);
+        else if (d == 3 && m == 2) hipLaunchKernelGGL((k_count16<3, 2, true>), g, b, 0, st, a);
+        else if (d == 2) hipLaunchKernelGGL((k_count64<2, true>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((k_count64<3, true>), g, b, 0, st, a);
+        return hipGetLastError();
+    }
+    if (d == 2 && m == 0) hipLaunchKernelGGL((k_count16<2, 0, false>), g, b, 0, st, a);
+    else if (d == 3 && m == 0) hipLaunchKernelGGL((k_count16<3, 0, false>), g, b, 0, st, a);
+    else if (d == 2 && m == 2) hipLaunchKernelGGL((k_count16<2, 2, false>), g, b, 0, st, a);
+    else if (d == 3 && m == 2) hipLaunchKernelGGL((k_count16<3, 2, false>), g, b, 0, st, a);
+    else if (d == 2) hipLaunchKernelGGL((k_count64<2, false>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((k_count64<3, false>), g, b, 0, st, a);
     return hipGetLastError();
 }
 
@@ -1580,11 +1600,15 @@ k_dense(SearchArgs a)
                 }
                 // candidate bits: bit it for candidate it*128 + 2 lane, bit 16 + it for the one
                 // after it; "in" and "in or band" from the sign bits of two 16-bit subtractions
-                uint32_t ebits = 0;
+                uint32_t ebits = 0, gt = 0;
 #pragma unroll
                 for (int it = 0; it < K / 128; ++it) {
                     if (it >= nit) break;
                     const int m = it * 64 + lane;
+                    if (!FILL && a.half) {  // half lists: candidates of larger original index
+                        const int2 oo = *reinterpret_cast<const int2*>(&sorig[2 * m]);
+                        gt |= (oo.x > oi ? 1u << it : 0u) | (oo.y > oi ? 1u << (16 + it) : 0u);
+                    }
                     if (F16) {
                         const uint4 A = recA[m];
                         const uint2 B = recB[m];
@@ -1690,6 +1714,7 @@ k_dense(SearchArgs a)
                     }
                 }
                 if constexpr (!FILL) {
+                    if (a.half) inb &= gt;
                     const int tot = static_cast<int>(wave_sum_u64(static_cast<unsigned long long>(__builtin_popcount(inb))));
                     if (lane == k) acc_k += tot;
                 } else {
@@ -1738,8 +1763,10 @@ k_dense(SearchArgs a)
                         uint32_t b2 = ((inb >> it) & 1u) | (((inb >> (16 + it)) & 1u) << 1);
                         const int e0 = it * 128 + 2 * lane;
                         const int2 oo = *reinterpret_cast<const int2*>(&sorig[e0]);
-                        if (oo.x == oi) b2 &= ~1u;  // the target itself is never its own neighbour
-                        if (oo.y == oi) b2 &= ~2u;
+                        // the target itself is never its own neighbour; half lists keep only
+                        // larger original indices
+                        if (oo.x == oi || (a.half && oo.x < oi)) b2 &= ~1u;
+                        if (oo.y == oi || (a.half && oo.y < oi)) b2 &= ~2u;
                         const uint64_t B0 = __ballot(b2 & 1u);
                         const uint64_t B1 = __ballot((b2 >> 1) & 1u);
                         if ((B0 | B1) == 0) continue;
@@ -1757,7 +1784,7 @@ k_dense(SearchArgs a)
             if (!FILL) {
                 // itself: "in" in FP16 when T_lo > 0, always in the FP64 baseline; never
                 // counted when every candidate is decided in FP64 (it is skipped there)
-                const int self = MODE == 1 ? 1 : (MODE == 2 ? 0 : (tlo > 0 ? 1 : 0));
+                const int self = a.half ? 0 : (MODE == 1 ? 1 : (MODE == 2 ? 0 : (tlo > 0 ? 1 : 0)));
                 a.counts[oi_k] = acc_k - self;
             } else if (acc_k != rl_k) {
                 atomicOr(a.err, kErrLongRow);

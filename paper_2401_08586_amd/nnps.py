@@ -72,7 +72,7 @@ EXPORTS = ["nnps_status_str", "nnps_validate", "nnps_grid", "nnps_ctx_create", "
            "nnps_search", "nnps_stats_get", "nnps_cells_set_profiling", "nnps_phase_times",
            "nnps_batch_build", "nnps_batch_count", "nnps_batch_fill", "nnps_batch_search",
            "nnps_batch_step", "nnps_cells_set_graphs", "nnps_batch_nnz", "nnps_batch_nnz_enqueue",
-           "nnps_batch_nnz_fetch", "nnps_sph_gradient"]
+           "nnps_batch_nnz_fetch", "nnps_sph_gradient", "nnps_cells_set_half"]
 
 PHASES = ["assign", "cellscan", "sort", "pack", "blocks", "unions", "count", "dcount", "rowscan", "fill",
           "longrows", "dfill"]
@@ -116,6 +116,7 @@ def load():
     lib.nnps_batch_search.argtypes = [P, P, ctypes.c_int32, ctypes.POINTER(Problem), P, P, P, P, P, P, P]
     lib.nnps_batch_step.argtypes = [P, P, ctypes.c_int32, ctypes.POINTER(Problem), P, P, P, P, P, P]
     lib.nnps_cells_set_graphs.argtypes = [P, ctypes.c_int]
+    lib.nnps_cells_set_half.argtypes = [P, ctypes.c_int]
     lib.nnps_batch_nnz.argtypes = [P, P, P]
     lib.nnps_phase_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), P]
     lib.nnps_sph_gradient.argtypes = [P, ctypes.c_int32, I64, ctypes.c_double, P, P, P, P, P, P, P, P]
@@ -302,6 +303,10 @@ class Cells:
             return list(nnz), code
         _check(code, "nnps_batch_nnz")
         return list(nnz)
+
+    def set_half(self, on: bool = True):
+        """Half lists: rows keep only neighbours of larger original index (nnps_cells_set_half)."""
+        _check(self._lib.nnps_cells_set_half(self._h, 1 if on else 0), "nnps_cells_set_half")
 
     def batch_nnz_enqueue(self, stream=None):
         """Queue the copies of each set's nnz and the error flags to pinned host memory."""
