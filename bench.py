@@ -26,8 +26,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of one fill launch at the default workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE per dispatch scaled by what they read for a 512 MiB device copy (x2.000 and
 # x1.000); valid only for the kernel source it was measured on (see profiles/).
-FILL_TRAFFIC = {"source_sha256_16": "2a763eca0a2034dd", "bytes": (229313 * 2.0 + 477314 * 1.0) * 1024,
-                "fetch_kib": 229313, "write_kib": 477314, "fetch_scale": 2.0, "write_scale": 1.0}
+FILL_TRAFFIC = {"source_sha256_16": "b1c988579c5dc601", "bytes": (230063 * 2.0 + 477159 * 1.0) * 1024,
+                "fetch_kib": 230063, "write_kib": 477159, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def fill_traffic():
@@ -139,6 +139,8 @@ def cpu_baseline(ps, budget_s=20.0):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the SPH-gradient and half-list legs (profiling runs of the search kernels)")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2", "c3"])
@@ -219,7 +221,7 @@ def main():
         out["count_only"] = {"fp16_ms": c16, "fp64_ms": c64, "speedup_fp16_over_fp64": c64 / c16,
                              "count_kernel_speedup": ph64["count"] / ph16["count"],
                              "note": "sum of per-phase means of build + count + row scan; not the headline"}
-    if args.workload in ("c1", "c2"):
+    if args.workload in ("c1", "c2") and not args.no_extras:
         out["sph_gradient"] = bench_gradient(ctx_grad_ps=ps, pos=pos, steps=max(args.steps, 5))
         # half lists (each unordered pair once): the same step with nnps_cells_set_half
         ctx_h = nnps.Context(0)
