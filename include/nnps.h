@@ -230,6 +230,20 @@ nnps_status nnps_batch_nnz(nnps_cells *cells, int64_t *h_nnz, void *stream);
 nnps_status nnps_batch_nnz_enqueue(nnps_cells *cells, void *stream);
 nnps_status nnps_batch_nnz_fetch(nnps_cells *cells, int64_t *h_nnz);
 
+/* ---- All-list search for small sets ------------------------------------------------
+ * Every particle tested against every other (SPH method section, Fig. 3a), in binary64
+ * with the cell-list paths' predicate, so row_ptr, col and dist are bit-identical to the
+ * FP64 cell list (prob->mode and prob->cell_size are not used; the box is only checked).
+ * Meant for small sets, where it needs three kernel launches and no cell structure:
+ * prob->n must not exceed 65536 (NNPS_EINVAL above; the work grows as n^2). Writes
+ * d_row_ptr [n+1], waits for the stream once to learn nnz (*nnz_out), then, if capacity
+ * >= nnz, queues the fill of d_col/d_dist (asynchronous) and returns NNPS_OK; otherwise
+ * returns NNPS_ECAPACITY with *nnz_out = nnz and only row_ptr written. NNPS_EDOMAIN if a
+ * position lies outside [lo, hi] or is not finite (nothing further written). */
+nnps_status nnps_allpairs_search(nnps_ctx *ctx, const nnps_problem *prob, const double *d_pos,
+                                 int64_t *d_row_ptr, int32_t *d_col, float *d_dist, int64_t capacity,
+                                 int64_t *nnz_out, void *stream);
+
 /* ---- SPH gradient over a neighbour list ------------------------------------------
  * The SPH approximation of the gradient of a scalar field f (SPH method section, Eq. 2,
  * with the cubic B-spline kernel of Eq. 3, support 2h) and the normalised, volume-free

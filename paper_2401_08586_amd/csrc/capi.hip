@@ -13,6 +13,7 @@
 #include "../../include/nnps.h"
 #include "build_kernels.h"
 #include "sph_kernels.h"
+#include "allpairs_kernels.h"
 
 using namespace nnps;
 
@@ -154,6 +155,7 @@ nnps_status frame_of(const nnps_problem* p, Frame* fr, int block_target)
 struct nnps_ctx {
     int device = 0;
     int64_t* h_pinned = nullptr;  // pinned staging for synchronous read-backs
+    int* d_flag = nullptr;        // device error word of the all-list path (allocated on first use)
     int max_lds = 65536;          // LDS bytes a workgroup may use on this device
     nnps_tuning tuning{80, 1024, 0, 0, 0, 0, 0};
 };
@@ -703,6 +705,7 @@ void nnps_ctx_destroy(nnps_ctx* c)
     if (!c) return;
     DeviceGuard g(c->device);
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+    if (c->d_flag) (void)hipFree(c->d_flag);
     delete c;
 }
 
@@ -807,6 +810,45 @@ nnps_status nnps_count(nnps_ctx* ctx, nnps_cells* c, int64_t* d_row_ptr, int64_t
     if (!c || c->nsets != 1) return c ? NNPS_EORDER : NNPS_EINVAL;
     int64_t* rp[1] = {d_row_ptr};
     return nnps_batch_count(ctx, c, rp, h_nnz, stream);
+}
+
+nnps_status nnps_allpairs_search(nnps_ctx* ctx, const nnps_problem* prob, const double* d_pos, int64_t* d_row_ptr,
+                                 int32_t* d_col, float* d_dist, int64_t capacity, int64_t* nnz_out, void* stream)
+{
+    if (!ctx || !prob || !d_row_ptr || !nnz_out || capacity < 0) return NNPS_EINVAL;
+    const nnps_status v = nnps_validate(prob);
+    if (v != NNPS_OK) return v;
+    if (prob->n > kAllPairsMaxN || (prob->n > 0 && !d_pos)) return NNPS_EINVAL;
+    if (capacity > 0 && (!d_col || !d_dist)) return NNPS_EINVAL;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return NNPS_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int n = static_cast<int>(prob->n);
+    *nnz_out = 0;
+    if (n == 0) {
+        HIP_TRY(hipMemsetAsync(d_row_ptr, 0, sizeof(int64_t), s));
+        return NNPS_OK;
+    }
+    if (!ctx->d_flag && hipMalloc(reinterpret_cast<void**>(&ctx->d_flag), 64) != hipSuccess) return NNPS_ENOMEM;
+    ApBox box{};
+    for (int k = 0; k < prob->dim; ++k) {
+        box.lo[k] = prob->lo[k];
+        box.hi[k] = prob->hi[k];
+    }
+    const double R2 = prob->radius * prob->radius;
+    HIP_TRY(hipMemsetAsync(ctx->d_flag, 0, sizeof(int), s));
+    HIP_TRY(launch_allpairs_count(prob->dim, n, d_pos, R2, box, d_row_ptr, ctx->d_flag, s));
+    int64_t* hp = ctx->h_pinned;
+    hp[0] = 0;
+    hp[1] = 0;
+    HIP_TRY(hipMemcpyAsync(hp, d_row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hp + 1, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *nnz_out = hp[0];
+    if (static_cast<int>(hp[1] & 0xFFFFFFFF) != 0) return NNPS_EDOMAIN;
+    if (hp[0] > capacity) return NNPS_ECAPACITY;
+    HIP_TRY(launch_allpairs_fill(prob->dim, n, d_pos, R2, box, d_row_ptr, d_col, d_dist, s));
+    return NNPS_OK;
 }
 
 nnps_status nnps_cells_set_half(nnps_cells* c, int on)

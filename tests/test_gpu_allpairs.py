@@ -1,0 +1,92 @@
+"""The all-list path (nnps_allpairs_search, Fig. 3a) against the oracle's brute force:
+row_ptr and col equal, distances bit-identical (both binary64, then rounded to FP32); the
+error paths (capacity, domain, size limit)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2401_08586_amd import nnps
+from paper_2401_08586_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = nnps.Context(0)
+    yield c
+    c.close()
+
+
+def run(ctx, ps):
+    pos = torch.from_numpy(np.ascontiguousarray(ps.pos)).cuda()
+    rp, col, dist = nnps.allpairs_search(pos, ps.lo, ps.hi, ps.radius, ctx=ctx)
+    torch.cuda.synchronize()
+    return rp.cpu().numpy(), col.cpu().numpy(), dist.cpu().numpy()
+
+
+CASES = [
+    lambda: W.uniform(2, 3000, seed=1),
+    lambda: W.uniform(3, 5000, seed=2),
+    lambda: W.lattice(2, 50, 0.02, 0.0, name="lat2d_perfect"),
+    lambda: W.lattice(3, 12, 1 / 12, 0.1, seed=3),
+    lambda: W.clustered(4000, 7, dim=3),
+    lambda: W.ring_pairs(500, 0.05, seed=8, dim=2),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_allpairs_matches_brute_force(ctx, case):
+    ps = CASES[case]()
+    print(f"[gpu] allpairs {ps.name} n={ps.n}", flush=True)
+    want = oracle.search_ps(ps, brute=True)
+    got = run(ctx, ps)
+    np.testing.assert_array_equal(got[0], want[0])
+    np.testing.assert_array_equal(got[1], want[1])
+    np.testing.assert_array_equal(got[2].view(np.uint32), want[2].view(np.uint32))
+
+
+def test_allpairs_equals_the_fp64_cell_list(ctx):
+    ps = W.uniform(3, 20000, seed=4)
+    pos = torch.from_numpy(ps.pos).cuda()
+    a = nnps.allpairs_search(pos, ps.lo, ps.hi, ps.radius, ctx=ctx)
+    b = nnps.search(pos, ps.lo, ps.hi, ps.cell_size, ps.radius, mode=nnps.MODE_FP64_BASELINE, ctx=ctx)[:3]
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 257])
+def test_allpairs_tiny_sets_and_duplicates(ctx, n):
+    rng = np.random.default_rng(n)
+    pos = rng.uniform(0, 1, (n, 3))
+    if n >= 2:
+        pos[1] = pos[0]  # coincident particles are neighbours
+    ps = W.ParticleSet(np.ascontiguousarray(pos), (0, 0, 0), (1, 1, 1), 0.3, 0.3, f"tiny{n}")
+    got = run(ctx, ps)
+    if n == 0:
+        assert got[0].tolist() == [0] and got[1].size == 0
+        return
+    want = oracle.search_ps(ps, brute=True)
+    for x, y in zip(got[:2], want[:2]):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_allpairs_errors(ctx):
+    lib = nnps.load()
+    import ctypes
+    pos = torch.tensor([[0.1, 0.1], [0.2, 0.2], [1.5, 0.5]], dtype=torch.float64, device="cuda")
+    rp = torch.empty(4, dtype=torch.int64, device="cuda")
+    nnz = ctypes.c_int64(0)
+    prob = nnps.make_problem(2, 3, (0, 0), (1, 1), 0.5, 0.5)
+    code = lib.nnps_allpairs_search(ctx._ctx, ctypes.byref(prob), nnps._ptr(pos), nnps._ptr(rp), None, None, 0,
+                                    ctypes.byref(nnz), None)
+    assert code == nnps.NNPS_EDOMAIN
+    pos[2, 0] = 0.3
+    code = lib.nnps_allpairs_search(ctx._ctx, ctypes.byref(prob), nnps._ptr(pos), nnps._ptr(rp), None, None, 0,
+                                    ctypes.byref(nnz), None)
+    assert code == nnps.NNPS_ECAPACITY and nnz.value == 6
+    big = nnps.make_problem(2, 65537, (0, 0), (1, 1), 0.5, 0.5)
+    code = lib.nnps_allpairs_search(ctx._ctx, ctypes.byref(big), nnps._ptr(pos), nnps._ptr(rp), None, None, 0,
+                                    ctypes.byref(nnz), None)
+    assert code == nnps.NNPS_EINVAL
