@@ -140,12 +140,13 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the SPH-gradient and half-list legs (profiling runs of the search kernels)")
+                    help="skip the SPH-gradient, half-list and all-list legs (profiling runs of the search kernels)")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2", "c3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 relative-coordinate leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-mix leg")
     ap.add_argument("--no-autotune", action="store_true", help="batch workload: keep the default tuning")
     ap.add_argument("--serving-requests", type=int, default=2000)
@@ -176,6 +177,16 @@ def main():
         log(f"[bench] fp64-baseline {ms64:.3f} ms/step phases={ph64}")
         res64 = {"value": nnz / (ms64 * 1e-3) / 1e9, "unit": "Gpairs/s", "ms_per_step": ms64,
                  "phases_ms": ph64, "speedup_fp16_over_fp64": ms64 / ms16}
+    res32 = None
+    if not args.no_fp32:
+        ms32, nnz32, st32, ph32 = time_mode(ctx, pos, ps, nnps.MODE_FP32_RCLL, args.steps, args.warmup)
+        assert nnz32 == nnz
+        log(f"[bench] fp32-rcll {ms32:.3f} ms/step phases={ph32}")
+        res32 = {"value": nnz / (ms32 * 1e-3) / 1e9, "unit": "Gpairs/s", "ms_per_step": ms32,
+                 "phases_ms": ph32, "speedup_fp16_over_fp32": ms32 / ms16,
+                 "count_kernel_ms": ph32["count"],
+                 "fp32_stats": {"band_pairs": st32["band_pairs"], "false_pos": st32["fp16_false_pos"],
+                                "false_neg": st32["fp16_false_neg"]}}
     ctx.close()
     if args.copy_probe:
         src = torch.ones(1 << 27, dtype=torch.float32, device="cuda")  # 512 MiB
@@ -212,6 +223,7 @@ def main():
         "fp16_stats": {k: st16[k] for k in ("candidates", "band_pairs", "fp16_false_pos",
                                               "fp16_false_neg", "heavy_rows", "dense_rows")},
         "fp64_baseline": res64,
+        "fp32_rcll": res32,
     }
     if res64 is not None:
         # build + count only (no CSR written), from the per-phase means: isolates the test
@@ -232,12 +244,55 @@ def main():
         out["half_list"] = {"ms_per_step": msh, "nnz": nnzh, "pairs_per_s": nnzh / (msh * 1e-3),
                             "directed_gpairs_per_s": 2 * nnzh / (msh * 1e-3) / 1e9,
                             "count_ms": phh["count"], "fill_ms": phh["fill"]}
+    if not args.no_extras:
+        out["allpairs_vs_cells"] = bench_allpairs()
     if not args.no_serving:
         out["serving"] = bench_serving(args)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(ps)
     print(json.dumps(out), flush=True)
+
+
+def bench_allpairs(sizes=(1000, 4000, 16000, 64000), reps=20):
+    """All-list search (Fig. 3a) against the FP64 and FP16 cell lists on small uniform 3D
+    sets, as whole calls (each returns a ready CSR; both read a count back to the host):
+    mean wall time per call over `reps` calls after one warm-up call."""
+    import torch
+    from paper_2401_08586_amd import nnps
+    from paper_2401_08586_amd import workloads as W
+    ctx = nnps.Context(0)
+    out = []
+    for n in sizes:
+        ps = W.uniform(3, n, seed=n)
+        pos = torch.from_numpy(ps.pos).cuda()
+        row = {"n": n}
+        c64, c16 = ctx.cells(), ctx.cells()  # cell structures reused across calls
+        calls = {
+            "allpairs_ms": lambda: nnps.allpairs_search(pos, ps.lo, ps.hi, ps.radius, ctx=ctx),
+            "cells_fp64_ms": lambda: nnps.search(pos, ps.lo, ps.hi, ps.cell_size, ps.radius,
+                                                 mode=nnps.MODE_FP64_BASELINE, ctx=ctx, cells=c64),
+            "cells_fp16_ms": lambda: nnps.search(pos, ps.lo, ps.hi, ps.cell_size, ps.radius, ctx=ctx,
+                                                 cells=c16),
+        }
+        for name, call in calls.items():
+            r = call()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                r = call()
+            torch.cuda.synchronize()
+            row[name] = (time.perf_counter() - t0) * 1e3 / reps
+            if name == "allpairs_ms":
+                row["nnz"] = int(r[1].numel())
+            else:
+                assert int(r[1].numel()) == row["nnz"]
+        c64.close()
+        c16.close()
+        log(f"[bench] allpairs vs cells {row}")
+        out.append(row)
+    ctx.close()
+    return out
 
 
 def bench_gradient(ctx_grad_ps, pos, steps):

@@ -59,9 +59,13 @@ typedef enum nnps_status {
 typedef enum nnps_mode {
     NNPS_MODE_FP16_RCLL = 0,      /* FP16 relative coordinates + FP64 guard-band recheck */
     NNPS_MODE_FP64_BASELINE = 1,  /* plain FP64 cell list (thread per particle, global loads) */
-    NNPS_MODE_RECHECK_ALL = 2     /* debug: FP16 pass plus FP64 on every candidate; the FP64
+    NNPS_MODE_RECHECK_ALL = 2,    /* debug: FP16 pass plus FP64 on every candidate; the FP64
                                      decision is used and FP16 disagreements outside the band
                                      are counted (must be 0) */
+    NNPS_MODE_FP32_RCLL = 3       /* FP32 relative coordinates (Eq. 6-7 in single precision) +
+                                     FP64 recheck in a guard band of 2^-15 squared cell widths;
+                                     dense cells and long rows are decided in FP64; distances
+                                     as in NNPS_MODE_FP64_BASELINE (bit-identical to binary64) */
 } nnps_mode;
 
 /* One search problem. Positions are d_pos[i*dim + k] (row-major, float64).
@@ -85,6 +89,8 @@ typedef struct nnps_stats {
     int64_t band_pairs;             /* FP16 r2 inside the guard band -> FP64 recheck */
     int64_t fp16_false_pos;         /* naive FP16 test (r2_16 <= cutoff) says in, FP64 says out */
     int64_t fp16_false_neg;         /* naive FP16 test says out, FP64 says in */
+                                    /* (NNPS_MODE_FP32_RCLL: the three above count the FP32
+                                       test of the block path; dense cells add none) */
     int64_t outside_band_disagree;  /* RECHECK_ALL only: FP16 decided outside the band but wrong */
     int64_t heavy_rows;             /* rows handled by the long-row path */
     int64_t dense_rows;             /* rows handled by the dense-cell path */

@@ -30,7 +30,7 @@ int64_t scan_partials_needed(int64_t m);
 int radix_tiles(int n);
 size_t radix_table_entries(int n);
 hipError_t launch_pack(const Launch& L, const uint32_t* skey, const int* perm, const double* X, ushort4* q4,
-                       double* spos, int* inv, hipStream_t st);
+                       double* spos, float4* rq, int* inv, hipStream_t st);
 hipError_t launch_blocks(const Launch& L, const int* cell_start, const int* wdense, int* boff, int* bstart, int* bset,
                          int64_t* partial, hipStream_t st);
 
@@ -74,7 +74,8 @@ struct SearchArgs {
     const int* perm;          // sorted position -> global particle index
     const int* cell_start;    // [ncell_tot + 1]
     const ushort4* q4;        // sorted FP16 relative coordinates (+ c_x mod 2^16)
-    const double* spos;       // sorted FP64 positions [ntot][4] (baseline only)
+    const double* spos;       // sorted FP64 positions [ntot][4] (FP64 and FP32 modes)
+    const float4* rq;         // sorted FP32 relative coordinates + packed cell bits (FP32 mode)
     const double* X;          // fixed-point positions (exact integers), global index, stride x_stride(dim)
     const int* bstart;        // block starts [nblk + 1]
     const int* bset;          // set of each block [nblk]

@@ -381,7 +381,7 @@ template <int DIM>
 __global__ void __launch_bounds__(256)
 k_pack(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nsets, int ntot,
        const uint32_t* __restrict__ skey, const int* __restrict__ perm, const double* __restrict__ X,
-       ushort4* __restrict__ q4, double* __restrict__ spos, int* __restrict__ inv)
+       ushort4* __restrict__ q4, double* __restrict__ spos, float4* __restrict__ rq, int* __restrict__ inv)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= ntot) return;
@@ -395,17 +395,23 @@ k_pack(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nset
                 spos[static_cast<size_t>(p) * 4 + k] = sd.pos[static_cast<size_t>(o - sd.poff) * DIM + k];
         }
         uint16_t h[4] = {0, 0, 0, 0};
+        float q32[3] = {0.0f, 0.0f, 0.0f};
+        uint32_t cbits = 0;
         const float scale = __builtin_ldexpf(1.0f, 1 - fr.F);
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
             const int64_t x = static_cast<int64_t>(X[static_cast<size_t>(o) * x_stride(DIM) + k]);
             const int64_t c = x >> fr.F;
             const int64_t D = x - (c << fr.F) - (int64_t(1) << (fr.F - 1));
-            const _Float16 q = static_cast<_Float16>(exact_i64_to_f32(D) * scale);
-            h[k] = __builtin_bit_cast(uint16_t, q);
+            q32[k] = exact_i64_to_f32(D) * scale;  // exact power-of-two scaling
+            h[k] = __builtin_bit_cast(uint16_t, static_cast<_Float16>(q32[k]));
             if (k == 0) h[3] = static_cast<uint16_t>(c & 0xFFFF);
+            cbits |= static_cast<uint32_t>(c & 1023) << (10 * k);
         }
         q4[p] = make_ushort4(h[0], h[1], h[2], h[3]);
+        // FP32 mode: the coordinate in f32 and the cell indices mod 2^10 (a pair's cell
+        // offsets are -1, 0 or 1 per axis, which their differences mod 2^10 recover)
+        if (rq) rq[p] = make_float4(q32[0], q32[1], q32[2], __builtin_bit_cast(float, cbits));
     };
     // a wavefront inside one set reads the set's fields with scalar loads
     const int s = find_set(coffs, nsets, static_cast<int>(skey[p]));
@@ -732,14 +738,14 @@ hipError_t radix_sort_kv_dev(int n, const int* ndev, int keybits, uint32_t* k0, 
 size_t radix_table_entries(int n) { return static_cast<size_t>(radix_tiles(n)) << kRsMaxBits; }
 
 hipError_t launch_pack(const Launch& L, const uint32_t* skey, const int* perm, const double* X, ushort4* q4,
-                       double* spos, int* inv, hipStream_t st)
+                       double* spos, float4* rq, int* inv, hipStream_t st)
 {
     if (L.ntot == 0) return hipSuccess;
     const dim3 g((L.ntot + 255) / 256), b(256);
     if (L.dim == 2)
-        hipLaunchKernelGGL(k_pack<2>, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, perm, X, q4, spos, inv);
+        hipLaunchKernelGGL(k_pack<2>, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, perm, X, q4, spos, rq, inv);
     else
-        hipLaunchKernelGGL(k_pack<3>, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, perm, X, q4, spos, inv);
+        hipLaunchKernelGGL(k_pack<3>, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, perm, X, q4, spos, rq, inv);
     return hipGetLastError();
 }
 

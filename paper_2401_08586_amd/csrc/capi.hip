@@ -43,6 +43,19 @@ struct DevBuf {
     T* as() const { return static_cast<T*>(p); }
 };
 
+// Modes that keep sorted FP64 positions (the FP64 test, and the FP32 mode's dense cells
+// and long rows).
+bool uses_spos(int mode) { return mode == NNPS_MODE_FP64_BASELINE || mode == NNPS_MODE_FP32_RCLL; }
+
+// Round a double to binary32 toward -inf (dir -1), nearest-even (0) or +inf (+1).
+float f32_dir(double x, int dir)
+{
+    float f = static_cast<float>(x);
+    if (dir < 0 && static_cast<double>(f) > x) f = nextafterf(f, -INFINITY);
+    if (dir > 0 && static_cast<double>(f) < x) f = nextafterf(f, INFINITY);
+    return f;
+}
+
 // Round a non-negative double to an IEEE binary16 bit pattern: dir 0 = nearest-even,
 // -1 = toward -inf, +1 = toward +inf. Negative inputs give 0 (never used otherwise).
 uint16_t f16_bits(double x, int dir)
@@ -128,6 +141,13 @@ nnps_status frame_of(const nnps_problem* p, Frame* fr, int block_target)
     fr->t_lo = f16_bits(4.0 * (rho2 - band), -1);
     fr->t_hi = f16_bits(4.0 * (rho2 + band), +1);
     fr->t_mid = f16_bits(4.0 * rho2, 0);
+    // FP32 thresholds: band 2^-15 squared cell widths, which covers the FP32 pass's error
+    // near the cutoff (fixed point, the stored f32 coordinate and the five f32 roundings
+    // of r2) for every admissible F >= 20
+    const double band32 = ldexp(1.0, -15);
+    fr->t32_lo = std::max(0.0f, f32_dir(4.0 * (rho2 - band32), -1));
+    fr->t32_hi = f32_dir(4.0 * (rho2 + band32), +1);
+    fr->t32_mid = f32_dir(4.0 * rho2, 0);
     // x-window of a work block: about block_target particles on average, so most windows
     // fill one wavefront and the candidate union stays small; and at most what keeps the
     // union of 3^(d-1) rows of xwin + 2 cells at 85 % of the fill's union limit on average
@@ -246,7 +266,7 @@ struct nnps_cells {
     uint64_t buf_gen = 0;                 // bumps whenever a device buffer moves
     uint32_t* skey = nullptr;
     int* perm = nullptr;
-    DevBuf d_sets, d_offs, X, k0, k1, v0, v1, cell_count, cell_start, q4, spos, boff, bstart, bset,
+    DevBuf d_sets, d_offs, X, k0, k1, v0, v1, cell_count, cell_start, q4, spos, rq, boff, bstart, bset,
         counts, table, partial, stats, blk_stats, cbits, err, heavy, nheavy, rowg, nnz, sink;
     // dense-cell path (see DenseBuild)
     bool dense = false;         // the tuning allows the dense-cell path
@@ -317,7 +337,8 @@ SearchArgs args_of(const nnps_cells* c)
     a.perm = c->perm;
     a.cell_start = c->cell_start.as<int>();
     a.q4 = c->q4.as<ushort4>();
-    a.spos = c->mode == NNPS_MODE_FP64_BASELINE ? c->spos.as<double>() : nullptr;
+    a.spos = uses_spos(c->mode) ? c->spos.as<double>() : nullptr;
+    a.rq = c->mode == NNPS_MODE_FP32_RCLL ? c->rq.as<float4>() : nullptr;
     a.X = c->X.as<double>();
     a.bstart = c->bstart.as<int>();
     a.bset = c->bset.as<int>();
@@ -462,7 +483,7 @@ nnps_status prepare(nnps_ctx* ctx, nnps_cells* c, int nsets, const nnps_problem*
     const int64_t scan_m = std::max<int64_t>({static_cast<int64_t>(nn) + 1, static_cast<int64_t>(nc) + 1,
                                               static_cast<int64_t>(table_n),
                                               static_cast<int64_t>(c->nrows_tot) + 1});
-    const bool base = c->mode == NNPS_MODE_FP64_BASELINE;
+    const bool base = uses_spos(c->mode);
     const int cw = c->dim == 3 ? kCandWords3 : kCandWords2;
     struct Need {
         DevBuf* b;
@@ -475,6 +496,7 @@ nnps_status prepare(nnps_ctx* ctx, nnps_cells* c, int nsets, const nnps_problem*
         {&c->cell_count, (nc + 1) * 4}, {&c->cell_start, (nc + 1) * 4},
         {&c->q4, nn * sizeof(ushort4)},
         {&c->spos, base ? nn * 4 * sizeof(double) : 0},
+        {&c->rq, c->mode == NNPS_MODE_FP32_RCLL ? nn * sizeof(float4) : 0},
         {&c->boff, (static_cast<size_t>(c->nrows_tot) + 1) * 4}, {&c->bstart, (nn + 2) * 4}, {&c->bset, (nn + 1) * 4},
         {&c->counts, nn * 4},
         {&c->table, table_n * 4},
@@ -531,7 +553,8 @@ nnps_status enqueue_build(nnps_cells* c, hipStream_t s)
     c->perm = vf;
     tm.begin(NNPS_PHASE_PACK, s);
     HIP_TRY(launch_pack(L, c->skey, c->perm, c->X.as<double>(), c->q4.as<ushort4>(),
-                        c->mode == NNPS_MODE_FP64_BASELINE ? c->spos.as<double>() : nullptr,
+                        uses_spos(c->mode) ? c->spos.as<double>() : nullptr,
+                        c->mode == NNPS_MODE_FP32_RCLL ? c->rq.as<float4>() : nullptr,
                         c->dense ? c->inv.as<int>() : nullptr, s));
     tm.end(NNPS_PHASE_PACK, s);
     // The dense-cell path runs unless the last synchronising call saw no dense cell; the
@@ -651,7 +674,7 @@ nnps_status nnps_validate(const nnps_problem* p)
 {
     if (!p) return NNPS_EINVAL;
     if (p->dim != 2 && p->dim != 3) return NNPS_EINVAL;
-    if (p->mode < NNPS_MODE_FP16_RCLL || p->mode > NNPS_MODE_RECHECK_ALL) return NNPS_EINVAL;
+    if (p->mode < NNPS_MODE_FP16_RCLL || p->mode > NNPS_MODE_FP32_RCLL) return NNPS_EINVAL;
     if (p->n < 0 || p->n >= (int64_t(1) << 31)) return NNPS_EINVAL;
     if (!(p->radius > 0.0) || !isfinite(p->radius)) return NNPS_EINVAL;
     if (!(p->cell_size >= p->radius) || !isfinite(p->cell_size)) return NNPS_EINVAL;
@@ -747,7 +770,7 @@ void nnps_cells_destroy(nnps_cells* c)
     DeviceGuard g(c->ctx->device);
     if (c->upload_pending) (void)hipEventSynchronize(c->upload_done);
     DevBuf* all[] = {&c->d_sets, &c->d_offs, &c->X, &c->k0, &c->k1, &c->v0, &c->v1, &c->cell_count,
-                     &c->cell_start, &c->q4, &c->spos, &c->boff, &c->bstart, &c->bset, &c->counts,
+                     &c->cell_start, &c->q4, &c->spos, &c->rq, &c->boff, &c->bstart, &c->bset, &c->counts,
                      &c->table, &c->partial, &c->stats, &c->blk_stats, &c->cbits, &c->err, &c->heavy,
                      &c->nheavy, &c->rowg, &c->nnz, &c->sink, &c->usz, &c->wdense, &c->uoff, &c->nsl, &c->unit_off,
                      &c->ucell, &c->dn, &c->ecnt, &c->epos, &c->uk0, &c->uk1, &c->uv0, &c->uv1, &c->inv,

@@ -70,6 +70,7 @@ struct Frame {
     int xwin;           // largest x-span of a work block, in cells
     int bmax;           // most targets of a work block (<= 64)
     uint16_t t_lo, t_hi, t_mid;  // FP16 thresholds on r2 = 4|delta|^2 (bit patterns)
+    float t32_lo, t32_hi, t32_mid;  // FP32 thresholds on the same r2
 };
 
 // One particle set of a launch. All sets of a launch share one global particle index

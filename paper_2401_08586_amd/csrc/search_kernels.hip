@@ -702,6 +702,101 @@ k_count64(SearchArgs a)
         a.blk_stats[static_cast<size_t>(b) * 5 + (threadIdx.x & 63)] = (threadIdx.x & 63) == 0 ? s : 0ull;
 }
 
+// FP32 r2 of Eq. 7 on twice the displacement in cell widths: per axis
+// t = (q_i - q_j) + 2 dc, then the squares summed left to right, every operation rounded
+// once to f32 (no contraction). The cell offsets dc come from the cell indices mod 2^10
+// packed in w: they are -1, 0 or 1, which the low ten bits of the difference determine.
+template <int DIM>
+__device__ __forceinline__ float r2_fp32(const float4& qi, const float4& qj)
+{
+#pragma clang fp contract(off)
+    const uint32_t ci = __builtin_bit_cast(uint32_t, qi.w), cj = __builtin_bit_cast(uint32_t, qj.w);
+    const float a[3] = {qi.x, qi.y, qi.z}, b[3] = {qj.x, qj.y, qj.z};
+    float r2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        const int dc = static_cast<int>(((ci >> (10 * k)) - (cj >> (10 * k))) << 22) >> 22;
+        const float t = (a[k] - b[k]) + static_cast<float>(2 * dc);
+        const float sq = t * t;
+        r2 = k == 0 ? sq : r2 + sq;
+    }
+    return r2;
+}
+
+// Count pass, FP32 relative coordinates (the paper's FP32 variant of the relative-
+// coordinate list): one lane per target, each candidate's {q_x, q_y, q_z, cell bits}
+// loaded from global memory (16 B); pairs whose FP32 r2 falls in the guard band
+// [T32_lo, T32_hi] are decided by the FP64 predicate on the caller's positions.
+template <int DIM, bool HALF>
+__global__ void __launch_bounds__(64)
+k_count32(SearchArgs a)
+{
+    using CB = CandBits<DIM>;
+    __shared__ uint32_t lbits[64 * (CB::CW + 1)];
+    const int b = blockIdx.x;
+    if (b >= *a.nblk) return;
+    if (dense_block(a, b)) {
+        if ((threadIdx.x & 63) < 5) a.blk_stats[static_cast<size_t>(b) * 5 + (threadIdx.x & 63)] = 0;
+        return;
+    }
+    Geom<DIM> g;
+    g.init(a, b);
+    const Frame& fr = g.fr;
+    CB cb_;
+    cb_.init(g, lbits);
+    int cnt = 0;
+    Tally t;
+    if (g.active) {
+        const int oi = a.perm[g.p];
+        const int poff = g.sd->poff;
+        const double* spos_set = g.sd->pos;
+        double pi[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) pi[k] = spos_set[static_cast<size_t>(oi - poff) * DIM + k];
+        const float4 qi = a.rq[g.p];
+#pragma unroll
+        for (int r = 0; r < Geom<DIM>::NSEG; ++r) {
+            const int ga = g.global_of(r, g.la[r]), gb = g.global_of(r, g.lb[r]);
+            const int pbase = g.la[r] - ga;  // union position = pbase + j
+            t.cand += gb - ga;
+            // four candidates per step, their loads issued together (the last index is
+            // repeated past the range end and its result dropped)
+            for (int j = ga; j < gb; j += 4) {
+                float r2[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) r2[u] = r2_fp32<DIM>(qi, a.rq[min(j + u, gb - 1)]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int jj = j + u;
+                    if (jj >= gb || jj == g.p) continue;
+                    bool nb = r2[u] < fr.t32_lo;
+                    if (!nb && r2[u] <= fr.t32_hi) {
+                        nb = recheck<DIM>(spos_set, pi, a.perm[jj] - poff, fr.R2);
+                        const bool naive = r2[u] <= fr.t32_mid;
+                        t.band++;
+                        t.fpos += naive && !nb;
+                        t.fneg += !naive && nb;
+                    }
+                    if (HALF && nb) nb = a.perm[jj] > oi;
+                    if (nb) {
+                        ++cnt;
+                        cb_.set(pbase + jj);
+                    }
+                }
+            }
+        }
+        t.cand -= 1;  // itself
+        a.counts[oi] = cnt;
+    }
+    cb_.store(a, g.p);
+    const unsigned long long v[5] = {t.cand, t.band, t.fpos, t.fneg, 0ull};
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const unsigned long long sum = wave_sum_u64(v[k]);
+        if ((threadIdx.x & 63) == 0) a.blk_stats[static_cast<size_t>(b) * 5 + k] = sum;
+    }
+}
+
 // Sum of the per-block statistics and of the dense path's per-workgroup statistics
 // (one workgroup; no contended atomics).
 __global__ void __launch_bounds__(1024)
@@ -1363,6 +1458,8 @@ hipError_t launch_count(const SearchArgs& a, int nblk_max, hipStream_t st)
         else if (d == 3 && m == 0) hipLaunchKernelGGL((k_count16<3, 0, true>), g, b, 0, st, a);
         else if (d == 2 && m == 2) hipLaunchKernelGGL((k_count16<2, 2, true>), g, b, 0, st, a);
         else if (d == 3 && m == 2) hipLaunchKernelGGL((k_count16<3, 2, true>), g, b, 0, st, a);
+        else if (d == 2 && m == 3) hipLaunchKernelGGL((k_count32<2, true>), g, b, 0, st, a);
+        else if (d == 3 && m == 3) hipLaunchKernelGGL((k_count32<3, true>), g, b, 0, st, a);
         else if (d == 2) hipLaunchKernelGGL((k_count64<2, true>), g, b, 0, st, a);
         else hipLaunchKernelGGL((k_count64<3, true>), g, b, 0, st, a);
         return hipGetLastError();
@@ -1371,6 +1468,8 @@ hipError_t launch_count(const SearchArgs& a, int nblk_max, hipStream_t st)
     else if (d == 3 && m == 0) hipLaunchKernelGGL((k_count16<3, 0, false>), g, b, 0, st, a);
     else if (d == 2 && m == 2) hipLaunchKernelGGL((k_count16<2, 2, false>), g, b, 0, st, a);
     else if (d == 3 && m == 2) hipLaunchKernelGGL((k_count16<3, 2, false>), g, b, 0, st, a);
+    else if (d == 2 && m == 3) hipLaunchKernelGGL((k_count32<2, false>), g, b, 0, st, a);
+    else if (d == 3 && m == 3) hipLaunchKernelGGL((k_count32<3, false>), g, b, 0, st, a);
     else if (d == 2) hipLaunchKernelGGL((k_count64<2, false>), g, b, 0, st, a);
     else hipLaunchKernelGGL((k_count64<3, false>), g, b, 0, st, a);
     return hipGetLastError();
@@ -1388,7 +1487,7 @@ hipError_t launch_fill(const SearchArgs& a, int nblk_max, hipStream_t st)
 {
     if (a.L.ntot == 0 || nblk_max == 0) return hipSuccess;
     const dim3 g(nblk_max), b(kFillThreads);
-    const int d = a.L.dim, m = a.L.mode;
+    const int d = a.L.dim, m = a.L.mode == 3 ? 1 : a.L.mode;  // FP32 mode: binary64 distances
     if (d == 2 && m == 0) hipLaunchKernelGGL((k_fill<2, 0>), g, b, 0, st, a);
     else if (d == 3 && m == 0) hipLaunchKernelGGL((k_fill<3, 0>), g, b, 0, st, a);
     else if (d == 2 && m == 2) hipLaunchKernelGGL((k_fill<2, 2>), g, b, 0, st, a);
@@ -1401,7 +1500,7 @@ hipError_t launch_fill(const SearchArgs& a, int nblk_max, hipStream_t st)
 hipError_t launch_long_rows(const SearchArgs& a, int grid, hipStream_t st)
 {
     if (a.L.ntot == 0) return hipSuccess;
-    const int d = a.L.dim, m = a.L.mode;
+    const int d = a.L.dim, m = a.L.mode == 3 ? 1 : a.L.mode;  // FP32 mode: long rows in FP64
     const dim3 gh(grid), bh(kLongThreads);
     const size_t lds = static_cast<size_t>(a.lr_keys) * 4;
     if (d == 2 && m == 0) hipLaunchKernelGGL((k_long<2, 0>), gh, bh, lds, st, a);
@@ -1812,7 +1911,7 @@ hipError_t launch_dense(const SearchArgs& a, bool fill, hipStream_t st)
     hipError_t e = launch_fill_i32(a.ucount, 1, 0, st);
     if (e != hipSuccess) return e;
     const dim3 g(a.dgrid), b(kDenseThreads);
-    const int d = a.L.dim, m = a.L.mode;
+    const int d = a.L.dim, m = a.L.mode == 3 ? 1 : a.L.mode;  // FP32 mode: dense cells in FP64
 #define NNPS_DENSE(D, M)                                                                      \
     do {                                                                                      \
         if (fill) hipLaunchKernelGGL((k_dense<D, M, true>), g, b, 0, st, a);                  \

@@ -27,6 +27,7 @@ NNPS_EUNSUPPORTED = -8
 MODE_FP16_RCLL = 0
 MODE_FP64_BASELINE = 1
 MODE_RECHECK_ALL = 2
+MODE_FP32_RCLL = 3
 
 
 class NnpsError(RuntimeError):

@@ -57,7 +57,8 @@ def P(**kw):
     (dict(cell_size=float("inf")), nnps.NNPS_EINVAL),
     (dict(hi=(1, 0, 1)), nnps.NNPS_EINVAL),          # empty box
     (dict(lo=(0, float("nan"), 0)), nnps.NNPS_EINVAL),
-    (dict(mode=3), nnps.NNPS_EINVAL),
+    (dict(mode=3), nnps.NNPS_OK),
+    (dict(mode=4), nnps.NNPS_EINVAL),
     (dict(hi=(1e4, 1e4, 1e4), cell_size=1.0, radius=1.0), nnps.NNPS_ETOOMANYCELLS),
 ])
 def test_validate(kw, want):

@@ -12,7 +12,7 @@ from paper_2401_08586_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-MODES = (nnps.MODE_FP16_RCLL, nnps.MODE_FP64_BASELINE, nnps.MODE_RECHECK_ALL)
+MODES = (nnps.MODE_FP16_RCLL, nnps.MODE_FP64_BASELINE, nnps.MODE_RECHECK_ALL, nnps.MODE_FP32_RCLL)
 
 
 @pytest.fixture(scope="module")
@@ -37,7 +37,7 @@ def check(got, want, mode, name):
     wrp, wcol, wdist = want
     np.testing.assert_array_equal(rp, wrp, err_msg=f"{name} row_ptr")
     np.testing.assert_array_equal(col, wcol, err_msg=f"{name} col")
-    if mode == nnps.MODE_FP64_BASELINE:
+    if mode in (nnps.MODE_FP64_BASELINE, nnps.MODE_FP32_RCLL):
         np.testing.assert_array_equal(dist.view(np.uint32), wdist.view(np.uint32), err_msg=f"{name} dist")
     else:
         wd = wdist.astype(np.float64)

@@ -1,13 +1,15 @@
 """GPU parity: the HIP library through its C ABI against the CPU oracle, element by element.
 
 Neighbour sets (row_ptr, col) must be bit-identical; FP32 distances within 1e-6 relative
-(FP16 path) or bit-identical (FP64 baseline, which rounds the same binary64 value); the
-FP16 statistics must equal the numpy model's exactly."""
+(FP16 path) or bit-identical (FP64 baseline and FP32 mode, which round the same binary64
+value); the
+FP16 and FP32 statistics must equal the numpy models' exactly."""
 import numpy as np
 import pytest
 
 import oracle
 from oracle import rcll_fp16 as M
+from oracle import rcll_fp32 as M32
 from paper_2401_08586_amd import workloads as W
 
 torch = pytest.importorskip("torch")
@@ -15,8 +17,9 @@ pytestmark = pytest.mark.gpu
 
 from paper_2401_08586_amd import nnps  # noqa: E402
 
-MODES = [nnps.MODE_FP16_RCLL, nnps.MODE_FP64_BASELINE, nnps.MODE_RECHECK_ALL]
-MODE_NAMES = {0: "fp16", 1: "fp64", 2: "recheck_all"}
+MODES = [nnps.MODE_FP16_RCLL, nnps.MODE_FP64_BASELINE, nnps.MODE_RECHECK_ALL, nnps.MODE_FP32_RCLL]
+MODE_NAMES = {0: "fp16", 1: "fp64", 2: "recheck_all", 3: "fp32"}
+EXACT_DIST = (nnps.MODE_FP64_BASELINE, nnps.MODE_FP32_RCLL)
 
 
 @pytest.fixture(scope="module")
@@ -46,7 +49,7 @@ def check_against_oracle(got, want, mode, name):
     assert rp.shape == wrp.shape, name
     np.testing.assert_array_equal(rp, wrp, err_msg=f"{name} row_ptr")
     np.testing.assert_array_equal(col, wcol, err_msg=f"{name} col")
-    if mode == nnps.MODE_FP64_BASELINE:
+    if mode in EXACT_DIST:
         np.testing.assert_array_equal(dist.view(np.uint32), wdist.view(np.uint32), err_msg=f"{name} dist")
     else:
         wd = wdist.astype(np.float64)
@@ -84,6 +87,9 @@ def small_cases():
     rng = np.random.default_rng(11)
     pos = np.stack([rng.uniform(0, 40, 30000), rng.uniform(0, 0.2, 30000)], axis=1)
     cases.append(W.ParticleSet(pos, (0, 0), (40, 0.2), 0.03, 0.03, "thin2d"))
+    # more than 1024 cells along z (cell indices mod 2^10 wrap inside the domain)
+    pos = np.stack([rng.uniform(0, 0.1, 30000), rng.uniform(0, 0.1, 30000), rng.uniform(0, 40, 30000)], axis=1)
+    cases.append(W.ParticleSet(pos, (0, 0, 0), (0.1, 0.1, 40), 0.03, 0.03, "thin3d_z"))
     return cases
 
 
@@ -96,7 +102,17 @@ def test_parity_small(ctx, case, mode):
     check_against_oracle(got, want, mode, case.name)
     st = got[3]
     assert st["nnz"] == want[0][-1]
-    if mode != nnps.MODE_FP64_BASELINE:
+    if mode == nnps.MODE_FP32_RCLL:
+        # statistics of the FP32 pass (dense cells are decided in FP64 and add none)
+        model = M32.stats(case.pos, case.lo, case.hi, case.cell_size, case.radius)
+        if st["dense_rows"] == 0:
+            assert st["candidates"] == model["candidates"]
+            assert st["band_pairs"] == model["band_pairs"]
+            assert st["fp16_false_pos"] == model["fp32_false_pos"]
+            assert st["fp16_false_neg"] == model["fp32_false_neg"]
+        else:
+            assert st["band_pairs"] <= model["band_pairs"]
+    elif mode != nnps.MODE_FP64_BASELINE:
         model = M.stats(case.pos, case.lo, case.hi, case.cell_size, case.radius)
         assert st["candidates"] == model["candidates"]
         assert st["band_pairs"] == model["band_pairs"]
@@ -106,7 +122,7 @@ def test_parity_small(ctx, case, mode):
 
 
 @pytest.mark.parametrize("which", ["c1", "c2"])
-@pytest.mark.parametrize("mode", [nnps.MODE_FP16_RCLL, nnps.MODE_FP64_BASELINE],
+@pytest.mark.parametrize("mode", [nnps.MODE_FP16_RCLL, nnps.MODE_FP64_BASELINE, nnps.MODE_FP32_RCLL],
                          ids=lambda m: MODE_NAMES[m])
 def test_parity_full_size(ctx, which, mode):
     ps = getattr(W, which)()
