@@ -456,6 +456,10 @@ struct CandBits {
     {
         if (keep) atomicOr(&w[posl >> 5], 1u << (posl & 31));
     }
+    __device__ __forceinline__ void clear(int posl)
+    {
+        if (keep) atomicAnd(&w[posl >> 5], ~(1u << (posl & 31)));
+    }
     // Bits of up to 4 consecutive positions starting at posl (bit k = position posl + k),
     // with no branch on the bits: two unconditional ORs, the second into the next word
     // (the padding word after the union's last one).
@@ -704,87 +708,132 @@ k_count64(SearchArgs a)
 
 // FP32 r2 of Eq. 7 on twice the displacement in cell widths: per axis
 // t = (q_i - q_j) + 2 dc, then the squares summed left to right, every operation rounded
-// once to f32 (no contraction). The cell offsets dc come from the cell indices mod 2^10
-// packed in w: they are -1, 0 or 1, which the low ten bits of the difference determine.
+// once to f32 (no contraction). 2 dc_x = w_i - w_j, where w is twice the cell's x offset
+// from the block's first stencil cell (small integers: exact); 2 dc_y and 2 dc_z are the
+// row segment's constants.
 template <int DIM>
-__device__ __forceinline__ float r2_fp32(const float4& qi, const float4& qj)
+__device__ __forceinline__ float r2_fp32(const float4& qi, float wi, float cy, float cz, const float4& s)
 {
 #pragma clang fp contract(off)
-    const uint32_t ci = __builtin_bit_cast(uint32_t, qi.w), cj = __builtin_bit_cast(uint32_t, qj.w);
-    const float a[3] = {qi.x, qi.y, qi.z}, b[3] = {qj.x, qj.y, qj.z};
-    float r2 = 0.0f;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-        const int dc = static_cast<int>(((ci >> (10 * k)) - (cj >> (10 * k))) << 22) >> 22;
-        const float t = (a[k] - b[k]) + static_cast<float>(2 * dc);
-        const float sq = t * t;
-        r2 = k == 0 ? sq : r2 + sq;
+    const float tx = (qi.x - s.x) + (wi - s.w);
+    const float ty = (qi.y - s.y) + cy;
+    float r2 = tx * tx + ty * ty;
+    if (DIM == 3) {
+        const float tz = (qi.z - s.z) + cz;
+        r2 = r2 + tz * tz;
     }
     return r2;
 }
 
+constexpr int kStage32 = 256;  // candidates per staged chunk of the FP32 count (16 B each)
+
 // Count pass, FP32 relative coordinates (the paper's FP32 variant of the relative-
-// coordinate list): one lane per target, each candidate's {q_x, q_y, q_z, cell bits}
-// loaded from global memory (16 B); pairs whose FP32 r2 falls in the guard band
-// [T32_lo, T32_hi] are decided by the FP64 predicate on the caller's positions.
+// coordinate list). The block's candidate union is staged in LDS chunk by chunk as
+// {q_x, q_y, q_z, 2 x-offset} (f32); each lane tests its own ranges four candidates per
+// step and turns the four results into "in" and "band" bits with no branch; the rare band
+// pairs are decided by the FP64 predicate on the caller's positions. The lane's own entry
+// (r2 = 0) is "in" when T32_lo > 0 and is taken out at the end; otherwise it is a band
+// entry and skipped there.
 template <int DIM, bool HALF>
 __global__ void __launch_bounds__(64)
 k_count32(SearchArgs a)
 {
     using CB = CandBits<DIM>;
+    // the staged chunk, and 4 more entries that the last step of a range may read past it
+    // (their results are dropped)
+    __shared__ float4 sq[kStage32 + 4];
+    // half lists: the staged candidates' original indices (same padding)
+    __shared__ int sorig[HALF ? kStage32 + 4 : 1];
     __shared__ uint32_t lbits[64 * (CB::CW + 1)];
     const int b = blockIdx.x;
     if (b >= *a.nblk) return;
+    const int lane = threadIdx.x & 63;
     if (dense_block(a, b)) {
-        if ((threadIdx.x & 63) < 5) a.blk_stats[static_cast<size_t>(b) * 5 + (threadIdx.x & 63)] = 0;
+        if (lane < 5) a.blk_stats[static_cast<size_t>(b) * 5 + lane] = 0;
         return;
     }
     Geom<DIM> g;
     g.init(a, b);
     const Frame& fr = g.fr;
+    const int pp = g.active ? g.p : g.p1 - 1;
+    const int oi = a.perm[pp];
+    const double* spos_set = g.sd->pos;
+    const int poff = g.sd->poff;
+    double pi[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) pi[k] = spos_set[static_cast<size_t>(oi - poff) * DIM + k];
+    const float4 qi = a.rq[pp];
+    const float wi = static_cast<float>(2 * (g.x - g.sx0));
+    const float tlo = fr.t32_lo, thi = fr.t32_hi, tmid = fr.t32_mid;
     CB cb_;
     cb_.init(g, lbits);
     int cnt = 0;
     Tally t;
-    if (g.active) {
-        const int oi = a.perm[g.p];
-        const int poff = g.sd->poff;
-        const double* spos_set = g.sd->pos;
-        double pi[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) pi[k] = spos_set[static_cast<size_t>(oi - poff) * DIM + k];
-        const float4 qi = a.rq[g.p];
+    const uint32_t sx0 = static_cast<uint32_t>(g.sx0);
+    for (int cb = 0; cb < g.U; cb += kStage32) {
+        const int ce = min(g.U, cb + kStage32);
+        __syncthreads();
+        for (int u = cb + lane; u < ce; u += 64) {
+            const float4 v = a.rq[g.global_of_any(u)];
+            // the union spans fewer than 2^10 cells in x, so the offset mod 2^10 is exact
+            const uint32_t rel = (__builtin_bit_cast(uint32_t, v.w) - sx0) & 1023u;
+            sq[u - cb] = make_float4(v.x, v.y, v.z, static_cast<float>(2 * static_cast<int>(rel)));
+            if (HALF) sorig[u - cb] = a.perm[g.global_of_any(u)];
+        }
+        __syncthreads();
+        if (!g.active) continue;
 #pragma unroll
         for (int r = 0; r < Geom<DIM>::NSEG; ++r) {
-            const int ga = g.global_of(r, g.la[r]), gb = g.global_of(r, g.lb[r]);
-            const int pbase = g.la[r] - ga;  // union position = pbase + j
-            t.cand += gb - ga;
-            // four candidates per step, their loads issued together (the last index is
-            // repeated past the range end and its result dropped)
-            for (int j = ga; j < gb; j += 4) {
-                float r2[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) r2[u] = r2_fp32<DIM>(qi, a.rq[min(j + u, gb - 1)]);
+            const int lo = max(g.la[r], cb), hi = min(g.lb[r], ce);
+            if (lo >= hi) continue;
+            const float cy = static_cast<float>(2 - 2 * (r % 3));                 // -2 dy
+            const float cz = DIM == 3 ? static_cast<float>(2 - 2 * (r / 3)) : 0.0f;  // -2 dz
+            for (int j = lo; j < hi; j += 4) {
+                uint32_t in4 = 0, band4 = 0;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const int jj = j + u;
-                    if (jj >= gb || jj == g.p) continue;
-                    bool nb = r2[u] < fr.t32_lo;
-                    if (!nb && r2[u] <= fr.t32_hi) {
-                        nb = recheck<DIM>(spos_set, pi, a.perm[jj] - poff, fr.R2);
-                        const bool naive = r2[u] <= fr.t32_mid;
+                    const float v = r2_fp32<DIM>(qi, wi, cy, cz, sq[j - cb + u]);
+                    in4 |= static_cast<uint32_t>(v < tlo) << u;
+                    band4 |= static_cast<uint32_t>(v <= thi) << u;
+                }
+                const int left = hi - j;
+                const uint32_t valid = left >= 4 ? 0xFu : (1u << left) - 1u;
+                in4 &= valid;
+                band4 &= valid & ~in4;
+                if (band4) {
+                    uint32_t bb = band4;
+                    while (bb) {
+                        const int k = __builtin_ctz(bb);
+                        bb &= bb - 1u;
+                        const int posl = j + k;
+                        if (posl == g.pself) continue;
+                        const float v = r2_fp32<DIM>(qi, wi, cy, cz, sq[j - cb + k]);
+                        const bool truth = recheck<DIM>(spos_set, pi, a.perm[g.global_of(r, posl)] - poff, fr.R2);
+                        const bool naive = v <= tmid;
                         t.band++;
-                        t.fpos += naive && !nb;
-                        t.fneg += !naive && nb;
-                    }
-                    if (HALF && nb) nb = a.perm[jj] > oi;
-                    if (nb) {
-                        ++cnt;
-                        cb_.set(pbase + jj);
+                        t.fpos += naive && !truth;
+                        t.fneg += !naive && truth;
+                        in4 |= static_cast<uint32_t>(truth) << k;
                     }
                 }
+                if (HALF) {
+                    uint32_t gt = 0;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) gt |= static_cast<uint32_t>(sorig[j - cb + u] > oi) << u;
+                    in4 &= gt;
+                }
+                cnt += __builtin_popcount(in4);
+                cb_.put(j, in4);
             }
         }
+    }
+    if (g.active) {
+        if (!HALF && tlo > 0.0f) {  // itself, taken as "in" (half lists never keep it)
+            cnt -= 1;
+            cb_.clear(g.pself);
+        }
+#pragma unroll
+        for (int r = 0; r < Geom<DIM>::NSEG; ++r) t.cand += g.lb[r] - g.la[r];
         t.cand -= 1;  // itself
         a.counts[oi] = cnt;
     }
@@ -793,7 +842,7 @@ k_count32(SearchArgs a)
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
         const unsigned long long sum = wave_sum_u64(v[k]);
-        if ((threadIdx.x & 63) == 0) a.blk_stats[static_cast<size_t>(b) * 5 + k] = sum;
+        if (lane == 0) a.blk_stats[static_cast<size_t>(b) * 5 + k] = sum;
     }
 }
 
