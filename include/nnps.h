@@ -240,12 +240,24 @@ nnps_status nnps_batch_nnz_fetch(nnps_cells *cells, int64_t *h_nnz);
  * Every particle tested against every other (SPH method section, Fig. 3a), in binary64
  * with the cell-list paths' predicate, so row_ptr, col and dist are bit-identical to the
  * FP64 cell list (prob->mode and prob->cell_size are not used; the box is only checked).
- * Meant for small sets, where it needs three kernel launches and no cell structure:
- * prob->n must not exceed 65536 (NNPS_EINVAL above; the work grows as n^2). Writes
- * d_row_ptr [n+1], waits for the stream once to learn nnz (*nnz_out), then, if capacity
- * >= nnz, queues the fill of d_col/d_dist (asynchronous) and returns NNPS_OK; otherwise
- * returns NNPS_ECAPACITY with *nnz_out = nnz and only row_ptr written. NNPS_EDOMAIN if a
- * position lies outside [lo, hi] or is not finite (nothing further written). */
+ * Meant for small sets, with no cell structure: prob->n must not exceed 65536
+ * (NNPS_EINVAL above; the work grows as n^2). Rows come out in ascending j.
+ *
+ * nnps_allpairs_count writes d_row_ptr [n+1] and waits for the stream once to return nnz
+ * (*nnz_out); NNPS_EDOMAIN if a position lies outside [lo, hi] or is not finite. The
+ * context keeps per-slice row counts (device memory it owns) for the fill that follows.
+ * nnps_allpairs_fill queues the fill of d_col/d_dist [nnz] (asynchronous); it must follow
+ * a successful count on the same context with the same problem, d_pos and d_row_ptr,
+ * whose contents are unchanged (else NNPS_EORDER), and needs capacity >= nnz (else
+ * NNPS_ECAPACITY, nothing written). A later count on the context replaces the kept
+ * counts: a fill still queued on another stream must have finished by then.
+ * nnps_allpairs_search is count then, if capacity >= nnz, fill: NNPS_OK, or
+ * NNPS_ECAPACITY with *nnz_out = nnz and only row_ptr written. */
+nnps_status nnps_allpairs_count(nnps_ctx *ctx, const nnps_problem *prob, const double *d_pos, int64_t *d_row_ptr,
+                                int64_t *nnz_out, void *stream);
+nnps_status nnps_allpairs_fill(nnps_ctx *ctx, const nnps_problem *prob, const double *d_pos,
+                               const int64_t *d_row_ptr, int32_t *d_col, float *d_dist, int64_t capacity,
+                               void *stream);
 nnps_status nnps_allpairs_search(nnps_ctx *ctx, const nnps_problem *prob, const double *d_pos,
                                  int64_t *d_row_ptr, int32_t *d_col, float *d_dist, int64_t capacity,
                                  int64_t *nnz_out, void *stream);

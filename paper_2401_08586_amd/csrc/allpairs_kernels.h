@@ -13,9 +13,22 @@ struct ApBox {
 // Largest set the all-list path takes (its work grows as n^2).
 constexpr int kAllPairsMaxN = 65536;
 
-hipError_t launch_allpairs_count(int dim, int n, const double* pos, double R2, const ApBox& box, int64_t* row_ptr,
-                                 int* err, hipStream_t st);
-hipError_t launch_allpairs_fill(int dim, int n, const double* pos, double R2, const ApBox& box,
+// Work split: rows in groups of 64 (one wavefront, one row per lane) times slices of the
+// candidate range, so that even small sets give the chip thousands of wavefronts.
+struct ApPlan {
+    int n = 0;
+    int slice = 0;   // candidates per slice (a multiple of 64)
+    int nslice = 0;  // slices per row
+};
+ApPlan allpairs_plan(int n);
+
+// Count: cnt[s * n + i] = neighbours of row i in slice s; row_ptr[1..n] = row totals, then
+// their inclusive scan (row_ptr[0] = 0); *err |= 1 for a position outside [lo, hi] or not
+// finite. cnt holds nslice * n ints.
+hipError_t launch_allpairs_count(int dim, const ApPlan& p, const double* pos, double R2, const ApBox& box, int* cnt,
+                                 int64_t* row_ptr, int* err, hipStream_t st);
+// Fill: row i's pairs of slice s at row_ptr[i] + sum_{t < s} cnt[t * n + i], ascending j.
+hipError_t launch_allpairs_fill(int dim, const ApPlan& p, const double* pos, double R2, const int* cnt,
                                 const int64_t* row_ptr, int32_t* col, float* dist, hipStream_t st);
 
 }  // namespace nnps

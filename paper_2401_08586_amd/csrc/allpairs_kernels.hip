@@ -4,17 +4,37 @@
 // (r2 = ((dx0^2) + dx1^2) + dx2^2 in that order, no contraction, r2 <= R^2), so rows and
 // distances are bit-identical to the FP64 cell list.
 //
-// One thread per target row; candidates are staged in LDS tiles of kApTile positions
-// that every thread of the workgroup reads in the same order (broadcast reads), so rows
-// come out in ascending index with no sort. Three launches: counts into row_ptr[1..n],
-// an in-place scan by one workgroup, and the fill.
+// A workgroup is one wavefront: 64 rows (one per lane) against one slice of the candidate
+// range. The slice's positions pass through LDS 64 at a time (one coalesced load per
+// lane); every lane then reads them in the same order (broadcast reads), so each row's
+// entries come out in ascending j with no sort. Slices give small sets enough wavefronts
+// to fill the chip. Launches: count, row totals, scan, and (after the caller has sized
+// the outputs) the fill.
 #include "allpairs_kernels.h"
+
+#include <algorithm>
 
 namespace nnps {
 
-constexpr int kApThreads = 256;
-constexpr int kApTile = 256;
+constexpr int kApRows = 64;
+constexpr int kApMinSlice = 256;
+constexpr int kApTargetWaves = 8192;  // about 8 wavefronts per SIMD
 constexpr int kApScanThreads = 1024;
+
+ApPlan allpairs_plan(int n)
+{
+    ApPlan p;
+    p.n = n;
+    if (n == 0) return p;
+    const int row_groups = (n + kApRows - 1) / kApRows;
+    int want = std::max(1, std::min((n + kApMinSlice - 1) / kApMinSlice,
+                                    (kApTargetWaves + row_groups - 1) / row_groups));
+    int slice = (n + want - 1) / want;
+    slice = (slice + 63) / 64 * 64;
+    p.slice = slice;
+    p.nslice = (n + slice - 1) / slice;
+    return p;
+}
 
 template <int DIM>
 __device__ __forceinline__ double ap_r2(const double* pi, const double* pj)
@@ -29,33 +49,43 @@ __device__ __forceinline__ double ap_r2(const double* pi, const double* pj)
     return r2;
 }
 
-// FILL = false: row_ptr[i + 1] = |N(i)| and *err |= 1 for a position outside [lo, hi] or
-// not finite. FILL = true: the row's (col, dist) pairs at row_ptr[i].. in ascending j.
+// grid (row groups, slices), 64 threads
 template <int DIM, bool FILL>
-__global__ void __launch_bounds__(kApThreads)
-k_allpairs(int n, const double* __restrict__ pos, double R2, ApBox box, int64_t* __restrict__ row_ptr,
-           int32_t* __restrict__ col, float* __restrict__ dist, int* __restrict__ err)
+__global__ void __launch_bounds__(kApRows)
+k_allpairs(int n, int slice, const double* __restrict__ pos, double R2, ApBox box, int* __restrict__ cnt,
+           const int64_t* __restrict__ row_ptr, int32_t* __restrict__ col, float* __restrict__ dist,
+           int* __restrict__ err)
 {
-    __shared__ double tile[kApTile * DIM];
-    const int i = blockIdx.x * kApThreads + threadIdx.x;
+    __shared__ double tile[kApRows * DIM];
+    const int lane = threadIdx.x;
+    const int i = blockIdx.x * kApRows + lane;
+    const int s = blockIdx.y;
+    const int j0 = s * slice, j1 = min(n, j0 + slice);
     const bool active = i < n;
     double pi[3] = {0.0, 0.0, 0.0};
     if (active) {
 #pragma unroll
         for (int k = 0; k < DIM; ++k) pi[k] = pos[static_cast<size_t>(i) * DIM + k];
-        if (!FILL) {
+        if (!FILL && s == 0) {
             bool bad = false;
 #pragma unroll
             for (int k = 0; k < DIM; ++k) bad |= !(pi[k] >= box.lo[k] && pi[k] <= box.hi[k]);
             if (bad) atomicOr(err, 1);
         }
     }
-    int64_t w = FILL && active ? row_ptr[i] : 0;
-    int cnt = 0;
-    for (int t0 = 0; t0 < n; t0 += kApTile) {
-        const int m = min(kApTile, n - t0);
+    int64_t w = 0;
+    if (FILL && active) {
+        w = row_ptr[i];
+        for (int t = 0; t < s; ++t) w += cnt[static_cast<size_t>(t) * n + i];
+    }
+    int c = 0;
+    for (int t0 = j0; t0 < j1; t0 += kApRows) {
+        const int m = min(kApRows, j1 - t0);
         __syncthreads();
-        for (int e = threadIdx.x; e < m * DIM; e += kApThreads) tile[e] = pos[static_cast<size_t>(t0) * DIM + e];
+        if (lane < m) {
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) tile[lane * DIM + k] = pos[static_cast<size_t>(t0 + lane) * DIM + k];
+        }
         __syncthreads();
         if (!active) continue;
         for (int e = 0; e < m; ++e) {
@@ -67,12 +97,23 @@ k_allpairs(int n, const double* __restrict__ pos, double R2, ApBox box, int64_t*
                     dist[w] = static_cast<float>(__dsqrt_rn(r2));
                     ++w;
                 } else {
-                    ++cnt;
+                    ++c;
                 }
             }
         }
     }
-    if (!FILL && active) row_ptr[i + 1] = cnt;
+    if (!FILL && active) cnt[static_cast<size_t>(s) * n + i] = c;
+}
+
+// row_ptr[i + 1] = sum over slices of cnt[s * n + i]
+__global__ void __launch_bounds__(256)
+k_allpairs_rows(int n, int nslice, const int* __restrict__ cnt, int64_t* __restrict__ row_ptr)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    int64_t t = 0;
+    for (int s = 0; s < nslice; ++s) t += cnt[static_cast<size_t>(s) * n + i];
+    row_ptr[i + 1] = t;
 }
 
 // One workgroup: row_ptr[0] = 0 and row_ptr[1..n] (counts) replaced by their inclusive
@@ -102,29 +143,34 @@ k_allpairs_scan(int n, int64_t* __restrict__ row_ptr)
     if (threadIdx.x == 0) row_ptr[0] = 0;
 }
 
-hipError_t launch_allpairs_count(int dim, int n, const double* pos, double R2, const ApBox& box, int64_t* row_ptr,
-                                 int* err, hipStream_t st)
+hipError_t launch_allpairs_count(int dim, const ApPlan& p, const double* pos, double R2, const ApBox& box, int* cnt,
+                                 int64_t* row_ptr, int* err, hipStream_t st)
 {
-    if (n == 0) return hipSuccess;
-    const dim3 g((n + kApThreads - 1) / kApThreads), b(kApThreads);
+    if (p.n == 0) return hipSuccess;
+    const dim3 g((p.n + kApRows - 1) / kApRows, p.nslice), b(kApRows);
     if (dim == 2)
-        hipLaunchKernelGGL((k_allpairs<2, false>), g, b, 0, st, n, pos, R2, box, row_ptr, nullptr, nullptr, err);
+        hipLaunchKernelGGL((k_allpairs<2, false>), g, b, 0, st, p.n, p.slice, pos, R2, box, cnt, nullptr, nullptr,
+                           nullptr, err);
     else
-        hipLaunchKernelGGL((k_allpairs<3, false>), g, b, 0, st, n, pos, R2, box, row_ptr, nullptr, nullptr, err);
-    hipLaunchKernelGGL(k_allpairs_scan, dim3(1), dim3(kApScanThreads), 0, st, n, row_ptr);
+        hipLaunchKernelGGL((k_allpairs<3, false>), g, b, 0, st, p.n, p.slice, pos, R2, box, cnt, nullptr, nullptr,
+                           nullptr, err);
+    hipLaunchKernelGGL(k_allpairs_rows, dim3((p.n + 255) / 256), dim3(256), 0, st, p.n, p.nslice, cnt, row_ptr);
+    hipLaunchKernelGGL(k_allpairs_scan, dim3(1), dim3(kApScanThreads), 0, st, p.n, row_ptr);
     return hipGetLastError();
 }
 
-hipError_t launch_allpairs_fill(int dim, int n, const double* pos, double R2, const ApBox& box,
+hipError_t launch_allpairs_fill(int dim, const ApPlan& p, const double* pos, double R2, const int* cnt,
                                 const int64_t* row_ptr, int32_t* col, float* dist, hipStream_t st)
 {
-    if (n == 0) return hipSuccess;
-    const dim3 g((n + kApThreads - 1) / kApThreads), b(kApThreads);
-    int64_t* rp = const_cast<int64_t*>(row_ptr);  // read only when filling
+    if (p.n == 0) return hipSuccess;
+    const dim3 g((p.n + kApRows - 1) / kApRows, p.nslice), b(kApRows);
+    int* c = const_cast<int*>(cnt);  // read only when filling
     if (dim == 2)
-        hipLaunchKernelGGL((k_allpairs<2, true>), g, b, 0, st, n, pos, R2, box, rp, col, dist, nullptr);
+        hipLaunchKernelGGL((k_allpairs<2, true>), g, b, 0, st, p.n, p.slice, pos, R2, ApBox{}, c, row_ptr, col, dist,
+                           nullptr);
     else
-        hipLaunchKernelGGL((k_allpairs<3, true>), g, b, 0, st, n, pos, R2, box, rp, col, dist, nullptr);
+        hipLaunchKernelGGL((k_allpairs<3, true>), g, b, 0, st, p.n, p.slice, pos, R2, ApBox{}, c, row_ptr, col, dist,
+                           nullptr);
     return hipGetLastError();
 }
 

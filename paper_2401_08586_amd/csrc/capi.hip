@@ -176,6 +176,17 @@ struct nnps_ctx {
     int device = 0;
     int64_t* h_pinned = nullptr;  // pinned staging for synchronous read-backs
     int* d_flag = nullptr;        // device error word of the all-list path (allocated on first use)
+    int* d_apcnt = nullptr;       // all-list per-slice row counts
+    size_t apcnt_cap = 0;         // ints in d_apcnt
+    struct {                      // the last successful all-list count (what a fill may follow)
+        bool valid = false;
+        int dim = 0;
+        const double* pos = nullptr;
+        const int64_t* row_ptr = nullptr;
+        double R2 = 0.0;
+        int64_t nnz = 0;
+        ApPlan plan;
+    } ap;
     int max_lds = 65536;          // LDS bytes a workgroup may use on this device
     nnps_tuning tuning{80, 1024, 0, 0, 0, 0, 0};
 };
@@ -729,6 +740,7 @@ void nnps_ctx_destroy(nnps_ctx* c)
     DeviceGuard g(c->device);
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     if (c->d_flag) (void)hipFree(c->d_flag);
+    if (c->d_apcnt) (void)hipFree(c->d_apcnt);
     delete c;
 }
 
@@ -835,43 +847,91 @@ nnps_status nnps_count(nnps_ctx* ctx, nnps_cells* c, int64_t* d_row_ptr, int64_t
     return nnps_batch_count(ctx, c, rp, h_nnz, stream);
 }
 
-nnps_status nnps_allpairs_search(nnps_ctx* ctx, const nnps_problem* prob, const double* d_pos, int64_t* d_row_ptr,
-                                 int32_t* d_col, float* d_dist, int64_t capacity, int64_t* nnz_out, void* stream)
+nnps_status nnps_allpairs_count(nnps_ctx* ctx, const nnps_problem* prob, const double* d_pos, int64_t* d_row_ptr,
+                                int64_t* nnz_out, void* stream)
 {
-    if (!ctx || !prob || !d_row_ptr || !nnz_out || capacity < 0) return NNPS_EINVAL;
+    if (!ctx || !prob || !d_row_ptr || !nnz_out) return NNPS_EINVAL;
     const nnps_status v = nnps_validate(prob);
     if (v != NNPS_OK) return v;
     if (prob->n > kAllPairsMaxN || (prob->n > 0 && !d_pos)) return NNPS_EINVAL;
-    if (capacity > 0 && (!d_col || !d_dist)) return NNPS_EINVAL;
     DeviceGuard g(ctx->device);
     if (!g.ok) return NNPS_EDEVICE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int n = static_cast<int>(prob->n);
+    ctx->ap.valid = false;
     *nnz_out = 0;
-    if (n == 0) {
-        HIP_TRY(hipMemsetAsync(d_row_ptr, 0, sizeof(int64_t), s));
-        return NNPS_OK;
-    }
-    if (!ctx->d_flag && hipMalloc(reinterpret_cast<void**>(&ctx->d_flag), 64) != hipSuccess) return NNPS_ENOMEM;
-    ApBox box{};
-    for (int k = 0; k < prob->dim; ++k) {
-        box.lo[k] = prob->lo[k];
-        box.hi[k] = prob->hi[k];
-    }
     const double R2 = prob->radius * prob->radius;
-    HIP_TRY(hipMemsetAsync(ctx->d_flag, 0, sizeof(int), s));
-    HIP_TRY(launch_allpairs_count(prob->dim, n, d_pos, R2, box, d_row_ptr, ctx->d_flag, s));
-    int64_t* hp = ctx->h_pinned;
-    hp[0] = 0;
-    hp[1] = 0;
-    HIP_TRY(hipMemcpyAsync(hp, d_row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(hp + 1, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    *nnz_out = hp[0];
-    if (static_cast<int>(hp[1] & 0xFFFFFFFF) != 0) return NNPS_EDOMAIN;
-    if (hp[0] > capacity) return NNPS_ECAPACITY;
-    HIP_TRY(launch_allpairs_fill(prob->dim, n, d_pos, R2, box, d_row_ptr, d_col, d_dist, s));
+    const ApPlan plan = allpairs_plan(n);
+    if (n == 0) {
+        HIP_TRY(launch_fill_i32(reinterpret_cast<int*>(d_row_ptr), 2, 0, s));  // row_ptr[0] = 0
+    } else {
+        const size_t need = static_cast<size_t>(plan.nslice) * static_cast<size_t>(n);
+        if (need > ctx->apcnt_cap) {
+            if (ctx->d_apcnt) {
+                HIP_TRY(hipStreamSynchronize(s));  // a queued fill of this context may still read it
+                (void)hipFree(ctx->d_apcnt);
+                ctx->d_apcnt = nullptr;
+                ctx->apcnt_cap = 0;
+            }
+            if (hipMalloc(reinterpret_cast<void**>(&ctx->d_apcnt), need * sizeof(int)) != hipSuccess) return NNPS_ENOMEM;
+            ctx->apcnt_cap = need;
+        }
+        if (!ctx->d_flag && hipMalloc(reinterpret_cast<void**>(&ctx->d_flag), 64) != hipSuccess) return NNPS_ENOMEM;
+        ApBox box{};
+        for (int k = 0; k < prob->dim; ++k) {
+            box.lo[k] = prob->lo[k];
+            box.hi[k] = prob->hi[k];
+        }
+        HIP_TRY(launch_fill_i32(ctx->d_flag, 1, 0, s));
+        HIP_TRY(launch_allpairs_count(prob->dim, plan, d_pos, R2, box, ctx->d_apcnt, d_row_ptr, ctx->d_flag, s));
+        int64_t* hp = ctx->h_pinned;
+        hp[0] = 0;
+        hp[1] = 0;
+        HIP_TRY(hipMemcpyAsync(hp, d_row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(hp + 1, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (static_cast<int>(hp[1] & 0xFFFFFFFF) != 0) return NNPS_EDOMAIN;
+        *nnz_out = hp[0];
+    }
+    ctx->ap.valid = true;
+    ctx->ap.dim = prob->dim;
+    ctx->ap.pos = d_pos;
+    ctx->ap.row_ptr = d_row_ptr;
+    ctx->ap.R2 = R2;
+    ctx->ap.nnz = *nnz_out;
+    ctx->ap.plan = plan;
     return NNPS_OK;
+}
+
+nnps_status nnps_allpairs_fill(nnps_ctx* ctx, const nnps_problem* prob, const double* d_pos,
+                               const int64_t* d_row_ptr, int32_t* d_col, float* d_dist, int64_t capacity,
+                               void* stream)
+{
+    if (!ctx || !prob || !d_row_ptr || capacity < 0) return NNPS_EINVAL;
+    if (capacity > 0 && (!d_col || !d_dist)) return NNPS_EINVAL;
+    const nnps_status v = nnps_validate(prob);
+    if (v != NNPS_OK) return v;
+    const auto& ap = ctx->ap;
+    if (!ap.valid || ap.plan.n != prob->n || ap.dim != prob->dim || ap.pos != d_pos || ap.row_ptr != d_row_ptr ||
+        ap.R2 != prob->radius * prob->radius)
+        return NNPS_EORDER;
+    if (ap.nnz > capacity) return NNPS_ECAPACITY;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return NNPS_EDEVICE;
+    HIP_TRY(launch_allpairs_fill(ap.dim, ap.plan, d_pos, ap.R2, ctx->d_apcnt, d_row_ptr, d_col, d_dist,
+                                 static_cast<hipStream_t>(stream)));
+    return NNPS_OK;
+}
+
+nnps_status nnps_allpairs_search(nnps_ctx* ctx, const nnps_problem* prob, const double* d_pos, int64_t* d_row_ptr,
+                                 int32_t* d_col, float* d_dist, int64_t capacity, int64_t* nnz_out, void* stream)
+{
+    if (!ctx || !prob || !d_row_ptr || !nnz_out || capacity < 0) return NNPS_EINVAL;
+    if (capacity > 0 && (!d_col || !d_dist)) return NNPS_EINVAL;
+    nnps_status st = nnps_allpairs_count(ctx, prob, d_pos, d_row_ptr, nnz_out, stream);
+    if (st != NNPS_OK) return st;
+    if (*nnz_out > capacity) return NNPS_ECAPACITY;
+    return nnps_allpairs_fill(ctx, prob, d_pos, d_row_ptr, d_col, d_dist, capacity, stream);
 }
 
 nnps_status nnps_cells_set_half(nnps_cells* c, int on)

@@ -73,7 +73,8 @@ EXPORTS = ["nnps_status_str", "nnps_validate", "nnps_grid", "nnps_ctx_create", "
            "nnps_search", "nnps_stats_get", "nnps_cells_set_profiling", "nnps_phase_times",
            "nnps_batch_build", "nnps_batch_count", "nnps_batch_fill", "nnps_batch_search",
            "nnps_batch_step", "nnps_cells_set_graphs", "nnps_batch_nnz", "nnps_batch_nnz_enqueue",
-           "nnps_batch_nnz_fetch", "nnps_sph_gradient", "nnps_cells_set_half", "nnps_allpairs_search"]
+           "nnps_batch_nnz_fetch", "nnps_sph_gradient", "nnps_cells_set_half", "nnps_allpairs_search",
+           "nnps_allpairs_count", "nnps_allpairs_fill"]
 
 PHASES = ["assign", "cellscan", "sort", "pack", "blocks", "unions", "count", "dcount", "rowscan", "fill",
           "longrows", "dfill"]
@@ -119,6 +120,8 @@ def load():
     lib.nnps_cells_set_graphs.argtypes = [P, ctypes.c_int]
     lib.nnps_cells_set_half.argtypes = [P, ctypes.c_int]
     lib.nnps_allpairs_search.argtypes = [P, ctypes.POINTER(Problem), P, P, P, P, I64, ctypes.POINTER(I64), P]
+    lib.nnps_allpairs_count.argtypes = [P, ctypes.POINTER(Problem), P, P, ctypes.POINTER(I64), P]
+    lib.nnps_allpairs_fill.argtypes = [P, ctypes.POINTER(Problem), P, P, P, P, I64, P]
     lib.nnps_batch_nnz.argtypes = [P, P, P]
     lib.nnps_phase_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), P]
     lib.nnps_sph_gradient.argtypes = [P, ctypes.c_int32, I64, ctypes.c_double, P, P, P, P, P, P, P, P]
@@ -380,8 +383,9 @@ def search_batch(sets, mode=MODE_FP16_RCLL, ctx: Context | None = None, cells: C
 
 
 def allpairs_search(pos, lo, hi, radius, ctx: Context | None = None, stream=None):
-    """All-list search of a small set (nnps_allpairs_search): returns (row_ptr, col, dist) as
-    CUDA tensors; binary64, the same result as the FP64 cell list."""
+    """All-list search of a small set (nnps_allpairs_count, then nnps_allpairs_fill into
+    outputs of exactly nnz entries): returns (row_ptr, col, dist) as CUDA tensors; binary64,
+    the same result as the FP64 cell list."""
     import torch
     n, dim = pos.shape
     assert pos.is_cuda and pos.dtype == torch.float64 and pos.is_contiguous()
@@ -391,17 +395,12 @@ def allpairs_search(pos, lo, hi, radius, ctx: Context | None = None, stream=None
         prob = make_problem(dim, n, lo, hi, radius, radius, MODE_FP64_BASELINE)
         rp = torch.empty(n + 1, dtype=torch.int64, device=pos.device)
         nnz = ctypes.c_int64(0)
-        code = ctx._lib.nnps_allpairs_search(ctx._ctx, ctypes.byref(prob), _ptr(pos), _ptr(rp), None, None, 0,
-                                             ctypes.byref(nnz), _stream_ptr(stream))
-        if code == NNPS_ECAPACITY:
-            col = torch.empty(nnz.value, dtype=torch.int32, device=pos.device)
-            dist = torch.empty(nnz.value, dtype=torch.float32, device=pos.device)
-            code = ctx._lib.nnps_allpairs_search(ctx._ctx, ctypes.byref(prob), _ptr(pos), _ptr(rp), _ptr(col),
-                                                 _ptr(dist), nnz.value, ctypes.byref(nnz), _stream_ptr(stream))
-        else:
-            col = torch.empty(0, dtype=torch.int32, device=pos.device)
-            dist = torch.empty(0, dtype=torch.float32, device=pos.device)
-        _check(code, "nnps_allpairs_search")
+        _check(ctx._lib.nnps_allpairs_count(ctx._ctx, ctypes.byref(prob), _ptr(pos), _ptr(rp), ctypes.byref(nnz),
+                                            _stream_ptr(stream)), "nnps_allpairs_count")
+        col = torch.empty(nnz.value, dtype=torch.int32, device=pos.device)
+        dist = torch.empty(nnz.value, dtype=torch.float32, device=pos.device)
+        _check(ctx._lib.nnps_allpairs_fill(ctx._ctx, ctypes.byref(prob), _ptr(pos), _ptr(rp), _ptr(col), _ptr(dist),
+                                           nnz.value, _stream_ptr(stream)), "nnps_allpairs_fill")
     finally:
         if own:
             torch.cuda.synchronize()

@@ -28,6 +28,7 @@ def run(ctx, ps):
 
 CASES = [
     lambda: W.uniform(2, 3000, seed=1),
+    lambda: W.uniform(3, 16001, seed=5),  # 32 slices of 512 candidates, ragged last slice and row group
     lambda: W.uniform(3, 5000, seed=2),
     lambda: W.lattice(2, 50, 0.02, 0.0, name="lat2d_perfect"),
     lambda: W.lattice(3, 12, 1 / 12, 0.1, seed=3),
@@ -47,13 +48,23 @@ def test_allpairs_matches_brute_force(ctx, case):
     np.testing.assert_array_equal(got[2].view(np.uint32), want[2].view(np.uint32))
 
 
-def test_allpairs_equals_the_fp64_cell_list(ctx):
-    ps = W.uniform(3, 20000, seed=4)
+@pytest.mark.parametrize("n", [20000, 65536])
+def test_allpairs_equals_the_fp64_cell_list(ctx, n):
+    """Up to the largest set the path takes; sampled rows also against the oracle."""
+    ps = W.uniform(3, n, seed=4)
     pos = torch.from_numpy(ps.pos).cuda()
     a = nnps.allpairs_search(pos, ps.lo, ps.hi, ps.radius, ctx=ctx)
     b = nnps.search(pos, ps.lo, ps.hi, ps.cell_size, ps.radius, mode=nnps.MODE_FP64_BASELINE, ctx=ctx)[:3]
     for x, y in zip(a, b):
         assert torch.equal(x, y)
+    rows = np.random.default_rng(n).choice(n, 200, replace=False)
+    wrp, wcol, wdist = oracle.search_rows(ps.pos, ps.lo, ps.hi, ps.cell_size, ps.radius, rows)
+    rp, col, dist = (t.cpu().numpy() for t in a)
+    for k, i in enumerate(rows):
+        got = slice(rp[i], rp[i + 1])
+        want = slice(wrp[k], wrp[k + 1])
+        np.testing.assert_array_equal(col[got], wcol[want])
+        np.testing.assert_array_equal(dist[got].view(np.uint32), wdist[want].view(np.uint32))
 
 
 @pytest.mark.parametrize("n", [0, 1, 2, 3, 257])
@@ -86,6 +97,26 @@ def test_allpairs_errors(ctx):
     code = lib.nnps_allpairs_search(ctx._ctx, ctypes.byref(prob), nnps._ptr(pos), nnps._ptr(rp), None, None, 0,
                                     ctypes.byref(nnz), None)
     assert code == nnps.NNPS_ECAPACITY and nnz.value == 6
+    # count then fill: the fill needs the count's problem, positions and row pointers
+    col = torch.empty(6, dtype=torch.int32, device="cuda")
+    dist = torch.empty(6, dtype=torch.float32, device="cuda")
+    assert lib.nnps_allpairs_count(ctx._ctx, ctypes.byref(prob), nnps._ptr(pos), nnps._ptr(rp), ctypes.byref(nnz),
+                                   None) == nnps.NNPS_OK and nnz.value == 6
+    rp2 = torch.empty(4, dtype=torch.int64, device="cuda")
+    assert lib.nnps_allpairs_fill(ctx._ctx, ctypes.byref(prob), nnps._ptr(pos), nnps._ptr(rp2), nnps._ptr(col),
+                                  nnps._ptr(dist), 6, None) == nnps.NNPS_EORDER
+    assert lib.nnps_allpairs_fill(ctx._ctx, ctypes.byref(prob), nnps._ptr(pos), nnps._ptr(rp), nnps._ptr(col),
+                                  nnps._ptr(dist), 5, None) == nnps.NNPS_ECAPACITY
+    assert lib.nnps_allpairs_fill(ctx._ctx, ctypes.byref(prob), nnps._ptr(pos), nnps._ptr(rp), nnps._ptr(col),
+                                  nnps._ptr(dist), 6, None) == nnps.NNPS_OK
+    torch.cuda.synchronize()
+    assert rp.cpu().tolist() == [0, 2, 4, 6] and col.cpu().tolist() == [1, 2, 0, 2, 0, 1]
+    # a count that fails leaves nothing to fill
+    pos[2, 0] = 1.5
+    assert lib.nnps_allpairs_count(ctx._ctx, ctypes.byref(prob), nnps._ptr(pos), nnps._ptr(rp), ctypes.byref(nnz),
+                                   None) == nnps.NNPS_EDOMAIN
+    assert lib.nnps_allpairs_fill(ctx._ctx, ctypes.byref(prob), nnps._ptr(pos), nnps._ptr(rp), nnps._ptr(col),
+                                  nnps._ptr(dist), 6, None) == nnps.NNPS_EORDER
     big = nnps.make_problem(2, 65537, (0, 0), (1, 1), 0.5, 0.5)
     code = lib.nnps_allpairs_search(ctx._ctx, ctypes.byref(big), nnps._ptr(pos), nnps._ptr(rp), None, None, 0,
                                     ctypes.byref(nnz), None)
