@@ -26,8 +26,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of one fill launch at the default workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE per dispatch scaled by what they read for a 512 MiB device copy (x2.000 and
 # x1.000); valid only for the kernel source it was measured on (see profiles/).
-FILL_TRAFFIC = {"source_sha256_16": "b1c988579c5dc601", "bytes": (230063 * 2.0 + 477159 * 1.0) * 1024,
-                "fetch_kib": 230063, "write_kib": 477159, "fetch_scale": 2.0, "write_scale": 1.0}
+FILL_TRAFFIC = {"source_sha256_16": "afab36279197d554", "bytes": (230188 * 2.0 + 477177 * 1.0) * 1024,
+                "fetch_kib": 230188, "write_kib": 477177, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def fill_traffic():
