@@ -30,6 +30,26 @@ FILL_TRAFFIC = {"source_sha256_16": "afab36279197d554", "bytes": (230188 * 2.0 +
                 "fetch_kib": 230188, "write_kib": 477177, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
+def measured_copy_gbs(nbytes=1 << 29, reps=10):
+    """HBM bandwidth a plain device-to-device copy reaches (bytes read + written per second,
+    HIP events around `reps` copies of `nbytes`): the practical ceiling beside the datasheet
+    peak."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def fill_traffic():
     """Measured fill traffic (bytes per launch) if the search kernels are unchanged since."""
     import hashlib
@@ -188,6 +208,8 @@ def main():
                  "fp32_stats": {"band_pairs": st32["band_pairs"], "false_pos": st32["fp16_false_pos"],
                                 "false_neg": st32["fp16_false_neg"]}}
     ctx.close()
+    copy_gbs = measured_copy_gbs()
+    log(f"[bench] device copy {copy_gbs:.0f} GB/s (read + write)")
     if args.copy_probe:
         src = torch.ones(1 << 27, dtype=torch.float32, device="cuda")  # 512 MiB
         dst = torch.empty_like(src)
@@ -216,7 +238,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_fill<3,0> (fill pass)", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": fill_traffic() if args.workload == "c2" else None,
-                     "algorithmic_bytes_per_launch": fb, "avg_launch_ms": fill_ms},
+                     "algorithmic_bytes_per_launch": fb, "avg_launch_ms": fill_ms,
+                     "measured_copy_gbs": copy_gbs},
         "particles_per_s": ps.n / (ms16 * 1e-3),
         "nnz": nnz,
         "phases_ms": ph16,
