@@ -8,6 +8,8 @@ touches it, and it shares no code with that path.
   (nnps_oracle.c), with the all-list brute force for small inputs.
 * `rcll_fp16`: a numpy model of the FP16 relative-coordinate test, used to check
   the GPU's FP16 statistics bit for bit.
+* `rcll_fp32`: the same for the FP32 relative-coordinate test.
+* `sph_gradient`: the SPH gradient sums (Eq. 2 with the kernel of Eq. 3, and Eq. A5).
 """
 from __future__ import annotations
 
