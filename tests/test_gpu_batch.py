@@ -32,7 +32,7 @@ def check(got, ps, mode, name):
     wrp, wcol, wdist = oracle.search_ps(ps)
     np.testing.assert_array_equal(rp, wrp, err_msg=f"{name} row_ptr")
     np.testing.assert_array_equal(col, wcol, err_msg=f"{name} col")
-    if mode == nnps.MODE_FP64_BASELINE:
+    if mode in (nnps.MODE_FP64_BASELINE, nnps.MODE_FP32_RCLL):
         np.testing.assert_array_equal(dist.view(np.uint32), wdist.view(np.uint32), err_msg=f"{name} dist")
     else:
         wd = wdist.astype(np.float64)
@@ -48,8 +48,8 @@ def uneven_batch(dim=3, seed=0, k=7):
     return sets
 
 
-@pytest.mark.parametrize("mode", [nnps.MODE_FP16_RCLL, nnps.MODE_FP64_BASELINE, nnps.MODE_RECHECK_ALL],
-                         ids=["fp16", "fp64", "recheck_all"])
+@pytest.mark.parametrize("mode", [nnps.MODE_FP16_RCLL, nnps.MODE_FP64_BASELINE, nnps.MODE_RECHECK_ALL,
+                                  nnps.MODE_FP32_RCLL], ids=["fp16", "fp64", "recheck_all", "fp32"])
 @pytest.mark.parametrize("dim", [2, 3])
 def test_batch_parity(ctx, dim, mode):
     pss = uneven_batch(dim, seed=dim)
@@ -91,23 +91,24 @@ def test_single_equals_batch(ctx):
     cells.close()
 
 
-def test_graph_step_replays(ctx):
+@pytest.mark.parametrize("mode", [nnps.MODE_FP16_RCLL, nnps.MODE_FP32_RCLL], ids=["fp16", "fp32"])
+def test_graph_step_replays(ctx, mode):
     """The captured step gives the eager result on every replay, also after the
     positions move (same sizes: the graph is replayed with the new pointers)."""
     pss = uneven_batch(3, seed=4, k=4)
     sets = as_sets(pss)
     eager_cells = ctx.cells()
-    ref, _ = nnps.search_batch(sets, ctx=ctx, cells=eager_cells)
+    ref, _ = nnps.search_batch(sets, mode=mode, ctx=ctx, cells=eager_cells)
     cells = ctx.cells()
     cells.set_graphs(True)
     rps = [torch.empty_like(r[0]) for r in ref]
     cols = [torch.empty(r[1].numel() + 64, dtype=torch.int32, device="cuda") for r in ref]
     dists = [torch.empty(r[2].numel() + 64, dtype=torch.float32, device="cuda") for r in ref]
     stream = torch.cuda.Stream()
-    print("[gpu] graph replays", flush=True)
+    print(f"[gpu] graph replays mode={mode}", flush=True)
     for rep in range(4):
         with torch.cuda.stream(stream):
-            cells.batch_step(sets, rps, cols, dists, stream=stream)
+            cells.batch_step(sets, rps, cols, dists, mode=mode, stream=stream)
         cells.batch_nnz_enqueue(stream=stream)
         nnz = cells.batch_nnz_fetch()
         assert nnz == cells.batch_nnz(stream=stream)
@@ -129,11 +130,11 @@ def test_graph_step_replays(ctx):
             mrps = [torch.empty_like(r) for r in rps]
             big = [torch.empty(c.numel() + 20000, dtype=torch.int32, device="cuda") for c in cols]
             bigd = [torch.empty(c.numel() + 20000, dtype=torch.float32, device="cuda") for c in cols]
-            cells.batch_step(msets, mrps, big, bigd, stream=stream)
+            cells.batch_step(msets, mrps, big, bigd, mode=mode, stream=stream)
         stream.synchronize()
         nnz_new = cells.batch_nnz(stream=stream)
         for s, ps in enumerate(moved):
-            check((mrps[s], big[s][:nnz_new[s]], bigd[s][:nnz_new[s]]), ps, 0, ps.name + "_moved")
+            check((mrps[s], big[s][:nnz_new[s]], bigd[s][:nnz_new[s]]), ps, mode, ps.name + "_moved")
     cells.close()
     eager_cells.close()
 
@@ -146,7 +147,7 @@ def test_long_rows_chunked_merge(ctx):
     for keys in (64, 256, 0):
         ctx.set_tuning(block_target=56, long_rows_grid=256, long_rows_keys=keys, dense_min_union=-1)
         print(f"[gpu] long rows keys={keys}", flush=True)
-        for mode in (nnps.MODE_FP16_RCLL, nnps.MODE_FP64_BASELINE):
+        for mode in (nnps.MODE_FP16_RCLL, nnps.MODE_FP64_BASELINE, nnps.MODE_FP32_RCLL):
             cells = ctx.cells()
             rp, col, dist, _ = nnps.search(torch.from_numpy(ps.pos).cuda(), ps.lo, ps.hi, ps.cell_size, ps.radius,
                                            mode=mode, ctx=ctx, cells=cells)

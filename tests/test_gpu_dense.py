@@ -45,7 +45,7 @@ def check(got, want, mode, name):
     wrp, wcol, wdist = want
     np.testing.assert_array_equal(rp, wrp, err_msg=f"{name} row_ptr")
     np.testing.assert_array_equal(col, wcol, err_msg=f"{name} col")
-    if mode == nnps.MODE_FP64_BASELINE:
+    if mode in (nnps.MODE_FP64_BASELINE, nnps.MODE_FP32_RCLL):
         np.testing.assert_array_equal(dist.view(np.uint32), wdist.view(np.uint32), err_msg=f"{name} dist")
     else:
         wd = wdist.astype(np.float64)
@@ -70,8 +70,9 @@ def cases():
     ]
 
 
-@pytest.mark.parametrize("mode", [nnps.MODE_FP16_RCLL, nnps.MODE_FP64_BASELINE, nnps.MODE_RECHECK_ALL],
-                         ids=["fp16", "fp64", "recheck_all"])
+@pytest.mark.parametrize("mode", [nnps.MODE_FP16_RCLL, nnps.MODE_FP64_BASELINE, nnps.MODE_RECHECK_ALL,
+                                  nnps.MODE_FP32_RCLL],
+                         ids=["fp16", "fp64", "recheck_all", "fp32"])
 def test_dense_path_parity(ctx, mode):
     for ps in cases():
         want = oracle.search_ps(ps)
@@ -89,7 +90,7 @@ def test_dense_path_parity(ctx, mode):
             if thr == -1:
                 assert st["dense_rows"] == 0, name
                 ref = st
-            else:
+            elif mode != nnps.MODE_FP32_RCLL:  # FP32 mode decides dense cells in FP64 (no band statistics)
                 for k in STAT_KEYS:
                     assert st[k] == ref[k], (name, k, st[k], ref[k])
             assert st["outside_band_disagree"] == 0
