@@ -267,19 +267,25 @@ nnps_status nnps_allpairs_search(nnps_ctx *ctx, const nnps_problem *prob, const 
  * with the cubic B-spline kernel of Eq. 3, support 2h) and the normalised, volume-free
  * first-order operator of the appendix (Eq. A5), in binary64, for one set of n particles
  * in dim (2 or 3) dimensions. d_pos [n][dim], d_f [n] and d_vol [n] (particle volumes V_j;
- * NULL means V_j = 1) are device arrays; d_row_ptr [n+1] and d_col [nnz] are a CSR
+ * NULL means V_j = 1) are device arrays; d_row_ptr [n+1] and d_col [ncol] are a CSR
  * neighbour list such as nnps_search writes (a row may hold any neighbours; those at
- * r >= 2h add nothing). Outputs, each NULL or a device array [n][dim]:
+ * r >= 2h add nothing; ncol >= d_row_ptr[n] is the caller's to ensure). The kernel reads
+ * d_col only in [0, ncol) (row bounds are clamped to it) and skips column indices
+ * outside [0, n), so a list that does not match ncol or n can give wrong sums for the
+ * rows concerned but never makes it read outside the arrays. Outputs, each NULL or a
+ * device array [n][dim]:
  *   d_grad[i][a]      = sum_j V_j f_j dW_ij/dx_i,a
  *   d_grad_norm[i][a] = sum_j (f_j - f_i) dW_ij/dx_i,a / sum_j (x_j,a - x_i,a) dW_ij/dx_i,a
  *                       (0 where the denominator is 0, e.g. an empty row),
  * with dW_ij/dx_i,a = alpha_d / h * dW/dq (q = r_ij / h) * (x_i,a - x_j,a) / r_ij (0 when
  * r_ij = 0), alpha_d = 15 / (7 pi h^2) in 2D and 3 / (2 pi h^3) in 3D. Every input pointer
- * but d_vol must be non-NULL when n > 0. Asynchronous on `stream`; NNPS_EINVAL for bad
- * arguments (h <= 0 or not finite, dim not 2 or 3, n outside [0, 2^31)). */
+ * but d_vol must be non-NULL when n > 0 (d_col when ncol > 0). Asynchronous on `stream`;
+ * NNPS_EINVAL for bad arguments (h <= 0 or not finite, dim not 2 or 3, n outside
+ * [0, 2^31), ncol < 0). */
 nnps_status nnps_sph_gradient(nnps_ctx *ctx, int32_t dim, int64_t n, double h, const double *d_pos,
                               const double *d_f, const double *d_vol, const int64_t *d_row_ptr,
-                              const int32_t *d_col, double *d_grad, double *d_grad_norm, void *stream);
+                              const int32_t *d_col, int64_t ncol, double *d_grad, double *d_grad_norm,
+                              void *stream);
 
 /* Phases timed when profiling is on, in launch order. */
 enum {

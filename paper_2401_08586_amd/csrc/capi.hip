@@ -943,14 +943,16 @@ nnps_status nnps_cells_set_half(nnps_cells* c, int on)
 }
 
 nnps_status nnps_sph_gradient(nnps_ctx* ctx, int32_t dim, int64_t n, double h, const double* d_pos, const double* d_f,
-                              const double* d_vol, const int64_t* d_row_ptr, const int32_t* d_col, double* d_grad,
-                              double* d_grad_norm, void* stream)
+                              const double* d_vol, const int64_t* d_row_ptr, const int32_t* d_col, int64_t ncol,
+                              double* d_grad, double* d_grad_norm, void* stream)
 {
-    if (!ctx || (dim != 2 && dim != 3) || n < 0 || n > INT32_MAX || !(h > 0.0) || !isfinite(h)) return NNPS_EINVAL;
-    if (n > 0 && (!d_pos || !d_f || !d_row_ptr || !d_col)) return NNPS_EINVAL;
+    if (!ctx || (dim != 2 && dim != 3) || n < 0 || n > INT32_MAX || !(h > 0.0) || !isfinite(h) || ncol < 0)
+        return NNPS_EINVAL;
+    if (n > 0 && (!d_pos || !d_f || !d_row_ptr)) return NNPS_EINVAL;
+    if (ncol > 0 && !d_col) return NNPS_EINVAL;
     DeviceGuard g(ctx->device);
     if (!g.ok) return NNPS_EDEVICE;
-    HIP_TRY(launch_sph_gradient(dim, n, h, d_pos, d_f, d_vol, d_row_ptr, d_col, d_grad, d_grad_norm,
+    HIP_TRY(launch_sph_gradient(dim, n, h, d_pos, d_f, d_vol, d_row_ptr, d_col, ncol, d_grad, d_grad_norm,
                                 static_cast<hipStream_t>(stream)));
     return NNPS_OK;
 }

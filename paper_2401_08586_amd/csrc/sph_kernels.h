@@ -7,7 +7,7 @@
 namespace nnps {
 
 hipError_t launch_sph_gradient(int dim, int64_t n, double h, const double* pos, const double* f, const double* vol,
-                               const int64_t* row_ptr, const int32_t* col, double* grad, double* grad_norm,
-                               hipStream_t st);
+                               const int64_t* row_ptr, const int32_t* col, int64_t ncol, double* grad,
+                               double* grad_norm, hipStream_t st);
 
 }  // namespace nnps

@@ -124,7 +124,7 @@ def load():
     lib.nnps_allpairs_fill.argtypes = [P, ctypes.POINTER(Problem), P, P, P, P, I64, P]
     lib.nnps_batch_nnz.argtypes = [P, P, P]
     lib.nnps_phase_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), P]
-    lib.nnps_sph_gradient.argtypes = [P, ctypes.c_int32, I64, ctypes.c_double, P, P, P, P, P, P, P, P]
+    lib.nnps_sph_gradient.argtypes = [P, ctypes.c_int32, I64, ctypes.c_double, P, P, P, P, P, I64, P, P, P]
     for name in EXPORTS:
         fn = getattr(lib, name)
         if name not in ("nnps_status_str", "nnps_ctx_destroy", "nnps_cells_destroy"):
@@ -424,10 +424,10 @@ def sph_gradient(pos, f, h, row_ptr, col, vol=None, ctx: Context | None = None, 
     try:
         grad = torch.empty((n, dim), dtype=torch.float64, device=pos.device) if "grad" in want else None
         gnorm = torch.empty((n, dim), dtype=torch.float64, device=pos.device) if "grad_norm" in want else None
-        colp = col if col.numel() > 0 else torch.zeros(1, dtype=torch.int32, device=pos.device)
+        # the kernel reads col only within its length (rows are clamped to it)
         _check(ctx._lib.nnps_sph_gradient(ctx._ctx, int(dim), int(n), float(h), _ptr(pos), _ptr(f),
-                                          _ptr(vol) if vol is not None else None, _ptr(row_ptr), _ptr(colp),
-                                          _ptr(grad) if grad is not None else None,
+                                          _ptr(vol) if vol is not None else None, _ptr(row_ptr), _ptr(col),
+                                          int(col.numel()), _ptr(grad) if grad is not None else None,
                                           _ptr(gnorm) if gnorm is not None else None, _stream_ptr(stream)),
                "nnps_sph_gradient")
     finally:

@@ -103,6 +103,32 @@ def test_bad_arguments(ctx):
             nnps.sph_gradient(pos, f, h, rp, col, ctx=ctx)
 
 
+def test_list_inconsistent_with_its_arrays_stays_in_bounds(ctx):
+    """A column array shorter than row_ptr[n] says, and column indices outside [0, n): the
+    kernel reads only within its arrays (rows clamped to the column count, bad indices
+    skipped). Rows wholly inside the shorter array are unchanged; results stay finite."""
+    ps = W.uniform(3, 4000, seed=3)
+    pos = torch.from_numpy(ps.pos).cuda()
+    rp, col, _, _ = nnps.search(pos, ps.lo, ps.hi, ps.cell_size, ps.radius, ctx=ctx)
+    f = (pos[:, 0] ** 3).contiguous()
+    h = ps.radius / 2.0
+    full = nnps.sph_gradient(pos, f, h, rp, col, ctx=ctx)
+    short = col[: col.numel() // 2].clone()
+    part = nnps.sph_gradient(pos, f, h, rp, short, ctx=ctx)
+    torch.cuda.synchronize()
+    inside = torch.from_numpy(rp.cpu().numpy()[1:] <= short.numel()).cuda()
+    assert 0 < int(inside.sum()) < ps.n
+    for a, b in zip(full, part):
+        assert torch.equal(a[inside], b[inside])
+        assert torch.isfinite(b).all()
+    bad = col.clone()
+    bad[::7] = ps.n + 5
+    bad[1::7] = -3
+    g_bad, n_bad = nnps.sph_gradient(pos, f, h, rp, bad, ctx=ctx)
+    torch.cuda.synchronize()
+    assert torch.isfinite(g_bad).all() and torch.isfinite(n_bad).all()
+
+
 def test_c2_sampled_rows(ctx):
     """The 1M-particle 3D lattice in the benchmark's configuration: the gradient of
     f = x^3 on 2000 sampled rows against the oracle's rows (searched one by one)."""
