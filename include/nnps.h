@@ -172,7 +172,8 @@ nnps_status nnps_count(nnps_ctx *ctx, nnps_cells *cells, int64_t *d_row_ptr, int
                        void *stream);
 
 /* Fill pass: writes col and dist (device, caller-owned, `capacity` entries each)
- * using the row_ptr written by nnps_count on the same structure. If row_ptr[n]
+ * using the row_ptr written by nnps_count on the same structure (d_row_ptr must still
+ * hold exactly what that count wrote: rows are written where it says). If row_ptr[n]
  * exceeds capacity nothing past capacity is written and NNPS_ECAPACITY is
  * reported at the next synchronising call. Asynchronous. */
 nnps_status nnps_fill(nnps_ctx *ctx, nnps_cells *cells, const int64_t *d_row_ptr,
