@@ -30,6 +30,30 @@ FILL_TRAFFIC = {"source_sha256_16": "afab36279197d554", "bytes": (230188 * 2.0 +
                 "fetch_kib": 230188, "write_kib": 477177, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
+# VALU wave-instructions per launch (SQ_INSTS_VALU) of the C2 search kernels, from the
+# profile of the same source; like the traffic, reported only while the source is unchanged
+VALU_INSTS = {"source_sha256_16": "afab36279197d554", "k_fill<3,0>": 204028128, "k_count16<3,0,false>": 130144579}
+# one VALU wave-instruction per cycle per compute unit: 256 CUs at 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 2.4e9
+
+
+def issue_rates(ph):
+    """Achieved VALU issue rate of the fill and count kernels (wave-instructions/s) from the
+    profiled instruction counts and this run's mean launch times, or None if the source
+    changed since the profile."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2401_08586_amd", "csrc", "search_kernels.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != VALU_INSTS["source_sha256_16"]:
+            return None
+    out = {}
+    for k, phase in (("k_fill<3,0>", "fill"), ("k_count16<3,0,false>", "count")):
+        rate = VALU_INSTS[k] / (ph[phase] * 1e-3)
+        out[k] = {"valu_insts_per_launch": VALU_INSTS[k], "avg_launch_ms": ph[phase], "achieved": rate,
+                  "peak": VALU_ISSUE_PEAK, "unit": "VALU wave-instructions/s", "frac": rate / VALU_ISSUE_PEAK}
+    return out
+
+
 def measured_copy_gbs(nbytes=1 << 29, reps=10):
     """HBM bandwidth a plain device-to-device copy reaches (bytes read + written per second,
     HIP events around `reps` copies of `nbytes`): the practical ceiling beside the datasheet
@@ -243,6 +267,7 @@ def main():
         "particles_per_s": ps.n / (ms16 * 1e-3),
         "nnz": nnz,
         "phases_ms": ph16,
+        "issue_rate": issue_rates(ph16) if args.workload == "c2" else None,
         "fp16_stats": {k: st16[k] for k in ("candidates", "band_pairs", "fp16_false_pos",
                                               "fp16_false_neg", "heavy_rows", "dense_rows")},
         "fp64_baseline": res64,
