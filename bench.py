@@ -26,13 +26,13 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of one fill launch at the default workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE per dispatch scaled by what they read for a 512 MiB device copy (x2.000 and
 # x1.000); valid only for the kernel source it was measured on (see profiles/).
-FILL_TRAFFIC = {"source_sha256_16": "afab36279197d554", "bytes": (230188 * 2.0 + 477177 * 1.0) * 1024,
-                "fetch_kib": 230188, "write_kib": 477177, "fetch_scale": 2.0, "write_scale": 1.0}
+FILL_TRAFFIC = {"source_sha256_16": "269b20a981b302ba", "bytes": (229886 * 2.0 + 477191 * 1.0) * 1024,
+                "fetch_kib": 229886, "write_kib": 477191, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 # VALU wave-instructions per launch (SQ_INSTS_VALU) of the C2 search kernels, from the
 # profile of the same source; like the traffic, reported only while the source is unchanged
-VALU_INSTS = {"source_sha256_16": "afab36279197d554", "k_fill<3,0>": 204028128, "k_count16<3,0,false>": 130144579}
+VALU_INSTS = {"source_sha256_16": "269b20a981b302ba", "k_fill<3,0>": 203754362, "k_count16<3,0,false>": 130140564}
 # one VALU wave-instruction per cycle per compute unit: 256 CUs at 2.4 GHz
 VALU_ISSUE_PEAK = 256 * 2.4e9
 

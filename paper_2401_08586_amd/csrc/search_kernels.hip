@@ -1022,6 +1022,65 @@ __device__ __forceinline__ void rank_union(int U, int Q, bool packed, int omin, 
     }
 }
 
+// Ranks by bitmap, for unions whose original indices span at most 32 BW values (the
+// common case when particles are numbered in space): one bit per index in [omin, omin +
+// range), an exclusive scan of the word popcounts, and a key's rank is the number of set
+// bits below it. Same outputs as rank_union: rank_of[e], and the original indices moved
+// into rank order (sorig[rank]). bw (BW words) and pc (BW 16-bit prefixes) are scratch.
+template <int UCAP, int NW, int BW>
+__device__ __forceinline__ void rank_bitmap(int U, int omin, int range, uint32_t* bw, uint16_t* pc, int* wsum,
+                                            uint16_t* rank_of, int* sorig)
+{
+    constexpr int NT = 64 * NW;
+    constexpr int EPT = UCAP / NT;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int W = (range + 31) >> 5;
+    for (int w = tid; w < W; w += NT) bw[w] = 0u;
+    __syncthreads();
+    int og[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * NT;
+        og[i] = e < U ? sorig[e] : omin;
+        if (e < U) {
+            const int o = og[i] - omin;
+            atomicOr(&bw[o >> 5], 1u << (o & 31));
+        }
+    }
+    __syncthreads();
+    // thread t takes words [t per, t per + per): their popcounts, scanned across the block
+    const int per = (W + NT - 1) / NT;
+    const int w0 = min(W, tid * per), w1 = min(W, w0 + per);
+    int cnt = 0;
+    for (int w = w0; w < w1; ++w) cnt += __builtin_popcount(bw[w]);
+    int wtot;
+    const int ex = wave_excl_scan_i32(cnt, &wtot);
+    if (lane == 0) wsum[wv] = wtot;
+    __syncthreads();
+    int run = ex;
+    for (int q = 0; q < wv; ++q) run += wsum[q];
+    for (int w = w0; w < w1; ++w) {
+        pc[w] = static_cast<uint16_t>(run);
+        run += __builtin_popcount(bw[w]);
+    }
+    __syncthreads();
+    int rk[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * NT;
+        const int o = og[i] - omin;
+        const int w = o >> 5;
+        rk[i] = pc[w] + __builtin_popcount(bw[w] & ((1u << (o & 31)) - 1u));
+        if (e < U) rank_of[e] = static_cast<uint16_t>(rk[i]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * NT;
+        if (e < U) sorig[rk[i]] = og[i];
+    }
+}
+
 __device__ __forceinline__ int wave_min_i32(int v)
 {
 #pragma unroll
@@ -1064,6 +1123,7 @@ k_fill(SearchArgs a)
     __shared__ double sxi[64 * DIM];  // targets' positions: fixed point, or FP64 (baseline)
     __shared__ int spart[NW][64];   // per-wave popcounts of each row's mask quarter
     __shared__ int sred[2][NW];
+    __shared__ int swsum[NW];
     uint16_t* rank_of = reinterpret_cast<uint16_t*>(smem);
     // flat list entry: target lane << SHIFT | the candidate's rank in the union
     uint16_t* flat = reinterpret_cast<uint16_t*>(smem);
@@ -1147,7 +1207,12 @@ k_fill(SearchArgs a)
         return packed ? (static_cast<uint32_t>(o - omin) << C::SHIFT) | static_cast<uint32_t>(e)
                       : static_cast<uint32_t>(o);
     };
-    if (Q <= 64) rank_union<C::UCAP, C::SHIFT, NW, 1>(U, Q, packed, omin, key_of, skeys, rank_of, sorig);
+    // unions spanning few original indices are ranked by bitmap (scratch after the rank table)
+    constexpr int BW = (kShared - C::UCAP * 2) / 6;
+    if (static_cast<unsigned>(omax - omin) < 32u * BW)
+        rank_bitmap<C::UCAP, NW, BW>(U, omin, omax - omin + 1, reinterpret_cast<uint32_t*>(smem + C::UCAP * 2),
+                                     reinterpret_cast<uint16_t*>(smem + C::UCAP * 2 + BW * 4), swsum, rank_of, sorig);
+    else if (Q <= 64) rank_union<C::UCAP, C::SHIFT, NW, 1>(U, Q, packed, omin, key_of, skeys, rank_of, sorig);
     else if (Q <= 128) rank_union<C::UCAP, C::SHIFT, NW, 2>(U, Q, packed, omin, key_of, skeys, rank_of, sorig);
     else rank_union<C::UCAP, C::SHIFT, NW, 4>(U, Q, packed, omin, key_of, skeys, rank_of, sorig);
     __syncthreads();
