@@ -58,7 +58,11 @@ typedef enum nnps_status {
 
 typedef enum nnps_mode {
     NNPS_MODE_FP16_RCLL = 0,      /* FP16 relative coordinates + FP64 guard-band recheck */
-    NNPS_MODE_FP64_BASELINE = 1,  /* plain FP64 cell list (thread per particle, global loads) */
+    NNPS_MODE_FP64_BASELINE = 1,  /* FP64 cell list: the binary64 predicate on every candidate,
+                                     read from sorted FP64 positions in global memory (one lane
+                                     per target), with the same cell build, work blocks, dense
+                                     and long-row paths and fill as the FP16 mode; distances
+                                     (float)sqrt(r2) in binary64 */
     NNPS_MODE_RECHECK_ALL = 2,    /* debug: FP16 pass plus FP64 on every candidate; the FP64
                                      decision is used and FP16 disagreements outside the band
                                      are counted (must be 0) */
@@ -150,6 +154,13 @@ nnps_status nnps_grid(const nnps_problem *prob, int32_t ncell[3], int32_t *frac_
  * in library calls). One context per host thread at a time. */
 nnps_status nnps_ctx_create(int device, nnps_ctx **out);
 void nnps_ctx_destroy(nnps_ctx *ctx);
+
+/* Waits for `stream`, then returns (and clears) the errors the device recorded for this
+ * context's asynchronous calls since the last check: NNPS_EORDER if an all-list fill met
+ * rows that did not match their count (positions or row pointers changed in between),
+ * NNPS_EINVAL if an SPH-gradient call met a neighbour list that did not match its arrays;
+ * otherwise NNPS_OK. */
+nnps_status nnps_ctx_check(nnps_ctx *ctx, void *stream);
 
 /* Work-shape parameters used by later calls on this context. */
 nnps_status nnps_ctx_set_tuning(nnps_ctx *ctx, const nnps_tuning *t);
@@ -248,10 +259,14 @@ nnps_status nnps_batch_nnz_fetch(nnps_cells *cells, int64_t *h_nnz);
  * (*nnz_out); NNPS_EDOMAIN if a position lies outside [lo, hi] or is not finite. The
  * context keeps per-slice row counts (device memory it owns) for the fill that follows.
  * nnps_allpairs_fill queues the fill of d_col/d_dist [nnz] (asynchronous); it must follow
- * a successful count on the same context with the same problem, d_pos and d_row_ptr,
- * whose contents are unchanged (else NNPS_EORDER), and needs capacity >= nnz (else
- * NNPS_ECAPACITY, nothing written). A later count on the context replaces the kept
- * counts: a fill still queued on another stream must have finished by then.
+ * a successful count on the same context with the same problem, d_pos and d_row_ptr
+ * (else NNPS_EORDER), and needs capacity >= nnz (else NNPS_ECAPACITY, nothing written).
+ * The contents of d_pos and d_row_ptr must also be unchanged since the count; the fill
+ * cannot tell a change from here, but it writes each row only inside [row_ptr[i],
+ * min(row_ptr[i+1], capacity)), and a row whose pairs no longer match its count is
+ * reported as NNPS_EORDER by the next nnps_ctx_check. A later count on the context
+ * replaces the kept counts: a fill still queued on another stream must have finished by
+ * then.
  * nnps_allpairs_search is count then, if capacity >= nnz, fill: NNPS_OK, or
  * NNPS_ECAPACITY with *nnz_out = nnz and only row_ptr written. */
 nnps_status nnps_allpairs_count(nnps_ctx *ctx, const nnps_problem *prob, const double *d_pos, int64_t *d_row_ptr,
@@ -273,7 +288,8 @@ nnps_status nnps_allpairs_search(nnps_ctx *ctx, const nnps_problem *prob, const 
  * r >= 2h add nothing; ncol >= d_row_ptr[n] is the caller's to ensure). The kernel reads
  * d_col only in [0, ncol) (row bounds are clamped to it) and skips column indices
  * outside [0, n), so a list that does not match ncol or n can give wrong sums for the
- * rows concerned but never makes it read outside the arrays. Outputs, each NULL or a
+ * rows concerned but never makes it read outside the arrays; such a list is reported as
+ * NNPS_EINVAL by the next nnps_ctx_check on the context. Outputs, each NULL or a
  * device array [n][dim]:
  *   d_grad[i][a]      = sum_j V_j f_j dW_ij/dx_i,a
  *   d_grad_norm[i][a] = sum_j (f_j - f_i) dW_ij/dx_i,a / sum_j (x_j,a - x_i,a) dW_ij/dx_i,a

@@ -27,8 +27,12 @@ ApPlan allpairs_plan(int n);
 // finite. cnt holds nslice * n ints.
 hipError_t launch_allpairs_count(int dim, const ApPlan& p, const double* pos, double R2, const ApBox& box, int* cnt,
                                  int64_t* row_ptr, int* err, hipStream_t st);
-// Fill: row i's pairs of slice s at row_ptr[i] + sum_{t < s} cnt[t * n + i], ascending j.
+// Fill: row i's pairs of slice s at row_ptr[i] + sum_{t < s} cnt[t * n + i], ascending j,
+// never at or past min(row_ptr[i + 1], cap); a slice whose pairs do not match its count
+// sets kApErrFill in *err.
+constexpr int kApErrFill = 1;
 hipError_t launch_allpairs_fill(int dim, const ApPlan& p, const double* pos, double R2, const int* cnt,
-                                const int64_t* row_ptr, int32_t* col, float* dist, hipStream_t st);
+                                const int64_t* row_ptr, int32_t* col, float* dist, int64_t cap, int* err,
+                                hipStream_t st);
 
 }  // namespace nnps

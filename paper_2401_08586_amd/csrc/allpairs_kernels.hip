@@ -16,6 +16,7 @@
 
 namespace nnps {
 
+
 constexpr int kApRows = 64;
 constexpr int kApMinSlice = 256;
 constexpr int kApTargetWaves = 8192;  // about 8 wavefronts per SIMD
@@ -49,12 +50,15 @@ __device__ __forceinline__ double ap_r2(const double* pi, const double* pj)
     return r2;
 }
 
-// grid (row groups, slices), 64 threads
+// grid (row groups, slices), 64 threads. The fill writes slice s of row i into
+// [w, w + cnt[s][i]) with w = row_ptr[i] + sum_{t < s} cnt[t][i], and never at or past
+// min(row_ptr[i + 1], cap): a slice that finds more or fewer pairs than its count (the
+// positions or row pointers changed since the count) sets bit kApErrFill of *err.
 template <int DIM, bool FILL>
 __global__ void __launch_bounds__(kApRows)
 k_allpairs(int n, int slice, const double* __restrict__ pos, double R2, ApBox box, int* __restrict__ cnt,
            const int64_t* __restrict__ row_ptr, int32_t* __restrict__ col, float* __restrict__ dist,
-           int* __restrict__ err)
+           int64_t cap, int* __restrict__ err)
 {
     __shared__ double tile[kApRows * DIM];
     const int lane = threadIdx.x;
@@ -73,10 +77,11 @@ k_allpairs(int n, int slice, const double* __restrict__ pos, double R2, ApBox bo
             if (bad) atomicOr(err, 1);
         }
     }
-    int64_t w = 0;
+    int64_t w = 0, wend = 0;
     if (FILL && active) {
         w = row_ptr[i];
         for (int t = 0; t < s; ++t) w += cnt[static_cast<size_t>(t) * n + i];
+        wend = min(min(w + cnt[static_cast<size_t>(s) * n + i], row_ptr[i + 1]), cap);
     }
     int c = 0;
     for (int t0 = j0; t0 < j1; t0 += kApRows) {
@@ -93,8 +98,10 @@ k_allpairs(int n, int slice, const double* __restrict__ pos, double R2, ApBox bo
             const double r2 = ap_r2<DIM>(pi, tile + e * DIM);
             if (r2 <= R2 && j != i) {
                 if (FILL) {
-                    col[w] = j;
-                    dist[w] = static_cast<float>(__dsqrt_rn(r2));
+                    if (w < wend) {
+                        col[w] = j;
+                        dist[w] = static_cast<float>(__dsqrt_rn(r2));
+                    }
                     ++w;
                 } else {
                     ++c;
@@ -103,6 +110,7 @@ k_allpairs(int n, int slice, const double* __restrict__ pos, double R2, ApBox bo
         }
     }
     if (!FILL && active) cnt[static_cast<size_t>(s) * n + i] = c;
+    if (FILL && active && w != wend) atomicOr(err, kApErrFill);
 }
 
 // row_ptr[i + 1] = sum over slices of cnt[s * n + i]
@@ -150,27 +158,28 @@ hipError_t launch_allpairs_count(int dim, const ApPlan& p, const double* pos, do
     const dim3 g((p.n + kApRows - 1) / kApRows, p.nslice), b(kApRows);
     if (dim == 2)
         hipLaunchKernelGGL((k_allpairs<2, false>), g, b, 0, st, p.n, p.slice, pos, R2, box, cnt, nullptr, nullptr,
-                           nullptr, err);
+                           nullptr, int64_t(0), err);
     else
         hipLaunchKernelGGL((k_allpairs<3, false>), g, b, 0, st, p.n, p.slice, pos, R2, box, cnt, nullptr, nullptr,
-                           nullptr, err);
+                           nullptr, int64_t(0), err);
     hipLaunchKernelGGL(k_allpairs_rows, dim3((p.n + 255) / 256), dim3(256), 0, st, p.n, p.nslice, cnt, row_ptr);
     hipLaunchKernelGGL(k_allpairs_scan, dim3(1), dim3(kApScanThreads), 0, st, p.n, row_ptr);
     return hipGetLastError();
 }
 
 hipError_t launch_allpairs_fill(int dim, const ApPlan& p, const double* pos, double R2, const int* cnt,
-                                const int64_t* row_ptr, int32_t* col, float* dist, hipStream_t st)
+                                const int64_t* row_ptr, int32_t* col, float* dist, int64_t cap, int* err,
+                                hipStream_t st)
 {
     if (p.n == 0) return hipSuccess;
     const dim3 g((p.n + kApRows - 1) / kApRows, p.nslice), b(kApRows);
     int* c = const_cast<int*>(cnt);  // read only when filling
     if (dim == 2)
         hipLaunchKernelGGL((k_allpairs<2, true>), g, b, 0, st, p.n, p.slice, pos, R2, ApBox{}, c, row_ptr, col, dist,
-                           nullptr);
+                           cap, err);
     else
         hipLaunchKernelGGL((k_allpairs<3, true>), g, b, 0, st, p.n, p.slice, pos, R2, ApBox{}, c, row_ptr, col, dist,
-                           nullptr);
+                           cap, err);
     return hipGetLastError();
 }
 

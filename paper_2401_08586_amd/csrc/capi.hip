@@ -175,7 +175,9 @@ nnps_status frame_of(const nnps_problem* p, Frame* fr, int block_target)
 struct nnps_ctx {
     int device = 0;
     int64_t* h_pinned = nullptr;  // pinned staging for synchronous read-backs
-    int* d_flag = nullptr;        // device error word of the all-list path (allocated on first use)
+    // device error words: [0] the all-list count's domain flag; [1] errors of the
+    // asynchronous calls (all-list fill, SPH gradient), kept until nnps_ctx_check reads them
+    int* d_flag = nullptr;
     int* d_apcnt = nullptr;       // all-list per-slice row counts
     size_t apcnt_cap = 0;         // ints in d_apcnt
     struct {                      // the last successful all-list count (what a fill may follow)
@@ -730,8 +732,31 @@ nnps_status nnps_ctx_create(int device, nnps_ctx** out)
         delete c;
         return NNPS_ENOMEM;
     }
+    if (hipMalloc(reinterpret_cast<void**>(&c->d_flag), 64) != hipSuccess ||
+        hipMemset(c->d_flag, 0, 64) != hipSuccess) {
+        if (c->d_flag) (void)hipFree(c->d_flag);
+        (void)hipHostFree(c->h_pinned);
+        delete c;
+        return NNPS_ENOMEM;
+    }
     *out = c;
     return NNPS_OK;
+}
+
+nnps_status nnps_ctx_check(nnps_ctx* ctx, void* stream)
+{
+    if (!ctx) return NNPS_EINVAL;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return NNPS_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int* hp = reinterpret_cast<int*>(ctx->h_pinned);
+    hp[0] = 0;
+    HIP_TRY(hipMemcpyAsync(hp, ctx->d_flag + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const int e = hp[0];
+    if (e == 0) return NNPS_OK;
+    HIP_TRY(launch_fill_i32(ctx->d_flag + 1, 1, 0, s));
+    return (e & kApErrFill) ? NNPS_EORDER : NNPS_EINVAL;
 }
 
 void nnps_ctx_destroy(nnps_ctx* c)
@@ -876,7 +901,6 @@ nnps_status nnps_allpairs_count(nnps_ctx* ctx, const nnps_problem* prob, const d
             if (hipMalloc(reinterpret_cast<void**>(&ctx->d_apcnt), need * sizeof(int)) != hipSuccess) return NNPS_ENOMEM;
             ctx->apcnt_cap = need;
         }
-        if (!ctx->d_flag && hipMalloc(reinterpret_cast<void**>(&ctx->d_flag), 64) != hipSuccess) return NNPS_ENOMEM;
         ApBox box{};
         for (int k = 0; k < prob->dim; ++k) {
             box.lo[k] = prob->lo[k];
@@ -918,8 +942,8 @@ nnps_status nnps_allpairs_fill(nnps_ctx* ctx, const nnps_problem* prob, const do
     if (ap.nnz > capacity) return NNPS_ECAPACITY;
     DeviceGuard g(ctx->device);
     if (!g.ok) return NNPS_EDEVICE;
-    HIP_TRY(launch_allpairs_fill(ap.dim, ap.plan, d_pos, ap.R2, ctx->d_apcnt, d_row_ptr, d_col, d_dist,
-                                 static_cast<hipStream_t>(stream)));
+    HIP_TRY(launch_allpairs_fill(ap.dim, ap.plan, d_pos, ap.R2, ctx->d_apcnt, d_row_ptr, d_col, d_dist, capacity,
+                                 ctx->d_flag + 1, static_cast<hipStream_t>(stream)));
     return NNPS_OK;
 }
 
@@ -953,7 +977,7 @@ nnps_status nnps_sph_gradient(nnps_ctx* ctx, int32_t dim, int64_t n, double h, c
     DeviceGuard g(ctx->device);
     if (!g.ok) return NNPS_EDEVICE;
     HIP_TRY(launch_sph_gradient(dim, n, h, d_pos, d_f, d_vol, d_row_ptr, d_col, ncol, d_grad, d_grad_norm,
-                                static_cast<hipStream_t>(stream)));
+                                ctx->d_flag + 1, static_cast<hipStream_t>(stream)));
     return NNPS_OK;
 }
 

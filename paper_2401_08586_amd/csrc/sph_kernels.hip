@@ -42,7 +42,7 @@ template <int DIM>
 __global__ void __launch_bounds__(kGradThreads)
 k_sph_gradient(int64_t n, double inv_h, double alpha_h, const double* __restrict__ pos, const double* __restrict__ f,
                const double* __restrict__ vol, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-               int64_t ncol, double* __restrict__ grad, double* __restrict__ grad_norm)
+               int64_t ncol, double* __restrict__ grad, double* __restrict__ grad_norm, int* __restrict__ err)
 {
     const int64_t i = (static_cast<int64_t>(blockIdx.x) * kGradThreads + threadIdx.x) / kRowLanes;
     const int sub = threadIdx.x & (kRowLanes - 1);
@@ -52,15 +52,21 @@ k_sph_gradient(int64_t n, double inv_h, double alpha_h, const double* __restrict
     for (int a = 0; a < DIM; ++a) xi[a] = pos[i * DIM + a];
     const double fi = f[i];
     // row bounds clamped to the column array, column indices outside [0, n) skipped: a
-    // list inconsistent with ncol or n cannot make the kernel read outside its arrays
-    const int64_t rs = min(max(row_ptr[i], int64_t(0)), ncol);
-    const int64_t re = min(max(row_ptr[i + 1], rs), ncol);
+    // list inconsistent with ncol or n cannot make the kernel read outside its arrays, and
+    // it is reported (kErrBadList) instead of passing silently
+    const int64_t r0 = row_ptr[i], r1 = row_ptr[i + 1];
+    const int64_t rs = min(max(r0, int64_t(0)), ncol);
+    const int64_t re = min(max(r1, rs), ncol);
+    bool bad = sub == 0 && (rs != r0 || re != r1);
     double s[DIM], num[DIM], den[DIM];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) s[a] = num[a] = den[a] = 0.0;
     for (int64_t k = rs + sub; k < re; k += kRowLanes) {
         const int64_t j = col[k];
-        if (j < 0 || j >= n) continue;
+        if (j < 0 || j >= n) {
+            bad = true;
+            continue;
+        }
         double dx[DIM];
 #pragma unroll
         for (int a = 0; a < DIM; ++a) dx[a] = __dsub_rn(pos[j * DIM + a], xi[a]);
@@ -87,6 +93,7 @@ k_sph_gradient(int64_t n, double inv_h, double alpha_h, const double* __restrict
         num[a] = row_sum_f64(num[a]);
         den[a] = row_sum_f64(den[a]);
     }
+    if (bad) atomicOr(err, kErrBadList);
     if (sub == 0) {
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
@@ -98,7 +105,7 @@ k_sph_gradient(int64_t n, double inv_h, double alpha_h, const double* __restrict
 
 hipError_t launch_sph_gradient(int dim, int64_t n, double h, const double* pos, const double* f, const double* vol,
                                const int64_t* row_ptr, const int32_t* col, int64_t ncol, double* grad,
-                               double* grad_norm, hipStream_t st)
+                               double* grad_norm, int* err, hipStream_t st)
 {
     if (n == 0) return hipSuccess;
     const double pi = 3.14159265358979323846;
@@ -108,10 +115,10 @@ hipError_t launch_sph_gradient(int dim, int64_t n, double h, const double* pos, 
     const dim3 g(static_cast<unsigned>((n + rows_per_block - 1) / rows_per_block)), b(kGradThreads);
     if (dim == 2)
         hipLaunchKernelGGL(k_sph_gradient<2>, g, b, 0, st, n, 1.0 / h, alpha_h, pos, f, vol, row_ptr, col, ncol,
-                           grad, grad_norm);
+                           grad, grad_norm, err);
     else
         hipLaunchKernelGGL(k_sph_gradient<3>, g, b, 0, st, n, 1.0 / h, alpha_h, pos, f, vol, row_ptr, col, ncol,
-                           grad, grad_norm);
+                           grad, grad_norm, err);
     return hipGetLastError();
 }
 

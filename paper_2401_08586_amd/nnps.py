@@ -74,7 +74,7 @@ EXPORTS = ["nnps_status_str", "nnps_validate", "nnps_grid", "nnps_ctx_create", "
            "nnps_batch_build", "nnps_batch_count", "nnps_batch_fill", "nnps_batch_search",
            "nnps_batch_step", "nnps_cells_set_graphs", "nnps_batch_nnz", "nnps_batch_nnz_enqueue",
            "nnps_batch_nnz_fetch", "nnps_sph_gradient", "nnps_cells_set_half", "nnps_allpairs_search",
-           "nnps_allpairs_count", "nnps_allpairs_fill"]
+           "nnps_allpairs_count", "nnps_allpairs_fill", "nnps_ctx_check"]
 
 PHASES = ["assign", "cellscan", "sort", "pack", "blocks", "unions", "count", "dcount", "rowscan", "fill",
           "longrows", "dfill"]
@@ -125,6 +125,7 @@ def load():
     lib.nnps_batch_nnz.argtypes = [P, P, P]
     lib.nnps_phase_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), P]
     lib.nnps_sph_gradient.argtypes = [P, ctypes.c_int32, I64, ctypes.c_double, P, P, P, P, P, I64, P, P, P]
+    lib.nnps_ctx_check.argtypes = [P, P]
     for name in EXPORTS:
         fn = getattr(lib, name)
         if name not in ("nnps_status_str", "nnps_ctx_destroy", "nnps_cells_destroy"):
@@ -222,6 +223,11 @@ class Context:
         c = Cells(self)
         self._cells.append(c)
         return c
+
+    def check(self, stream=None) -> int:
+        """nnps_ctx_check: waits for the stream and returns (and clears) the status of the
+        errors the device recorded for this context's asynchronous calls."""
+        return self._lib.nnps_ctx_check(self._ctx, _stream_ptr(stream))
 
 
 class Cells:

@@ -121,3 +121,39 @@ def test_allpairs_errors(ctx):
     code = lib.nnps_allpairs_search(ctx._ctx, ctypes.byref(big), nnps._ptr(pos), nnps._ptr(rp), None, None, 0,
                                     ctypes.byref(nnz), None)
     assert code == nnps.NNPS_EINVAL
+
+
+def test_allpairs_fill_stays_in_its_rows_when_counts_are_stale(ctx):
+    """The fill writes row i only inside [row_ptr[i], min(row_ptr[i+1], capacity)). Row
+    pointers that no longer match the count (rows shortened after the count) leave the
+    entries past each row and past the capacity untouched, and nnps_ctx_check reports the
+    mismatch once."""
+    import ctypes
+    ps = W.uniform(3, 3000, seed=4)
+    pos = torch.from_numpy(ps.pos).cuda()
+    prob = nnps.make_problem(3, ps.n, ps.lo, ps.hi, ps.radius, ps.radius, nnps.MODE_FP64_BASELINE)
+    rp = torch.empty(ps.n + 1, dtype=torch.int64, device="cuda")
+    nnz = ctypes.c_int64(0)
+    lib = ctx._lib
+    assert lib.nnps_allpairs_count(ctx._ctx, ctypes.byref(prob), nnps._ptr(pos), nnps._ptr(rp),
+                                   ctypes.byref(nnz), None) == nnps.NNPS_OK
+    assert ctx.check() == nnps.NNPS_OK
+    ref_rp = rp.cpu().numpy()
+    nz = int(nnz.value)
+    assert nz > 1000
+    # every row start moved back by half of its row: rows overlap less than counted
+    half = ref_rp.copy()
+    lens = np.diff(ref_rp)
+    half[1:] = ref_rp[1:] - lens // 2
+    half = np.maximum.accumulate(half)
+    rp.copy_(torch.from_numpy(half))
+    cap = nz - 17
+    col = torch.full((nz + 64,), -7, dtype=torch.int32, device="cuda")
+    dist = torch.full((nz + 64,), -1.0, dtype=torch.float32, device="cuda")
+    assert lib.nnps_allpairs_fill(ctx._ctx, ctypes.byref(prob), nnps._ptr(pos), nnps._ptr(rp), nnps._ptr(col),
+                                  nnps._ptr(dist), cap, None) == nnps.NNPS_OK
+    torch.cuda.synchronize()
+    c = col.cpu().numpy()
+    assert np.all(c[cap:] == -7)
+    assert ctx.check() == nnps.NNPS_EORDER
+    assert ctx.check() == nnps.NNPS_OK

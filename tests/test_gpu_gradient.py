@@ -127,6 +127,14 @@ def test_list_inconsistent_with_its_arrays_stays_in_bounds(ctx):
     g_bad, n_bad = nnps.sph_gradient(pos, f, h, rp, bad, ctx=ctx)
     torch.cuda.synchronize()
     assert torch.isfinite(g_bad).all() and torch.isfinite(n_bad).all()
+    # both mismatches were reported to the context (once: the check clears them), and a
+    # consistent list reports nothing
+    assert ctx.check() == nnps.NNPS_EINVAL
+    assert ctx.check() == nnps.NNPS_OK
+    nnps.sph_gradient(pos, f, h, rp, short, ctx=ctx)
+    assert ctx.check() == nnps.NNPS_EINVAL
+    nnps.sph_gradient(pos, f, h, rp, col, ctx=ctx)
+    assert ctx.check() == nnps.NNPS_OK
 
 
 def test_c2_sampled_rows(ctx):
