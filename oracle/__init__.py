@@ -6,6 +6,9 @@ touches it, and it shares no code with that path.
 
 * `search` / `search_rows`: the serial FP64 cell link-list search in plain C
   (nnps_oracle.c), with the all-list brute force for small inputs.
+* `count_rows` / `search_par`: the same cell-list search with rows computed in parallel
+  (OpenMP over rows; each row exactly as in the serial search), for the full-size
+  clustered batch and the all-core CPU baseline.
 * `rcll_fp16`: a numpy model of the FP16 relative-coordinate test, used to check
   the GPU's FP16 statistics bit for bit.
 * `rcll_fp32`: the same for the FP32 relative-coordinate test.
@@ -37,7 +40,7 @@ def build(force: bool = True) -> str:
     """Compile nnps_oracle.c with plain IEEE binary64 semantics (no contraction)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fopenmp",
                                "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -56,6 +59,12 @@ def _load():
         lib.orc_search_rows.argtypes = [ctypes.c_int, ctypes.c_int64, P, P, P, ctypes.c_double,
                                         ctypes.c_double, P, ctypes.c_int64, ctypes.POINTER(P)]
         lib.orc_search_rows.restype = ctypes.c_int
+        lib.orc_count_rows.argtypes = [ctypes.c_int, ctypes.c_int64, P, P, P, ctypes.c_double, ctypes.c_double,
+                                       P, ctypes.c_int64, ctypes.c_int, P]
+        lib.orc_count_rows.restype = ctypes.c_int
+        lib.orc_search_par.argtypes = [ctypes.c_int, ctypes.c_int64, P, P, P, ctypes.c_double, ctypes.c_double,
+                                       P, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(P)]
+        lib.orc_search_par.restype = ctypes.c_int
         lib.orc_nnz.argtypes = [P]
         lib.orc_nnz.restype = ctypes.c_int64
         lib.orc_copy.argtypes = [P, P, P, P]
@@ -115,6 +124,38 @@ def search_rows(pos, lo, hi, cell_size, radius, rows):
     if st != ORC_OK:
         raise OracleError(st)
     return _collect(lib, h, rows.size)
+
+
+def count_rows(pos, lo, hi, cell_size, radius, rows=None, threads=0):
+    """Neighbour count of every row (or of the listed rows), int64; rows in parallel."""
+    lib = _load()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    n, dim = pos.shape
+    lo3, hi3 = _box(lo, hi, dim)
+    r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    m = n if r is None else r.size
+    out = np.empty(m, dtype=np.int64)
+    st = lib.orc_count_rows(dim, n, _ptr(pos), _ptr(lo3), _ptr(hi3), float(cell_size), float(radius),
+                            _ptr(r), m, int(threads), _ptr(out))
+    if st != ORC_OK:
+        raise OracleError(st)
+    return out
+
+
+def search_par(pos, lo, hi, cell_size, radius, rows=None, threads=0):
+    """`search` (or `search_rows` when rows are given) with rows computed in parallel."""
+    lib = _load()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    n, dim = pos.shape
+    lo3, hi3 = _box(lo, hi, dim)
+    r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    m = n if r is None else r.size
+    h = ctypes.c_void_p()
+    st = lib.orc_search_par(dim, n, _ptr(pos), _ptr(lo3), _ptr(hi3), float(cell_size), float(radius),
+                            _ptr(r), m, int(threads), ctypes.byref(h))
+    if st != ORC_OK:
+        raise OracleError(st)
+    return _collect(lib, h, m)
 
 
 def search_ps(ps, brute=False):

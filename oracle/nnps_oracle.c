@@ -30,6 +30,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_OK 0
 #define ORC_EINVAL (-1)
@@ -265,4 +268,210 @@ void orc_free(orc_result *r)
     free(r->col);
     free(r->dist);
     free(r);
+}
+
+/* ---------------------------------------------------------------------------------
+ * Row-parallel forms of the same search, for large inputs (the whole clustered batch)
+ * and for the all-core CPU baseline. They build the same grid (cell link list with
+ * head/next chains) and apply the same predicate; each row is computed exactly as in
+ * search_impl, by one thread, and rows are independent, so the result does not depend
+ * on the thread count. nthreads <= 0 takes OpenMP's default.
+ */
+typedef struct {
+    int dim;
+    int64_t n;
+    const double *pos;
+    double R2;
+    int64_t nc[3];
+    int64_t *head, *next, *cell;
+} orc_grid;
+
+static void grid_free(orc_grid *g)
+{
+    free(g->head);
+    free(g->next);
+    free(g->cell);
+}
+
+/* The grid of search_impl: cell width max(cell_size, radius)(1 + 2^-20), widened while the
+ * cell count exceeds 2^26; chains built by prepending in index order. */
+static int grid_build(int dim, int64_t n, const double *pos, const double *lo, const double *hi,
+                      double cell_size, double radius, orc_grid *g)
+{
+    memset(g, 0, sizeof(*g));
+    int st = validate(dim, n, pos, lo, hi, cell_size, radius);
+    if (st) return st;
+    g->dim = dim;
+    g->n = n;
+    g->pos = pos;
+    g->R2 = radius * radius;
+    double w = (cell_size > radius ? cell_size : radius) * (1.0 + ldexp(1.0, -20));
+    int64_t ncell;
+    g->nc[0] = g->nc[1] = g->nc[2] = 1;
+    for (;;) {
+        for (int k = 0; k < dim; k++) {
+            double c = ceil((hi[k] - lo[k]) / w);
+            g->nc[k] = c < 1.0 ? 1 : (int64_t)c;
+        }
+        ncell = g->nc[0] * g->nc[1] * g->nc[2];
+        if (ncell <= ((int64_t)1 << 26)) break;
+        w *= 2.0;
+    }
+    g->head = (int64_t *)malloc((size_t)ncell * sizeof(int64_t));
+    g->next = (int64_t *)malloc((size_t)(n ? n : 1) * sizeof(int64_t));
+    g->cell = (int64_t *)malloc((size_t)(n ? n : 1) * 3 * sizeof(int64_t));
+    if (!g->head || !g->next || !g->cell) {
+        grid_free(g);
+        return ORC_ENOMEM;
+    }
+    for (int64_t c = 0; c < ncell; c++) g->head[c] = -1;
+    for (int64_t i = 0; i < n; i++) {
+        int64_t key = 0, mul = 1;
+        for (int k = 0; k < 3; k++) g->cell[i * 3 + k] = 0;
+        for (int k = 0; k < dim; k++) {
+            double t = floor((pos[i * dim + k] - lo[k]) / w);
+            int64_t c = (int64_t)t;
+            if (c < 0) c = 0;
+            if (c > g->nc[k] - 1) c = g->nc[k] - 1;
+            g->cell[i * 3 + k] = c;
+            key += c * mul;
+            mul *= g->nc[k];
+        }
+        g->next[i] = g->head[key];
+        g->head[key] = i;
+    }
+    return ORC_OK;
+}
+
+/* Neighbours of row i through the clipped 3^d block of cells: their number, and, when
+ * out != NULL, the pairs (j, (float)sqrt(r2)) in chain order. */
+static int64_t grid_row(const orc_grid *g, int64_t i, orc_pair *out)
+{
+    const int dim = g->dim;
+    const double *pi = g->pos + i * dim;
+    int64_t lo3[3] = {0, 0, 0}, hi3[3] = {0, 0, 0};
+    for (int k = 0; k < dim; k++) {
+        lo3[k] = g->cell[i * 3 + k] > 0 ? g->cell[i * 3 + k] - 1 : 0;
+        hi3[k] = g->cell[i * 3 + k] < g->nc[k] - 1 ? g->cell[i * 3 + k] + 1 : g->nc[k] - 1;
+    }
+    int64_t m = 0;
+    for (int64_t cz = lo3[2]; cz <= hi3[2]; cz++)
+        for (int64_t cy = lo3[1]; cy <= hi3[1]; cy++)
+            for (int64_t cx = lo3[0]; cx <= hi3[0]; cx++) {
+                int64_t key = cx + g->nc[0] * (cy + g->nc[1] * cz);
+                for (int64_t j = g->head[key]; j >= 0; j = g->next[j]) {
+                    if (j == i) continue;
+                    double r2 = pair_r2(dim, pi, g->pos + j * dim);
+                    if (r2 <= g->R2) {
+                        if (out) {
+                            out[m].j = (int32_t)j;
+                            out[m].d = (float)sqrt(r2);
+                        }
+                        m++;
+                    }
+                }
+            }
+    return m;
+}
+
+/* counts[r] = |N(rows[r])| (or |N(r)| for every row when rows == NULL, nrows = n). */
+int orc_count_rows(int dim, int64_t n, const double *pos, const double *lo, const double *hi,
+                   double cell_size, double radius, const int64_t *rows, int64_t nrows, int nthreads,
+                   int64_t *counts)
+{
+    if (!counts || (rows && nrows < 0)) return ORC_EINVAL;
+    orc_grid g;
+    int st = grid_build(dim, n, pos, lo, hi, cell_size, radius, &g);
+    if (st) return st;
+    if (!rows) nrows = n;
+    for (int64_t r = 0; rows && r < nrows; r++)
+        if (rows[r] < 0 || rows[r] >= n) {
+            grid_free(&g);
+            return ORC_EINVAL;
+        }
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads)
+#endif
+    for (int64_t r = 0; r < nrows; r++) counts[r] = grid_row(&g, rows ? rows[r] : r, NULL);
+    (void)nthreads;
+    grid_free(&g);
+    return ORC_OK;
+}
+
+/* The CSR of search_impl (cell-list form), rows computed in parallel: a counting pass,
+ * the row offsets, then each row written at its offset and sorted by j. */
+int orc_search_par(int dim, int64_t n, const double *pos, const double *lo, const double *hi,
+                   double cell_size, double radius, const int64_t *rows, int64_t nrows, int nthreads,
+                   orc_result **out)
+{
+    *out = NULL;
+    if (rows && nrows < 0) return ORC_EINVAL;
+    orc_grid g;
+    int st = grid_build(dim, n, pos, lo, hi, cell_size, radius, &g);
+    if (st) return st;
+    if (!rows) nrows = n;
+    for (int64_t r = 0; rows && r < nrows; r++)
+        if (rows[r] < 0 || rows[r] >= n) {
+            grid_free(&g);
+            return ORC_EINVAL;
+        }
+    orc_result *res = (orc_result *)calloc(1, sizeof(orc_result));
+    int64_t *cnt = (int64_t *)malloc((size_t)(nrows ? nrows : 1) * sizeof(int64_t));
+    if (!res || !cnt) {
+        free(res);
+        free(cnt);
+        grid_free(&g);
+        return ORC_ENOMEM;
+    }
+    res->n = nrows;
+    res->row_ptr = (int64_t *)calloc((size_t)nrows + 1, sizeof(int64_t));
+    if (!res->row_ptr) {
+        st = ORC_ENOMEM;
+        goto done;
+    }
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads)
+#endif
+    for (int64_t r = 0; r < nrows; r++) cnt[r] = grid_row(&g, rows ? rows[r] : r, NULL);
+    for (int64_t r = 0; r < nrows; r++) res->row_ptr[r + 1] = res->row_ptr[r] + cnt[r];
+    res->nnz = res->row_ptr[nrows];
+    {
+        size_t m = (size_t)(res->nnz ? res->nnz : 1);
+        orc_pair *pairs = (orc_pair *)malloc(m * sizeof(orc_pair));
+        res->col = (int32_t *)malloc(m * sizeof(int32_t));
+        res->dist = (float *)malloc(m * sizeof(float));
+        if (!pairs || !res->col || !res->dist) {
+            free(pairs);
+            st = ORC_ENOMEM;
+            goto done;
+        }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads)
+#endif
+        for (int64_t r = 0; r < nrows; r++) {
+            orc_pair *row = pairs + res->row_ptr[r];
+            int64_t len = grid_row(&g, rows ? rows[r] : r, row);
+            qsort(row, (size_t)len, sizeof(orc_pair), cmp_pair);
+            for (int64_t e = 0; e < len; e++) {
+                res->col[res->row_ptr[r] + e] = row[e].j;
+                res->dist[res->row_ptr[r] + e] = row[e].d;
+            }
+        }
+        free(pairs);
+    }
+done:
+    free(cnt);
+    grid_free(&g);
+    if (st) {
+        free(res->row_ptr);
+        free(res->col);
+        free(res->dist);
+        free(res);
+        return st;
+    }
+    (void)nthreads;
+    *out = res;
+    return ORC_OK;
 }

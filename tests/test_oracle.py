@@ -231,3 +231,43 @@ def test_validation_errors():
     assert e.value.code == oracle.ORC_EDOMAIN
     rp, col, dist = oracle.search(np.zeros((0, 3)), (0, 0, 0), (1, 1, 1), 0.2, 0.2)
     assert list(rp) == [0] and col.size == 0
+
+
+# --- the row-parallel forms (count_rows, search_par) ----------------------------------
+@pytest.mark.parametrize("case", _random_cases()[::3], ids=lambda c: c[0])
+@pytest.mark.parametrize("threads", [1, 4])
+def test_parallel_forms_equal_brute_force(case, threads):
+    """Rows computed in parallel give the brute force's CSR, and the row counts its row
+    lengths, whatever the thread count."""
+    name, pos, lo, hi, cell, radius = case
+    want = oracle.search(pos, lo, hi, cell, radius, brute=True)
+    got = oracle.search_par(pos, lo, hi, cell, radius, threads=threads)
+    for x, y in zip(got, want):
+        np.testing.assert_array_equal(x, y)
+    np.testing.assert_array_equal(oracle.count_rows(pos, lo, hi, cell, radius, threads=threads),
+                                  np.diff(want[0]))
+
+
+@pytest.mark.parametrize("dim,n", [(2, 100), (3, 30), (2, 1000)])
+def test_parallel_forms_perfect_lattice_totals(dim, n):
+    ps = W.lattice(dim, n, 1.0 / n, jitter=0.0)
+    counts = oracle.count_rows(ps.pos, ps.lo, ps.hi, ps.cell_size, ps.radius, threads=4)
+    assert counts.sum() == lattice_nnz(n, dim, 5.76)
+    assert counts.max() == (20 if dim == 2 else 56)
+
+
+def test_parallel_forms_selected_rows():
+    ps = W.clustered(5000, 9, dim=3)
+    rows = np.random.default_rng(1).choice(ps.n, 300, replace=False)
+    want = oracle.search_rows(ps.pos, ps.lo, ps.hi, ps.cell_size, ps.radius, rows)
+    got = oracle.search_par(ps.pos, ps.lo, ps.hi, ps.cell_size, ps.radius, rows=rows, threads=3)
+    for x, y in zip(got, want):
+        np.testing.assert_array_equal(x, y)
+    cnt = oracle.count_rows(ps.pos, ps.lo, ps.hi, ps.cell_size, ps.radius, rows=rows, threads=2)
+    np.testing.assert_array_equal(cnt, np.diff(want[0]))
+    with pytest.raises(oracle.OracleError):
+        oracle.count_rows(ps.pos, ps.lo, ps.hi, ps.cell_size, ps.radius, rows=np.array([ps.n]))
+    bad = ps.pos.copy()
+    bad[3, 0] = 1.5
+    with pytest.raises(oracle.OracleError):
+        oracle.search_par(bad, ps.lo, ps.hi, ps.cell_size, ps.radius)
