@@ -125,9 +125,9 @@ def test_allpairs_errors(ctx):
 
 def test_allpairs_fill_stays_in_its_rows_when_counts_are_stale(ctx):
     """The fill writes row i only inside [row_ptr[i], min(row_ptr[i+1], capacity)). Row
-    pointers that no longer match the count (rows shortened after the count) leave the
-    entries past each row and past the capacity untouched, and nnps_ctx_check reports the
-    mismatch once."""
+    pointers that no longer match the count (rows shortened, or moved past the capacity,
+    after the count) leave every entry outside those bounds untouched, and nnps_ctx_check
+    reports the mismatch once."""
     import ctypes
     ps = W.uniform(3, 3000, seed=4)
     pos = torch.from_numpy(ps.pos).cuda()
@@ -141,19 +141,22 @@ def test_allpairs_fill_stays_in_its_rows_when_counts_are_stale(ctx):
     ref_rp = rp.cpu().numpy()
     nz = int(nnz.value)
     assert nz > 1000
-    # every row start moved back by half of its row: rows overlap less than counted
-    half = ref_rp.copy()
     lens = np.diff(ref_rp)
-    half[1:] = ref_rp[1:] - lens // 2
-    half = np.maximum.accumulate(half)
-    rp.copy_(torch.from_numpy(half))
-    cap = nz - 17
-    col = torch.full((nz + 64,), -7, dtype=torch.int32, device="cuda")
-    dist = torch.full((nz + 64,), -1.0, dtype=torch.float32, device="cuda")
-    assert lib.nnps_allpairs_fill(ctx._ctx, ctypes.byref(prob), nnps._ptr(pos), nnps._ptr(rp), nnps._ptr(col),
-                                  nnps._ptr(dist), cap, None) == nnps.NNPS_OK
-    torch.cuda.synchronize()
-    c = col.cpu().numpy()
-    assert np.all(c[cap:] == -7)
-    assert ctx.check() == nnps.NNPS_EORDER
-    assert ctx.check() == nnps.NNPS_OK
+    short = ref_rp.copy()
+    short[1:] = np.maximum.accumulate(ref_rp[1:] - lens // 2)   # every row shorter than counted
+    shifted = ref_rp + 100                                        # the last rows run past nz
+    for name, new_rp in (("short", short), ("shifted", shifted)):
+        rp.copy_(torch.from_numpy(new_rp))
+        col = torch.full((nz + 200,), -7, dtype=torch.int32, device="cuda")
+        dist = torch.full((nz + 200,), -1.0, dtype=torch.float32, device="cuda")
+        assert lib.nnps_allpairs_fill(ctx._ctx, ctypes.byref(prob), nnps._ptr(pos), nnps._ptr(rp),
+                                      nnps._ptr(col), nnps._ptr(dist), nz, None) == nnps.NNPS_OK, name
+        torch.cuda.synchronize()
+        c = col.cpu().numpy()
+        assert np.all(c[nz:] == -7), name                       # nothing at or past the capacity
+        inside = np.zeros(nz + 200, bool)
+        for i in range(ps.n):
+            inside[new_rp[i]:min(new_rp[i + 1], nz)] = True
+        assert np.all(c[~inside] == -7), name                   # nothing outside the rows
+        assert ctx.check() == nnps.NNPS_EORDER, name
+        assert ctx.check() == nnps.NNPS_OK, name
