@@ -278,6 +278,23 @@ nnps_status nnps_allpairs_search(nnps_ctx *ctx, const nnps_problem *prob, const 
                                  int64_t *d_row_ptr, int32_t *d_col, float *d_dist, int64_t capacity,
                                  int64_t *nnz_out, void *stream);
 
+/* The same search for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): count and fill as in
+ * nnps_allpairs_search, with the per-slice row counts and the error word kept in a
+ * static device array of the library (2.25 MiB per device, held until the process ends;
+ * its address is looked up when a context is created on the device) instead of memory
+ * the context allocates. Makes no hipMalloc, hipFree or other allocating call. The same
+ * limits: prob->n <= 65536 (NNPS_EINVAL above; the array is sized for that maximum);
+ * waits for the stream once (after the count) to return *nnz_out; NNPS_EDOMAIN,
+ * NNPS_ECAPACITY (with *nnz_out = nnz and only row_ptr written) as there; NNPS_EDEVICE
+ * if the array's address could not be found. Every call on a device shares that
+ * device's array, so calls that overlap on one device (other host threads or streams)
+ * race and must be serialised by the caller; the array keeps the last call's contents
+ * (each call clears what it needs). Leaves the context's all-list count state alone. */
+nnps_status nnps_allpairs_search_noalloc(nnps_ctx *ctx, const nnps_problem *prob, const double *d_pos,
+                                         int64_t *d_row_ptr, int32_t *d_col, float *d_dist, int64_t capacity,
+                                         int64_t *nnz_out, void *stream);
+
 /* ---- SPH gradient over a neighbour list ------------------------------------------
  * The SPH approximation of the gradient of a scalar field f (SPH method section, Eq. 2,
  * with the cubic B-spline kernel of Eq. 3, support 2h) and the normalised, volume-free

@@ -12,6 +12,16 @@ struct ApBox {
 
 // Largest set the all-list path takes (its work grows as n^2).
 constexpr int kAllPairsMaxN = 65536;
+// The allocation-free all-list search keeps its per-slice row counts in a static device
+// array: kApStaticCounts is the largest nslice * n of allpairs_plan over n <= kAllPairsMaxN
+// (589,248 at n = 65,472; 2.25 MiB), followed by kApStaticFlags error words.
+constexpr int64_t kApStaticCounts = 589248;
+constexpr int kApStaticFlags = 64;
+// Looks up, once per device (the device must be current), the address of that device's
+// copy of the static array; returns the lookup's status.
+hipError_t allpairs_static_scratch_init(int device);
+// The address found by allpairs_static_scratch_init(device), or nullptr.
+int* allpairs_static_scratch(int device);
 
 // Work split: rows in groups of 64 (one wavefront, one row per lane) times slices of the
 // candidate range, so that even small sets give the chip thousands of wavefronts.

@@ -13,9 +13,45 @@
 #include "allpairs_kernels.h"
 
 #include <algorithm>
+#include <mutex>
 
 namespace nnps {
 
+// Device scratch of the allocation-free all-list search: the per-slice row counts of the
+// largest admissible set (kApStaticCounts ints), then kApStaticFlags error words. Every
+// device the library runs on holds its own copy until the process ends; host code must
+// never pass this name to a kernel (it is a host-side stand-in): it uses the per-device
+// address looked up below.
+static __device__ __align__(256) int scratch[kApStaticCounts + kApStaticFlags];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+}  // namespace
+
+hipError_t allpairs_static_scratch_init(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_done[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_scratch_err[device] = e;
+        g_scratch_ptr[device] = e == hipSuccess ? static_cast<int*>(p) : nullptr;
+        g_scratch_done[device] = true;
+    }
+    return g_scratch_err[device];
+}
+
+int* allpairs_static_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
 
 constexpr int kApRows = 64;
 constexpr int kApMinSlice = 256;

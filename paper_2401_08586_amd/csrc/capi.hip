@@ -727,6 +727,10 @@ nnps_status nnps_ctx_create(int device, nnps_ctx** out)
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
         c->max_lds = lds;
+    // the allocation-free all-list search finds this device's static scratch here, once
+    // per device (with the device current); a failed lookup makes that call return
+    // NNPS_EDEVICE and leaves every other call unaffected
+    (void)allpairs_static_scratch_init(device);
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_pinned), 64 * sizeof(int64_t), hipHostMallocDefault) !=
         hipSuccess) {
         delete c;
@@ -956,6 +960,52 @@ nnps_status nnps_allpairs_search(nnps_ctx* ctx, const nnps_problem* prob, const 
     if (st != NNPS_OK) return st;
     if (*nnz_out > capacity) return NNPS_ECAPACITY;
     return nnps_allpairs_fill(ctx, prob, d_pos, d_row_ptr, d_col, d_dist, capacity, stream);
+}
+
+nnps_status nnps_allpairs_search_noalloc(nnps_ctx* ctx, const nnps_problem* prob, const double* d_pos,
+                                         int64_t* d_row_ptr, int32_t* d_col, float* d_dist, int64_t capacity,
+                                         int64_t* nnz_out, void* stream)
+{
+    if (!ctx || !prob || !d_row_ptr || !nnz_out || capacity < 0) return NNPS_EINVAL;
+    if (capacity > 0 && (!d_col || !d_dist)) return NNPS_EINVAL;
+    const nnps_status v = nnps_validate(prob);
+    if (v != NNPS_OK) return v;
+    if (prob->n > kAllPairsMaxN || (prob->n > 0 && !d_pos)) return NNPS_EINVAL;
+    const int n = static_cast<int>(prob->n);
+    const ApPlan plan = allpairs_plan(n);
+    if (static_cast<int64_t>(plan.nslice) * n > kApStaticCounts) return NNPS_EUNSUPPORTED;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return NNPS_EDEVICE;
+    int* scr = allpairs_static_scratch(ctx->device);
+    if (!scr) return NNPS_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    *nnz_out = 0;
+    if (n == 0) {
+        HIP_TRY(launch_fill_i32(reinterpret_cast<int*>(d_row_ptr), 2, 0, s));  // row_ptr[0] = 0
+        return NNPS_OK;
+    }
+    int* cnt = scr;
+    int* flag = scr + kApStaticCounts;
+    const double R2 = prob->radius * prob->radius;
+    ApBox box{};
+    for (int k = 0; k < prob->dim; ++k) {
+        box.lo[k] = prob->lo[k];
+        box.hi[k] = prob->hi[k];
+    }
+    HIP_TRY(launch_fill_i32(flag, 1, 0, s));
+    HIP_TRY(launch_allpairs_count(prob->dim, plan, d_pos, R2, box, cnt, d_row_ptr, flag, s));
+    int64_t* hp = ctx->h_pinned;
+    hp[0] = 0;
+    hp[1] = 0;
+    HIP_TRY(hipMemcpyAsync(hp, d_row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hp + 1, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (static_cast<int>(hp[1] & 0xFFFFFFFF) != 0) return NNPS_EDOMAIN;
+    *nnz_out = hp[0];
+    if (hp[0] > capacity) return NNPS_ECAPACITY;
+    HIP_TRY(launch_allpairs_fill(prob->dim, plan, d_pos, R2, cnt, d_row_ptr, d_col, d_dist, capacity,
+                                 ctx->d_flag + 1, s));
+    return NNPS_OK;
 }
 
 nnps_status nnps_cells_set_half(nnps_cells* c, int on)

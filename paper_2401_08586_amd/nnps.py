@@ -74,7 +74,8 @@ EXPORTS = ["nnps_status_str", "nnps_validate", "nnps_grid", "nnps_ctx_create", "
            "nnps_batch_build", "nnps_batch_count", "nnps_batch_fill", "nnps_batch_search",
            "nnps_batch_step", "nnps_cells_set_graphs", "nnps_batch_nnz", "nnps_batch_nnz_enqueue",
            "nnps_batch_nnz_fetch", "nnps_sph_gradient", "nnps_cells_set_half", "nnps_allpairs_search",
-           "nnps_allpairs_count", "nnps_allpairs_fill", "nnps_ctx_check"]
+           "nnps_allpairs_count", "nnps_allpairs_fill", "nnps_ctx_check",
+           "nnps_allpairs_search_noalloc"]
 
 PHASES = ["assign", "cellscan", "sort", "pack", "blocks", "unions", "count", "dcount", "rowscan", "fill",
           "longrows", "dfill"]
@@ -126,6 +127,8 @@ def load():
     lib.nnps_phase_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), P]
     lib.nnps_sph_gradient.argtypes = [P, ctypes.c_int32, I64, ctypes.c_double, P, P, P, P, P, I64, P, P, P]
     lib.nnps_ctx_check.argtypes = [P, P]
+    lib.nnps_allpairs_search_noalloc.argtypes = [P, ctypes.POINTER(Problem), P, P, P, P, I64,
+                                                 ctypes.POINTER(I64), P]
     for name in EXPORTS:
         fn = getattr(lib, name)
         if name not in ("nnps_status_str", "nnps_ctx_destroy", "nnps_cells_destroy"):
@@ -412,6 +415,23 @@ def allpairs_search(pos, lo, hi, radius, ctx: Context | None = None, stream=None
             torch.cuda.synchronize()
             ctx.close()
     return rp, col, dist
+
+
+def allpairs_search_noalloc(pos, lo, hi, radius, row_ptr, col, dist, ctx: Context, stream=None):
+    """nnps_allpairs_search_noalloc into caller-sized outputs (row_ptr [n+1] int64, col
+    int32 and dist float32 of equal length, the capacity): returns (status, nnz). The
+    library allocates nothing for it; its scratch is a static device array."""
+    import torch
+    n, dim = pos.shape
+    assert pos.is_cuda and pos.dtype == torch.float64 and pos.is_contiguous()
+    assert row_ptr.dtype == torch.int64 and row_ptr.numel() == n + 1
+    assert col.dtype == torch.int32 and dist.dtype == torch.float32 and col.numel() == dist.numel()
+    prob = make_problem(dim, n, lo, hi, radius, radius, MODE_FP64_BASELINE)
+    nnz = ctypes.c_int64(0)
+    st = ctx._lib.nnps_allpairs_search_noalloc(ctx._ctx, ctypes.byref(prob), _ptr(pos), _ptr(row_ptr), _ptr(col),
+                                               _ptr(dist), int(col.numel()), ctypes.byref(nnz),
+                                               _stream_ptr(stream))
+    return st, int(nnz.value)
 
 
 def sph_gradient(pos, f, h, row_ptr, col, vol=None, ctx: Context | None = None, want=("grad", "grad_norm"),
