@@ -1081,6 +1081,90 @@ __device__ __forceinline__ void rank_bitmap(int U, int omin, int range, uint32_t
     }
 }
 
+// Ranks by a two-level bitmap, for unions whose original indices span fewer than 2^17
+// values but too many for one bit per index (3D lattices numbered row by row: a union
+// covers a few planes of indices, sparsely). Level 1 marks which 32-index chunks of
+// [omin, omin + 2^17) hold a union index (4096 bits); the occupied chunks are numbered in
+// order by a scan of the level-1 word popcounts; level 2 keeps one 32-bit word of index
+// bits per occupied chunk; a key's rank is the set level-2 bits before it (a block scan of
+// the level-2 word popcounts, plus the bits below it in its own word). Same outputs as
+// rank_union: rank_of[e], and the original indices moved into rank order (sorig[rank]).
+// l1 (128 words), l1pre (128), l2 (UCAP words) and l2pre (UCAP) are scratch.
+template <int UCAP, int NW>
+__device__ __forceinline__ void rank_bitmap2(int U, int omin, uint32_t* l1, uint16_t* l1pre, uint32_t* l2,
+                                             uint16_t* l2pre, int* wsum, uint16_t* rank_of, int* sorig)
+{
+    constexpr int NT = 64 * NW;
+    constexpr int EPT = UCAP / NT;
+    static_assert(NT >= 128 && UCAP % NT == 0, "the level-1 words fit one pass of the block");
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (tid < 128) l1[tid] = 0u;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) l2[tid * EPT + i] = 0u;
+    __syncthreads();
+    int og[EPT], ch[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * NT;
+        og[i] = e < U ? sorig[e] - omin : 0;
+        ch[i] = og[i] >> 5;
+        if (e < U) atomicOr(&l1[ch[i] >> 5], 1u << (ch[i] & 31));
+    }
+    __syncthreads();
+    // number the occupied chunks: exclusive scan of the 128 level-1 popcounts (waves 0, 1)
+    {
+        const int c = tid < 128 ? __builtin_popcount(l1[tid]) : 0;
+        int tot;
+        const int ex = wave_excl_scan_i32(c, &tot);
+        if (lane == 0 && wv < 2) wsum[wv] = tot;
+        __syncthreads();
+        if (tid < 128) l1pre[tid] = static_cast<uint16_t>(ex + (wv == 1 ? wsum[0] : 0));
+    }
+    __syncthreads();
+    int slot[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * NT;
+        const int w1 = ch[i] >> 5;
+        slot[i] = l1pre[w1] + __builtin_popcount(l1[w1] & ((1u << (ch[i] & 31)) - 1u));
+        if (e < U) atomicOr(&l2[slot[i]], 1u << (og[i] & 31));
+    }
+    __syncthreads();
+    // exclusive scan of the level-2 popcounts: thread t takes slots [t EPT, t EPT + EPT)
+    {
+        int c[EPT], sum = 0;
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            c[i] = __builtin_popcount(l2[tid * EPT + i]);
+            sum += c[i];
+        }
+        int tot;
+        int run = wave_excl_scan_i32(sum, &tot);
+        if (lane == 0) wsum[wv] = tot;
+        __syncthreads();
+        for (int q = 0; q < wv; ++q) run += wsum[q];
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            l2pre[tid * EPT + i] = static_cast<uint16_t>(run);
+            run += c[i];
+        }
+    }
+    __syncthreads();
+    int rk[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * NT;
+        rk[i] = l2pre[slot[i]] + __builtin_popcount(l2[slot[i]] & ((1u << (og[i] & 31)) - 1u));
+        if (e < U) rank_of[e] = static_cast<uint16_t>(rk[i]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * NT;
+        if (e < U) sorig[rk[i]] = og[i] + omin;
+    }
+}
+
 __device__ __forceinline__ int wave_min_i32(int v)
 {
 #pragma unroll
@@ -1209,9 +1293,17 @@ k_fill(SearchArgs a)
     };
     // unions spanning few original indices are ranked by bitmap (scratch after the rank table)
     constexpr int BW = (kShared - C::UCAP * 2) / 6;
+    // the two-level bitmap's tables after the rank table: level 1 (512 B) and its prefixes
+    // (256 B), level 2 (4 UCAP B) and its prefixes (2 UCAP B)
+    constexpr bool kTwoLevel = C::UCAP * 2 + 768 + C::UCAP * 6 <= kShared;
     if (static_cast<unsigned>(omax - omin) < 32u * BW)
         rank_bitmap<C::UCAP, NW, BW>(U, omin, omax - omin + 1, reinterpret_cast<uint32_t*>(smem + C::UCAP * 2),
                                      reinterpret_cast<uint16_t*>(smem + C::UCAP * 2 + BW * 4), swsum, rank_of, sorig);
+    else if (kTwoLevel && static_cast<unsigned>(omax - omin) < (1u << 17))
+        rank_bitmap2<C::UCAP, NW>(U, omin, reinterpret_cast<uint32_t*>(smem + C::UCAP * 2),
+                                  reinterpret_cast<uint16_t*>(smem + C::UCAP * 2 + 512),
+                                  reinterpret_cast<uint32_t*>(smem + C::UCAP * 2 + 768),
+                                  reinterpret_cast<uint16_t*>(smem + C::UCAP * 6 + 768), swsum, rank_of, sorig);
     else if (Q <= 64) rank_union<C::UCAP, C::SHIFT, NW, 1>(U, Q, packed, omin, key_of, skeys, rank_of, sorig);
     else if (Q <= 128) rank_union<C::UCAP, C::SHIFT, NW, 2>(U, Q, packed, omin, key_of, skeys, rank_of, sorig);
     else rank_union<C::UCAP, C::SHIFT, NW, 4>(U, Q, packed, omin, key_of, skeys, rank_of, sorig);
