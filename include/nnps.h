@@ -248,6 +248,34 @@ nnps_status nnps_batch_nnz(nnps_cells *cells, int64_t *h_nnz, void *stream);
 nnps_status nnps_batch_nnz_enqueue(nnps_cells *cells, void *stream);
 nnps_status nnps_batch_nnz_fetch(nnps_cells *cells, int64_t *h_nnz);
 
+/* ---- Incremental update between time steps -----------------------------------------
+ * After the particles of a built structure moved, bring the structure up to date without
+ * rebuilding it (Mixed-precision SPH framework section: the relative-coordinate update of
+ * Eq. 8 and the cell migration of Eq. 9, Fig. 6). The structure works on the position
+ * arrays of its last build (nnps_cells_build / nnps_batch_build / nnps_batch_step), which
+ * must still be valid. d_disp is NULL, or a host array of nsets entries, each NULL or a
+ * device array [n][dim] of float64 displacements of that set:
+ *   - with a displacement array, the call advances the positions in place,
+ *     pos[i][k] = pos[i][k] + disp[i][k] (one binary64 addition each; the caller's
+ *     position array is written);
+ *   - without one, the caller has already moved the positions in place.
+ * Either way each particle's fixed-point position, cell and relative coordinate are
+ * recomputed from its binary64 position (so no rounding error builds up from step to
+ * step), particles whose cell is unchanged keep their order in it, particles that changed
+ * cell are removed from the old one and appended to the new one, and cell starts, the
+ * sorted arrays and the work blocks are repaired. The result of the count and fill that
+ * follow is exactly that of a fresh build on the moved positions (same row_ptr, col and
+ * dist). Positions outside [lo, hi] are reported as NNPS_EDOMAIN by the next
+ * synchronising call. NNPS_EORDER if the structure was never built. Asynchronous. */
+nnps_status nnps_cells_update(nnps_ctx *ctx, nnps_cells *cells, const double *const *d_disp, void *stream);
+/* Update + count + fill without waiting, as nnps_batch_step does for build + count + fill
+ * (outputs per set, capacities known in advance). With graphs on and a non-null stream the
+ * sequence is captured once and replayed while the grids, the tuning and the library's
+ * buffers stay the same; displacement and output pointers may change between replays. */
+nnps_status nnps_batch_update_step(nnps_ctx *ctx, nnps_cells *cells, const double *const *d_disp,
+                                   int64_t *const *d_row_ptr, int32_t *const *d_col, float *const *d_dist,
+                                   const int64_t *capacity, void *stream);
+
 /* ---- All-list search for small sets ------------------------------------------------
  * Every particle tested against every other (SPH method section, Fig. 3a), in binary64
  * with the cell-list paths' predicate, so row_ptr, col and dist are bit-identical to the
@@ -320,6 +348,18 @@ nnps_status nnps_sph_gradient(nnps_ctx *ctx, int32_t dim, int64_t n, double h, c
                               const double *d_f, const double *d_vol, const int64_t *d_row_ptr,
                               const int32_t *d_col, int64_t ncol, double *d_grad, double *d_grad_norm,
                               void *stream);
+
+/* ---- Measurement helper (not part of the search) -------------------------------------
+ * The VALU issue rate device `device` reaches on long runs of independent vector
+ * instructions of one kind: kind 0 packed FP16 fused multiply-add (two FP16 lanes per
+ * instruction, the search's test), 1 FP32 fused multiply-add, 2 32-bit integer add and
+ * xor. Every SIMD gets several wavefronts; one launch is timed with HIP events on the
+ * null stream (the call waits for it). *rate receives wave64 instructions per second;
+ * *insts_per_wave (may be NULL) the timed loop's VALU instructions per wavefront, for
+ * checking against a profiler's instruction count. It allocates and frees 64 bytes of
+ * device memory. NNPS_EINVAL for a kind outside 0..2 or a NULL rate, NNPS_EDEVICE if a
+ * HIP call fails. */
+nnps_status nnps_probe_valu_rate(int32_t device, int32_t kind, double *rate, int64_t *insts_per_wave);
 
 /* Phases timed when profiling is on, in launch order. */
 enum {

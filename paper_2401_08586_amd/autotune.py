@@ -128,7 +128,7 @@ def stencil_sizes(ps_list, sample: int = 20000, seed: int = 0):
 
 
 def tune(ctx, sets, pss=None, mode: int = 0, steps: int = 3, warmup: int = 1, space=None, cache: Cache | None = None,
-         use_cache: bool = True, log=None):
+         use_cache: bool = True, log=None, sweeps: int = 2):
     """Pick nnps_tuning for `sets` (list of (pos, lo, hi, cell_size, radius) device sets);
     `pss` (workloads.ParticleSet list of the same sets) keys the cache. Leaves the chosen
     tuning set on `ctx` and returns (params, ms per step, evaluations)."""
@@ -174,7 +174,7 @@ def tune(ctx, sets, pss=None, mode: int = 0, steps: int = 3, warmup: int = 1, sp
         return ms
 
     try:
-        best, ms, evals = coordinate_descent(cost, space=space)
+        best, ms, evals = coordinate_descent(cost, space=space, sweeps=sweeps)
     finally:
         cells.close()
     ctx.set_tuning(**best)

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnnps.so")
-SOURCES = ["capi.hip", "build_kernels.hip", "search_kernels.hip", "sph_kernels.hip", "allpairs_kernels.hip"]
+SOURCES = ["capi.hip", "build_kernels.hip", "search_kernels.hip", "sph_kernels.hip", "allpairs_kernels.hip",
+           "probe_kernels.hip"]
 ARCH = os.environ.get("NNPS_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -30,7 +30,29 @@ int64_t scan_partials_needed(int64_t m);
 int radix_tiles(int n);
 size_t radix_table_entries(int n);
 hipError_t launch_pack(const Launch& L, const uint32_t* skey, const int* perm, const double* X, ushort4* q4,
-                       double* spos, float4* rq, int* inv, hipStream_t st);
+                       double* spos, float4* rq, int* inv, hipStream_t st, uint32_t* skey_out = nullptr,
+                       int* perm_out = nullptr);
+
+// Incremental update of a built structure (see k_upd_move): device tables of one update.
+struct Update {
+    uint32_t* knew;           // [ntot] new cell key by old sorted position
+    unsigned long long* mig;  // [ceil(ntot / 64)] bit s: the particle at old position s changed cell
+    int* leave;               // [ncell_tot + 1] migrants out of each cell (zeroed before the update)
+    int* arrive;              // [ncell_tot + 1] migrants into each cell (zeroed before the update)
+    int* aslot;               // [ntot] a migrant's arrival slot in its new cell
+    int* cs_old;              // [ncell_tot + 1] cell starts before the update
+    uint32_t* skey2;          // [ntot] new order: cell keys
+    int* perm2;               // [ntot] new order: particle indices
+};
+// U1: move (when the set has displacements), fixed point, cells, migrant flags and counts.
+hipError_t launch_update_move(const Launch& L, const uint32_t* skey, const int* perm, double* X, const Update& u,
+                              int* err, hipStream_t st);
+// U2: new cell occupancies and starts (cell_start is rewritten; the old one goes to cs_old).
+hipError_t launch_update_cells(const Launch& L, int* cell_start, int* cnt, const Update& u, int64_t* partial,
+                               hipStream_t st);
+// U3: every particle's new sorted position (into skey2 / perm2).
+hipError_t launch_update_place(const Launch& L, const uint32_t* skey, const int* perm, const int* cell_start,
+                               const Update& u, hipStream_t st);
 hipError_t launch_blocks(const Launch& L, const int* cell_start, const int* wdense, int* boff, int* bstart, int* bset,
                          int64_t* partial, hipStream_t st);
 

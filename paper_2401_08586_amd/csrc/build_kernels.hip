@@ -381,12 +381,18 @@ template <int DIM>
 __global__ void __launch_bounds__(256)
 k_pack(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nsets, int ntot,
        const uint32_t* __restrict__ skey, const int* __restrict__ perm, const double* __restrict__ X,
-       ushort4* __restrict__ q4, double* __restrict__ spos, float4* __restrict__ rq, int* __restrict__ inv)
+       ushort4* __restrict__ q4, double* __restrict__ spos, float4* __restrict__ rq, int* __restrict__ inv,
+       uint32_t* __restrict__ skey_out, int* __restrict__ perm_out)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= ntot) return;
     const int o = perm[p];
     if (inv) inv[o] = p;
+    // the incremental update places into a second pair of arrays: copied back here
+    if (perm_out) {
+        perm_out[p] = o;
+        skey_out[p] = skey[p];
+    }
     auto pack = [&](const SetDesc& sd) {
         const Frame& fr = sd.fr;
         if (spos) {
@@ -418,6 +424,122 @@ k_pack(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nset
     const int s0 = __builtin_amdgcn_readfirstlane(s);
     if (__all(s == s0)) pack(sets[s0]);
     else pack(sets[s]);
+}
+
+// ---------------------------------------------------------------------------
+// Incremental update after the particles moved (Mixed-precision SPH framework section,
+// Eq. 8-9, Fig. 6): a particle's relative coordinate advances by its displacement, and a
+// particle leaving its cell migrates to the new one. Here the advance is made on the
+// binary64 position (p = p + dp, one rounding, written back when a displacement array is
+// given) and the fixed-point position and cell are recomputed from it exactly as the
+// assignment computes them, so the relative coordinate carries no error from earlier
+// steps and the structure equals a fresh build's up to the order inside cells. Only
+// migrants are re-binned: the sorted order is kept, stayers keep their relative order in
+// their cell, and each cell's migrants are appended after its stayers.
+
+// U1 (per sorted position s): move, recompute X and the cell; bit s of `mig` says the
+// cell changed. A migrant counts out of its old cell and takes an arrival slot in its
+// new one; every particle's new cell key is kept by sorted position (knew).
+template <int DIM>
+__global__ void __launch_bounds__(256)
+k_upd_move(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nsets, int ntot,
+           const uint32_t* __restrict__ skey, const int* __restrict__ perm, double* __restrict__ X,
+           uint32_t* __restrict__ knew, unsigned long long* __restrict__ mig, int* __restrict__ leave,
+           int* __restrict__ arrive, int* __restrict__ aslot, int* __restrict__ err)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= ntot) return;  // the active lanes of a wavefront are a prefix of it
+    const uint32_t kold = skey[s];
+    const int o = perm[s];
+    bool bad = false;
+    auto cell_of = [&](const SetDesc& sd) -> uint32_t {
+        const Frame& fr = sd.fr;
+        const int li = o - sd.poff;
+        double* pos = const_cast<double*>(sd.pos);  // the caller lent them for the update
+        int64_t c[3] = {0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            const size_t at = static_cast<size_t>(li) * DIM + k;
+            double p = pos[at];
+            if (sd.disp) {
+                p = __dadd_rn(p, sd.disp[at]);
+                pos[at] = p;
+            }
+            if (!(p >= fr.lo[k] && p <= fr.hi[k])) {
+                bad = true;
+                p = fr.lo[k];
+            }
+            const double d = __dsub_rn(p, fr.lo[k]);
+            const double t = rint(__dmul_rn(d, fr.s));
+            X[static_cast<size_t>(o) * x_stride(DIM) + k] = t;
+            c[k] = static_cast<int64_t>(t) >> fr.F;
+        }
+        return static_cast<uint32_t>(sd.coff + c[0] + fr.nc[0] * (c[1] + fr.nc[1] * c[2]));
+    };
+    const int st = find_set(coffs, nsets, static_cast<int>(kold));
+    const int s0 = __builtin_amdgcn_readfirstlane(st);
+    const uint32_t kn = __all(st == s0) ? cell_of(sets[s0]) : cell_of(sets[st]);
+    knew[s] = kn;
+    const bool moved = kn != kold;
+    const unsigned long long bal = __ballot(moved);
+    if ((threadIdx.x & 63) == 0) mig[s >> 6] = bal;  // s is the wavefront's first position
+    if (moved) {
+        atomicAdd(&leave[kold], 1);
+        aslot[s] = atomicAdd(&arrive[kn], 1);
+    }
+    if (bad) atomicOr(err, kErrDomain);
+}
+
+// U2 (per cell, and one more thread for the end): the new occupancy, old count - leavers
+// + arrivals, as the scan's input, and a copy of the old cell starts (the scan writes the
+// new ones in place).
+__global__ void __launch_bounds__(256)
+k_upd_counts(int ncell, const int* __restrict__ cell_start, const int* __restrict__ leave,
+             const int* __restrict__ arrive, int* __restrict__ cnt, int* __restrict__ cs_old)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > ncell) return;
+    const int a = cell_start[c];
+    cs_old[c] = a;
+    if (c < ncell) cnt[c] = cell_start[c + 1] - a - leave[c] + arrive[c];
+}
+
+// Set bits of `mig` at positions [a, b).
+__device__ __forceinline__ int mig_bits(const unsigned long long* __restrict__ mig, int a, int b)
+{
+    int n = 0;
+    for (int w = a >> 6; (w << 6) < b; ++w) {
+        unsigned long long m = mig[w];
+        const int lo = a - (w << 6), hi = b - (w << 6);  // bit range of this word, clipped below
+        if (lo > 0) m &= ~0ull << lo;
+        if (hi < 64) m &= (1ull << hi) - 1ull;
+        n += __popcll(m);
+    }
+    return n;
+}
+
+// U3 (per old sorted position s): the particle's new sorted position. A stayer keeps its
+// rank among the stayers of its cell (its old offset less the leavers before it); a
+// migrant goes after the stayers of its new cell, at its arrival slot.
+__global__ void __launch_bounds__(256)
+k_upd_place(int ntot, const uint32_t* __restrict__ skey, const int* __restrict__ perm,
+            const uint32_t* __restrict__ knew, const unsigned long long* __restrict__ mig,
+            const int* __restrict__ leave, const int* __restrict__ aslot, const int* __restrict__ cs_old,
+            const int* __restrict__ cs_new, uint32_t* __restrict__ skey2, int* __restrict__ perm2)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= ntot) return;
+    const uint32_t kold = skey[s], kn = knew[s];
+    int at;
+    if (kn == kold) {
+        const int a = cs_old[kold];
+        const int lb = leave[kold] > 0 ? mig_bits(mig, a, s) : 0;
+        at = cs_new[kold] + (s - a) - lb;
+    } else {
+        at = cs_new[kn] + (cs_old[kn + 1] - cs_old[kn] - leave[kn]) + aslot[s];
+    }
+    skey2[at] = kn;
+    perm2[at] = perm[s];
 }
 
 // ---------------------------------------------------------------------------
@@ -738,14 +860,48 @@ hipError_t radix_sort_kv_dev(int n, const int* ndev, int keybits, uint32_t* k0, 
 size_t radix_table_entries(int n) { return static_cast<size_t>(radix_tiles(n)) << kRsMaxBits; }
 
 hipError_t launch_pack(const Launch& L, const uint32_t* skey, const int* perm, const double* X, ushort4* q4,
-                       double* spos, float4* rq, int* inv, hipStream_t st)
+                       double* spos, float4* rq, int* inv, hipStream_t st, uint32_t* skey_out, int* perm_out)
 {
     if (L.ntot == 0) return hipSuccess;
     const dim3 g((L.ntot + 255) / 256), b(256);
     if (L.dim == 2)
-        hipLaunchKernelGGL(k_pack<2>, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, perm, X, q4, spos, rq, inv);
+        hipLaunchKernelGGL(k_pack<2>, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, perm, X, q4, spos, rq, inv,
+                           skey_out, perm_out);
     else
-        hipLaunchKernelGGL(k_pack<3>, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, perm, X, q4, spos, rq, inv);
+        hipLaunchKernelGGL(k_pack<3>, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, perm, X, q4, spos, rq, inv,
+                           skey_out, perm_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_move(const Launch& L, const uint32_t* skey, const int* perm, double* X, const Update& u,
+                              int* err, hipStream_t st)
+{
+    if (L.ntot == 0) return hipSuccess;
+    const dim3 g((L.ntot + 255) / 256), b(256);
+    if (L.dim == 2)
+        hipLaunchKernelGGL(k_upd_move<2>, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, perm, X, u.knew, u.mig,
+                           u.leave, u.arrive, u.aslot, err);
+    else
+        hipLaunchKernelGGL(k_upd_move<3>, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, perm, X, u.knew, u.mig,
+                           u.leave, u.arrive, u.aslot, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_cells(const Launch& L, int* cell_start, int* cnt, const Update& u, int64_t* partial,
+                               hipStream_t st)
+{
+    const int nc = L.ncell_tot;
+    hipLaunchKernelGGL(k_upd_counts, dim3((nc + 256) / 256), dim3(256), 0, st, nc, cell_start, u.leave, u.arrive,
+                       cnt, u.cs_old);
+    return scan_exclusive<int, int>(cnt, nc, cell_start, partial, st);
+}
+
+hipError_t launch_update_place(const Launch& L, const uint32_t* skey, const int* perm, const int* cell_start,
+                               const Update& u, hipStream_t st)
+{
+    if (L.ntot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_upd_place, dim3((L.ntot + 255) / 256), dim3(256), 0, st, L.ntot, skey, perm, u.knew,
+                       u.mig, u.leave, u.aslot, u.cs_old, cell_start, u.skey2, u.perm2);
     return hipGetLastError();
 }
 

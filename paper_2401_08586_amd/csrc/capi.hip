@@ -289,6 +289,9 @@ struct nnps_cells {
     int64_t dcap = 0;
     int* ulist = nullptr;
     DevBuf usz, wdense, uoff, nsl, unit_off, ucell, dn, ecnt, epos, uk0, uk1, uv0, uv1, inv, ucount, dstats, dseen;
+    // incremental update (nnps_cells_update): see Update
+    DevBuf umig, uleave, uarrive, ucs_old, uskey2, uperm2;
+    GraphCache ugraph;  // a captured update + count + fill sequence
 };
 
 #define HIP_TRY(x)                                  \
@@ -528,6 +531,8 @@ nnps_status prepare(nnps_ctx* ctx, nnps_cells* c, int nsets, const nnps_problem*
         {&c->inv, c->dense ? nn * 4 : 0}, {&c->ucount, c->dense ? size_t(4) : size_t(0)},
         {&c->dstats, c->dense ? static_cast<size_t>(c->dgrid) * kDenseStats * 8 : 0},
         {&c->dseen, c->dense ? size_t(4) : size_t(0)},
+        {&c->umig, (nn + 63) / 64 * 8}, {&c->uleave, (nc + 1) * 4}, {&c->uarrive, (nc + 1) * 4},
+        {&c->ucs_old, (nc + 1) * 4}, {&c->uskey2, nn * 4}, {&c->uperm2, nn * 4},
     };
     for (auto& q : need) {
         if (q.bytes == 0) continue;
@@ -539,6 +544,52 @@ nnps_status prepare(nnps_ctx* ctx, nnps_cells* c, int nsets, const nnps_problem*
     c->built = false;
     c->counted = false;
     return NNPS_OK;
+}
+
+nnps_status enqueue_build_tail(nnps_cells* c, hipStream_t s);
+
+Update update_of(nnps_cells* c)
+{
+    Update u{};
+    u.knew = c->k0.as<uint32_t>();  // the build's unsorted keys and slots are free after it
+    u.aslot = c->v1.as<int>();
+    u.mig = c->umig.as<unsigned long long>();
+    u.leave = c->uleave.as<int>();
+    u.arrive = c->uarrive.as<int>();
+    u.cs_old = c->ucs_old.as<int>();
+    u.skey2 = c->uskey2.as<uint32_t>();
+    u.perm2 = c->uperm2.as<int>();
+    return u;
+}
+
+// The stream-ordered incremental update: move and re-bin (the assignment phase), new
+// cell starts (cell scan), new sorted positions (sort), pack (and copy the new order
+// back), then the same dense tables and blocks as a build.
+nnps_status enqueue_update(nnps_cells* c, hipStream_t s)
+{
+    const Launch L = launch_of(c);
+    PhaseTimer& tm = c->timer;
+    const Update u = update_of(c);
+    const int64_t nc1 = static_cast<int64_t>(c->ncell_tot) + 1;
+    HIP_TRY(launch_fill_i32(u.leave, nc1, 0, s));
+    HIP_TRY(launch_fill_i32(u.arrive, nc1, 0, s));
+    HIP_TRY(launch_fill_i32(c->err.as<int>(), 1, 0, s));
+    tm.begin(NNPS_PHASE_ASSIGN, s);
+    HIP_TRY(launch_update_move(L, c->skey, c->perm, c->X.as<double>(), u, c->err.as<int>(), s));
+    tm.end(NNPS_PHASE_ASSIGN, s);
+    tm.begin(NNPS_PHASE_CELLSCAN, s);
+    HIP_TRY(launch_update_cells(L, c->cell_start.as<int>(), c->cell_count.as<int>(), u, c->partial.as<int64_t>(), s));
+    tm.end(NNPS_PHASE_CELLSCAN, s);
+    tm.begin(NNPS_PHASE_SORT, s);
+    HIP_TRY(launch_update_place(L, c->skey, c->perm, c->cell_start.as<int>(), u, s));
+    tm.end(NNPS_PHASE_SORT, s);
+    tm.begin(NNPS_PHASE_PACK, s);
+    HIP_TRY(launch_pack(L, u.skey2, u.perm2, c->X.as<double>(), c->q4.as<ushort4>(),
+                        uses_spos(c->mode) ? c->spos.as<double>() : nullptr,
+                        c->mode == NNPS_MODE_FP32_RCLL ? c->rq.as<float4>() : nullptr,
+                        c->dense ? c->inv.as<int>() : nullptr, s, c->skey, c->perm));
+    tm.end(NNPS_PHASE_PACK, s);
+    return enqueue_build_tail(c, s);
 }
 
 // The stream-ordered build: assign, cell starts, sort, pack, blocks.
@@ -570,6 +621,15 @@ nnps_status enqueue_build(nnps_cells* c, hipStream_t s)
                         c->mode == NNPS_MODE_FP32_RCLL ? c->rq.as<float4>() : nullptr,
                         c->dense ? c->inv.as<int>() : nullptr, s));
     tm.end(NNPS_PHASE_PACK, s);
+    return enqueue_build_tail(c, s);
+}
+
+// After the cells and the sorted arrays are in place (build or update): the dense-cell
+// tables and the work blocks.
+nnps_status enqueue_build_tail(nnps_cells* c, hipStream_t s)
+{
+    const Launch L = launch_of(c);
+    PhaseTimer& tm = c->timer;
     // The dense-cell path runs unless the last synchronising call saw no dense cell; the
     // stencil sizes are computed either way, so a change is seen at the next such call.
     c->dense_active = c->dense && c->dense_seen != 0;
@@ -815,10 +875,12 @@ void nnps_cells_destroy(nnps_cells* c)
                      &c->table, &c->partial, &c->stats, &c->blk_stats, &c->cbits, &c->err, &c->heavy,
                      &c->nheavy, &c->rowg, &c->nnz, &c->sink, &c->usz, &c->wdense, &c->uoff, &c->nsl, &c->unit_off,
                      &c->ucell, &c->dn, &c->ecnt, &c->epos, &c->uk0, &c->uk1, &c->uv0, &c->uv1, &c->inv,
-                     &c->ucount, &c->dstats, &c->dseen};
+                     &c->ucount, &c->dstats, &c->dseen, &c->umig, &c->uleave, &c->uarrive, &c->ucs_old,
+                     &c->uskey2, &c->uperm2};
     for (DevBuf* b : all) b->release();
     c->timer.release();
     c->graph.reset();
+    c->ugraph.reset();
     if (c->upload_done) (void)hipEventDestroy(c->upload_done);
     if (c->h_sets) (void)hipHostFree(c->h_sets);
     if (c->h_offs) (void)hipHostFree(c->h_offs);
@@ -1157,6 +1219,95 @@ nnps_status nnps_batch_step(nnps_ctx* ctx, nnps_cells* c, int32_t nsets, const n
         c->graph.sig = sig;
     }
     HIP_TRY(hipGraphLaunch(c->graph.exec, s));
+    c->built = true;
+    c->counted = true;
+    return NNPS_OK;
+}
+
+namespace {
+
+// Point the set table at this update's displacements (or none) and queue its upload.
+nnps_status stage_update(nnps_cells* c, const double* const* d_disp, int64_t* const* row_ptr, int32_t* const* col,
+                         float* const* dist, const int64_t* capacity, hipStream_t s)
+{
+    nnps_status st = wait_upload(c);
+    if (st != NNPS_OK) return st;
+    for (int k = 0; k < c->nsets; ++k) c->h_sets[k].disp = d_disp ? d_disp[k] : nullptr;
+    set_outputs(c, row_ptr, col, dist, capacity);
+    return upload(c, false, s);
+}
+
+}  // namespace
+
+nnps_status nnps_cells_update(nnps_ctx* ctx, nnps_cells* c, const double* const* d_disp, void* stream)
+{
+    if (!ctx || !c || c->ctx != ctx) return NNPS_EINVAL;
+    if (!c->built) return NNPS_EORDER;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return NNPS_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    nnps_status st = stage_update(c, d_disp, nullptr, nullptr, nullptr, nullptr, s);
+    if (st != NNPS_OK) return st;
+    return enqueue_update(c, s);
+}
+
+nnps_status nnps_batch_update_step(nnps_ctx* ctx, nnps_cells* c, const double* const* d_disp,
+                                   int64_t* const* d_row_ptr, int32_t* const* d_col, float* const* d_dist,
+                                   const int64_t* capacity, void* stream)
+{
+    if (!ctx || !c || c->ctx != ctx || !d_row_ptr || !d_col || !d_dist || !capacity) return NNPS_EINVAL;
+    if (!c->built) return NNPS_EORDER;
+    for (int k = 0; k < c->nsets; ++k) {
+        if (!d_row_ptr[k] || capacity[k] < 0) return NNPS_EINVAL;
+        if (capacity[k] > 0 && (!d_col[k] || !d_dist[k])) return NNPS_EINVAL;
+    }
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return NNPS_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    nnps_status st = stage_update(c, d_disp, d_row_ptr, d_col, d_dist, capacity, s);
+    if (st != NNPS_OK) return st;
+    const bool graphs = c->use_graphs && s != nullptr && !c->timer.on;
+    if (!graphs) {
+        if ((st = enqueue_update(c, s)) != NNPS_OK) return st;
+        if ((st = enqueue_count(c, s)) != NNPS_OK) return st;
+        return enqueue_fill(c, s);
+    }
+    // the graph depends on the grids, the device buffers, the tuning and the dense plan;
+    // positions, displacements and outputs travel in the uploaded set table
+    std::vector<unsigned char> sig(sizeof(Frame) * c->nsets + sizeof(uint64_t) + sizeof(nnps_tuning) + 8);
+    unsigned char* q = sig.data();
+    memcpy(q, c->frames.data(), sizeof(Frame) * c->nsets);
+    q += sizeof(Frame) * c->nsets;
+    memcpy(q, &c->buf_gen, sizeof(uint64_t));
+    q += sizeof(uint64_t);
+    memcpy(q, &ctx->tuning, sizeof(nnps_tuning));
+    q += sizeof(nnps_tuning);
+    memcpy(q, &c->nsets, 4);
+    q += 4;
+    const int plan = (c->dense && c->dense_seen != 0 ? 1 : 0) | (c->half ? 2 : 0);
+    memcpy(q, &plan, 4);
+    if (!c->ugraph.exec || c->ugraph.sig != sig) {
+        c->ugraph.reset();
+        hipGraph_t graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        nnps_status cst = enqueue_update(c, s);
+        if (cst == NNPS_OK) cst = enqueue_count(c, s);
+        if (cst == NNPS_OK) cst = enqueue_fill(c, s);
+        const hipError_t ee = hipStreamEndCapture(s, &graph);
+        if (cst != NNPS_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return cst;
+        }
+        if (ee != hipSuccess) return NNPS_EDEVICE;
+        const hipError_t ie = hipGraphInstantiate(&c->ugraph.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+            c->ugraph.exec = nullptr;
+            return NNPS_EDEVICE;
+        }
+        c->ugraph.sig = sig;
+    }
+    HIP_TRY(hipGraphLaunch(c->ugraph.exec, s));
     c->built = true;
     c->counted = true;
     return NNPS_OK;

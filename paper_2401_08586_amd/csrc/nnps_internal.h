@@ -80,6 +80,7 @@ struct SetDesc {
     Frame fr;                // fr.n = this set's particle count
     int poff, coff;          // first global particle / cell index
     const double* pos;       // caller's positions [n][dim] (float64)
+    const double* disp;      // incremental update: displacements [n][dim] added to pos, or null
     int64_t* row_ptr;        // caller's CSR row pointers [n + 1]
     int32_t* col;            // caller's CSR column indices (set-local)
     float* dist;             // caller's CSR distances

@@ -75,7 +75,8 @@ EXPORTS = ["nnps_status_str", "nnps_validate", "nnps_grid", "nnps_ctx_create", "
            "nnps_batch_step", "nnps_cells_set_graphs", "nnps_batch_nnz", "nnps_batch_nnz_enqueue",
            "nnps_batch_nnz_fetch", "nnps_sph_gradient", "nnps_cells_set_half", "nnps_allpairs_search",
            "nnps_allpairs_count", "nnps_allpairs_fill", "nnps_ctx_check",
-           "nnps_allpairs_search_noalloc"]
+           "nnps_allpairs_search_noalloc", "nnps_cells_update", "nnps_batch_update_step",
+           "nnps_probe_valu_rate"]
 
 PHASES = ["assign", "cellscan", "sort", "pack", "blocks", "unions", "count", "dcount", "rowscan", "fill",
           "longrows", "dfill"]
@@ -129,6 +130,10 @@ def load():
     lib.nnps_ctx_check.argtypes = [P, P]
     lib.nnps_allpairs_search_noalloc.argtypes = [P, ctypes.POINTER(Problem), P, P, P, P, I64,
                                                  ctypes.POINTER(I64), P]
+    lib.nnps_cells_update.argtypes = [P, P, P, P]
+    lib.nnps_batch_update_step.argtypes = [P, P, P, P, P, P, P, P]
+    lib.nnps_probe_valu_rate.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(I64)]
     for name in EXPORTS:
         fn = getattr(lib, name)
         if name not in ("nnps_status_str", "nnps_ctx_destroy", "nnps_cells_destroy"):
@@ -243,6 +248,7 @@ class Cells:
         _check(self._lib.nnps_cells_create(ctx._ctx, ctypes.byref(h)), "nnps_cells_create")
         self._h = h
         self.n = 0
+        self.nsets = 0
         self._pos = None
 
     def close(self):
@@ -259,6 +265,7 @@ class Cells:
         _check(self._lib.nnps_cells_build(self.ctx._ctx, self._h, ctypes.byref(prob), _ptr(pos),
                                           _stream_ptr(stream)), "nnps_cells_build")
         self.n = n
+        self.nsets = 1
         self._pos = pos  # keep alive: the recheck reads it
         return self
 
@@ -308,6 +315,34 @@ class Cells:
         self.nsets = len(sets)
         self._pos = [t[0] for t in sets]
 
+    def update(self, disp=None, stream=None):
+        """Incremental update after the particles moved (nnps_cells_update). disp: None (the
+        positions of the last build were moved in place by the caller), a float64 CUDA
+        tensor [n, dim] for a single-set structure, or a list with one tensor or None per
+        set; given displacements are added to the positions in place."""
+        _check(self._lib.nnps_cells_update(self.ctx._ctx, self._h, self._disp_array(disp), _stream_ptr(stream)),
+               "nnps_cells_update")
+        return self
+
+    def batch_update_step(self, row_ptrs, cols, dists, disp=None, stream=None):
+        """Update + count + fill without waiting (nnps_batch_update_step); outputs must
+        already be large enough."""
+        cap = (ctypes.c_int64 * len(cols))(*[c.numel() for c in cols])
+        _check(self._lib.nnps_batch_update_step(self.ctx._ctx, self._h, self._disp_array(disp), _ptr_array(row_ptrs),
+                                                _ptr_array(cols), _ptr_array(dists), cap, _stream_ptr(stream)),
+               "nnps_batch_update_step")
+
+    def _disp_array(self, disp):
+        import torch
+        if disp is None:
+            return None
+        if isinstance(disp, torch.Tensor):
+            disp = [disp]
+        for d in disp:
+            assert d is None or (d.is_cuda and d.dtype == torch.float64 and d.is_contiguous())
+        self._disp = disp  # keep alive until the caller synchronises
+        return _ptr_array([d if d is not None else None for d in disp])
+
     def batch_nnz(self, stream=None, check: bool = True):
         """Each set's nnz of the last count (waits for the stream). With check=False returns
         (nnz list, status) instead of raising on a device-reported error."""
@@ -353,6 +388,19 @@ class Cells:
         code = self._lib.nnps_stats_get(self._h, ctypes.byref(st), _stream_ptr(stream))
         _check(code, "nnps_stats_get")
         return st.as_dict()
+
+
+PROBE_KINDS = {"pk_fma_f16": 0, "fma_f32": 1, "int32": 2}
+
+
+def probe_valu_rate(kind: str, device: int = 0):
+    """nnps_probe_valu_rate: (wave64 VALU instructions per second, instructions per wave)
+    on long runs of independent instructions of `kind` (a key of PROBE_KINDS)."""
+    rate = ctypes.c_double(0.0)
+    per = ctypes.c_int64(0)
+    _check(load().nnps_probe_valu_rate(int(device), PROBE_KINDS[kind], ctypes.byref(rate), ctypes.byref(per)),
+           "nnps_probe_valu_rate")
+    return rate.value, per.value
 
 
 def _ptr_array(tensors):

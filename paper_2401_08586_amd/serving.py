@@ -1,23 +1,26 @@
 """Serving loop: neighbour-search requests from many concurrent simulations on one GPU.
 
 Each simulation keeps its particles, its CSR outputs and its sorted cell structure
-resident in HBM between time steps; a request asks for one step (the particles move, then
-a rebuild + search of that simulation). Requests are served continuously: whenever one
-of the stream slots is free, the oldest queued request whose simulation is idle starts
-on it, so requests that arrive while others run are admitted as slots and memory free
-up, and their work overlaps on the device. Each step of a simulation replays the HIP
-graph its cell structure captured on the first step (one launch per request). With
-per_sim=False the requests of a slot are instead batched (up to a particle budget) into
-one library batch call on a structure per slot. Simulations are admitted into HBM by a
-byte budget: before a request runs, idle simulations are evicted (positions to pinned
-host memory, outputs and cell structure freed) in least-recently-used order until it
-fits.
+resident in HBM between time steps; a request asks for one step (the particles move by the
+simulation's displacement, then the structure is updated and searched). Requests are
+served continuously: whenever one of the stream slots is free, the oldest queued request
+whose simulation is idle starts on it, so requests that arrive while others run are
+admitted as slots and memory free up, and their work overlaps on the device. The first
+step of a resident simulation builds its structure; every later step is the incremental
+update (the displacement applied on the device and only migrating particles re-binned)
+plus count and fill, replayed from the HIP graph its structure captured (one launch per
+request). With per_sim=False the requests of a slot are instead batched (up to a particle
+budget) into one library batch call (move, then a full build + search) on a structure per
+slot. Simulations are admitted into HBM by a byte budget, by default the device's free
+memory (re-read before every admission) less a reserve: before a request runs, idle
+simulations are evicted (positions to pinned host memory, outputs and cell structure
+freed) in least-recently-used order until it fits.
 
 The scheduler (`Scheduler`) is host logic only and is tested on the CPU; `Server` drives
 the library through the binding in `nnps.py`. Every search runs in the HIP library; the
-particle motion between steps (the simulation's own work, not the search) is a few
-elementwise torch operations on the slot's stream, ordered before the sim's next search
-by an event.
+simulation's own work between steps, drawing its displacement (uniform per component,
+reflected at the box), is a few elementwise torch operations on the slot's stream,
+ordered before the sim's next step by an event.
 """
 from __future__ import annotations
 
@@ -35,6 +38,7 @@ class Request:
     arrival: float                 # seconds after the run's start
     issued: float | None = None    # host time the batch holding it was launched (s)
     done_ms: float | None = None   # device completion time (ms after the run's start)
+    device_ms: float = 0.0         # device time of its batch (events around the step)
     nnz: int = 0
     batch: int = -1
     step: int = -1
@@ -42,6 +46,12 @@ class Request:
     @property
     def latency_ms(self) -> float:
         return self.done_ms - 1e3 * self.arrival
+
+    @property
+    def queue_ms(self) -> float:
+        """Arrival to launch: waiting for a slot, for its simulation's previous step, or
+        for the scheduler loop to see it."""
+        return 1e3 * (self.issued - self.arrival)
 
 
 class Scheduler:
@@ -146,9 +156,9 @@ class Server:
     """Runs the request loop on one GPU. `sims` are workloads.ParticleSet; `slots` is the
     number of batches that may be on the device at once (one stream each)."""
 
-    def __init__(self, sims, slots: int = 4, budget_bytes: float = math.inf, max_batch_particles: int = 1 << 23,
+    def __init__(self, sims, slots: int = 4, budget_bytes: float | None = None, max_batch_particles: int = 1 << 23,
                  seed: int = 4, frac: float = 0.05, headroom: float = 1.1, ctx=None, keep_results: bool = False,
-                 per_sim: bool = True):
+                 per_sim: bool = True, reserve_bytes: float = 2 << 30, use_update: bool = True):
         import torch
         from . import nnps
         self.torch = torch
@@ -165,7 +175,13 @@ class Server:
         # one replay of that structure's captured graph; otherwise the requests of a slot
         # are batched into one library batch call on the slot's structure
         self.per_sim = per_sim
+        # per_sim: steps after a simulation's first one update its structure incrementally
+        self.use_update = use_update and per_sim
+        # budget_bytes None: free device memory, re-read before each admission, less a reserve
+        self.auto_budget = budget_bytes is None
+        self.reserve = reserve_bytes
         self.cells = [None] * len(sims)
+        self.built = [False] * len(sims)   # the simulation's own structure holds its last step
         n = len(sims)
         self.step = [0] * n
         self.pos = [None] * n       # device positions (resident) or None
@@ -177,6 +193,7 @@ class Server:
         self.ready = [None] * n     # event: positions of the next step are in place
         self.gen = {}               # per-simulation device generator (reseeded every step)
         self.disp = {}              # per-simulation displacement buffer of the motion
+        self.pending = [False] * n  # a displacement is drawn but not yet applied
         self.box = [(torch.tensor(ps.lo, dtype=torch.float64, device="cuda"),
                      torch.tensor(ps.hi, dtype=torch.float64, device="cuda")) for ps in sims]
         # initial capacity estimate per simulation from one search of its starting positions
@@ -189,8 +206,8 @@ class Server:
             del pos, rp, col
         cells.close()
         nbytes = [self._footprint(s) for s in range(len(sims))]
-        self.sched = Scheduler([ps.n for ps in sims], nbytes, budget_bytes, 1 if per_sim else max_batch_particles,
-                               groups=[ps.dim for ps in sims])
+        self.sched = Scheduler([ps.n for ps in sims], nbytes, math.inf if budget_bytes is None else budget_bytes,
+                               1 if per_sim else max_batch_particles, groups=[ps.dim for ps in sims])
         self.slots = []
         for _ in range(slots):
             c = self.ctx.cells()
@@ -209,6 +226,15 @@ class Server:
             b += ps.n * (200 + 16 * 3 ** ps.dim)
         return b
 
+    def _free_budget(self):
+        """Bytes the resident simulations may hold: what they hold now plus the device's free
+        memory (the driver's, and blocks torch's allocator has cached but not handed out)
+        less the reserve."""
+        torch = self.torch
+        free, _ = torch.cuda.mem_get_info()
+        cached = torch.cuda.memory_reserved() - torch.cuda.memory_allocated()
+        return self.sched.resident_bytes() + free + cached - self.reserve
+
     def _admit(self, s, stream):
         torch = self.torch
         ps = self.sims[s]
@@ -218,6 +244,7 @@ class Server:
             self.col[s] = torch.empty(self.cap[s], dtype=torch.int32, device="cuda")
             self.dist[s] = torch.empty(self.cap[s], dtype=torch.float32, device="cuda")
         self.host[s] = None
+        self.built[s] = False
         if self.per_sim:
             self.cells[s] = self.ctx.cells()
             self.cells[s].set_graphs(True)
@@ -227,20 +254,31 @@ class Server:
         # an idle simulation: its last step (and motion) finished; wait for that motion
         if self.ready[s] is not None:
             self.ready[s].synchronize()
+        self._apply(s, torch.cuda.current_stream())  # a drawn displacement goes with the positions
+        torch.cuda.current_stream().synchronize()
         host = torch.empty(self.pos[s].shape, dtype=torch.float64, pin_memory=True)
         host.copy_(self.pos[s])
         self.host[s] = host
         self.pos[s] = self.rp[s] = self.col[s] = self.dist[s] = None
         self.disp.pop(s, None)
         self.ready[s] = None
+        self.built[s] = False
         if self.cells[s] is not None:
             self.cells[s].close()
             self.cells[s] = None
 
+    def _apply(self, s, stream):
+        """Add a drawn displacement to the positions (paths that rebuild instead of updating)."""
+        if self.pending[s]:
+            with self.torch.cuda.stream(stream):
+                self.pos[s].add_(self.disp[s])
+            self.pending[s] = False
+
     def _move(self, s, stream):
-        """The simulation's time step: every particle moves by U(-frac dx, +frac dx) per
-        component, dx = radius / 2.4, and is clamped to the box (seeded per simulation and
-        step; three device launches)."""
+        """The simulation's time step: a displacement U(-frac dx, +frac dx) per component,
+        dx = radius / 2.4, with a component's sign flipped where it would take the particle
+        out of the box (a reflection at the walls; seeded per simulation and step). It is
+        applied by the next step's update (or added before its rebuild)."""
         torch = self.torch
         ps = self.sims[s]
         g = self.gen.get(s)
@@ -254,11 +292,12 @@ class Server:
             if d is None or d.shape != p.shape:
                 d = self.disp[s] = torch.empty_like(p)
             d.uniform_(-a, a, generator=g)
-            p.add_(d)
             lo, hi = self.box[s]
-            p.clamp_(lo, hi)
+            new = p + d  # the binary64 sum the update forms
+            d.copy_(torch.where((new < lo) | (new > hi), -d, d))
             ev = torch.cuda.Event()
             ev.record(stream)
+        self.pending[s] = True
         self.ready[s] = ev
 
     # -- the loop -------------------------------------------------------------------------
@@ -266,6 +305,8 @@ class Server:
         torch, nnps = self.torch, self.nnps
         stream = slot["stream"]
         sims = [r.sim for r in reqs]
+        if self.auto_budget:
+            self.sched.budget = self._free_budget()
         admit, evict = self.sched.admit(sims)
         for s in evict:
             self._evict(s)
@@ -277,9 +318,20 @@ class Server:
         sets = [(self.pos[s], self.sims[s].lo, self.sims[s].hi, self.sims[s].cell_size, self.sims[s].radius)
                 for s in sims]
         cells = self.cells[sims[0]] if self.per_sim else slot["cells"]
+        outs = ([self.rp[s] for s in sims], [self.col[s] for s in sims], [self.dist[s] for s in sims])
         with torch.cuda.stream(stream):
-            cells.batch_step(sets, [self.rp[s] for s in sims], [self.col[s] for s in sims],
-                             [self.dist[s] for s in sims], stream=stream)
+            begin = torch.cuda.Event(enable_timing=True)
+            begin.record(stream)
+            if self.use_update and self.built[sims[0]]:
+                s0 = sims[0]
+                cells.batch_update_step(*outs, disp=[self.disp[s0] if self.pending[s0] else None], stream=stream)
+                self.pending[s0] = False
+            else:
+                for s in sims:
+                    self._apply(s, stream)
+                cells.batch_step(sets, *outs, stream=stream)
+                if self.per_sim:
+                    self.built[sims[0]] = True
             done = torch.cuda.Event(enable_timing=True)
             done.record(stream)
             cells.batch_nnz_enqueue(stream=stream)
@@ -292,6 +344,7 @@ class Server:
         self.sched.start(sims)
         slot["batch"] = reqs
         slot["done"] = done
+        slot["begin"] = begin
         self.batches += 1
 
     def _finish(self, slot, ref):
@@ -299,6 +352,7 @@ class Server:
         reqs = slot["batch"]
         stream = slot["stream"]
         done_ms = ref.elapsed_time(slot["done"])
+        device_ms = slot["begin"].elapsed_time(slot["done"])
         nnz, code = slot["used"].batch_nnz_fetch(check=False)
         sims = [r.sim for r in reqs]
         redo = []
@@ -309,6 +363,7 @@ class Server:
                 continue
             r.nnz = int(k)
             r.done_ms = done_ms
+            r.device_ms = device_ms
             if self.keep_results:  # copies ordered before the motion on the same stream
                 with torch.cuda.stream(stream):
                     self.results[(s, self.step[s])] = (self.pos[s].clone(), self.rp[s].clone(),
@@ -317,8 +372,9 @@ class Server:
             self._move(s, stream)
         if code not in (nnps.NNPS_OK, nnps.NNPS_ECAPACITY):
             raise nnps.NnpsError(code, "serving batch")
-        for r in redo:  # outputs too small: grow them and run that step again first
+        for r in redo:  # outputs too small: grow them and run that step again (rebuilt) first
             s = r.sim
+            self.built[s] = False
             self.cap[s] = int(nnz[sims.index(s)] * self.headroom) + 4096
             self.sched.nbytes[s] = self._footprint(s)
             with torch.cuda.stream(stream):
@@ -374,6 +430,12 @@ class Server:
         torch.cuda.synchronize()
         return done
 
+    def counters(self) -> dict:
+        """Admissions and evictions so far, and the budget last used."""
+        return {"admissions": self.sched.admissions, "evictions": self.sched.evictions,
+                "budget_bytes": None if math.isinf(self.sched.budget) else float(self.sched.budget),
+                "auto_budget": self.auto_budget}
+
     def close(self):
         for slot in self.slots:
             slot["cells"].close()
@@ -395,8 +457,17 @@ def summarize(done, warmup: int = 0):
     t_last = max(r.done_ms for r in reqs)
     pairs = sum(r.nnz for r in reqs)
     span_s = max((t_last - t_first) * 1e-3, 1e-9)
-    return {"requests": len(reqs), "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+    qw = [r.queue_ms for r in reqs]
+    dev = [r.device_ms for r in reqs]
+    # the tail: requests at or above the p99 latency, their mean queue wait and device time
+    p99 = percentile(lat, 99)
+    tail = [r for r in reqs if r.latency_ms >= p99]
+    return {"requests": len(reqs), "p50_ms": percentile(lat, 50), "p99_ms": p99,
             "mean_ms": float(np.mean(lat)), "max_ms": float(np.max(lat)),
             "gpairs_per_s": pairs / span_s / 1e9, "requests_per_s": len(reqs) / span_s,
             "batches": len({r.batch for r in reqs}),
-            "mean_batch": len(reqs) / max(len({r.batch for r in reqs}), 1)}
+            "mean_batch": len(reqs) / max(len({r.batch for r in reqs}), 1),
+            "queue_p50_ms": percentile(qw, 50), "queue_p99_ms": percentile(qw, 99),
+            "device_p50_ms": percentile(dev, 50), "device_p99_ms": percentile(dev, 99),
+            "tail_queue_ms": float(np.mean([r.queue_ms for r in tail])),
+            "tail_device_ms": float(np.mean([r.device_ms for r in tail]))}

@@ -163,3 +163,19 @@ def step_displacement(ps: ParticleSet, step: int, seed: int, frac: float = 0.05)
     new = np.where(new < lo, 2 * lo - new, new)
     new = np.where(new > hi, 2 * hi - new, new)
     return np.clip(new, lo, hi)
+
+
+def reflected_displacement(pos: np.ndarray, lo, hi, amp: float, seed) -> np.ndarray:
+    """A seeded displacement U(-amp, +amp) per component for the particles at `pos`, with the
+    sign of a component flipped where pos + d (one binary64 addition, as the update applies
+    it) would leave [lo, hi]; pos + d then stays inside the box while amp is well below the
+    box size."""
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(-amp, amp, size=pos.shape)
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    new = pos + d
+    d = np.where((new < lo) | (new > hi), -d, d)
+    new = pos + d
+    assert np.all((new >= lo) & (new <= hi)), "displacement too large for the box"
+    return np.ascontiguousarray(d)

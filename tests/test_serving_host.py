@@ -87,11 +87,17 @@ def test_summary():
     for i in range(100):
         r = Request(i % 4, arrival=i * 1e-3)
         r.done_ms = i + 1.0 + (i % 10)   # latency 1..10 ms
+        r.issued = r.arrival + 1e-3 * (i % 10) / 2  # half of it queued
+        r.device_ms = 1.0 + (i % 10) / 2
         r.nnz = 1000
         r.batch = i // 2
         reqs.append(r)
     out = summarize(reqs, warmup=0)
     assert out["requests"] == 100
+    assert math.isclose(out["queue_p50_ms"], percentile([(i % 10) / 2 for i in range(100)], 50))
+    assert math.isclose(out["device_p99_ms"], percentile([1 + (i % 10) / 2 for i in range(100)], 99))
+    # the tail (latency 10 ms) queued 4.5 ms and ran 5.5 ms
+    assert math.isclose(out["tail_queue_ms"], 4.5) and math.isclose(out["tail_device_ms"], 5.5)
     assert math.isclose(out["p50_ms"], percentile([1 + (i % 10) for i in range(100)], 50))
     assert out["p99_ms"] == percentile([1 + (i % 10) for i in range(100)], 99)
     assert out["mean_batch"] == 2.0
