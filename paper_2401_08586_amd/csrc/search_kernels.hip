@@ -202,6 +202,20 @@ __device__ __forceinline__ bool recheck_g(const NNPS_GLOBAL double* __restrict__
     return r2_fp64<DIM>(pi, pj) <= R2;
 }
 
+// The work block a workgroup takes. Workgroups are dealt to the eight XCDs in turn (the
+// i-th to XCD i mod 8), each XCD with its own L2, while neighbouring blocks share most of
+// their candidate unions. So XCD k is given the k-th contiguous eighth of the blocks,
+// walked in order: block = (i mod 8) * ceil(nblk / 8) + i / 8. Returns -1 for workgroups
+// with no block (the grid is sized for an upper bound of the count).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int nblk)
+{
+    const int i = blockIdx.x;
+    const int per = (nblk + kXcds - 1) / kXcds;
+    const int b = (i % kXcds) * per + i / kXcds;
+    return (i / kXcds < per && b < nblk) ? b : -1;
+}
+
 // Blocks of the dense-cell path's windows are left to that path.
 __device__ __forceinline__ bool dense_block(const SearchArgs& a, int b)
 {
@@ -497,8 +511,8 @@ k_count16(SearchArgs a)
     // half lists: the staged candidates' original indices (same padding)
     __shared__ __attribute__((aligned(16))) int corig[HALF ? kStage + 2 * kGroup : 1];
     __shared__ uint32_t lbits[64 * (CB::CW + 1)];
-    const int b = blockIdx.x;
-    if (b >= *a.nblk) return;
+    const int b = xcd_block(*a.nblk);
+    if (b < 0) return;
     const int lane = threadIdx.x & 63;
     if (dense_block(a, b)) {
         if (lane < 5) a.blk_stats[static_cast<size_t>(b) * 5 + lane] = 0;
@@ -656,8 +670,8 @@ k_count64(SearchArgs a)
 {
     using CB = CandBits<DIM>;
     __shared__ uint32_t lbits[64 * (CB::CW + 1)];
-    const int b = blockIdx.x;
-    if (b >= *a.nblk) return;
+    const int b = xcd_block(*a.nblk);
+    if (b < 0) return;
     if (dense_block(a, b)) {
         if ((threadIdx.x & 63) < 5) a.blk_stats[static_cast<size_t>(b) * 5 + (threadIdx.x & 63)] = 0;
         return;
@@ -745,8 +759,8 @@ k_count32(SearchArgs a)
     // half lists: the staged candidates' original indices (same padding)
     __shared__ int sorig[HALF ? kStage32 + 4 : 1];
     __shared__ uint32_t lbits[64 * (CB::CW + 1)];
-    const int b = blockIdx.x;
-    if (b >= *a.nblk) return;
+    const int b = xcd_block(*a.nblk);
+    if (b < 0) return;
     const int lane = threadIdx.x & 63;
     if (dense_block(a, b)) {
         if (lane < 5) a.blk_stats[static_cast<size_t>(b) * 5 + lane] = 0;
@@ -1213,8 +1227,8 @@ k_fill(SearchArgs a)
     uint16_t* flat = reinterpret_cast<uint16_t*>(smem);
     static_assert(64 << C::SHIFT <= 65536 && (1 << C::SHIFT) == C::UCAP, "flat entries fit 16 bits");
 
-    const int b = blockIdx.x;
-    if (b >= *a.nblk || dense_block(a, b)) return;
+    const int b = xcd_block(*a.nblk);
+    if (b < 0 || dense_block(a, b)) return;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront index, uniform
     // every wavefront holds the block's geometry; lane = target
@@ -1654,10 +1668,14 @@ k_long(SearchArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Grid of the block kernels: a whole number of rounds over the XCDs, so xcd_block reaches
+// every block of any count up to nblk_max.
+static dim3 block_grid(int nblk_max) { return dim3((nblk_max + kXcds - 1) / kXcds * kXcds); }
+
 hipError_t launch_count(const SearchArgs& a, int nblk_max, hipStream_t st)
 {
     if (a.L.ntot == 0 || nblk_max == 0) return hipSuccess;
-    const dim3 g(nblk_max), b(64);
+    const dim3 g = block_grid(nblk_max), b(64);
     const int d = a.L.dim, m = a.L.mode;
     if (a.half) {
         if (d == 2 && m == 0) hipLaunchKernelGGL((k_count16<2, 0, true>), g, b, 0, st, a);
@@ -1692,7 +1710,7 @@ hipError_t launch_stats(const SearchArgs& a, hipStream_t st)
 hipError_t launch_fill(const SearchArgs& a, int nblk_max, hipStream_t st)
 {
     if (a.L.ntot == 0 || nblk_max == 0) return hipSuccess;
-    const dim3 g(nblk_max), b(kFillThreads);
+    const dim3 g = block_grid(nblk_max), b(kFillThreads);
     const int d = a.L.dim, m = a.L.mode == 3 ? 1 : a.L.mode;  // FP32 mode: binary64 distances
     if (d == 2 && m == 0) hipLaunchKernelGGL((k_fill<2, 0>), g, b, 0, st, a);
     else if (d == 3 && m == 0) hipLaunchKernelGGL((k_fill<3, 0>), g, b, 0, st, a);
