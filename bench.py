@@ -559,7 +559,7 @@ def bench_serving(args, nsims=64, slots=4, load=0.7):
     """Serving mix: 64 simulations (half 2D, half 3D lattices, 1e3..2e6 particles), each
     request one time step (move by U(+-0.05 dx) reflected at the box, update the resident
     structure, search). Latency = arrival to CSR ready (device event). Legs: the default
-    (incremental updates, admission by free HBM), the same with a byte budget of 40 % of
+    (incremental updates, admission by free HBM), the same with a byte budget of 60 % of
     the mix's footprint (forces admissions and evictions), full rebuilds instead of
     updates, and requests batched per slot (one batch call per slot, rebuilt)."""
     import torch
@@ -576,7 +576,7 @@ def bench_serving(args, nsims=64, slots=4, load=0.7):
     total = sum(p.n * p.dim * 16 + (p.n + 1) * 8 + int(p.n * (20 if p.dim == 2 else 60) * 1.1 * 8) + 4096 * 8
                 + p.n * (200 + 16 * 3 ** p.dim) for p in sims)
     legs = {}
-    for name, kw in (("budget_40pct", {"budget_bytes": 0.4 * total}), ("rebuild", {"use_update": False}),
+    for name, kw in (("budget_60pct", {"budget_bytes": 0.6 * total}), ("rebuild", {"use_update": False}),
                      ("batched", {"per_sim": False})):
         r = serving_leg(sims, args, slots, load, **kw)
         log(f"[bench] serving ({name}): p50 {r['p50_ms']:.3f} ms p99 {r['p99_ms']:.3f} ms "
@@ -588,7 +588,7 @@ def bench_serving(args, nsims=64, slots=4, load=0.7):
         torch.cuda.empty_cache()
     res.update({"sims": nsims, "particles": sum(p.n for p in sims), "footprint_bytes_estimate": total,
                 "workload": "64 jittered lattices (32 2D, 32 3D), n log-uniform 1e3..2e6, per-step move "
-                            "U(+-0.05 dx) reflected at the box, Poisson arrivals",
+                            "U(+-0.05 dx) reflected at the box faces, Poisson arrivals",
                 "legs": legs})
     return res
 

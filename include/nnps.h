@@ -257,7 +257,8 @@ nnps_status nnps_batch_nnz_fetch(nnps_cells *cells, int64_t *h_nnz);
  * device array [n][dim] of float64 displacements of that set:
  *   - with a displacement array, the call advances the positions in place,
  *     pos[i][k] = pos[i][k] + disp[i][k] (one binary64 addition each; the caller's
- *     position array is written);
+ *     position array is written), except that a component whose sum would fall outside
+ *     [lo[k], hi[k]] moves by -disp[i][k] instead (a reflection at the box faces);
  *   - without one, the caller has already moved the positions in place.
  * Either way each particle's fixed-point position, cell and relative coordinate are
  * recomputed from its binary64 position (so no rounding error builds up from step to

@@ -35,17 +35,18 @@ hipError_t launch_pack(const Launch& L, const uint32_t* skey, const int* perm, c
 
 // Incremental update of a built structure (see k_upd_move): device tables of one update.
 struct Update {
-    uint32_t* knew;           // [ntot] new cell key by old sorted position
-    unsigned long long* mig;  // [ceil(ntot / 64)] bit s: the particle at old position s changed cell
-    int* leave;               // [ncell_tot + 1] migrants out of each cell (zeroed before the update)
-    int* arrive;              // [ncell_tot + 1] migrants into each cell (zeroed before the update)
-    int* aslot;               // [ntot] a migrant's arrival slot in its new cell
+    uint32_t* knew;           // [ntot] new cell key by particle
+    uint32_t* mig;            // [ceil(ntot / 32)] bit s: the particle at old position s changed cell
+    int* leave;               // [ncell_tot + 1] migrants out of each cell
+    int* arrive;              // [ncell_tot + 1] migrants into each cell
+                              // (leave, arrive and mig are one zeroed block: see update_of)
+    int* aslot;               // [ntot] by particle: a migrant's arrival slot in its new cell
     int* cs_old;              // [ncell_tot + 1] cell starts before the update
     uint32_t* skey2;          // [ntot] new order: cell keys
     int* perm2;               // [ntot] new order: particle indices
 };
 // U1: move (when the set has displacements), fixed point, cells, migrant flags and counts.
-hipError_t launch_update_move(const Launch& L, const uint32_t* skey, const int* perm, double* X, const Update& u,
+hipError_t launch_update_move(const Launch& L, const uint32_t* skey, const int* inv, double* X, const Update& u,
                               int* err, hipStream_t st);
 // U2: new cell occupancies and starts (cell_start is rewritten; the old one goes to cs_old).
 hipError_t launch_update_cells(const Launch& L, int* cell_start, int* cnt, const Update& u, int64_t* partial,

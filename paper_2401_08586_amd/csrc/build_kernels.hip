@@ -437,55 +437,76 @@ k_pack(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nset
 // migrants are re-binned: the sorted order is kept, stayers keep their relative order in
 // their cell, and each cell's migrants are appended after its stayers.
 
-// U1 (per sorted position s): move, recompute X and the cell; bit s of `mig` says the
-// cell changed. A migrant counts out of its old cell and takes an arrival slot in its
-// new one; every particle's new cell key is kept by sorted position (knew).
+// U1 (per particle, in the caller's order so positions, displacements and fixed-point
+// positions stream): move, recompute X and the cell. A displacement component that would
+// take the particle out of [lo, hi] is applied with its sign flipped (a reflection at the
+// box faces). A particle whose cell changed is a migrant: bit inv[i] of `mig` is set, it
+// counts out of its old cell and takes an arrival slot in its new one. Every particle's
+// new cell key is kept by particle index (knew).
 template <int DIM>
 __global__ void __launch_bounds__(256)
-k_upd_move(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, int nsets, int ntot,
-           const uint32_t* __restrict__ skey, const int* __restrict__ perm, double* __restrict__ X,
-           uint32_t* __restrict__ knew, unsigned long long* __restrict__ mig, int* __restrict__ leave,
+k_upd_move(const SetDesc* __restrict__ sets, const int* __restrict__ poffs, int nsets, int ntot,
+           const uint32_t* __restrict__ skey, const int* __restrict__ inv, double* __restrict__ X,
+           uint32_t* __restrict__ knew, uint32_t* __restrict__ mig, int* __restrict__ leave,
            int* __restrict__ arrive, int* __restrict__ aslot, int* __restrict__ err)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= ntot) return;  // the active lanes of a wavefront are a prefix of it
-    const uint32_t kold = skey[s];
-    const int o = perm[s];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ntot) return;
     bool bad = false;
     auto cell_of = [&](const SetDesc& sd) -> uint32_t {
-        const Frame& fr = sd.fr;
-        const int li = o - sd.poff;
-        double* pos = const_cast<double*>(sd.pos);  // the caller lent them for the update
-        int64_t c[3] = {0, 0, 0};
+        // the set's fields in registers: read through the table they would be loaded again
+        // after every store below (the compiler cannot tell the stores from the table)
+        double lo[DIM], hi[DIM];
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
-            const size_t at = static_cast<size_t>(li) * DIM + k;
-            double p = pos[at];
-            if (sd.disp) {
-                p = __dadd_rn(p, sd.disp[at]);
-                pos[at] = p;
-            }
-            if (!(p >= fr.lo[k] && p <= fr.hi[k])) {
-                bad = true;
-                p = fr.lo[k];
-            }
-            const double d = __dsub_rn(p, fr.lo[k]);
-            const double t = rint(__dmul_rn(d, fr.s));
-            X[static_cast<size_t>(o) * x_stride(DIM) + k] = t;
-            c[k] = static_cast<int64_t>(t) >> fr.F;
+            lo[k] = sd.fr.lo[k];
+            hi[k] = sd.fr.hi[k];
         }
-        return static_cast<uint32_t>(sd.coff + c[0] + fr.nc[0] * (c[1] + fr.nc[1] * c[2]));
+        const double scale = sd.fr.s;
+        const int F = sd.fr.F, ncx = sd.fr.nc[0], ncy = sd.fr.nc[1], coff = sd.coff;
+        const int li = i - sd.poff;
+        double* pos = const_cast<double*>(sd.pos);  // the caller lent them for the update
+        const double* disp = sd.disp;
+        double p[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) p[k] = pos[static_cast<size_t>(li) * DIM + k];
+        if (disp) {
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                const double d = disp[static_cast<size_t>(li) * DIM + k];
+                const double q = __dadd_rn(p[k], d);
+                p[k] = (q >= lo[k] && q <= hi[k]) ? q : __dadd_rn(p[k], -d);
+            }
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) pos[static_cast<size_t>(li) * DIM + k] = p[k];
+        }
+        int64_t c[3] = {0, 0, 0};
+        double t[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            double pk = p[k];
+            if (!(pk >= lo[k] && pk <= hi[k])) {
+                bad = true;
+                pk = lo[k];
+            }
+            t[k] = rint(__dmul_rn(__dsub_rn(pk, lo[k]), scale));
+            c[k] = static_cast<int64_t>(t[k]) >> F;
+        }
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) X[static_cast<size_t>(i) * x_stride(DIM) + k] = t[k];
+        return static_cast<uint32_t>(coff + c[0] + ncx * (c[1] + ncy * c[2]));
     };
-    const int st = find_set(coffs, nsets, static_cast<int>(kold));
+    // a wavefront inside one set reads the set's fields with scalar loads
+    const int st = find_set(poffs, nsets, i);
     const int s0 = __builtin_amdgcn_readfirstlane(st);
     const uint32_t kn = __all(st == s0) ? cell_of(sets[s0]) : cell_of(sets[st]);
-    knew[s] = kn;
-    const bool moved = kn != kold;
-    const unsigned long long bal = __ballot(moved);
-    if ((threadIdx.x & 63) == 0) mig[s >> 6] = bal;  // s is the wavefront's first position
-    if (moved) {
+    knew[i] = kn;
+    const int sp = inv[i];
+    const uint32_t kold = skey[sp];
+    if (kn != kold) {
+        atomicOr(&mig[sp >> 5], 1u << (sp & 31));
         atomicAdd(&leave[kold], 1);
-        aslot[s] = atomicAdd(&arrive[kn], 1);
+        aslot[i] = atomicAdd(&arrive[kn], 1);
     }
     if (bad) atomicOr(err, kErrDomain);
 }
@@ -505,15 +526,15 @@ k_upd_counts(int ncell, const int* __restrict__ cell_start, const int* __restric
 }
 
 // Set bits of `mig` at positions [a, b).
-__device__ __forceinline__ int mig_bits(const unsigned long long* __restrict__ mig, int a, int b)
+__device__ __forceinline__ int mig_bits(const uint32_t* __restrict__ mig, int a, int b)
 {
     int n = 0;
-    for (int w = a >> 6; (w << 6) < b; ++w) {
-        unsigned long long m = mig[w];
-        const int lo = a - (w << 6), hi = b - (w << 6);  // bit range of this word, clipped below
-        if (lo > 0) m &= ~0ull << lo;
-        if (hi < 64) m &= (1ull << hi) - 1ull;
-        n += __popcll(m);
+    for (int w = a >> 5; (w << 5) < b; ++w) {
+        uint32_t m = mig[w];
+        const int lo = a - (w << 5), hi = b - (w << 5);  // bit range of this word, clipped below
+        if (lo > 0) m &= ~0u << lo;
+        if (hi < 32) m &= (1u << hi) - 1u;
+        n += __builtin_popcount(m);
     }
     return n;
 }
@@ -523,23 +544,24 @@ __device__ __forceinline__ int mig_bits(const unsigned long long* __restrict__ m
 // migrant goes after the stayers of its new cell, at its arrival slot.
 __global__ void __launch_bounds__(256)
 k_upd_place(int ntot, const uint32_t* __restrict__ skey, const int* __restrict__ perm,
-            const uint32_t* __restrict__ knew, const unsigned long long* __restrict__ mig,
-            const int* __restrict__ leave, const int* __restrict__ aslot, const int* __restrict__ cs_old,
-            const int* __restrict__ cs_new, uint32_t* __restrict__ skey2, int* __restrict__ perm2)
+            const uint32_t* __restrict__ knew, const uint32_t* __restrict__ mig, const int* __restrict__ leave,
+            const int* __restrict__ aslot, const int* __restrict__ cs_old, const int* __restrict__ cs_new,
+            uint32_t* __restrict__ skey2, int* __restrict__ perm2)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= ntot) return;
-    const uint32_t kold = skey[s], kn = knew[s];
+    const int o = perm[s];
+    const uint32_t kold = skey[s], kn = knew[o];
     int at;
     if (kn == kold) {
         const int a = cs_old[kold];
         const int lb = leave[kold] > 0 ? mig_bits(mig, a, s) : 0;
         at = cs_new[kold] + (s - a) - lb;
     } else {
-        at = cs_new[kn] + (cs_old[kn + 1] - cs_old[kn] - leave[kn]) + aslot[s];
+        at = cs_new[kn] + (cs_old[kn + 1] - cs_old[kn] - leave[kn]) + aslot[o];
     }
     skey2[at] = kn;
-    perm2[at] = perm[s];
+    perm2[at] = o;
 }
 
 // ---------------------------------------------------------------------------
@@ -873,16 +895,16 @@ hipError_t launch_pack(const Launch& L, const uint32_t* skey, const int* perm, c
     return hipGetLastError();
 }
 
-hipError_t launch_update_move(const Launch& L, const uint32_t* skey, const int* perm, double* X, const Update& u,
+hipError_t launch_update_move(const Launch& L, const uint32_t* skey, const int* inv, double* X, const Update& u,
                               int* err, hipStream_t st)
 {
     if (L.ntot == 0) return hipSuccess;
     const dim3 g((L.ntot + 255) / 256), b(256);
     if (L.dim == 2)
-        hipLaunchKernelGGL(k_upd_move<2>, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, perm, X, u.knew, u.mig,
+        hipLaunchKernelGGL(k_upd_move<2>, g, b, 0, st, L.sets, L.poffs, L.nsets, L.ntot, skey, inv, X, u.knew, u.mig,
                            u.leave, u.arrive, u.aslot, err);
     else
-        hipLaunchKernelGGL(k_upd_move<3>, g, b, 0, st, L.sets, L.coffs, L.nsets, L.ntot, skey, perm, X, u.knew, u.mig,
+        hipLaunchKernelGGL(k_upd_move<3>, g, b, 0, st, L.sets, L.poffs, L.nsets, L.ntot, skey, inv, X, u.knew, u.mig,
                            u.leave, u.arrive, u.aslot, err);
     return hipGetLastError();
 }

@@ -290,7 +290,7 @@ struct nnps_cells {
     int* ulist = nullptr;
     DevBuf usz, wdense, uoff, nsl, unit_off, ucell, dn, ecnt, epos, uk0, uk1, uv0, uv1, inv, ucount, dstats, dseen;
     // incremental update (nnps_cells_update): see Update
-    DevBuf umig, uleave, uarrive, ucs_old, uskey2, uperm2;
+    DevBuf uleave, ucs_old, uskey2, uperm2;
     GraphCache ugraph;  // a captured update + count + fill sequence
 };
 
@@ -528,10 +528,11 @@ nnps_status prepare(nnps_ctx* ctx, nnps_cells* c, int nsets, const nnps_problem*
         {&c->unit_off, c->dense ? (nc + 1) * 4 : 0}, {&c->ucell, c->dense ? (nn + 1) * 4 : 0},
         {&c->dn, c->dense ? size_t(4) : size_t(0)}, {&c->ecnt, c->dense ? nn * 4 : 0}, {&c->epos, c->dense ? (nn + 1) * 4 : 0},
         {&c->uk0, dcap * 4}, {&c->uk1, dcap * 4}, {&c->uv0, dcap * 4}, {&c->uv1, dcap * 4},
-        {&c->inv, c->dense ? nn * 4 : 0}, {&c->ucount, c->dense ? size_t(4) : size_t(0)},
+        {&c->inv, nn * 4}, {&c->ucount, c->dense ? size_t(4) : size_t(0)},
         {&c->dstats, c->dense ? static_cast<size_t>(c->dgrid) * kDenseStats * 8 : 0},
         {&c->dseen, c->dense ? size_t(4) : size_t(0)},
-        {&c->umig, (nn + 63) / 64 * 8}, {&c->uleave, (nc + 1) * 4}, {&c->uarrive, (nc + 1) * 4},
+        // leave, arrive (ncell + 1 each) and the migrant bits (ceil(n / 32) words), one block
+        {&c->uleave, (2 * (nc + 1) + (nn + 31) / 32) * 4},
         {&c->ucs_old, (nc + 1) * 4}, {&c->uskey2, nn * 4}, {&c->uperm2, nn * 4},
     };
     for (auto& q : need) {
@@ -553,9 +554,9 @@ Update update_of(nnps_cells* c)
     Update u{};
     u.knew = c->k0.as<uint32_t>();  // the build's unsorted keys and slots are free after it
     u.aslot = c->v1.as<int>();
-    u.mig = c->umig.as<unsigned long long>();
     u.leave = c->uleave.as<int>();
-    u.arrive = c->uarrive.as<int>();
+    u.arrive = u.leave + c->ncell_tot + 1;
+    u.mig = reinterpret_cast<uint32_t*>(u.arrive + c->ncell_tot + 1);
     u.cs_old = c->ucs_old.as<int>();
     u.skey2 = c->uskey2.as<uint32_t>();
     u.perm2 = c->uperm2.as<int>();
@@ -570,12 +571,11 @@ nnps_status enqueue_update(nnps_cells* c, hipStream_t s)
     const Launch L = launch_of(c);
     PhaseTimer& tm = c->timer;
     const Update u = update_of(c);
-    const int64_t nc1 = static_cast<int64_t>(c->ncell_tot) + 1;
-    HIP_TRY(launch_fill_i32(u.leave, nc1, 0, s));
-    HIP_TRY(launch_fill_i32(u.arrive, nc1, 0, s));
+    const int64_t zero = 2 * (static_cast<int64_t>(c->ncell_tot) + 1) + (c->ntot + 31) / 32;
+    HIP_TRY(launch_fill_i32(u.leave, zero, 0, s));
     HIP_TRY(launch_fill_i32(c->err.as<int>(), 1, 0, s));
     tm.begin(NNPS_PHASE_ASSIGN, s);
-    HIP_TRY(launch_update_move(L, c->skey, c->perm, c->X.as<double>(), u, c->err.as<int>(), s));
+    HIP_TRY(launch_update_move(L, c->skey, c->inv.as<int>(), c->X.as<double>(), u, c->err.as<int>(), s));
     tm.end(NNPS_PHASE_ASSIGN, s);
     tm.begin(NNPS_PHASE_CELLSCAN, s);
     HIP_TRY(launch_update_cells(L, c->cell_start.as<int>(), c->cell_count.as<int>(), u, c->partial.as<int64_t>(), s));
@@ -587,7 +587,7 @@ nnps_status enqueue_update(nnps_cells* c, hipStream_t s)
     HIP_TRY(launch_pack(L, u.skey2, u.perm2, c->X.as<double>(), c->q4.as<ushort4>(),
                         uses_spos(c->mode) ? c->spos.as<double>() : nullptr,
                         c->mode == NNPS_MODE_FP32_RCLL ? c->rq.as<float4>() : nullptr,
-                        c->dense ? c->inv.as<int>() : nullptr, s, c->skey, c->perm));
+                        c->inv.as<int>(), s, c->skey, c->perm));
     tm.end(NNPS_PHASE_PACK, s);
     return enqueue_build_tail(c, s);
 }
@@ -619,7 +619,7 @@ nnps_status enqueue_build(nnps_cells* c, hipStream_t s)
     HIP_TRY(launch_pack(L, c->skey, c->perm, c->X.as<double>(), c->q4.as<ushort4>(),
                         uses_spos(c->mode) ? c->spos.as<double>() : nullptr,
                         c->mode == NNPS_MODE_FP32_RCLL ? c->rq.as<float4>() : nullptr,
-                        c->dense ? c->inv.as<int>() : nullptr, s));
+                        c->inv.as<int>(), s));
     tm.end(NNPS_PHASE_PACK, s);
     return enqueue_build_tail(c, s);
 }
@@ -875,7 +875,7 @@ void nnps_cells_destroy(nnps_cells* c)
                      &c->table, &c->partial, &c->stats, &c->blk_stats, &c->cbits, &c->err, &c->heavy,
                      &c->nheavy, &c->rowg, &c->nnz, &c->sink, &c->usz, &c->wdense, &c->uoff, &c->nsl, &c->unit_off,
                      &c->ucell, &c->dn, &c->ecnt, &c->epos, &c->uk0, &c->uk1, &c->uv0, &c->uv1, &c->inv,
-                     &c->ucount, &c->dstats, &c->dseen, &c->umig, &c->uleave, &c->uarrive, &c->ucs_old,
+                     &c->ucount, &c->dstats, &c->dseen, &c->uleave, &c->ucs_old,
                      &c->uskey2, &c->uperm2};
     for (DevBuf* b : all) b->release();
     c->timer.release();

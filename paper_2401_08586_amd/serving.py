@@ -268,17 +268,23 @@ class Server:
             self.cells[s] = None
 
     def _apply(self, s, stream):
-        """Add a drawn displacement to the positions (paths that rebuild instead of updating)."""
+        """Apply a drawn displacement to the positions as the library's update does (paths
+        that rebuild instead of updating): p + d, or p - d for a component where p + d would
+        leave the box."""
         if self.pending[s]:
-            with self.torch.cuda.stream(stream):
-                self.pos[s].add_(self.disp[s])
+            torch = self.torch
+            lo, hi = self.box[s]
+            with torch.cuda.stream(stream):
+                p, d = self.pos[s], self.disp[s]
+                q = p + d
+                p.copy_(torch.where((q >= lo) & (q <= hi), q, p - d))
             self.pending[s] = False
 
     def _move(self, s, stream):
         """The simulation's time step: a displacement U(-frac dx, +frac dx) per component,
-        dx = radius / 2.4, with a component's sign flipped where it would take the particle
-        out of the box (a reflection at the walls; seeded per simulation and step). It is
-        applied by the next step's update (or added before its rebuild)."""
+        dx = radius / 2.4 (seeded per simulation and step; one device launch). The next
+        step's update applies it, reflecting a component that would leave the box (the
+        rebuild paths apply it the same way first)."""
         torch = self.torch
         ps = self.sims[s]
         g = self.gen.get(s)
@@ -292,9 +298,6 @@ class Server:
             if d is None or d.shape != p.shape:
                 d = self.disp[s] = torch.empty_like(p)
             d.uniform_(-a, a, generator=g)
-            lo, hi = self.box[s]
-            new = p + d  # the binary64 sum the update forms
-            d.copy_(torch.where((new < lo) | (new > hi), -d, d))
             ev = torch.cuda.Event()
             ev.record(stream)
         self.pending[s] = True
