@@ -23,16 +23,21 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic of one fill launch at the default workload, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE per dispatch scaled by what they read for a 512 MiB device copy (x2.000 and
-# x1.000); valid only for the kernel source it was measured on (see profiles/).
-FILL_TRAFFIC = {"source_sha256_16": "269b20a981b302ba", "bytes": (229886 * 2.0 + 477191 * 1.0) * 1024,
-                "fetch_kib": 229886, "write_kib": 477191, "fetch_scale": 2.0, "write_scale": 1.0}
+# HBM traffic of one fill launch at the default workload, measured by rocprofv3 on the
+# kernel source with this hash (profiles/k_fill_k_count_lattice3d_1M.md):
+#   DRAM bytes: TCC_EA0_RDREQ_DRAM_32B_sum and TCC_EA0_WRREQ_WRITE_DRAM_32B_sum count
+#     32-byte units of DRAM traffic; a 512 MiB device copy reads and writes exactly 2^24
+#     of each (calibration factor 1.000);
+#   FETCH_SIZE / WRITE_SIZE (KiB): the copy reads 262,144 KiB fetched and 524,288 KiB
+#     written for 524,288 KiB moved each way, so they scale by 2.000 and 1.000.
+# Reported only while the source is unchanged (the counters belong to that code).
+FILL_TRAFFIC = {"source_sha256_16": "58090986a0527b89", "dram_read_bytes": 216.1e6, "dram_write_bytes": 486.1e6,
+                "fetch_kib": 106857, "write_kib": 474695, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 # VALU wave-instructions per launch (SQ_INSTS_VALU) of the C2 search kernels, from the
 # profile of the same source; like the traffic, reported only while the source is unchanged
-VALU_INSTS = {"source_sha256_16": "269b20a981b302ba", "k_fill<3,0>": 203754362, "k_count16<3,0,false>": 130140564}
+VALU_INSTS = {"source_sha256_16": "58090986a0527b89", "k_fill<3,0>": 157913880, "k_count16<3,0,false>": 130146013}
 
 
 def valu_ceilings():
@@ -88,12 +93,19 @@ def measured_copy_gbs(nbytes=1 << 29, reps=10):
 
 
 def fill_traffic():
-    """Measured fill traffic (bytes per launch) if the search kernels are unchanged since."""
+    """Measured fill traffic per launch if the search kernels are unchanged since the profile:
+    DRAM bytes (read + write) and the FETCH_SIZE/WRITE_SIZE reading scaled by the copy."""
     import hashlib
     src = os.path.join(ROOT, "paper_2401_08586_amd", "csrc", "search_kernels.hip")
     with open(src, "rb") as f:
         h = hashlib.sha256(f.read()).hexdigest()[:16]
-    return FILL_TRAFFIC["bytes"] if h == FILL_TRAFFIC["source_sha256_16"] else None
+    if h != FILL_TRAFFIC["source_sha256_16"]:
+        return None, None
+    t = FILL_TRAFFIC
+    dram = t["dram_read_bytes"] + t["dram_write_bytes"]
+    fw = (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024
+    return dram, {"dram_read_bytes": t["dram_read_bytes"], "dram_write_bytes": t["dram_write_bytes"],
+                  "fetch_write_size_bytes": fw, "source_sha256_16": h}
 
 
 def log(*a):
@@ -295,6 +307,7 @@ def main():
 
     fill_ms = ph16["fill"]
     fb = fill_bytes(ps, nnz, st16["band_pairs"])
+    traffic, traffic_detail = fill_traffic() if args.workload == "c2" else (None, None)
     achieved = fb / (fill_ms * 1e-3) / 1e9
     out = {
         "metric": "Gpairs/s at 1M-particle 3D NNPS, FP16 RCLL vs FP64; p50/p99 request latency",
@@ -312,7 +325,8 @@ def main():
         "config": describe(ps),
         "roofline": {"bound": "hbm", "kernel": "k_fill<3,0> (fill pass)", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": fill_traffic() if args.workload == "c2" else None,
+                     "traffic": traffic,
+                     "traffic_detail": traffic_detail,
                      "algorithmic_bytes_per_launch": fb, "avg_launch_ms": fill_ms,
                      "measured_copy_gbs": copy_gbs},
         "particles_per_s": ps.n / (ms16 * 1e-3),
