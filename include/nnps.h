@@ -18,7 +18,9 @@
  * plus the integer offset of the two cells (Eq. 7, with the factor 1/2 Eq. 7 drops).
  * Pairs whose FP16 r2 lies within a guard band of the cutoff are decided again in
  * FP64 from the caller's positions, so the neighbour set is exactly the binary64
- * one above. FP64 is used on the GPU only for cell assignment and that recheck.
+ * one above. FP64 arithmetic on the GPU is used for cell assignment, that recheck, and
+ * one exact subtraction per coordinate of two fixed-point positions (integers below 2^52
+ * held as doubles) for each emitted FP32 distance; the neighbour test itself is FP16.
  *
  * Memory: every pointer named d_* is device memory on the context's device.
  * The caller owns positions and all outputs; the library owns the context and
