@@ -86,8 +86,10 @@ hipError_t launch_dense_cells(const Launch& L, const int* cell_start, const Dens
 // After the sort and pack: the union lists. *ulist receives the sorted list array.
 hipError_t launch_dense_unions(const Launch& L, const uint32_t* skey, const int* inv, const DenseBuild& d,
                                hipStream_t st, int** ulist);
+// Row pointers of every set from the counts; also each particle's row start by sorted
+// position (rsort[inv[i]]).
 hipError_t launch_rowptr(const Launch& L, const int* counts, int64_t* rowg, int64_t* partial, int64_t* nnz,
-                         hipStream_t st);
+                         const int* inv, int64_t* rsort, hipStream_t st);
 
 // Search passes over every block of every set. `nblk_max` bounds the number of blocks
 // (the exact count is on the device).
@@ -104,6 +106,9 @@ struct SearchArgs {
     const int* bset;          // set of each block [nblk]
     const int* nblk;          // device pointer to the block count
     int* counts;              // per global particle (count pass)
+    int* counts_s;            // the same by sorted position (the fill reads them in block order)
+    int64_t* rsort;           // each particle's row start in its set's output, by sorted position
+    int* bdesc;               // [nblk_max][24] per-block descriptors the count pass leaves for the fill
     int* heavy;               // sorted positions of long rows
     int* nheavy;
     unsigned long long* stats;      // [kStCount] totals

@@ -648,7 +648,8 @@ k_row_blocks(const SetDesc* __restrict__ sets, const int* __restrict__ roffs, in
 // row boundary: set s has n_s + 1 of them), and each set's nnz.
 __global__ void __launch_bounds__(256)
 k_rowptr_scatter(const SetDesc* __restrict__ sets, const int* __restrict__ poffs, int nsets, int ntot,
-                 const int64_t* __restrict__ rowg, int64_t* __restrict__ nnz)
+                 const int64_t* __restrict__ rowg, int64_t* __restrict__ nnz, const int* __restrict__ inv,
+                 int64_t* __restrict__ rsort)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ntot + nsets) return;
@@ -664,6 +665,7 @@ k_rowptr_scatter(const SetDesc* __restrict__ sets, const int* __restrict__ poffs
     const int64_t v = rowg[sd.poff + i] - rowg[sd.poff];
     if (sd.row_ptr) sd.row_ptr[i] = v;
     if (i == sd.fr.n) nnz[lo] = v;
+    else rsort[inv[sd.poff + i]] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -1001,13 +1003,13 @@ hipError_t launch_dense_unions(const Launch& L, const uint32_t* skey, const int*
 }
 
 hipError_t launch_rowptr(const Launch& L, const int* counts, int64_t* rowg, int64_t* partial, int64_t* nnz,
-                         hipStream_t st)
+                         const int* inv, int64_t* rsort, hipStream_t st)
 {
     hipError_t e = scan_exclusive<int, int64_t>(counts, L.ntot, rowg, partial, st);
     if (e != hipSuccess) return e;
     const int m = L.ntot + L.nsets;
     hipLaunchKernelGGL(k_rowptr_scatter, dim3((m + 255) / 256), dim3(256), 0, st, L.sets, L.poffs, L.nsets,
-                       L.ntot, rowg, nnz);
+                       L.ntot, rowg, nnz, inv, rsort);
     return hipGetLastError();
 }
 

@@ -279,6 +279,7 @@ struct nnps_cells {
     uint64_t buf_gen = 0;                 // bumps whenever a device buffer moves
     uint32_t* skey = nullptr;
     int* perm = nullptr;
+    DevBuf counts_s, rsort, bdesc;
     DevBuf d_sets, d_offs, X, k0, k1, v0, v1, cell_count, cell_start, q4, spos, rq, boff, bstart, bset,
         counts, table, partial, stats, blk_stats, cbits, err, heavy, nheavy, rowg, nnz, sink;
     // dense-cell path (see DenseBuild)
@@ -360,6 +361,9 @@ SearchArgs args_of(const nnps_cells* c)
     a.bset = c->bset.as<int>();
     a.nblk = c->boff.as<int>() + c->nrows_tot;
     a.counts = c->counts.as<int>();
+    a.counts_s = c->counts_s.as<int>();
+    a.rsort = c->rsort.as<int64_t>();
+    a.bdesc = c->bdesc.as<int>();
     a.heavy = c->heavy.as<int>();
     a.nheavy = c->nheavy.as<int>();
     a.stats = c->stats.as<unsigned long long>();
@@ -514,7 +518,8 @@ nnps_status prepare(nnps_ctx* ctx, nnps_cells* c, int nsets, const nnps_problem*
         {&c->spos, base ? nn * 4 * sizeof(double) : 0},
         {&c->rq, c->mode == NNPS_MODE_FP32_RCLL ? nn * sizeof(float4) : 0},
         {&c->boff, (static_cast<size_t>(c->nrows_tot) + 1) * 4}, {&c->bstart, (nn + 2) * 4}, {&c->bset, (nn + 1) * 4},
-        {&c->counts, nn * 4},
+        {&c->counts, nn * 4}, {&c->counts_s, nn * 4}, {&c->rsort, nn * 8},
+        {&c->bdesc, static_cast<size_t>(std::max(c->nblk_max, 1) + kXcdPad) * kBlockDescInts * 4},
         {&c->table, table_n * 4},
         {&c->partial, static_cast<size_t>(scan_partials_needed(scan_m) + 1) * 8},
         {&c->stats, kStCount * 8},
@@ -669,7 +674,7 @@ nnps_status enqueue_count(nnps_cells* c, hipStream_t s)
     HIP_TRY(launch_stats(a, s));
     c->timer.begin(NNPS_PHASE_ROWSCAN, s);
     HIP_TRY(launch_rowptr(a.L, c->counts.as<int>(), c->rowg.as<int64_t>(), c->partial.as<int64_t>(),
-                          c->nnz.as<int64_t>(), s));
+                          c->nnz.as<int64_t>(), c->inv.as<int>(), c->rsort.as<int64_t>(), s));
     c->timer.end(NNPS_PHASE_ROWSCAN, s);
     c->counted = true;
     return NNPS_OK;
@@ -876,7 +881,7 @@ void nnps_cells_destroy(nnps_cells* c)
                      &c->nheavy, &c->rowg, &c->nnz, &c->sink, &c->usz, &c->wdense, &c->uoff, &c->nsl, &c->unit_off,
                      &c->ucell, &c->dn, &c->ecnt, &c->epos, &c->uk0, &c->uk1, &c->uv0, &c->uv1, &c->inv,
                      &c->ucount, &c->dstats, &c->dseen, &c->uleave, &c->ucs_old,
-                     &c->uskey2, &c->uperm2};
+                     &c->uskey2, &c->uperm2, &c->counts_s, &c->rsort, &c->bdesc};
     for (DevBuf* b : all) b->release();
     c->timer.release();
     c->graph.reset();

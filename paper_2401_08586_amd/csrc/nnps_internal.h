@@ -37,6 +37,11 @@ constexpr int kDenseGrid = 1024;
 constexpr int64_t kDenseMaxEntries = int64_t(1) << 28;
 constexpr int kDenseStats = 6;  // candidates, band, false pos, false neg, outside disagree, rows
 
+// Per-block descriptors the count pass leaves for the fill (ints per block), and the
+// spare descriptors of the last round over the XCDs.
+constexpr int kBlockDescInts = 24;
+constexpr int kXcdPad = 8;
+
 // Device error flags.
 constexpr int kErrDomain = 1;
 constexpr int kErrCapacity = 2;

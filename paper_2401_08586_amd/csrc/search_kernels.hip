@@ -169,6 +169,71 @@ struct Geom {
     }
 };
 
+// Per-block descriptor the count pass leaves for the fill, so the fill's set-up reads the
+// block's geometry with one load instead of re-deriving it through the block table, the
+// sorted cell keys and the cell starts: [0] first particle, [1] end, [2] set, [3] union
+// size, [4] 1 for a block of the dense-cell path, then the NSEG segment first-particle
+// indices and the NSEG segment union offsets.
+constexpr int kDescInts = kBlockDescInts;
+
+template <int DIM>
+__device__ __forceinline__ void write_desc(const SearchArgs& a, const Geom<DIM>& g, int b)
+{
+    const int lane = threadIdx.x & 63;
+    int v = 0;
+    if (lane == 0) v = g.p0;
+    if (lane == 1) v = g.p1;
+    if (lane == 2) v = a.bset[b];
+    if (lane == 3) v = g.U;
+#pragma unroll
+    for (int r = 0; r < Geom<DIM>::NSEG; ++r) {
+        if (lane == 5 + r) v = g.seg_g0[r];
+        if (lane == 5 + Geom<DIM>::NSEG + r) v = g.seg_base[r];
+    }
+    if (lane < kDescInts) a.bdesc[static_cast<size_t>(b) * kDescInts + lane] = v;
+}
+
+// A dense-cell block: only its flag is written.
+__device__ __forceinline__ void write_desc_dense(const SearchArgs& a, int b)
+{
+    if ((threadIdx.x & 63) == 4) a.bdesc[static_cast<size_t>(b) * kDescInts + 4] = 1;
+}
+
+// The fill's view of a block, from its descriptor (lane = target).
+template <int DIM>
+struct FillGeom {
+    static constexpr int NSEG = Geom<DIM>::NSEG;
+    static constexpr int SELF = Geom<DIM>::SELF;
+    int p0, p1, p, U, pself;
+    bool active;
+    int seg_g0[NSEG], seg_base[NSEG];
+    const SetDesc* sd;
+    __device__ __forceinline__ void init(const SearchArgs& a, const int* __restrict__ d)
+    {
+        const int lane = threadIdx.x & 63;
+        p0 = d[0];
+        p1 = d[1];
+        sd = a.L.sets + d[2];
+        U = d[3];
+#pragma unroll
+        for (int r = 0; r < NSEG; ++r) {
+            seg_g0[r] = d[5 + r];
+            seg_base[r] = d[5 + NSEG + r];
+        }
+        p = p0 + lane;
+        active = p < p1;
+        pself = seg_base[SELF] + (p - seg_g0[SELF]);
+    }
+    __device__ __forceinline__ int global_of_any(int posl) const
+    {
+        int gi = posl - seg_base[0] + seg_g0[0];
+#pragma unroll
+        for (int k = 1; k < NSEG; ++k)
+            if (posl >= seg_base[k]) gi = posl - seg_base[k] + seg_g0[k];
+        return gi;
+    }
+};
+
 // The fields of a set a kernel uses in its loops, read once into registers. Read through
 // the set table instead, they would be loaded again after every store (the compiler
 // cannot tell the stores from the table), each time waiting on memory. The outputs are
@@ -516,10 +581,12 @@ k_count16(SearchArgs a)
     const int lane = threadIdx.x & 63;
     if (dense_block(a, b)) {
         if (lane < 5) a.blk_stats[static_cast<size_t>(b) * 5 + lane] = 0;
+        write_desc_dense(a, b);
         return;
     }
     Geom<DIM> g;
     g.init(a, b);
+    write_desc(a, g, b);
     const Frame& fr = g.fr;
     const int pp = g.active ? g.p : g.p1 - 1;
     const int oi = a.perm[pp];
@@ -653,7 +720,10 @@ k_count16(SearchArgs a)
         // candidates: the lane's ranges minus itself
         if (g.active) t.cand += cb_.total - 1;
     }
-    if (g.active) a.counts[oi] = static_cast<int>(cnt);
+    if (g.active) {
+        a.counts[oi] = static_cast<int>(cnt);
+        a.counts_s[g.p] = static_cast<int>(cnt);
+    }
     cb_.store(a, g.p);
     unsigned long long v[5] = {t.cand, t.band, t.fpos, t.fneg, t.odis};
 #pragma unroll
@@ -674,10 +744,12 @@ k_count64(SearchArgs a)
     if (b < 0) return;
     if (dense_block(a, b)) {
         if ((threadIdx.x & 63) < 5) a.blk_stats[static_cast<size_t>(b) * 5 + (threadIdx.x & 63)] = 0;
+        write_desc_dense(a, b);
         return;
     }
     Geom<DIM> g;
     g.init(a, b);
+    write_desc(a, g, b);
     const Frame& fr = g.fr;
     CB cb_;
     cb_.init(g, lbits);
@@ -713,6 +785,7 @@ k_count64(SearchArgs a)
         if (!HALF) cnt -= 1;  // itself (r2 = 0)
         cand -= 1;
         a.counts[oi] = cnt;
+        a.counts_s[g.p] = cnt;
     }
     cb_.store(a, g.p);
     const unsigned long long s = wave_sum_u64(cand);
@@ -764,10 +837,12 @@ k_count32(SearchArgs a)
     const int lane = threadIdx.x & 63;
     if (dense_block(a, b)) {
         if (lane < 5) a.blk_stats[static_cast<size_t>(b) * 5 + lane] = 0;
+        write_desc_dense(a, b);
         return;
     }
     Geom<DIM> g;
     g.init(a, b);
+    write_desc(a, g, b);
     const Frame& fr = g.fr;
     const int pp = g.active ? g.p : g.p1 - 1;
     const int oi = a.perm[pp];
@@ -850,6 +925,7 @@ k_count32(SearchArgs a)
         for (int r = 0; r < Geom<DIM>::NSEG; ++r) t.cand += g.lb[r] - g.la[r];
         t.cand -= 1;  // itself
         a.counts[oi] = cnt;
+        a.counts_s[g.p] = cnt;
     }
     cb_.store(a, g.p);
     const unsigned long long v[5] = {t.cand, t.band, t.fpos, t.fneg, 0ull};
@@ -1228,19 +1304,20 @@ k_fill(SearchArgs a)
     static_assert(64 << C::SHIFT <= 65536 && (1 << C::SHIFT) == C::UCAP, "flat entries fit 16 bits");
 
     const int b = xcd_block(*a.nblk);
-    if (b < 0 || dense_block(a, b)) return;
+    if (b < 0) return;
+    // the block's geometry from the count pass's descriptor (wave-uniform), and each
+    // target's row start and length in sorted order: no chain of dependent loads
+    const int* __restrict__ dsc = a.bdesc + static_cast<size_t>(b) * kDescInts;
+    if (dsc[4]) return;  // a block of the dense-cell path
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront index, uniform
-    // every wavefront holds the block's geometry; lane = target
-    Geom<DIM> g;
-    g.init(a, b);
-    const Frame& fr = g.fr;
+    FillGeom<DIM> g;
+    g.init(a, dsc);
     const SetView sd(*g.sd);
+    const float dist_scale = g.sd->fr.dist_scale;  // in a register: stores below cannot change it
     const int pp = g.active ? g.p : g.p1 - 1;
-    const int oi = a.perm[pp];
-    const int li = oi - sd.poff;
-    const long long rs = sd.row_ptr[li];
-    const int rlen = g.active ? static_cast<int>(sd.row_ptr[li + 1] - rs) : 0;
+    const long long rs = a.rsort[pp];
+    const int rlen = g.active ? a.counts_s[g.p] : 0;
     int E;
     const int off = wave_excl_scan_i32(rlen, &E);
     E = __builtin_amdgcn_readfirstlane(E);  // the block's entry count, wave-uniform
@@ -1280,6 +1357,8 @@ k_fill(SearchArgs a)
     }
     if (wv == 0) {
         sbase[lane] = rs - off;
+        const int oi = a.perm[pp];
+        const int li = oi - sd.poff;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
             // the target's own coordinates for the distance: fixed point, or FP64 bits (baseline)
@@ -1410,7 +1489,7 @@ k_fill(SearchArgs a)
                 const float f = static_cast<float>(s.xj[c] - sxi[s.t * DIM + c]);  // exact difference, one rounding
                 s2 = s2 + f * f;
             }
-            return __builtin_amdgcn_sqrtf(s2) * fr.dist_scale;  // <= 1 ulp; s2 >= 1 or 0
+            return __builtin_amdgcn_sqrtf(s2) * dist_scale;  // <= 1 ulp; s2 >= 1 or 0
         }
     };
     constexpr int R = 64 * NW;  // stride between a wavefront's rounds
