@@ -1402,28 +1402,60 @@ k_fill(SearchArgs a)
     else rank_union<C::UCAP, C::SHIFT, NW, 4>(U, Q, packed, omin, key_of, skeys, rank_of, sorig);
     __syncthreads();
     // 3. accepted candidates from the count pass, re-indexed by rank into each target's
-    // mask; wavefront wv takes the target's bit words w = wv (mod 4)
+    // mask. Wavefront wv holds the bit words w = wv (mod 4) of every target; it lists its
+    // nonzero ones (one ballot per word) in LDS and then takes one listed word per lane,
+    // so a round of bit extraction waits for the fullest of 64 nonzero words, not for the
+    // fullest lane of every word. The list lives in the ranking scratch, dead by now.
     uint32_t* mk = masks + lane * (C::MW + 1);
-    if (g.active) {
+    {
+        constexpr int kListBytes = kShared - C::UCAP * 2;
+        constexpr int LCAP = (kListBytes / NW / 6) & ~63;  // entries per wavefront
+        static_assert(LCAP >= 64, "a wavefront lists at least one word per lane");
+        uint32_t* lbits = reinterpret_cast<uint32_t*>(smem + C::UCAP * 2) + wv * LCAP;
+        uint16_t* ltw = reinterpret_cast<uint16_t*>(smem + C::UCAP * 2 + NW * LCAP * 4) + wv * LCAP;
+        auto drain = [&](int n) {
+            for (int e = lane; e < n; e += 64) {
+                uint32_t bits = lbits[e];
+                const int tw = ltw[e];
+                uint32_t* mt = masks + (tw & 63) * (C::MW + 1);
+                const int w32 = (tw >> 6) * 32;
+                // four bits per round: their rank lookups are issued together, and bits past
+                // the word's last read entry 0 and OR nothing
+                while (bits) {
+                    uint32_t rk[4], on[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        on[j] = bits != 0u ? 1u : 0u;
+                        const int posl = w32 + __builtin_ctz(bits | (on[j] ? 0u : 1u));
+                        bits &= bits - 1u;
+                        rk[j] = rank_of[on[j] ? posl : 0];
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) atomicOr(&mt[rk[j] >> 5], on[j] << (rk[j] & 31));
+                }
+            }
+        };
+        int qn = 0;
 #pragma unroll
         for (int k = 0; k < KW; ++k) {
             const int w = wv + NW * k;
-            uint32_t bits = wbits[k];
-            // four bits per round: their rank lookups are issued together, and bits past
-            // the word's last read entry 0 and OR nothing
-            while (bits) {
-                uint32_t rk[4], on[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    on[j] = bits != 0u ? 1u : 0u;
-                    const int posl = 32 * w + __builtin_ctz(bits | (on[j] ? 0u : 1u));
-                    bits &= bits - 1u;
-                    rk[j] = rank_of[on[j] ? posl : 0];
-                }
-#pragma unroll
-                for (int j = 0; j < 4; ++j) atomicOr(&mk[rk[j] >> 5], on[j] << (rk[j] & 31));
+            const uint32_t word = g.active ? wbits[k] : 0u;
+            const uint64_t nz = __builtin_amdgcn_ballot_w64(word != 0u);
+            const int add = __builtin_popcountll(nz);
+            if (qn + add > LCAP) {  // wave-uniform
+                drain(qn);
+                qn = 0;
             }
+            if (word) {
+                const int at = qn + static_cast<int>(__builtin_amdgcn_mbcnt_hi(
+                                        static_cast<uint32_t>(nz >> 32),
+                                        __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(nz), 0u)));
+                lbits[at] = word;
+                ltw[at] = static_cast<uint16_t>(lane | (w << 6));
+            }
+            qn += add;
         }
+        drain(qn);
     }
     // the target's own bit (set by the count pass when it accepted the target itself) is
     // masked out below

@@ -181,6 +181,36 @@ def test_long_rows(ctx):
         assert got[3]["dense_rows"] > 0
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_many_band_pairs_per_target(ctx, dim):
+    """Centres with 24 neighbours each at distance R (1 + k 2^-12), k in {-1, 0, 1}: every
+    one of them is a band pair of its centre, more than the count pass queues per target,
+    so the rest are decided on the spot; the CSR and the FP16 statistics must still be
+    the oracle's and the model's."""
+    rng = np.random.default_rng(40 + dim)
+    R = 0.02
+    side = 12
+    g = (np.stack(np.meshgrid(*[np.arange(side)] * dim, indexing="ij"), -1).reshape(-1, dim) + 0.5) * (3.2 * R)
+    pts = [g]
+    for k in (-1, 0, 1):
+        for _ in range(8):
+            d = rng.normal(size=g.shape)
+            d /= np.linalg.norm(d, axis=1, keepdims=True)
+            pts.append(g + d * R * (1.0 + k * 2.0 ** -12))
+    pos = np.concatenate(pts)
+    box = side * 3.2 * R
+    ps = W.ParticleSet(np.ascontiguousarray(pos), (0.0,) * dim, (box,) * dim, R, R, f"band_shells_{dim}d")
+    print(f"[gpu] band shells {ps.name} n={ps.n}", flush=True)
+    want = oracle.search_ps(ps)
+    got = gpu_search(ctx, ps, nnps.MODE_FP16_RCLL)
+    check_against_oracle(got, want, nnps.MODE_FP16_RCLL, ps.name)
+    model = M.stats(ps.pos, ps.lo, ps.hi, ps.cell_size, ps.radius)
+    st = got[3]
+    assert model["band_pairs"] >= 24 * side ** dim
+    for key in ("candidates", "band_pairs", "fp16_false_pos", "fp16_false_neg"):
+        assert st[key] == model[key], key
+
+
 @pytest.mark.parametrize("radius_factor,block_target", [(2.6, 80), (2.6, 128), (2.4, 128), (2.9, 64)])
 def test_block_shape_stays_within_the_fill_limits(ctx, radius_factor, block_target):
     """More neighbours per particle than the default workloads, and large block targets:
