@@ -1342,11 +1342,24 @@ k_fill(SearchArgs a)
     // 1. stage the union's original indices; clear the masks
     const int U = g.U;
     int omin = 0x7FFFFFFF, omax = 0;
-    for (int e = tid; e < U; e += kFillThreads) {
-        const int o = a.perm[g.global_of_any(e)];
-        sorig[e] = o;
-        omin = min(omin, o);
-        omax = max(omax, o);
+    {
+        // a thread's gathers are issued together, then stored
+        constexpr int EPT = C::UCAP / kFillThreads;
+        int og[EPT];
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = tid + i * kFillThreads;
+            og[i] = e < U ? a.perm[g.global_of_any(e)] : -1;
+        }
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = tid + i * kFillThreads;
+            if (e < U) {
+                sorig[e] = og[i];
+                omin = min(omin, og[i]);
+                omax = max(omax, og[i]);
+            }
+        }
     }
     for (int i = tid; i < 64 * (C::MW + 1); i += kFillThreads) masks[i] = 0;
     omin = wave_min_i32(omin);
@@ -1542,21 +1555,25 @@ k_fill(SearchArgs a)
             sd.col[s.idx] = s.oj - sd.poff;
             sd.dist[s.idx] = d;
         };
-        // three entry sets in rotation: the fetch two rounds ahead never waits for a copy
-        Ent A, B, Cn;
+        // four entry sets in rotation: the fetch three rounds ahead never waits for a copy
+        Ent A, B, Cn, D;
         int e0 = wv * 64;
         if (e0 < E) {
             fetch(e0 + lane, A);
             fetch(e0 + R + lane, B);
+            fetch(e0 + 2 * R + lane, Cn);
             for (;;) {
-                fetch(e0 + 2 * R + lane, Cn);
+                fetch(e0 + 3 * R + lane, D);
                 emit(A);
                 if ((e0 += R) >= E) break;
-                fetch(e0 + 2 * R + lane, A);
+                fetch(e0 + 3 * R + lane, A);
                 emit(B);
                 if ((e0 += R) >= E) break;
-                fetch(e0 + 2 * R + lane, B);
+                fetch(e0 + 3 * R + lane, B);
                 emit(Cn);
+                if ((e0 += R) >= E) break;
+                fetch(e0 + 3 * R + lane, Cn);
+                emit(D);
                 if ((e0 += R) >= E) break;
             }
         }
