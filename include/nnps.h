@@ -199,7 +199,9 @@ nnps_status nnps_search(nnps_ctx *ctx, nnps_cells *cells, const nnps_problem *pr
                         const double *d_pos, int64_t *d_row_ptr, int32_t *d_col, float *d_dist,
                         int64_t capacity, int64_t *nnz_out, void *stream);
 
-/* Waits for the stream, then copies the statistics of the last count pass.
+/* Sums the last count pass's per-block statistics on `stream` (the count pass leaves
+ * them per block, so a search step does not pay for the sum), waits for the stream and
+ * copies them; all zero if nothing was counted since the last build.
  * Returns any device-detected error (NNPS_EDOMAIN, NNPS_ECAPACITY, NNPS_EUNSUPPORTED). */
 nnps_status nnps_stats_get(nnps_cells *cells, nnps_stats *out, void *stream);
 

@@ -19,6 +19,7 @@ struct Launch {
 };
 
 hipError_t launch_fill_i32(int* p, int64_t m, int v, hipStream_t st);
+hipError_t launch_fill2_i32(int* p, int64_t m, int* q, int64_t k, int v, hipStream_t st);
 int row_segments(int ncx);  // pieces a row of ncx cells is walked in
 hipError_t launch_assign(const Launch& L, double* X, uint32_t* key, int* slot, int* cell_count, int* err,
                          hipStream_t st);

@@ -101,6 +101,16 @@ k_fill_i32(int* __restrict__ p, int64_t m, int v)
         p[i] = v;
 }
 
+// Two arrays in one launch.
+__global__ void __launch_bounds__(256)
+k_fill2_i32(int* __restrict__ p, int64_t m, int* __restrict__ q, int64_t k, int v)
+{
+    const int64_t i0 = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = i0; i < m; i += step) p[i] = v;
+    for (int64_t i = i0; i < k; i += step) q[i] = v;
+}
+
 // ---------------------------------------------------------------------------
 // Device-wide exclusive scan (int32 in, TOut out), three phases over tiles of
 // kScanTile elements: tile sums, a scan of the tile sums, then each tile scanned
@@ -813,6 +823,15 @@ k_union_emit(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, in
 // ---------------------------------------------------------------------------
 // Host-side launchers.
 int row_segments(int ncx) { return (ncx + kRowSegment - 1) / kRowSegment; }
+
+hipError_t launch_fill2_i32(int* p, int64_t m, int* q, int64_t k, int v, hipStream_t st)
+{
+    const int64_t n = std::max(m, k);
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill2_i32, dim3(blocks), dim3(256), 0, st, p, m, q, k, v);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill_i32(int* p, int64_t m, int v, hipStream_t st)
 {

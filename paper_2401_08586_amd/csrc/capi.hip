@@ -272,6 +272,9 @@ struct nnps_cells {
     int h_cap = 0;                        // sets the pinned mirrors can hold
     hipEvent_t upload_done = nullptr;     // last upload from the pinned mirrors
     bool upload_pending = false;
+    // what the device tables hold (bytes of the last upload, and the buffers' generation)
+    std::vector<unsigned char> up_sets, up_offs;
+    uint64_t up_gen = ~0ull;
     int64_t* h_report = nullptr;          // pinned: nnz per set, then error and dense words
     int h_report_cap = 0;
     hipEvent_t report_done = nullptr;     // the last enqueued report's copies
@@ -320,11 +323,27 @@ nnps_status wait_upload(nnps_cells* c)
     return NNPS_OK;
 }
 
+// Queue the copies of the set table (and the offsets) to the device, unless the device
+// tables already hold exactly these bytes: no kernel writes them, so they hold what was
+// last copied into the same buffers. Repeated steps over the same sets and outputs then
+// copy nothing.
 nnps_status upload(nnps_cells* c, bool with_offsets, hipStream_t s)
 {
-    HIP_TRY(hipMemcpyAsync(c->d_sets.p, c->h_sets, sizeof(SetDesc) * c->nsets, hipMemcpyHostToDevice, s));
-    if (with_offsets)
-        HIP_TRY(hipMemcpyAsync(c->d_offs.p, c->h_offs, sizeof(int) * 3 * (c->nsets + 1), hipMemcpyHostToDevice, s));
+    const size_t ns = sizeof(SetDesc) * c->nsets, no = sizeof(int) * 3 * (c->nsets + 1);
+    const unsigned char* hs = reinterpret_cast<const unsigned char*>(c->h_sets);
+    const unsigned char* ho = reinterpret_cast<const unsigned char*>(c->h_offs);
+    const bool gen_ok = c->up_gen == c->buf_gen;
+    const bool sets_ok = gen_ok && c->up_sets.size() == ns && memcmp(c->up_sets.data(), hs, ns) == 0;
+    const bool offs_ok = !with_offsets || (gen_ok && c->up_offs.size() == no && memcmp(c->up_offs.data(), ho, no) == 0);
+    if (sets_ok && offs_ok) return NNPS_OK;
+    if (!gen_ok) c->up_offs.clear();  // the offsets buffer moved too: not known to hold anything
+    HIP_TRY(hipMemcpyAsync(c->d_sets.p, c->h_sets, ns, hipMemcpyHostToDevice, s));
+    c->up_sets.assign(hs, hs + ns);
+    if (with_offsets) {
+        HIP_TRY(hipMemcpyAsync(c->d_offs.p, c->h_offs, no, hipMemcpyHostToDevice, s));
+        c->up_offs.assign(ho, ho + no);
+    }
+    c->up_gen = c->buf_gen;
     HIP_TRY(hipEventRecord(c->upload_done, s));
     c->upload_pending = true;
     return NNPS_OK;
@@ -577,8 +596,7 @@ nnps_status enqueue_update(nnps_cells* c, hipStream_t s)
     PhaseTimer& tm = c->timer;
     const Update u = update_of(c);
     const int64_t zero = 2 * (static_cast<int64_t>(c->ncell_tot) + 1) + (c->ntot + 31) / 32;
-    HIP_TRY(launch_fill_i32(u.leave, zero, 0, s));
-    HIP_TRY(launch_fill_i32(c->err.as<int>(), 1, 0, s));
+    HIP_TRY(launch_fill2_i32(u.leave, zero, c->err.as<int>(), 1, 0, s));
     tm.begin(NNPS_PHASE_ASSIGN, s);
     HIP_TRY(launch_update_move(L, c->skey, c->inv.as<int>(), c->X.as<double>(), u, c->err.as<int>(), s));
     tm.end(NNPS_PHASE_ASSIGN, s);
@@ -602,8 +620,7 @@ nnps_status enqueue_build(nnps_cells* c, hipStream_t s)
 {
     const Launch L = launch_of(c);
     PhaseTimer& tm = c->timer;
-    HIP_TRY(launch_fill_i32(c->cell_count.as<int>(), static_cast<int64_t>(c->ncell_tot) + 1, 0, s));
-    HIP_TRY(launch_fill_i32(c->err.as<int>(), 1, 0, s));
+    HIP_TRY(launch_fill2_i32(c->cell_count.as<int>(), static_cast<int64_t>(c->ncell_tot) + 1, c->err.as<int>(), 1, 0, s));
     tm.begin(NNPS_PHASE_ASSIGN, s);
     HIP_TRY(launch_assign(L, c->X.as<double>(), c->k0.as<uint32_t>(), c->v1.as<int>(), c->cell_count.as<int>(),
                           c->err.as<int>(), s));
@@ -662,7 +679,6 @@ nnps_status enqueue_build_tail(nnps_cells* c, hipStream_t s)
 nnps_status enqueue_count(nnps_cells* c, hipStream_t s)
 {
     SearchArgs a = args_of(c);
-    HIP_TRY(launch_fill_i32(c->stats.as<int>(), 2 * kStCount, 0, s));
     c->timer.begin(NNPS_PHASE_COUNT, s);
     HIP_TRY(launch_count(a, c->nblk_max, s));
     c->timer.end(NNPS_PHASE_COUNT, s);
@@ -671,7 +687,8 @@ nnps_status enqueue_count(nnps_cells* c, hipStream_t s)
         HIP_TRY(launch_dense(a, false, s));
         c->timer.end(NNPS_PHASE_DCOUNT, s);
     }
-    HIP_TRY(launch_stats(a, s));
+    // the per-block statistics stay in place until the next count; nnps_stats_get sums
+    // them when asked, so a step does not pay for the reduction
     c->timer.begin(NNPS_PHASE_ROWSCAN, s);
     HIP_TRY(launch_rowptr(a.L, c->counts.as<int>(), c->rowg.as<int64_t>(), c->partial.as<int64_t>(),
                           c->nnz.as<int64_t>(), c->inv.as<int>(), c->rsort.as<int64_t>(), s));
@@ -1381,6 +1398,10 @@ nnps_status nnps_stats_get(nnps_cells* c, nnps_stats* out, void* stream)
     hipStream_t s = static_cast<hipStream_t>(stream);
     unsigned long long st[kStCount];
     int err = 0, nh = 0;
+    // the sums of the last count pass's per-block (and dense-path) statistics; none
+    // before a count
+    HIP_TRY(launch_fill_i32(c->stats.as<int>(), 2 * kStCount, 0, s));
+    if (c->counted) HIP_TRY(launch_stats(args_of(c), s));
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipMemcpy(st, c->stats.p, sizeof(st), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(&err, c->err.p, 4, hipMemcpyDeviceToHost));
