@@ -295,22 +295,43 @@ __device__ __forceinline__ void stage(const SearchArgs& a, const Geom<DIM>& g, i
     const int lane = threadIdx.x & 63;
     const int m0 = cb >> 1, m1 = (ce + 1) >> 1;
     const uint16_t base16 = static_cast<uint16_t>(g.sx0 & 0xFFFF);
-    for (int m = m0 + lane; m < m1; m += 64) {
+    // a chunk is at most kStage / 128 records per lane: every gather is issued before
+    // the first record is built
+    constexpr int RPL = kStage / 128;
+    ushort4 v[RPL][2];
+    int o[RPL][2];
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+        const int m = m0 + lane + 64 * i;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int posl = 2 * m + h;
+            v[i][h] = make_ushort4(0, 0, 0, 0);
+            o[i][h] = 0;
+            if (m < m1 && posl < ce) {
+                const int gi = g.global_of_any(posl);
+                v[i][h] = a.q4[gi];
+                if (ORIG) o[i][h] = a.perm[gi];
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+        const int m = m0 + lane + 64 * i;
+        if (m >= m1) continue;
         uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int posl = 2 * m + h;
             if (posl < ce) {
-                const int gi = g.global_of_any(posl);
-                const ushort4 v = a.q4[gi];
-                const uint16_t rel = static_cast<uint16_t>(v.w - base16);
+                const uint16_t rel = static_cast<uint16_t>(v[i][h].w - base16);
                 const _Float16 cx2 = static_cast<_Float16>(2 * static_cast<int>(rel));
                 const uint32_t sh = 16u * h;
-                w0 |= static_cast<uint32_t>(v.x) << sh;
-                w1 |= static_cast<uint32_t>(v.y) << sh;
-                w2 |= static_cast<uint32_t>(v.z) << sh;
+                w0 |= static_cast<uint32_t>(v[i][h].x) << sh;
+                w1 |= static_cast<uint32_t>(v[i][h].y) << sh;
+                w2 |= static_cast<uint32_t>(v[i][h].z) << sh;
                 w3 |= static_cast<uint32_t>(__builtin_bit_cast(uint16_t, cx2)) << sh;
-                if (ORIG) sorig[posl - cb] = a.perm[gi];
+                if (ORIG) sorig[posl - cb] = o[i][h];
             }
         }
         srec[m - m0] = make_uint4(w0, w1, w2, w3);
