@@ -31,13 +31,13 @@ HBM_PEAK_GBS = 8000.0
 #   FETCH_SIZE / WRITE_SIZE (KiB): the copy reads 262,144 KiB fetched and 524,288 KiB
 #     written for 524,288 KiB moved each way, so they scale by 2.000 and 1.000.
 # Reported only while the source is unchanged (the counters belong to that code).
-FILL_TRAFFIC = {"source_sha256_16": "58090986a0527b89", "dram_read_bytes": 216.1e6, "dram_write_bytes": 486.1e6,
-                "fetch_kib": 106857, "write_kib": 474695, "fetch_scale": 2.0, "write_scale": 1.0}
+FILL_TRAFFIC = {"source_sha256_16": "f02e3c28ced6173d", "dram_read_bytes": 220.3e6, "dram_write_bytes": 487.1e6,
+                "fetch_kib": 108471, "write_kib": 475827, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 # VALU wave-instructions per launch (SQ_INSTS_VALU) of the C2 search kernels, from the
 # profile of the same source; like the traffic, reported only while the source is unchanged
-VALU_INSTS = {"source_sha256_16": "58090986a0527b89", "k_fill<3,0>": 157913880, "k_count16<3,0,false>": 130146013}
+VALU_INSTS = {"source_sha256_16": "f02e3c28ced6173d", "k_fill<3,0>": 136443896, "k_count16<3,0,false>": 129011482}
 
 
 def valu_ceilings():

@@ -678,6 +678,56 @@ k_rowptr_scatter(const SetDesc* __restrict__ sets, const int* __restrict__ poffs
     else rsort[inv[sd.poff + i]] = v;
 }
 
+// One set: its row pointers are the global exclusive scan of the counts, so the scan's
+// final phase (as k_scan_down_fold) writes them, each particle's row start by sorted
+// position, row_ptr[n] and nnz directly.
+__global__ void __launch_bounds__(kScanThreads)
+k_rowptr_fold1(const SetDesc* __restrict__ sets, const int* __restrict__ counts, int64_t m,
+               const int64_t* __restrict__ partial, int64_t* __restrict__ nnz, const int* __restrict__ inv,
+               int64_t* __restrict__ rsort)
+{
+    __shared__ int64_t sh[4];
+    int64_t* row_ptr = sets[0].row_ptr;
+    int64_t before = 0;
+    for (int64_t t = threadIdx.x; t < blockIdx.x; t += kScanThreads) before += partial[t];
+    int64_t offset;
+    block_excl_scan(before, &offset, sh);
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int64_t s = 0;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        const int64_t idx = base + r;
+        v[r] = idx < m ? counts[idx] : 0;
+        s += v[r];
+    }
+    int64_t tot;
+    // the tile's exclusive prefixes pass through LDS, one pad entry per 16, so the writes
+    // below go out lane by lane: coalesced row pointers and inverse-permutation reads
+    __shared__ int64_t sloc[kScanTile + kScanTile / 16];
+    int64_t run = block_excl_scan(s, &tot, sh);
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        const int e = threadIdx.x * kScanItems + r;
+        sloc[e + (e >> 4)] = run;
+        run += v[r];
+    }
+    __syncthreads();
+    const int64_t tile0 = static_cast<int64_t>(blockIdx.x) * kScanTile;
+    for (int e = threadIdx.x; e < kScanTile; e += kScanThreads) {
+        const int64_t idx = tile0 + e;
+        if (idx < m) {
+            const int64_t val = offset + sloc[e + (e >> 4)];
+            if (row_ptr) row_ptr[idx] = val;
+            rsort[inv[idx]] = val;
+        }
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        if (row_ptr) row_ptr[m] = offset + tot;
+        nnz[0] = offset + tot;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Dense-cell path tables. Where clustering piles hundreds or thousands of particles
 // into a cell, every target of the cell tests the same stencil union, and its rows are
@@ -1024,6 +1074,15 @@ hipError_t launch_dense_unions(const Launch& L, const uint32_t* skey, const int*
 hipError_t launch_rowptr(const Launch& L, const int* counts, int64_t* rowg, int64_t* partial, int64_t* nnz,
                          const int* inv, int64_t* rsort, hipStream_t st)
 {
+    const int64_t nt = (static_cast<int64_t>(L.ntot) + kScanTile - 1) / kScanTile;
+    if (L.nsets == 1 && nt >= 1 && nt <= kScanFold) {
+        if (nt > 1)
+            hipLaunchKernelGGL(k_scan_reduce<int>, dim3(nt), dim3(kScanThreads), 0, st, counts,
+                               static_cast<int64_t>(L.ntot), partial, nullptr);
+        hipLaunchKernelGGL(k_rowptr_fold1, dim3(nt), dim3(kScanThreads), 0, st, L.sets, counts,
+                           static_cast<int64_t>(L.ntot), partial, nnz, inv, rsort);
+        return hipGetLastError();
+    }
     hipError_t e = scan_exclusive<int, int64_t>(counts, L.ntot, rowg, partial, st);
     if (e != hipSuccess) return e;
     const int m = L.ntot + L.nsets;
