@@ -1923,8 +1923,11 @@ template <int DIM, int MODE, bool FILL>
 __global__ void __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_dense(SearchArgs a)
 {
-    constexpr int K = kDenseChunk;
     constexpr bool F16 = MODE != 1;
+    constexpr int K = (FILL && F16) ? kDenseChunkFill : kDenseChunk;
+    constexpr int QCAP = kDenseQueue;
+    static_assert(K % 128 == 0 && K <= 2048, "whole 128-candidate groups, chunk positions fit 16 bits");
+    static_assert((QCAP & (QCAP - 1)) == 0 && QCAP >= 63 + 128, "a queue holds 63 entries plus a group");
     __shared__ uint4 recA[F16 ? K / 2 : 1];               // qx, qy, qz, 2(c_x - c_jx) pairs
     __shared__ uint2 recB[F16 ? K / 2 : 1];               // 2(c_y - c_jy), 2(c_z - c_jz) pairs
     __shared__ __attribute__((aligned(16))) int sorig[K];
@@ -1935,6 +1938,11 @@ k_dense(SearchArgs a)
     double* const spj = sdbl;
     double* const sX = sdbl;
     __shared__ unsigned long long s_red[FILL ? 1 : kDenseThreads / 64][kDenseStats];  // count pass only
+    // fill: per-wavefront circular queues of accepted candidates (chunk positions, in row order)
+    __shared__ uint16_t squeue[FILL ? (kDenseThreads / 64) * QCAP : 1];
+    // fill: each target's position in the union (found while staging; kNotSeen before)
+    __shared__ int sself[FILL ? kDenseSlice : 1];
+    constexpr int kNotSeen = 1 << 30;
     // the unit counter's broadcast slot: the first record word, free between the last use of
     // one unit's staged chunk and the staging of the next unit's first chunk
     int* const s_unit = reinterpret_cast<int*>(recA);
@@ -1997,6 +2005,9 @@ k_dense(SearchArgs a)
                 tc[5] += 1;
             }
         }
+        if (FILL) {
+            for (int t = threadIdx.x; t < kDenseSlice; t += kDenseThreads) sself[t] = kNotSeen;
+        }
         for (int c0 = 0; c0 < U; c0 += K) {
             const int nc = min(K, U - c0);
             __syncthreads();
@@ -2031,6 +2042,7 @@ k_dense(SearchArgs a)
 #pragma unroll
                                 for (int k = 0; k < DIM; ++k)
                                     sX[k * K + e] = a.X[static_cast<size_t>(oj) * x_stride(DIM) + k];
+                                if (j >= t0 && j < t1) sself[j - t0] = c0 + e;  // a target of this unit
                             }
                         } else {
                             w0 |= 0x7C00u << sh;  // qx = +inf: r2 = +inf
@@ -2045,6 +2057,7 @@ k_dense(SearchArgs a)
                     if (e < nc) {
                         const int j = a.ulist[ub + c0 + e];
                         sorig[e] = a.perm[j];
+                        if (FILL && j >= t0 && j < t1) sself[j - t0] = c0 + e;  // a target of this unit
 #pragma unroll
                         for (int k = 0; k < DIM; ++k) spj[e * DIM + k] = a.spos[static_cast<size_t>(j) * 4 + k];
                     } else {
@@ -2191,10 +2204,12 @@ k_dense(SearchArgs a)
                     if (lane == k) acc_k += tot;
                 } else {
                     // ascending emission: candidate order is original-index order. Each
-                    // group of 128 candidates (two per lane) writes its accepted ones straight
-                    // to the next CSR slots, a lane's slot being the row's count so far plus
-                    // the accepted candidates of lower lanes (ballot prefix); the stores of a
-                    // group cover at most 128 consecutive slots.
+                    // group of 128 candidates (two per lane) appends its accepted ones to the
+                    // wavefront's queue in LDS, a lane's queue position being the queue's tail
+                    // plus the accepted candidates of lower lanes (ballot prefix); whenever 64
+                    // are queued, lane i takes queue entry i, computes its distance and writes
+                    // it to the row's next slot, so every store covers 64 consecutive slots
+                    // with all lanes active. The rest is written when the chunk ends.
                     const long long rs = rl64(rs_k, k);
                     const int rl = rl32(rl_k, k);
                     const int done = rl32(acc_k, k);
@@ -2231,22 +2246,50 @@ k_dense(SearchArgs a)
                             }
                         }
                     };
-                    for (int it = 0; it < nit; ++it) {
-                        uint32_t b2 = ((inb >> it) & 1u) | (((inb >> (16 + it)) & 1u) << 1);
-                        const int e0 = it * 128 + 2 * lane;
-                        const int2 oo = *reinterpret_cast<const int2*>(&sorig[e0]);
-                        // the target itself is never its own neighbour; half lists keep only
-                        // larger original indices
-                        if (oo.x == oi || (a.half && oo.x < oi)) b2 &= ~1u;
-                        if (oo.y == oi || (a.half && oo.y < oi)) b2 &= ~2u;
-                        const uint64_t B0 = __ballot(b2 & 1u);
-                        const uint64_t B1 = __ballot((b2 >> 1) & 1u);
-                        if ((B0 | B1) == 0) continue;
-                        const int pre = w + __popcll(B0 & lt) + __popcll(B1 & lt);
-                        if (b2 & 1u) emit(e0, pre, oo.x);
-                        if (b2 & 2u) emit(e0 + 1, pre + static_cast<int>(b2 & 1u), oo.y);
-                        w += __popcll(B0) + __popcll(B1);
+                    // the target itself is never its own neighbour and half lists keep only
+                    // larger original indices: the union is in original-index order, so both
+                    // are a condition on the chunk position against the target's own, p
+                    const int p = sself[wv + 4 * k] - c0;
+                    uint32_t keep = inb;
+                    if (a.half) {
+                        // lane bits: it for position it*128 + 2 lane, 16 + it for the next one
+                        const int a0 = p - 2 * lane, a1 = a0 - 1;
+                        const uint32_t m0 = a0 < 0 ? 0xFFFFu : (0xFFFEu << min(a0 >> 7, 15)) & 0xFFFFu;
+                        const uint32_t m1 = a1 < 0 ? 0xFFFFu : (0xFFFEu << min(a1 >> 7, 15)) & 0xFFFFu;
+                        keep &= m0 | (m1 << 16);
+                    } else if (p >= 0 && p < nc && lane == ((p >> 1) & 63)) {
+                        keep &= ~(1u << ((p >> 7) + 16 * (p & 1)));
                     }
+                    uint16_t* const q = squeue + wv * QCAP;
+                    int qh = 0, qt = 0;  // queue head and tail (wave-uniform, never wrapped)
+                    // writes the cnt (<= 64) entries at the queue's head to slots w, w + 1, ...
+                    auto flush = [&](int cnt) {
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        if (lane < cnt) {
+                            const int e = q[(qh + lane) & (QCAP - 1)];
+                            emit(e, w + lane, sorig[e]);
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        qh += cnt;
+                        w += cnt;
+                    };
+                    for (int it = 0; it < nit; ++it) {
+                        const uint32_t b0 = (keep >> it) & 1u, b1 = (keep >> (16 + it)) & 1u;
+                        const uint64_t B0 = __ballot(b0);
+                        const uint64_t B1 = __ballot(b1);
+                        if ((B0 | B1) == 0) continue;
+                        // at most 63 queued before and 128 added: the queue never overruns
+                        uint32_t pre = __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(B0), static_cast<uint32_t>(qt));
+                        pre = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(B0 >> 32), pre);
+                        pre = __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(B1), pre);
+                        pre = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(B1 >> 32), pre);
+                        const int e0 = it * 128 + 2 * lane;
+                        if (b0) q[pre & (QCAP - 1)] = static_cast<uint16_t>(e0);
+                        if (b1) q[(pre + b0) & (QCAP - 1)] = static_cast<uint16_t>(e0 + 1);
+                        qt += __popcll(B0) + __popcll(B1);
+                        while (qt - qh >= 64) flush(64);
+                    }
+                    if (qt > qh) flush(qt - qh);
                     if (!room && lane == 0 && w > done) atomicOr(a.err, kErrCapacity);
                     if (lane == k) acc_k = w;
                 }
