@@ -1931,12 +1931,9 @@ k_dense(SearchArgs a)
     __shared__ uint4 recA[F16 ? K / 2 : 1];               // qx, qy, qz, 2(c_x - c_jx) pairs
     __shared__ uint2 recB[F16 ? K / 2 : 1];               // 2(c_y - c_jy), 2(c_z - c_jz) pairs
     __shared__ __attribute__((aligned(16))) int sorig[K];
-    // candidate positions: FP64 (baseline) or fixed point, axis-major [DIM][K] (FP16 fill);
-    // one array serves both so that the FP16 fill's tables are exactly 40 KiB (four
-    // workgroups per CU)
+    // candidates' FP64 positions: [K][DIM] (baseline), axis-major [DIM][K] (FP16 fill)
     __shared__ double sdbl[(!F16 || FILL) ? K * DIM : 1];
     double* const spj = sdbl;
-    double* const sX = sdbl;
     __shared__ unsigned long long s_red[FILL ? 1 : kDenseThreads / 64][kDenseStats];  // count pass only
     // fill: per-wavefront circular queues of accepted candidates (chunk positions, in row order)
     __shared__ uint16_t squeue[FILL ? (kDenseThreads / 64) * QCAP : 1];
@@ -1962,7 +1959,6 @@ k_dense(SearchArgs a)
         const SetView sd(sdesc);
         const int poff = sd.poff;
         const double R2 = sdesc.fr.R2;
-        const float dscale = sdesc.fr.dist_scale;
         const int ncx = sdesc.fr.nc[0], ncy = sdesc.fr.nc[1];
         const uint32_t coff = static_cast<uint32_t>(sdesc.coff);
         const int lk = g - sdesc.coff;
@@ -1981,7 +1977,6 @@ k_dense(SearchArgs a)
         const int nt = (t1 - t0 > wv) ? (t1 - t0 - wv + 3) / 4 : 0;
         int oi_k = 0, q01_k = 0, q2_k = 0, acc_k = 0, rl_k = 0;
         long long rs_k = 0;
-        double xi_k[3] = {0, 0, 0};
         double pi_k[3] = {0, 0, 0};
         if (vk) {
             oi_k = a.perm[pk];
@@ -1996,10 +1991,6 @@ k_dense(SearchArgs a)
             if (FILL) {
                 rs_k = sd.row_ptr[li];
                 rl_k = static_cast<int>(sd.row_ptr[li + 1] - rs_k);
-                if (F16) {
-#pragma unroll
-                    for (int k = 0; k < DIM; ++k) xi_k[k] = a.X[static_cast<size_t>(oi_k) * x_stride(DIM) + k];
-                }
             } else {
                 tc[0] += static_cast<unsigned long long>(U - 1);
                 tc[5] += 1;
@@ -2041,7 +2032,7 @@ k_dense(SearchArgs a)
                             if (FILL) {
 #pragma unroll
                                 for (int k = 0; k < DIM; ++k)
-                                    sX[k * K + e] = a.X[static_cast<size_t>(oj) * x_stride(DIM) + k];
+                                    spj[k * K + e] = sd.pos[static_cast<size_t>(oj - poff) * DIM + k];
                                 if (j >= t0 && j < t1) sself[j - t0] = c0 + e;  // a target of this unit
                             }
                         } else {
@@ -2122,6 +2113,17 @@ k_dense(SearchArgs a)
                     }
                 }
                 bnd = ebits & ~inb;
+                // the FP64 recheck of candidate e: from the staged positions in the fill
+                auto recheck = [&](int e, int oj) -> bool {
+                    if constexpr (FILL && F16) {
+                        double pj[3];
+#pragma unroll
+                        for (int d = 0; d < DIM; ++d) pj[d] = spj[d * K + e];
+                        return r2_fp64<DIM>(pi, pj) <= R2;
+                    } else {
+                        return recheck_g<DIM>(sd.pos, pi, oj - poff, R2);
+                    }
+                };
                 if (MODE == 2) {
                     // every candidate decided in FP64; the FP16 classes are only compared
                     uint32_t all = 0;
@@ -2136,7 +2138,7 @@ k_dense(SearchArgs a)
                         const int e = (bb & 15) * 128 + 2 * lane + (bb >> 4);
                         const int oj = sorig[e];
                         if (oj == oi) continue;
-                        const bool truth = recheck_g<DIM>(sd.pos, pi, oj - poff, R2);
+                        const bool truth = recheck(e, oj);
                         if (truth) dec |= 1u << bb;
                         if (!FILL) {
                             const bool band = (bnd >> bb) & 1u;
@@ -2173,7 +2175,7 @@ k_dense(SearchArgs a)
                         const int e = (bb & 15) * 128 + 2 * lane + (bb >> 4);
                         const int oj = sorig[e];
                         if (oj == oi) continue;  // itself (a band pair only when T_lo = 0)
-                        const bool truth = recheck_g<DIM>(sd.pos, pi, oj - poff, R2);
+                        const bool truth = recheck(e, oj);
                         if (truth) inb |= 1u << bb;
                         if (!FILL) {
                             const uint4 A = recA[e >> 1];
@@ -2214,9 +2216,6 @@ k_dense(SearchArgs a)
                     const int rl = rl32(rl_k, k);
                     const int done = rl32(acc_k, k);
                     const bool room = rs + rl <= sd.capacity;
-                    double xi[3];
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) xi[d] = rlf64(xi_k[d], k);
                     const double* pis = pi;
                     int w = done;  // CSR entries of this row written so far
                     // the row's output, wave-uniform: entries are addressed by a 32-bit slot
@@ -2226,13 +2225,14 @@ k_dense(SearchArgs a)
                         if (slot < rl && room) {
                             float dv;
                             if (F16) {
+                                // the FP64 displacement rounded once to FP32 per axis
                                 float s2 = 0.0f;
 #pragma unroll
                                 for (int d = 0; d < DIM; ++d) {
-                                    const float f = static_cast<float>(sX[d * K + e] - xi[d]);
+                                    const float f = static_cast<float>(spj[d * K + e] - pi[d]);
                                     s2 = s2 + f * f;
                                 }
-                                dv = __builtin_amdgcn_sqrtf(s2) * dscale;
+                                dv = __builtin_amdgcn_sqrtf(s2);
                             } else {
                                 dv = static_cast<float>(__dsqrt_rn(r2_fp64<DIM>(pis, spj + e * DIM)));
                             }
