@@ -1888,12 +1888,13 @@ hipError_t launch_long_rows(const SearchArgs& a, int grid, hipStream_t st)
 // ---------------------------------------------------------------------------
 // Dense-cell path. A work unit is up to kDenseSlice targets of one dense cell, all with
 // the same stencil union (the cell's list, ascending original index). A workgroup of
-// four wavefronts takes units from a counter; for each chunk of kDenseChunk candidates it
-// stages their FP16 pair records (and, for the fill, original indices and fixed-point
-// positions) in LDS, then each wavefront runs its targets one at a time over the chunk:
-// a lane tests two consecutive candidates per packed FP16 instruction with the same op
-// sequence as the block kernels, band pairs are settled by the FP64 recheck, and the
-// accepted candidates of each 128-candidate step are written with one ballot prefix, so
+// four wavefronts takes units from a counter; for each chunk of candidates (kDenseChunkFill
+// in the FP16 fill) it stages their FP16 pair records and original indices (and, for the
+// fill, FP64 positions) in LDS, then each wavefront runs its targets one at a time over the
+// chunk: a lane tests two consecutive candidates per packed FP16 instruction with the same
+// op sequence as the block kernels, band pairs are settled by the FP64 recheck (on the
+// staged positions in the fill), and the fill queues the accepted candidates of each
+// 128-candidate step in order (ballot prefix) and writes them 64 at a time, so
 // consecutive lanes store consecutive CSR entries and the row comes out ascending.
 // Wavefront w of a unit holds targets w, w + 4, ...: lane k keeps target w + 4k's data
 // in registers, read by the whole wavefront with readlane when its turn comes.
@@ -2113,7 +2114,7 @@ k_dense(SearchArgs a)
                     }
                 }
                 bnd = ebits & ~inb;
-                // the FP64 recheck of candidate e: from the staged positions in the fill
+                // the FP64 recheck of candidate e: from its staged position in the fill
                 auto recheck = [&](int e, int oj) -> bool {
                     if constexpr (FILL && F16) {
                         double pj[3];
