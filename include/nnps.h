@@ -19,8 +19,9 @@
  * Pairs whose FP16 r2 lies within a guard band of the cutoff are decided again in
  * FP64 from the caller's positions, so the neighbour set is exactly the binary64
  * one above. FP64 arithmetic on the GPU is used for cell assignment, that recheck, and
- * one exact subtraction per coordinate of two fixed-point positions (integers below 2^52
- * held as doubles) for each emitted FP32 distance; the neighbour test itself is FP16.
+ * one subtraction per coordinate for each emitted FP32 distance: of two fixed-point
+ * positions (integers below 2^52 held as doubles, so exact) in the block path, of the
+ * two FP64 positions in the dense-cell path; the neighbour test itself is FP16.
  *
  * Memory: every pointer named d_* is device memory on the context's device.
  * The caller owns positions and all outputs; the library owns the context and
