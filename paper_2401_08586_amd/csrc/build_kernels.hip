@@ -293,6 +293,10 @@ constexpr int kRsThreads = 256;
 constexpr int kRsRounds = 16;
 constexpr int kRsTile = kRsThreads * kRsRounds;
 constexpr int kRsMaxBits = 11;
+// Digit width per pass: at most 8 bits, so a tile's keys fall into runs of 16 or more per
+// digit on average and the scatter's stores fill whole cache lines (with 10- or 11-bit
+// digits a tile has 2-4 keys per digit and nearly every store writes its own line).
+constexpr int kRsPassBits = 8;
 
 __global__ void __launch_bounds__(kRsThreads)
 k_radix_hist(const uint32_t* __restrict__ keys, int n, int shift, int bits,
@@ -929,7 +933,7 @@ hipError_t radix_sort_kv_dev(int n, const int* ndev, int keybits, uint32_t* k0, 
                              uint32_t* table, int64_t* partial, hipStream_t st, uint32_t** kfinal, int** vfinal)
 {
     const int ntiles = radix_tiles(n);
-    const int passes = keybits <= 0 ? 1 : (keybits + kRsMaxBits - 1) / kRsMaxBits;
+    const int passes = keybits <= 0 ? 1 : (keybits + kRsPassBits - 1) / kRsPassBits;
     const int bits = keybits <= 0 ? 1 : (keybits + passes - 1) / passes;
     uint32_t *kin = k0, *kout = k1;
     int *vin = v0, *vout = v1;
