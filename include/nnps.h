@@ -127,14 +127,21 @@ typedef struct nnps_stats {
  * dense_max_entries: bound on the summed stencil-union sizes of dense cells per build
  *   (device scratch: 16 bytes per entry, allocated as min(3^d n, bound)). Beyond it a
  *   build falls back to the block and long-row paths. 0 = default (2^28). Valid
- *   0..2^31-1. */
+ *   0..2^31-1.
+ * dense_bits_mib: bound (MiB) on the device scratch in which the FP16 dense count keeps
+ *   every target's accepted bits per candidate chunk (16 bits per 128 candidates per
+ *   lane: about one bit per candidate) so that the fill does not test again. The
+ *   structure sizes it at a build from what the last call that synchronised (a count
+ *   with h_nnz, a search) found the dense cells need; while it is too small, or above
+ *   the bound, the fill tests the candidates again (same result). 0 = default (16384);
+ *   -1 = never. Valid -1..2^20. */
 typedef struct nnps_tuning {
     int32_t block_target;
     int32_t long_rows_grid;
     int32_t long_rows_keys;
     int32_t dense_min_union;
     int32_t dense_grid;
-    int32_t reserved;
+    int32_t dense_bits_mib;
     int64_t dense_max_entries;
 } nnps_tuning;
 

@@ -79,6 +79,8 @@ struct DenseBuild {
     uint32_t* table;        // radix scratch
     int64_t* partial;       // scan scratch
     int* seen;              // [1] set to 1 when any cell is dense
+    int* dbn;               // [ncell_tot] (target, chunk) pairs of each dense cell (FP16 chunks)
+    int64_t* dboff;         // [ncell_tot + 1] exclusive scan of dbn
 };
 // Stencil sizes and the dense flag only (the path is not used by this build).
 hipError_t launch_dense_detect(const Launch& L, const int* cell_start, const DenseBuild& d, hipStream_t st);
@@ -132,6 +134,12 @@ struct SearchArgs {
     int* ucount;                    // work-unit counter (zeroed before each launch)
     unsigned long long* dstats;     // [dgrid][kDenseStats] per-workgroup statistics
     int dgrid;
+    // FP16 dense passes: the count keeps each target's accepted bits per chunk (64 lanes x
+    // 16 bits) at dbits[(dboff[cell] + target_in_cell * chunks + chunk) * 64 + lane] when
+    // dboff[ncell_tot] * 64 <= dbits_cap, and the fill then reads them instead of testing
+    const int64_t* dboff;
+    uint16_t* dbits;
+    int64_t dbits_cap;
 };
 
 hipError_t launch_count(const SearchArgs& a, int nblk_max, hipStream_t st);

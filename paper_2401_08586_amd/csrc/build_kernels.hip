@@ -793,7 +793,8 @@ k_dense_cells(const SetDesc* __restrict__ sets, const int* __restrict__ coffs, i
 // units. dn receives the number of list entries in use (0 = path off).
 __global__ void __launch_bounds__(256)
 k_dense_units(int ncell_tot, const int* __restrict__ cell_start, const int64_t* __restrict__ uoff, int64_t cap,
-              int* __restrict__ usz, int* __restrict__ wdense, int* __restrict__ nsl, int* __restrict__ dn)
+              int* __restrict__ usz, int* __restrict__ wdense, int* __restrict__ nsl, int* __restrict__ dn,
+              int* __restrict__ dbn)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t ue = uoff[ncell_tot];
@@ -805,7 +806,9 @@ k_dense_units(int ncell_tot, const int* __restrict__ cell_start, const int64_t* 
         wdense[g] = 0;
     }
     const int occ = cell_start[g + 1] - cell_start[g];
-    nsl[g] = (!over && usz[g] > 0) ? (occ + kDenseSlice - 1) / kDenseSlice : 0;
+    const bool on = !over && usz[g] > 0;
+    nsl[g] = on ? (occ + kDenseSlice - 1) / kDenseSlice : 0;
+    dbn[g] = on ? occ * ((usz[g] + kDenseChunkF16 - 1) / kDenseChunkF16) : 0;
 }
 
 __global__ void __launch_bounds__(256)
@@ -1040,8 +1043,10 @@ hipError_t launch_dense_cells(const Launch& L, const int* cell_start, const Dens
     e = scan_exclusive<int, int64_t>(d.usz, nc, d.uoff, d.partial, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_dense_units, dim3((nc + 256) / 256), b, 0, st, nc, cell_start, d.uoff, d.cap, d.usz,
-                       d.wdense, d.nsl, d.dn);
+                       d.wdense, d.nsl, d.dn, d.dbn);
     e = scan_exclusive<int, int>(d.nsl, nc, d.unit_off, d.partial, st);
+    if (e != hipSuccess) return e;
+    e = scan_exclusive<int, int64_t>(d.dbn, nc, d.dboff, d.partial, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_dense_unit_cells, g, b, 0, st, nc, d.nsl, d.unit_off, d.dn, d.ucell);
     return hipGetLastError();

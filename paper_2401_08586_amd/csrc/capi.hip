@@ -293,6 +293,10 @@ struct nnps_cells {
     int64_t dcap = 0;
     int* ulist = nullptr;
     DevBuf usz, wdense, uoff, nsl, unit_off, ucell, dn, ecnt, epos, uk0, uk1, uv0, uv1, inv, ucount, dstats, dseen;
+    // FP16 dense passes: (target, chunk) offsets per cell and the count's accepted bits,
+    // sized at a build from what the last synchronising call found the dense cells need
+    DevBuf dbn, dboff, dbits;
+    size_t dbits_want = 0;  // bytes
     // incremental update (nnps_cells_update): see Update
     DevBuf uleave, ucs_old, uskey2, uperm2;
     GraphCache ugraph;  // a captured update + count + fill sequence
@@ -347,6 +351,20 @@ nnps_status upload(nnps_cells* c, bool with_offsets, hipStream_t s)
     HIP_TRY(hipEventRecord(c->upload_done, s));
     c->upload_pending = true;
     return NNPS_OK;
+}
+
+// The FP16 dense passes (FP16 RCLL and its recheck-all mode) may keep the count's
+// accepted bits for the fill, within a bound on the scratch (tuning; -1 = never).
+bool dense_bits_on(const nnps_cells* c)
+{
+    return c->dense && (c->mode == NNPS_MODE_FP16_RCLL || c->mode == NNPS_MODE_RECHECK_ALL) &&
+           c->ctx->tuning.dense_bits_mib >= 0;
+}
+
+size_t dense_bits_bound(const nnps_cells* c)
+{
+    const int mib = c->ctx->tuning.dense_bits_mib > 0 ? c->ctx->tuning.dense_bits_mib : kDenseBitsMiB;
+    return static_cast<size_t>(mib) << 20;
 }
 
 Launch launch_of(const nnps_cells* c)
@@ -405,6 +423,11 @@ SearchArgs args_of(const nnps_cells* c)
         a.ucount = c->ucount.as<int>();
         a.dstats = c->dstats.as<unsigned long long>();
         a.dgrid = c->dgrid;
+        a.dboff = c->dboff.as<int64_t>();
+        if (dense_bits_on(c) && c->dbits.p) {
+            a.dbits = c->dbits.as<uint16_t>();
+            a.dbits_cap = static_cast<int64_t>(c->dbits.cap / sizeof(uint16_t));
+        }
     }
     return a;
 }
@@ -430,6 +453,8 @@ DenseBuild dense_of(nnps_cells* c)
     d.table = c->table.as<uint32_t>();
     d.partial = c->partial.as<int64_t>();
     d.seen = c->dseen.as<int>();
+    d.dbn = c->dbn.as<int>();
+    d.dboff = c->dboff.as<int64_t>();
     return d;
 }
 
@@ -555,6 +580,8 @@ nnps_status prepare(nnps_ctx* ctx, nnps_cells* c, int nsets, const nnps_problem*
         {&c->inv, nn * 4}, {&c->ucount, c->dense ? size_t(4) : size_t(0)},
         {&c->dstats, c->dense ? static_cast<size_t>(c->dgrid) * kDenseStats * 8 : 0},
         {&c->dseen, c->dense ? size_t(4) : size_t(0)},
+        {&c->dbn, c->dense ? (nc + 1) * 4 : 0}, {&c->dboff, c->dense ? (nc + 1) * 8 : 0},
+        {&c->dbits, dense_bits_on(c) ? c->dbits_want : 0},
         // leave, arrive (ncell + 1 each) and the migrant bits (ceil(n / 32) words), one block
         {&c->uleave, (2 * (nc + 1) + (nn + 31) / 32) * 4},
         {&c->ucs_old, (nc + 1) * 4}, {&c->uskey2, nn * 4}, {&c->uperm2, nn * 4},
@@ -731,16 +758,25 @@ nnps_status read_nnz(nnps_cells* c, int64_t* h_nnz, hipStream_t s)
 {
     int64_t* hp = c->ctx->h_pinned;
     nnps_status st = NNPS_OK;
-    // the pinned staging holds 64 values; larger batches are read in pieces
-    for (int s0 = 0; s0 < c->nsets; s0 += 63) {
-        const int k = std::min(63, c->nsets - s0);
+    // the pinned staging holds 64 values: up to 62 counts per piece, the dense cells'
+    // (target, chunk) pairs, the error word and the dense flag
+    const bool bits = c->dense_active && dense_bits_on(c);
+    for (int s0 = 0; s0 < c->nsets; s0 += 62) {
+        const int k = std::min(62, c->nsets - s0);
         HIP_TRY(hipMemcpyAsync(hp, c->nnz.as<int64_t>() + s0, 8 * k, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(hp + 63, c->err.p, 4, hipMemcpyDeviceToHost, s));
         if (c->dense) HIP_TRY(hipMemcpyAsync(reinterpret_cast<int*>(hp + 63) + 1, c->dseen.p, 4, hipMemcpyDeviceToHost, s));
+        if (bits && s0 == 0)
+            HIP_TRY(hipMemcpyAsync(hp + 62, c->dboff.as<int64_t>() + launch_of(c).ncell_tot, 8, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         for (int i = 0; i < k; ++i) h_nnz[s0 + i] = hp[i];
         st = err_status(static_cast<int>(hp[63] & 0xFFFFFFFF));
         if (c->dense) c->dense_seen = reinterpret_cast<int*>(hp + 63)[1] != 0 ? 1 : 0;
+        if (bits && s0 == 0) {
+            // the next build keeps room for the count's bits if they fit the bound
+            const size_t want = static_cast<size_t>(hp[62]) * 64 * sizeof(uint16_t);
+            if (want <= dense_bits_bound(c)) c->dbits_want = std::max(c->dbits_want, want);
+        }
     }
     return st;
 }
@@ -865,8 +901,8 @@ nnps_status nnps_ctx_set_tuning(nnps_ctx* ctx, const nnps_tuning* t)
     if (t->dense_min_union < -1 || t->dense_min_union > (1 << 30)) return NNPS_EINVAL;
     if (t->dense_grid < 0 || t->dense_grid > (1 << 20)) return NNPS_EINVAL;
     if (t->dense_max_entries < 0 || t->dense_max_entries > INT32_MAX) return NNPS_EINVAL;
+    if (t->dense_bits_mib < -1 || t->dense_bits_mib > (1 << 20)) return NNPS_EINVAL;
     ctx->tuning = *t;
-    ctx->tuning.reserved = 0;
     return NNPS_OK;
 }
 

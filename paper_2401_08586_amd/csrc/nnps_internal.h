@@ -29,10 +29,13 @@ constexpr int kMaxXWin = 256;
 // Dense-cell path: candidates staged per chunk, targets per work unit (a workgroup of
 // four wavefronts, 64 targets each) and the default thresholds.
 constexpr int kDenseChunk = 1024;
-// The FP16 fill stages fewer candidates per chunk, so that its tables (records, FP64
-// positions and the per-wavefront queues of accepted candidates) still fit four
-// workgroups per CU (a multiple of 128).
-constexpr int kDenseChunkFill = 896;
+// The FP16 passes stage fewer candidates per chunk, so that the fill's tables (records,
+// FP64 positions and the per-wavefront queues of accepted candidates) still fit four
+// workgroups per CU (a multiple of 128); the count uses the same chunks, so that the
+// accepted bits it keeps per target and chunk are the fill's.
+constexpr int kDenseChunkF16 = 896;
+// Default bound on the device scratch for those bits (MiB).
+constexpr int kDenseBitsMiB = 16384;
 constexpr int kDenseQueue = 256;  // per-wavefront queue of accepted candidates (power of two)
 constexpr int kDenseThreads = 256;
 constexpr int kDenseSlice = 256;

@@ -1925,10 +1925,13 @@ __global__ void __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per
 k_dense(SearchArgs a)
 {
     constexpr bool F16 = MODE != 1;
-    constexpr int K = (FILL && F16) ? kDenseChunkFill : kDenseChunk;
+    constexpr int K = F16 ? kDenseChunkF16 : kDenseChunk;
     constexpr int QCAP = kDenseQueue;
     static_assert(K % 128 == 0 && K <= 2048, "whole 128-candidate groups, chunk positions fit 16 bits");
     static_assert((QCAP & (QCAP - 1)) == 0 && QCAP >= 63 + 128, "a queue holds 63 entries plus a group");
+    static_assert(!F16 || K / 128 <= 7, "a lane's accepted bits of a chunk fit 14 bits");
+    static_assert(!F16 || sizeof(uint4) * (K / 2) >= (kDenseThreads / 64) * 8 * 64 * sizeof(uint16_t),
+                  "the record table holds eight targets' bits per wavefront");
     __shared__ uint4 recA[F16 ? K / 2 : 1];               // qx, qy, qz, 2(c_x - c_jx) pairs
     __shared__ uint2 recB[F16 ? K / 2 : 1];               // 2(c_y - c_jy), 2(c_z - c_jz) pairs
     __shared__ __attribute__((aligned(16))) int sorig[K];
@@ -1938,6 +1941,8 @@ k_dense(SearchArgs a)
     __shared__ unsigned long long s_red[FILL ? 1 : kDenseThreads / 64][kDenseStats];  // count pass only
     // fill: per-wavefront circular queues of accepted candidates (chunk positions, in row order)
     __shared__ uint16_t squeue[FILL ? (kDenseThreads / 64) * QCAP : 1];
+    // FP16 count keeping its bits: eight targets' bit words per wavefront, stored together
+    __shared__ uint16_t sbits[(!FILL && F16) ? (kDenseThreads / 64) * 8 * 64 : 1];
     // fill: each target's position in the union (found while staging; kNotSeen before)
     __shared__ int sself[FILL ? kDenseSlice : 1];
     constexpr int kNotSeen = 1 << 30;
@@ -1947,6 +1952,9 @@ k_dense(SearchArgs a)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const int nunits = *a.dn > 0 ? a.unit_off[a.L.ncell_tot] : 0;
+    // FP16: the count keeps the accepted bits of every (target, chunk) when they fit, and
+    // the fill then takes them instead of testing again
+    const bool bits = F16 && a.dbits && nunits > 0 && a.dboff[a.L.ncell_tot] * 64 <= a.dbits_cap;
     unsigned long long tc[kDenseStats] = {0, 0, 0, 0, 0, 0};
     for (;;) {
         __syncthreads();  // the previous unit is done with s_unit and the staged chunk
@@ -1968,6 +1976,9 @@ k_dense(SearchArgs a)
         const int t1 = min(a.cell_start[g + 1], t0 + kDenseSlice);
         const int U = a.usz[g];
         const int64_t ub = a.uoff[g];
+        const int nchunk = (U + K - 1) / K;
+        // this wavefront's first (target, chunk) bit row: targets wv + 4k of the unit
+        const int64_t brow = bits ? a.dboff[g] + static_cast<int64_t>(slice * kDenseSlice + wv) * nchunk : 0;
         Thresh th;
         th.init(sdesc.fr);
         const uint16_t tmid = sdesc.fr.t_mid;
@@ -2004,7 +2015,22 @@ k_dense(SearchArgs a)
             const int nc = min(K, U - c0);
             __syncthreads();
             // stage the chunk (padding tests as +inf / far away: never a neighbour)
-            if (F16) {
+            if (F16 && FILL && bits) {
+                // the fill with the count's bits: original indices and FP64 positions only
+                for (int e = threadIdx.x; e < K; e += kDenseThreads) {
+                    if (e < nc) {
+                        const int j = a.ulist[ub + c0 + e];
+                        const int oj = a.perm[j];
+                        sorig[e] = oj;
+#pragma unroll
+                        for (int k = 0; k < DIM; ++k)
+                            spj[k * K + e] = sd.pos[static_cast<size_t>(oj - poff) * DIM + k];
+                        if (j >= t0 && j < t1) sself[j - t0] = c0 + e;  // a target of this unit
+                    } else {
+                        sorig[e] = -1;
+                    }
+                }
+            } else if (F16) {
                 for (int m = threadIdx.x; m < K / 2; m += kDenseThreads) {
                     uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0;
 #pragma unroll
@@ -2061,143 +2087,271 @@ k_dense(SearchArgs a)
             }
             __syncthreads();
             const int nit = (nc + 127) >> 7;
+            // bit row of target k of this wavefront in this chunk
+            auto bit_index = [&](int k) {
+                return (brow + static_cast<int64_t>(4 * k) * nchunk + c0 / K) * 64 + lane;
+            };
+            // the fill's emission of target k's accepted bits in this chunk
+            auto fill_row = [&](int k, uint32_t inb, const double* pi) {
+                // ascending emission: candidate order is original-index order. Each
+                // group of 128 candidates (two per lane) appends its accepted ones to the
+                // wavefront's queue in LDS, a lane's queue position being the queue's tail
+                // plus the accepted candidates of lower lanes (ballot prefix); whenever 64
+                // are queued, lane i takes queue entry i, computes its distance and writes
+                // it to the row's next slot, so every store covers 64 consecutive slots
+                // with all lanes active. The rest is written when the chunk ends.
+                const long long rs = rl64(rs_k, k);
+                const int rl = rl32(rl_k, k);
+                const int done = rl32(acc_k, k);
+                const bool room = rs + rl <= sd.capacity;
+                const double* pis = pi;
+                int w = done;  // CSR entries of this row written so far
+                // the row's output, wave-uniform: entries are addressed by a 32-bit slot
+                NNPS_GLOBAL int32_t* const rcol = uniform_ptr(sd.col + rs);
+                NNPS_GLOBAL float* const rdist = uniform_ptr(sd.dist + rs);
+                auto emit = [&](int e, int slot, int oj) {
+                    if (slot < rl && room) {
+                        float dv;
+                        if (F16) {
+                            // the FP64 displacement rounded once to FP32 per axis
+                            float s2 = 0.0f;
+#pragma unroll
+                            for (int d = 0; d < DIM; ++d) {
+                                const float f = static_cast<float>(spj[d * K + e] - pi[d]);
+                                s2 = s2 + f * f;
+                            }
+                            dv = __builtin_amdgcn_sqrtf(s2);
+                        } else {
+                            dv = static_cast<float>(__dsqrt_rn(r2_fp64<DIM>(pis, spj + e * DIM)));
+                        }
+                        if (rl <= (1 << 30)) {  // byte offsets within the row fit 32 bits
+                            const uint32_t off = static_cast<uint32_t>(slot) * 4u;
+                            *(NNPS_GLOBAL int32_t*)((NNPS_GLOBAL char*)rcol + off) = oj - poff;
+                            *(NNPS_GLOBAL float*)((NNPS_GLOBAL char*)rdist + off) = dv;
+                        } else {
+                            rcol[slot] = oj - poff;
+                            rdist[slot] = dv;
+                        }
+                    }
+                };
+                // the target itself is never its own neighbour and half lists keep only
+                // larger original indices: the union is in original-index order, so both
+                // are a condition on the chunk position against the target's own, p
+                const int p = sself[wv + 4 * k] - c0;
+                uint32_t keep = inb;
+                if (a.half) {
+                    // lane bits: it for position it*128 + 2 lane, 16 + it for the next one
+                    const int a0 = p - 2 * lane, a1 = a0 - 1;
+                    const uint32_t m0 = a0 < 0 ? 0xFFFFu : (0xFFFEu << min(a0 >> 7, 15)) & 0xFFFFu;
+                    const uint32_t m1 = a1 < 0 ? 0xFFFFu : (0xFFFEu << min(a1 >> 7, 15)) & 0xFFFFu;
+                    keep &= m0 | (m1 << 16);
+                } else if (p >= 0 && p < nc && lane == ((p >> 1) & 63)) {
+                    keep &= ~(1u << ((p >> 7) + 16 * (p & 1)));
+                }
+                uint16_t* const q = squeue + wv * QCAP;
+                int qh = 0, qt = 0;  // queue head and tail (wave-uniform, never wrapped)
+                // writes the cnt (<= 64) entries at the queue's head to slots w, w + 1, ...
+                auto flush = [&](int cnt) {
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    if (lane < cnt) {
+                        const int e = q[(qh + lane) & (QCAP - 1)];
+                        emit(e, w + lane, sorig[e]);
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    qh += cnt;
+                    w += cnt;
+                };
+                for (int it = 0; it < nit; ++it) {
+                    const uint32_t b0 = (keep >> it) & 1u, b1 = (keep >> (16 + it)) & 1u;
+                    const uint64_t B0 = __ballot(b0);
+                    const uint64_t B1 = __ballot(b1);
+                    if ((B0 | B1) == 0) continue;
+                    // at most 63 queued before and 128 added: the queue never overruns
+                    uint32_t pre = __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(B0), static_cast<uint32_t>(qt));
+                    pre = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(B0 >> 32), pre);
+                    pre = __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(B1), pre);
+                    pre = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(B1 >> 32), pre);
+                    const int e0 = it * 128 + 2 * lane;
+                    if (b0) q[pre & (QCAP - 1)] = static_cast<uint16_t>(e0);
+                    if (b1) q[(pre + b0) & (QCAP - 1)] = static_cast<uint16_t>(e0 + 1);
+                    qt += __popcll(B0) + __popcll(B1);
+                    while (qt - qh >= 64) flush(64);
+                }
+                if (qt > qh) flush(qt - qh);
+                if (!room && lane == 0 && w > done) atomicOr(a.err, kErrCapacity);
+                if (lane == k) acc_k = w;
+            };
+            if (FILL && bits) {
+                // the count's bits, loaded for eight targets at a time (waiting for a load
+                // also waits for every store issued before it, so that wait is paid once per
+                // eight rows) and kept in LDS, in the record table this path does not use;
+                // a lane reads back only what it wrote
+                uint16_t* const wbuf = reinterpret_cast<uint16_t*>(recA) + wv * 8 * 64;
+                for (int k = 0; k < nt; ++k) {
+                    if ((k & 7) == 0) {
+                        uint32_t wb[8];
+#pragma unroll
+                        for (int t = 0; t < 8; ++t) wb[t] = a.dbits[bit_index(min(k + t, nt - 1))];
+#pragma unroll
+                        for (int t = 0; t < 8; ++t) wbuf[t * 64 + lane] = static_cast<uint16_t>(wb[t]);
+                    }
+                    const uint32_t w16 = wbuf[(k & 7) * 64 + lane];
+                    double pi[3];
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) pi[d] = rlf64(pi_k[d], k);
+                    fill_row(k, (w16 & 0x7Fu) | ((w16 & 0x3F80u) << 9), pi);
+                }
+                continue;
+            }
             for (int k = 0; k < nt; ++k) {
                 const int oi = rl32(oi_k, k);
                 double pi[3];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) pi[d] = rlf64(pi_k[d], k);
-                uint32_t inb = 0, bnd = 0;
-                h2 qix2, qiy2, qiz2;
-                if (F16) {
-                    const uint32_t q01 = static_cast<uint32_t>(rl32(q01_k, k));
-                    const uint32_t q2 = static_cast<uint32_t>(rl32(q2_k, k));
-                    qix2 = splat(as_f16(static_cast<uint16_t>(q01 & 0xFFFF)));
-                    qiy2 = splat(as_f16(static_cast<uint16_t>(q01 >> 16)));
-                    qiz2 = splat(as_f16(static_cast<uint16_t>(q2 & 0xFFFF)));
-                }
-                // candidate bits: bit it for candidate it*128 + 2 lane, bit 16 + it for the one
-                // after it; "in" and "in or band" from the sign bits of two 16-bit subtractions
-                uint32_t ebits = 0, gt = 0;
-#pragma unroll
-                for (int it = 0; it < K / 128; ++it) {
-                    if (it >= nit) break;
-                    const int m = it * 64 + lane;
-                    if (!FILL && a.half) {  // half lists: candidates of larger original index
-                        const int2 oo = *reinterpret_cast<const int2*>(&sorig[2 * m]);
-                        gt |= (oo.x > oi ? 1u << it : 0u) | (oo.y > oi ? 1u << (16 + it) : 0u);
-                    }
+                uint32_t inb = 0, bnd = 0, gt = 0;
+                {
+                    h2 qix2, qiy2, qiz2;
                     if (F16) {
-                        const uint4 A = recA[m];
-                        const uint2 B = recB[m];
-                        const h2 s = qix2 - as_h2(A.x);
-                        const h2 tx = s + as_h2(A.w);
-                        const h2 ay = qiy2 + as_h2(B.x);
-                        const h2 ty = ay - as_h2(A.y);
-                        h2 r2;
-                        if (DIM == 3) {
-                            const h2 az = qiz2 + as_h2(B.y);
-                            const h2 tz = az - as_h2(A.z);
-                            r2 = tz * tz;
-                            r2 = __builtin_elementwise_fma(ty, ty, r2);
+                        const uint32_t q01 = static_cast<uint32_t>(rl32(q01_k, k));
+                        const uint32_t q2 = static_cast<uint32_t>(rl32(q2_k, k));
+                        qix2 = splat(as_f16(static_cast<uint16_t>(q01 & 0xFFFF)));
+                        qiy2 = splat(as_f16(static_cast<uint16_t>(q01 >> 16)));
+                        qiz2 = splat(as_f16(static_cast<uint16_t>(q2 & 0xFFFF)));
+                    }
+                    // candidate bits: bit it for candidate it*128 + 2 lane, bit 16 + it for the one
+                    // after it; "in" and "in or band" from the sign bits of two 16-bit subtractions
+                    uint32_t ebits = 0;
+#pragma unroll
+                    for (int it = 0; it < K / 128; ++it) {
+                        if (it >= nit) break;
+                        const int m = it * 64 + lane;
+                        if (!FILL && a.half) {  // half lists: candidates of larger original index
+                            const int2 oo = *reinterpret_cast<const int2*>(&sorig[2 * m]);
+                            gt |= (oo.x > oi ? 1u << it : 0u) | (oo.y > oi ? 1u << (16 + it) : 0u);
+                        }
+                        if (F16) {
+                            const uint4 A = recA[m];
+                            const uint2 B = recB[m];
+                            const h2 s = qix2 - as_h2(A.x);
+                            const h2 tx = s + as_h2(A.w);
+                            const h2 ay = qiy2 + as_h2(B.x);
+                            const h2 ty = ay - as_h2(A.y);
+                            h2 r2;
+                            if (DIM == 3) {
+                                const h2 az = qiz2 + as_h2(B.y);
+                                const h2 tz = az - as_h2(A.z);
+                                r2 = tz * tz;
+                                r2 = __builtin_elementwise_fma(ty, ty, r2);
+                            } else {
+                                r2 = ty * ty;
+                            }
+                            r2 = __builtin_elementwise_fma(tx, tx, r2);
+                            const u16x2 dd = as_u16x2(as_u32(r2)) - th.tlo2;
+                            const u16x2 ee = dd - th.w12;
+                            inb |= (u16x2_bits(dd) >> (15 - it)) & (0x10001u << it);
+                            ebits |= (u16x2_bits(ee) >> (15 - it)) & (0x10001u << it);
                         } else {
-                            r2 = ty * ty;
-                        }
-                        r2 = __builtin_elementwise_fma(tx, tx, r2);
-                        const u16x2 dd = as_u16x2(as_u32(r2)) - th.tlo2;
-                        const u16x2 ee = dd - th.w12;
-                        inb |= (u16x2_bits(dd) >> (15 - it)) & (0x10001u << it);
-                        ebits |= (u16x2_bits(ee) >> (15 - it)) & (0x10001u << it);
-                    } else {
 #pragma unroll
-                        for (int h = 0; h < 2; ++h)
-                            if (r2_fp64<DIM>(pi, spj + (2 * m + h) * DIM) <= R2) inb |= 1u << (it + 16 * h);
-                    }
-                }
-                bnd = ebits & ~inb;
-                // the FP64 recheck of candidate e: from its staged position in the fill
-                auto recheck = [&](int e, int oj) -> bool {
-                    if constexpr (FILL && F16) {
-                        double pj[3];
-#pragma unroll
-                        for (int d = 0; d < DIM; ++d) pj[d] = spj[d * K + e];
-                        return r2_fp64<DIM>(pi, pj) <= R2;
-                    } else {
-                        return recheck_g<DIM>(sd.pos, pi, oj - poff, R2);
-                    }
-                };
-                if (MODE == 2) {
-                    // every candidate decided in FP64; the FP16 classes are only compared
-                    uint32_t all = 0;
-                    for (int it = 0; it < nit; ++it) {
-                        const int e0 = it * 128 + 2 * lane;
-                        all |= (e0 < nc ? 1u << it : 0u) | (e0 + 1 < nc ? 1u << (16 + it) : 0u);
-                    }
-                    uint32_t dec = 0;
-                    while (all) {
-                        const int bb = __builtin_ctz(all);
-                        all &= all - 1;
-                        const int e = (bb & 15) * 128 + 2 * lane + (bb >> 4);
-                        const int oj = sorig[e];
-                        if (oj == oi) continue;
-                        const bool truth = recheck(e, oj);
-                        if (truth) dec |= 1u << bb;
-                        if (!FILL) {
-                            const bool band = (bnd >> bb) & 1u;
-                            const bool in16 = (inb >> bb) & 1u;
-                            // naive FP16 test: r2 <= RN16(4 rho^2), from the staged record
-                            const uint4 A = recA[e >> 1];
-                            const uint2 B = recB[e >> 1];
-                            const h2 s = qix2 - as_h2(A.x);
-                            const h2 tx = s + as_h2(A.w);
-                            const h2 ty = (qiy2 + as_h2(B.x)) - as_h2(A.y);
-                            h2 r2;
-                            if (DIM == 3) {
-                                const h2 tz = (qiz2 + as_h2(B.y)) - as_h2(A.z);
-                                r2 = tz * tz;
-                                r2 = __builtin_elementwise_fma(ty, ty, r2);
-                            } else {
-                                r2 = ty * ty;
-                            }
-                            r2 = __builtin_elementwise_fma(tx, tx, r2);
-                            const uint16_t r2h = static_cast<uint16_t>((as_u32(r2) >> (16 * (e & 1))) & 0xFFFF);
-                            const bool naive = r2h <= tmid;
-                            tc[1] += band;
-                            tc[2] += naive && !truth;
-                            tc[3] += !naive && truth;
-                            tc[4] += !band && (in16 != truth);
+                            for (int h = 0; h < 2; ++h)
+                                if (r2_fp64<DIM>(pi, spj + (2 * m + h) * DIM) <= R2) inb |= 1u << (it + 16 * h);
                         }
                     }
-                    inb = dec;
-                } else if (MODE == 0) {
-                    uint32_t bb_all = bnd;
-                    while (bb_all) {
-                        const int bb = __builtin_ctz(bb_all);
-                        bb_all &= bb_all - 1;
-                        const int e = (bb & 15) * 128 + 2 * lane + (bb >> 4);
-                        const int oj = sorig[e];
-                        if (oj == oi) continue;  // itself (a band pair only when T_lo = 0)
-                        const bool truth = recheck(e, oj);
-                        if (truth) inb |= 1u << bb;
-                        if (!FILL) {
-                            const uint4 A = recA[e >> 1];
-                            const uint2 B = recB[e >> 1];
-                            const h2 s = qix2 - as_h2(A.x);
-                            const h2 tx = s + as_h2(A.w);
-                            const h2 ty = (qiy2 + as_h2(B.x)) - as_h2(A.y);
-                            h2 r2;
-                            if (DIM == 3) {
-                                const h2 tz = (qiz2 + as_h2(B.y)) - as_h2(A.z);
-                                r2 = tz * tz;
-                                r2 = __builtin_elementwise_fma(ty, ty, r2);
-                            } else {
-                                r2 = ty * ty;
+                    bnd = ebits & ~inb;
+                    // the FP64 recheck of candidate e: from its staged position in the fill
+                    auto recheck = [&](int e, int oj) -> bool {
+                        if constexpr (FILL && F16) {
+                            double pj[3];
+#pragma unroll
+                            for (int d = 0; d < DIM; ++d) pj[d] = spj[d * K + e];
+                            return r2_fp64<DIM>(pi, pj) <= R2;
+                        } else {
+                            return recheck_g<DIM>(sd.pos, pi, oj - poff, R2);
+                        }
+                    };
+                    if (MODE == 2) {
+                        // every candidate decided in FP64; the FP16 classes are only compared
+                        uint32_t all = 0;
+                        for (int it = 0; it < nit; ++it) {
+                            const int e0 = it * 128 + 2 * lane;
+                            all |= (e0 < nc ? 1u << it : 0u) | (e0 + 1 < nc ? 1u << (16 + it) : 0u);
+                        }
+                        uint32_t dec = 0;
+                        while (all) {
+                            const int bb = __builtin_ctz(all);
+                            all &= all - 1;
+                            const int e = (bb & 15) * 128 + 2 * lane + (bb >> 4);
+                            const int oj = sorig[e];
+                            if (oj == oi) continue;
+                            const bool truth = recheck(e, oj);
+                            if (truth) dec |= 1u << bb;
+                            if (!FILL) {
+                                const bool band = (bnd >> bb) & 1u;
+                                const bool in16 = (inb >> bb) & 1u;
+                                // naive FP16 test: r2 <= RN16(4 rho^2), from the staged record
+                                const uint4 A = recA[e >> 1];
+                                const uint2 B = recB[e >> 1];
+                                const h2 s = qix2 - as_h2(A.x);
+                                const h2 tx = s + as_h2(A.w);
+                                const h2 ty = (qiy2 + as_h2(B.x)) - as_h2(A.y);
+                                h2 r2;
+                                if (DIM == 3) {
+                                    const h2 tz = (qiz2 + as_h2(B.y)) - as_h2(A.z);
+                                    r2 = tz * tz;
+                                    r2 = __builtin_elementwise_fma(ty, ty, r2);
+                                } else {
+                                    r2 = ty * ty;
+                                }
+                                r2 = __builtin_elementwise_fma(tx, tx, r2);
+                                const uint16_t r2h = static_cast<uint16_t>((as_u32(r2) >> (16 * (e & 1))) & 0xFFFF);
+                                const bool naive = r2h <= tmid;
+                                tc[1] += band;
+                                tc[2] += naive && !truth;
+                                tc[3] += !naive && truth;
+                                tc[4] += !band && (in16 != truth);
                             }
-                            r2 = __builtin_elementwise_fma(tx, tx, r2);
-                            const uint16_t r2h = static_cast<uint16_t>((as_u32(r2) >> (16 * (e & 1))) & 0xFFFF);
-                            const bool naive = r2h <= tmid;
-                            tc[1] += 1;
-                            tc[2] += naive && !truth;
-                            tc[3] += !naive && truth;
+                        }
+                        inb = dec;
+                    } else if (MODE == 0) {
+                        uint32_t bb_all = bnd;
+                        while (bb_all) {
+                            const int bb = __builtin_ctz(bb_all);
+                            bb_all &= bb_all - 1;
+                            const int e = (bb & 15) * 128 + 2 * lane + (bb >> 4);
+                            const int oj = sorig[e];
+                            if (oj == oi) continue;  // itself (a band pair only when T_lo = 0)
+                            const bool truth = recheck(e, oj);
+                            if (truth) inb |= 1u << bb;
+                            if (!FILL) {
+                                const uint4 A = recA[e >> 1];
+                                const uint2 B = recB[e >> 1];
+                                const h2 s = qix2 - as_h2(A.x);
+                                const h2 tx = s + as_h2(A.w);
+                                const h2 ty = (qiy2 + as_h2(B.x)) - as_h2(A.y);
+                                h2 r2;
+                                if (DIM == 3) {
+                                    const h2 tz = (qiz2 + as_h2(B.y)) - as_h2(A.z);
+                                    r2 = tz * tz;
+                                    r2 = __builtin_elementwise_fma(ty, ty, r2);
+                                } else {
+                                    r2 = ty * ty;
+                                }
+                                r2 = __builtin_elementwise_fma(tx, tx, r2);
+                                const uint16_t r2h = static_cast<uint16_t>((as_u32(r2) >> (16 * (e & 1))) & 0xFFFF);
+                                const bool naive = r2h <= tmid;
+                                tc[1] += 1;
+                                tc[2] += naive && !truth;
+                                tc[3] += !naive && truth;
+                            }
+                        }
+                    }
+                    if (!FILL && bits) {
+                        // the decided bits, before the half-list mask; stored eight targets at
+                        // a time, so the band recheck's loads seldom wait for a store
+                        uint16_t* const cb = sbits + wv * 8 * 64;
+                        cb[(k & 7) * 64 + lane] = static_cast<uint16_t>((inb & 0x7Fu) | ((inb >> 9) & 0x3F80u));
+                        if ((k & 7) == 7 || k == nt - 1) {
+                            const int k0 = k & ~7;
+                            for (int t = 0; t <= (k & 7); ++t) a.dbits[bit_index(k0 + t)] = cb[t * 64 + lane];
                         }
                     }
                 }
@@ -2206,93 +2360,7 @@ k_dense(SearchArgs a)
                     const int tot = static_cast<int>(wave_sum_u64(static_cast<unsigned long long>(__builtin_popcount(inb))));
                     if (lane == k) acc_k += tot;
                 } else {
-                    // ascending emission: candidate order is original-index order. Each
-                    // group of 128 candidates (two per lane) appends its accepted ones to the
-                    // wavefront's queue in LDS, a lane's queue position being the queue's tail
-                    // plus the accepted candidates of lower lanes (ballot prefix); whenever 64
-                    // are queued, lane i takes queue entry i, computes its distance and writes
-                    // it to the row's next slot, so every store covers 64 consecutive slots
-                    // with all lanes active. The rest is written when the chunk ends.
-                    const long long rs = rl64(rs_k, k);
-                    const int rl = rl32(rl_k, k);
-                    const int done = rl32(acc_k, k);
-                    const bool room = rs + rl <= sd.capacity;
-                    const double* pis = pi;
-                    int w = done;  // CSR entries of this row written so far
-                    // the row's output, wave-uniform: entries are addressed by a 32-bit slot
-                    NNPS_GLOBAL int32_t* const rcol = uniform_ptr(sd.col + rs);
-                    NNPS_GLOBAL float* const rdist = uniform_ptr(sd.dist + rs);
-                    auto emit = [&](int e, int slot, int oj) {
-                        if (slot < rl && room) {
-                            float dv;
-                            if (F16) {
-                                // the FP64 displacement rounded once to FP32 per axis
-                                float s2 = 0.0f;
-#pragma unroll
-                                for (int d = 0; d < DIM; ++d) {
-                                    const float f = static_cast<float>(spj[d * K + e] - pi[d]);
-                                    s2 = s2 + f * f;
-                                }
-                                dv = __builtin_amdgcn_sqrtf(s2);
-                            } else {
-                                dv = static_cast<float>(__dsqrt_rn(r2_fp64<DIM>(pis, spj + e * DIM)));
-                            }
-                            if (rl <= (1 << 30)) {  // byte offsets within the row fit 32 bits
-                                const uint32_t off = static_cast<uint32_t>(slot) * 4u;
-                                *(NNPS_GLOBAL int32_t*)((NNPS_GLOBAL char*)rcol + off) = oj - poff;
-                                *(NNPS_GLOBAL float*)((NNPS_GLOBAL char*)rdist + off) = dv;
-                            } else {
-                                rcol[slot] = oj - poff;
-                                rdist[slot] = dv;
-                            }
-                        }
-                    };
-                    // the target itself is never its own neighbour and half lists keep only
-                    // larger original indices: the union is in original-index order, so both
-                    // are a condition on the chunk position against the target's own, p
-                    const int p = sself[wv + 4 * k] - c0;
-                    uint32_t keep = inb;
-                    if (a.half) {
-                        // lane bits: it for position it*128 + 2 lane, 16 + it for the next one
-                        const int a0 = p - 2 * lane, a1 = a0 - 1;
-                        const uint32_t m0 = a0 < 0 ? 0xFFFFu : (0xFFFEu << min(a0 >> 7, 15)) & 0xFFFFu;
-                        const uint32_t m1 = a1 < 0 ? 0xFFFFu : (0xFFFEu << min(a1 >> 7, 15)) & 0xFFFFu;
-                        keep &= m0 | (m1 << 16);
-                    } else if (p >= 0 && p < nc && lane == ((p >> 1) & 63)) {
-                        keep &= ~(1u << ((p >> 7) + 16 * (p & 1)));
-                    }
-                    uint16_t* const q = squeue + wv * QCAP;
-                    int qh = 0, qt = 0;  // queue head and tail (wave-uniform, never wrapped)
-                    // writes the cnt (<= 64) entries at the queue's head to slots w, w + 1, ...
-                    auto flush = [&](int cnt) {
-                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                        if (lane < cnt) {
-                            const int e = q[(qh + lane) & (QCAP - 1)];
-                            emit(e, w + lane, sorig[e]);
-                        }
-                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                        qh += cnt;
-                        w += cnt;
-                    };
-                    for (int it = 0; it < nit; ++it) {
-                        const uint32_t b0 = (keep >> it) & 1u, b1 = (keep >> (16 + it)) & 1u;
-                        const uint64_t B0 = __ballot(b0);
-                        const uint64_t B1 = __ballot(b1);
-                        if ((B0 | B1) == 0) continue;
-                        // at most 63 queued before and 128 added: the queue never overruns
-                        uint32_t pre = __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(B0), static_cast<uint32_t>(qt));
-                        pre = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(B0 >> 32), pre);
-                        pre = __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(B1), pre);
-                        pre = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(B1 >> 32), pre);
-                        const int e0 = it * 128 + 2 * lane;
-                        if (b0) q[pre & (QCAP - 1)] = static_cast<uint16_t>(e0);
-                        if (b1) q[(pre + b0) & (QCAP - 1)] = static_cast<uint16_t>(e0 + 1);
-                        qt += __popcll(B0) + __popcll(B1);
-                        while (qt - qh >= 64) flush(64);
-                    }
-                    if (qt > qh) flush(qt - qh);
-                    if (!room && lane == 0 && w > done) atomicOr(a.err, kErrCapacity);
-                    if (lane == k) acc_k = w;
+                    fill_row(k, inb, pi);
                 }
             }
         }

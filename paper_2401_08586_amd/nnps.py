@@ -60,11 +60,11 @@ class Stats(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("block_target", ctypes.c_int32), ("long_rows_grid", ctypes.c_int32),
                 ("long_rows_keys", ctypes.c_int32), ("dense_min_union", ctypes.c_int32),
-                ("dense_grid", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("dense_grid", ctypes.c_int32), ("dense_bits_mib", ctypes.c_int32),
                 ("dense_max_entries", ctypes.c_int64)]
 
     NAMES = ("block_target", "long_rows_grid", "long_rows_keys", "dense_min_union", "dense_grid",
-             "dense_max_entries")
+             "dense_bits_mib", "dense_max_entries")
 
 
 EXPORTS = ["nnps_status_str", "nnps_validate", "nnps_grid", "nnps_ctx_create", "nnps_ctx_destroy",
@@ -217,9 +217,10 @@ class Context:
             pass
 
     def set_tuning(self, block_target: int = 80, long_rows_grid: int = 1024, long_rows_keys: int = 0,
-                   dense_min_union: int = 0, dense_grid: int = 0, dense_max_entries: int = 0):
+                   dense_min_union: int = 0, dense_grid: int = 0, dense_max_entries: int = 0,
+                   dense_bits_mib: int = 0):
         t = Tuning(int(block_target), int(long_rows_grid), int(long_rows_keys), int(dense_min_union),
-                   int(dense_grid), 0, int(dense_max_entries))
+                   int(dense_grid), int(dense_bits_mib), int(dense_max_entries))
         _check(self._lib.nnps_ctx_set_tuning(self._ctx, ctypes.byref(t)), "nnps_ctx_set_tuning")
 
     def get_tuning(self) -> dict:

@@ -150,3 +150,49 @@ def test_dense_batch_and_graph_replays(ctx):
         gcells.close()
     finally:
         ctx.set_tuning()
+
+
+def upper(rp, col, dist):
+    """The oracle's CSR restricted to entries j > i (half lists)."""
+    n = len(rp) - 1
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    keep = col > rows
+    hrp = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows[keep], minlength=n), out=hrp[1:])
+    return hrp, col[keep], dist[keep]
+
+
+@pytest.mark.parametrize("mode", [nnps.MODE_FP16_RCLL, nnps.MODE_RECHECK_ALL], ids=["fp16", "recheck_all"])
+@pytest.mark.parametrize("half", [False, True], ids=["full", "half"])
+def test_dense_kept_bits(ctx, mode, half):
+    """The FP16 dense count keeps its accepted bits for the fill once a call that
+    synchronised has sized the scratch: on one structure the first search tests again in
+    the fill (no scratch yet) and the second takes the kept bits; a bound too small for
+    them (1 MiB, for a structure of several MiB) and the bits switched off (-1) test
+    again. Every result is the oracle's, with the same statistics."""
+    ps = W.clustered(60000, 43, dim=3)
+    want = oracle.search_ps(ps)
+    if half:
+        want = upper(*want)
+    pos = torch.from_numpy(np.ascontiguousarray(ps.pos)).cuda()
+    ref = None
+    for mib in (0, 1, -1):
+        ctx.set_tuning(dense_min_union=1, dense_bits_mib=mib)
+        try:
+            cells = ctx.cells()
+            cells.set_half(half)
+            for rep in range(3):
+                name = f"bits{mib}_rep{rep}_m{mode}_h{int(half)}"
+                print(f"[gpu] dense kept bits {name}", flush=True)
+                rp, col, dist, _ = nnps.search(pos, ps.lo, ps.hi, ps.cell_size, ps.radius, mode=mode, ctx=ctx,
+                                               cells=cells)
+                check((rp.cpu().numpy(), col.cpu().numpy(), dist.cpu().numpy(), None), want, mode, name)
+                st = cells.stats()
+                assert st["dense_rows"] > 0 and st["outside_band_disagree"] == 0, name
+                if ref is None:
+                    ref = st
+                for k in STAT_KEYS:
+                    assert st[k] == ref[k], (name, k, st[k], ref[k])
+            cells.close()
+        finally:
+            ctx.set_tuning()
