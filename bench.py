@@ -31,13 +31,13 @@ HBM_PEAK_GBS = 8000.0
 #   FETCH_SIZE / WRITE_SIZE (KiB): the copy reads 262,144 KiB fetched and 524,288 KiB
 #     written for 524,288 KiB moved each way, so they scale by 2.000 and 1.000.
 # Reported only while the source is unchanged (the counters belong to that code).
-FILL_TRAFFIC = {"source_sha256_16": "f02e3c28ced6173d", "dram_read_bytes": 220.3e6, "dram_write_bytes": 487.1e6,
-                "fetch_kib": 108471, "write_kib": 475827, "fetch_scale": 2.0, "write_scale": 1.0}
+FILL_TRAFFIC = {"source_sha256_16": "00af0aadfd72fcfb", "dram_read_bytes": 220.2e6, "dram_write_bytes": 487.1e6,
+                "fetch_kib": 108450, "write_kib": 475732, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 # VALU wave-instructions per launch (SQ_INSTS_VALU) of the C2 search kernels, from the
 # profile of the same source; like the traffic, reported only while the source is unchanged
-VALU_INSTS = {"source_sha256_16": "f02e3c28ced6173d", "k_fill<3,0>": 136443896, "k_count16<3,0,false>": 129011482}
+VALU_INSTS = {"source_sha256_16": "00af0aadfd72fcfb", "k_fill<3,0>": 136444504, "k_count16<3,0,false>": 129010668}
 
 
 def valu_ceilings():
@@ -430,6 +430,7 @@ def bench_update(ps, pos, steps, warmup, rebuild_ms, rebuild_phases, frac=0.05):
     col = torch.empty(cap, dtype=torch.int32, device="cuda")
     dist = torch.empty(cap, dtype=torch.float32, device="cuda")
     cells.fill(rp, col, dist)
+    torch.cuda.synchronize()  # the steps below rewrite this structure on another stream
     stream = torch.cuda.Stream()
     cells.set_graphs(True)
     k = 0
@@ -530,6 +531,7 @@ def bench_gradient(ctx_grad_ps, pos, steps):
     nnz = int(col.numel())
     f = (pos[:, 0] ** 3).contiguous()
     h = ps.radius / 2.0
+    torch.cuda.synchronize()  # the list is written on the null stream, read on another
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         nnps.sph_gradient(pos, f, h, rp, col, ctx=ctx, stream=stream)

@@ -31,7 +31,12 @@
  * its stream.
  *
  * Streams: `stream` is a hipStream_t (NULL = the null stream). Every call is
- * stream-ordered and returns without waiting, except where stated. Errors the
+ * stream-ordered and returns without waiting, except where stated. A cell
+ * structure's device arrays are rewritten by every build and read by every pass:
+ * calls on one structure made on different streams must be ordered by the caller
+ * (an event, or a synchronisation), like any other stream-ordered work on shared
+ * memory; a build queued on a non-blocking stream while a pass of the previous
+ * search still runs on another stream corrupts that pass. Errors the
  * device detects (positions outside the box, an output buffer too small) are
  * recorded on the device and reported by the next call that synchronises
  * (nnps_count with a host nnz pointer, nnps_stats_get, nnps_search).

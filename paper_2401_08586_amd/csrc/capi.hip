@@ -367,6 +367,19 @@ size_t dense_bits_bound(const nnps_cells* c)
     return static_cast<size_t>(mib) << 20;
 }
 
+// Sorted FP64 positions: always in the FP64 and FP32 modes; in the FP16 modes while the
+// dense-cell path runs (its fill stages the candidates' positions from them, contiguous in
+// sorted order, instead of gathering them by original index). The pack and the search
+// passes of one step see the same answer unless a synchronising call in between finds
+// that the dense cells are gone; the dense fill then gathers from the caller's positions.
+double* spos_of(const nnps_cells* c)
+{
+    if (uses_spos(c->mode)) return c->spos.as<double>();
+    if (c->dense && c->dense_seen != 0 && c->spos.p && c->spos.cap >= static_cast<size_t>(c->ntot) * 4 * sizeof(double))
+        return c->spos.as<double>();
+    return nullptr;
+}
+
 Launch launch_of(const nnps_cells* c)
 {
     Launch L{};
@@ -391,7 +404,7 @@ SearchArgs args_of(const nnps_cells* c)
     a.perm = c->perm;
     a.cell_start = c->cell_start.as<int>();
     a.q4 = c->q4.as<ushort4>();
-    a.spos = uses_spos(c->mode) ? c->spos.as<double>() : nullptr;
+    a.spos = spos_of(c);
     a.rq = c->mode == NNPS_MODE_FP32_RCLL ? c->rq.as<float4>() : nullptr;
     a.X = c->X.as<double>();
     a.bstart = c->bstart.as<int>();
@@ -559,7 +572,7 @@ nnps_status prepare(nnps_ctx* ctx, nnps_cells* c, int nsets, const nnps_problem*
         {&c->k0, nn * 4}, {&c->k1, nn * 4}, {&c->v0, nn * 4}, {&c->v1, nn * 4},
         {&c->cell_count, (nc + 1) * 4}, {&c->cell_start, (nc + 1) * 4},
         {&c->q4, nn * sizeof(ushort4)},
-        {&c->spos, base ? nn * 4 * sizeof(double) : 0},
+        {&c->spos, (base || (c->dense && c->dense_seen != 0)) ? nn * 4 * sizeof(double) : 0},
         {&c->rq, c->mode == NNPS_MODE_FP32_RCLL ? nn * sizeof(float4) : 0},
         {&c->boff, (static_cast<size_t>(c->nrows_tot) + 1) * 4}, {&c->bstart, (nn + 2) * 4}, {&c->bset, (nn + 1) * 4},
         {&c->counts, nn * 4}, {&c->counts_s, nn * 4}, {&c->rsort, nn * 8},
@@ -635,7 +648,7 @@ nnps_status enqueue_update(nnps_cells* c, hipStream_t s)
     tm.end(NNPS_PHASE_SORT, s);
     tm.begin(NNPS_PHASE_PACK, s);
     HIP_TRY(launch_pack(L, u.skey2, u.perm2, c->X.as<double>(), c->q4.as<ushort4>(),
-                        uses_spos(c->mode) ? c->spos.as<double>() : nullptr,
+                        spos_of(c),
                         c->mode == NNPS_MODE_FP32_RCLL ? c->rq.as<float4>() : nullptr,
                         c->inv.as<int>(), s, c->skey, c->perm));
     tm.end(NNPS_PHASE_PACK, s);
@@ -666,7 +679,7 @@ nnps_status enqueue_build(nnps_cells* c, hipStream_t s)
     c->perm = vf;
     tm.begin(NNPS_PHASE_PACK, s);
     HIP_TRY(launch_pack(L, c->skey, c->perm, c->X.as<double>(), c->q4.as<ushort4>(),
-                        uses_spos(c->mode) ? c->spos.as<double>() : nullptr,
+                        spos_of(c),
                         c->mode == NNPS_MODE_FP32_RCLL ? c->rq.as<float4>() : nullptr,
                         c->inv.as<int>(), s));
     tm.end(NNPS_PHASE_PACK, s);

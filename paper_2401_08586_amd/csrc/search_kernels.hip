@@ -2024,7 +2024,8 @@ k_dense(SearchArgs a)
                         sorig[e] = oj;
 #pragma unroll
                         for (int k = 0; k < DIM; ++k)
-                            spj[k * K + e] = sd.pos[static_cast<size_t>(oj - poff) * DIM + k];
+                            spj[k * K + e] = a.spos ? a.spos[static_cast<size_t>(j) * 4 + k]
+                                                    : sd.pos[static_cast<size_t>(oj - poff) * DIM + k];
                         if (j >= t0 && j < t1) sself[j - t0] = c0 + e;  // a target of this unit
                     } else {
                         sorig[e] = -1;
@@ -2059,7 +2060,8 @@ k_dense(SearchArgs a)
                             if (FILL) {
 #pragma unroll
                                 for (int k = 0; k < DIM; ++k)
-                                    spj[k * K + e] = sd.pos[static_cast<size_t>(oj - poff) * DIM + k];
+                                    spj[k * K + e] = a.spos ? a.spos[static_cast<size_t>(j) * 4 + k]
+                                                        : sd.pos[static_cast<size_t>(oj - poff) * DIM + k];
                                 if (j >= t0 && j < t1) sself[j - t0] = c0 + e;  // a target of this unit
                             }
                         } else {
