@@ -284,11 +284,13 @@ hipError_t scan_exclusive(const TIn* in, int64_t m, TOut* out, int64_t* partial,
 int64_t scan_partials_needed(int64_t m) { return (m + kScanTile - 1) / kScanTile + 1; }
 
 // ---------------------------------------------------------------------------
-// A2: stable LSD radix sort of (key, index) pairs, up to 11 bits per pass.
-// Tiles of kRsTile keys; each wave of a tile owns 1024 consecutive keys and ranks
-// them 64 at a time: lanes holding the same digit find each other with one ballot
-// per digit bit, and a per-wave LDS counter per digit keeps the order of rounds.
+// A2: stable LSD radix sort of (key, index) pairs (the dense cells' union lists), up to
+// 8 bits per pass. Tiles of kRsTile keys; each wave of a tile owns 1024 consecutive keys
+// and ranks them 64 at a time: lanes holding the same digit find each other with one
+// ballot per digit bit, and a per-wave LDS counter per digit keeps the order of rounds.
 // Tile order, then wave, then round, then lane equals index order: the sort is stable.
+// The tile is put in output order in LDS first, so a digit's run is written by
+// consecutive threads.
 constexpr int kRsThreads = 256;
 constexpr int kRsRounds = 16;
 constexpr int kRsTile = kRsThreads * kRsRounds;
@@ -330,11 +332,19 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const int* __restrict__ vin,
         if (*ndev == 0) return;
         n = min(n, *ndev);
     }
-    __shared__ uint32_t cw[kRsThreads / 64][1 << kRsMaxBits];
-    const int bins = 1 << bits;
+    if (blockIdx.x * kRsTile >= n) return;  // a tile past the keys (the grid is sized for a bound)
+    constexpr int MB = 1 << kRsPassBits;
+    constexpr int NWV = kRsThreads / 64;
+    static_assert(MB <= kRsThreads, "one thread per digit in the tile's digit scan");
+    __shared__ uint32_t cw[NWV][MB];
+    __shared__ uint32_t tstart[MB];  // the tile's first position of each digit
+    __shared__ uint32_t wtot[NWV];
+    __shared__ uint32_t sk[kRsTile];  // the tile's keys and values in output order
+    __shared__ int sv[kRsTile];
+    const int bins = 1 << bits;  // bits <= kRsPassBits
     const uint32_t mask = bins - 1;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int i = threadIdx.x; i < (kRsThreads / 64) * bins; i += kRsThreads) cw[i / bins][i % bins] = 0;
+    for (int i = threadIdx.x; i < NWV * MB; i += kRsThreads) cw[i / MB][i % MB] = 0;
     __syncthreads();
     const int base = blockIdx.x * kRsTile + w * (kRsRounds * 64);
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -365,25 +375,49 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const int* __restrict__ vin,
         rank[r] = b0 + rnk;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < bins; i += kRsThreads) {
-        uint32_t run = 0;
+    // per digit: each wavefront's offset inside the tile's run of that digit, and the run's
+    // length; then the runs' starts (exclusive scan over the digits, one thread per digit)
+    uint32_t len = 0;
+    if (threadIdx.x < bins) {
 #pragma unroll
-        for (int k = 0; k < kRsThreads / 64; ++k) {
-            const uint32_t t = cw[k][i];
-            cw[k][i] = run;
-            run += t;
+        for (int k = 0; k < NWV; ++k) {
+            const uint32_t t = cw[k][threadIdx.x];
+            cw[k][threadIdx.x] = len;
+            len += t;
         }
     }
+    uint32_t inc = len;  // inclusive scan inside the wavefront
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) wtot[w] = inc;
     __syncthreads();
+    uint32_t before = 0;
+    for (int k = 0; k < w; ++k) before += wtot[k];
+    if (threadIdx.x < bins) tstart[threadIdx.x] = before + inc - len;
+    __syncthreads();
+    // the tile in output order, in LDS
 #pragma unroll
     for (int r = 0; r < kRsRounds; ++r) {
         const int idx = base + r * 64 + lane;
         if (idx < n) {
             const uint32_t d = (myk[r] >> shift) & mask;
-            const uint32_t p = offs[static_cast<size_t>(d) * ntiles + blockIdx.x] + cw[w][d] + rank[r];
-            kout[p] = myk[r];
-            vout[p] = myv[r];
+            const uint32_t lp = tstart[d] + cw[w][d] + rank[r];
+            sk[lp] = myk[r];
+            sv[lp] = myv[r];
         }
+    }
+    __syncthreads();
+    // consecutive threads write consecutive positions of a digit's run
+    const int nvalid = min(kRsTile, n - static_cast<int>(blockIdx.x) * kRsTile);
+    for (int i = threadIdx.x; i < nvalid; i += kRsThreads) {
+        const uint32_t k = sk[i];
+        const uint32_t d = (k >> shift) & mask;
+        const uint32_t p = offs[static_cast<size_t>(d) * ntiles + blockIdx.x] + (static_cast<uint32_t>(i) - tstart[d]);
+        kout[p] = k;
+        vout[p] = sv[i];
     }
 }
 
@@ -938,6 +972,7 @@ hipError_t radix_sort_kv_dev(int n, const int* ndev, int keybits, uint32_t* k0, 
     const int ntiles = radix_tiles(n);
     const int passes = keybits <= 0 ? 1 : (keybits + kRsPassBits - 1) / kRsPassBits;
     const int bits = keybits <= 0 ? 1 : (keybits + passes - 1) / passes;
+    if (bits > kRsPassBits) return hipErrorInvalidValue;  // cannot happen: passes fit the bound
     uint32_t *kin = k0, *kout = k1;
     int *vin = v0, *vout = v1;
     for (int p = 0; p < passes; ++p) {
