@@ -855,28 +855,30 @@ k_dense_unit_cells(int ncell_tot, const int* __restrict__ nsl, const int* __rest
     for (int s = 0; s < k; ++s) ucell[u0 + s] = g;
 }
 
-// Visit the dense cells whose stencil holds the particle at sorted position j.
+// Visit the dense cells whose stencil holds the particle at sorted position j. The 3^d
+// stencil sizes are loaded together first (cells outside the grid read as 0), then the
+// dense ones are visited in x-fastest order.
 template <int DIM, typename F>
 __device__ __forceinline__ void for_dense_stencils(const SetDesc* __restrict__ sets, const int* __restrict__ coffs,
                                                    int nsets, const uint32_t* __restrict__ skey,
                                                    const int* __restrict__ usz, int j, F&& f)
 {
+    constexpr int NS = DIM == 3 ? 27 : 9;
     const int gk = static_cast<int>(skey[j]);
     const SetDesc& sd = sets[find_set(coffs, nsets, gk)];
     const CellXYZ c(sd.fr, gk - sd.coff);
-    for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz) {
-        const int zz = c.z + dz;
-        if (zz < 0 || zz >= c.ncz) continue;
-        for (int dy = -1; dy <= 1; ++dy) {
-            const int yy = c.y + dy;
-            if (yy < 0 || yy >= c.ncy) continue;
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int xx = c.x + dx;
-                if (xx < 0 || xx >= c.ncx) continue;
-                const int g2 = gk + dx + c.ncx * (dy + c.ncy * dz);
-                if (usz[g2] > 0) f(g2);
-            }
-        }
+    int sz[NS];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = DIM == 3 ? t / 9 - 1 : 0;
+        const int xx = c.x + dx, yy = c.y + dy, zz = c.z + dz;
+        const bool in = xx >= 0 && xx < c.ncx && yy >= 0 && yy < c.ncy && zz >= 0 && zz < c.ncz;
+        sz[t] = in ? usz[gk + dx + c.ncx * (dy + c.ncy * dz)] : 0;
+    }
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = DIM == 3 ? t / 9 - 1 : 0;
+        if (sz[t] > 0) f(gk + dx + c.ncx * (dy + c.ncy * dz));
     }
 }
 
