@@ -192,3 +192,30 @@ def test_batch_global_indices_past_the_packed_key_range(ctx):
     lens = np.diff(rpc)
     assert set(down.tolist()) <= set(rpc[1:-1][lens[1:] > 0].tolist())
     cells.close()
+
+
+def test_autotune_on_the_gpu(ctx, tmp_path):
+    """The autotuner on a small clustered batch: coordinate descent over a reduced space
+    times real graph-free steps on the GPU, leaves its choice on the context, and the
+    search with the chosen shapes gives the oracle's lists; a second call with the same
+    cache file takes the cached choice without timing anything."""
+    from paper_2401_08586_amd import autotune as A
+    pss = [W.clustered(n, 70 + i, dim=3) for i, n in enumerate([4000, 12000, 30000])]
+    sets = as_sets(pss)
+    space = {"block_target": [48, 80], "dense_min_union": [1, 512, -1], "dense_grid": [256, 2048]}
+    path = str(tmp_path / "tune.json")
+    try:
+        print("[gpu] autotune", flush=True)
+        best, ms, evals = A.tune(ctx, sets, pss, nnps.MODE_FP16_RCLL, steps=2, warmup=1, space=space,
+                                 cache=A.Cache(path), sweeps=1)
+        assert evals >= 2 and ms > 0
+        for k, vals in space.items():
+            assert best[k] in vals or best[k] == A.DEFAULTS[k]
+            assert ctx.get_tuning()[k] == best[k]
+        res, _ = nnps.search_batch(sets, ctx=ctx)
+        for r, p in zip(res, pss):
+            check(r, p, nnps.MODE_FP16_RCLL, f"tuned_{p.name}")
+        best2, ms2, evals2 = A.tune(ctx, sets, pss, nnps.MODE_FP16_RCLL, space=space, cache=A.Cache(path))
+        assert best2 == best and evals2 == 0 and ms2 is None
+    finally:
+        ctx.set_tuning()
