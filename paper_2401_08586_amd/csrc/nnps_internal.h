@@ -36,7 +36,7 @@ constexpr int kDenseChunk = 1024;
 constexpr int kDenseChunkF16 = 896;
 // Default bound on the device scratch for those bits (MiB).
 constexpr int kDenseBitsMiB = 16384;
-constexpr int kDenseQueue = 256;  // per-wavefront queue of accepted candidates (power of two)
+constexpr int kDenseQueue = 512;  // per-wavefront queue of a row's accepted candidates in a chunk
 constexpr int kDenseThreads = 256;
 constexpr int kDenseSlice = 256;
 constexpr int kDenseUnion3 = 512;

@@ -1928,7 +1928,7 @@ k_dense(SearchArgs a)
     constexpr int K = F16 ? kDenseChunkF16 : kDenseChunk;
     constexpr int QCAP = kDenseQueue;
     static_assert(K % 128 == 0 && K <= 2048, "whole 128-candidate groups, chunk positions fit 16 bits");
-    static_assert((QCAP & (QCAP - 1)) == 0 && QCAP >= 63 + 128, "a queue holds 63 entries plus a group");
+    static_assert(QCAP >= 64 && K <= 65536, "a queue holds a full store; chunk positions fit 16 bits");
     static_assert(!F16 || K / 128 <= 7, "a lane's accepted bits of a chunk fit 14 bits");
     static_assert(!F16 || sizeof(uint4) * (K / 2) >= (kDenseThreads / 64) * 8 * 64 * sizeof(uint16_t),
                   "the record table holds eight targets' bits per wavefront");
@@ -1939,7 +1939,8 @@ k_dense(SearchArgs a)
     __shared__ double sdbl[(!F16 || FILL) ? K * DIM : 1];
     double* const spj = sdbl;
     __shared__ unsigned long long s_red[FILL ? 1 : kDenseThreads / 64][kDenseStats];  // count pass only
-    // fill: per-wavefront circular queues of accepted candidates (chunk positions, in row order)
+    // fill: per-wavefront queues of a row's accepted candidates in a chunk (chunk positions,
+    // in row order)
     __shared__ uint16_t squeue[FILL ? (kDenseThreads / 64) * QCAP : 1];
     // FP16 count keeping its bits: eight targets' bit words per wavefront, stored together
     __shared__ uint16_t sbits[(!FILL && F16) ? (kDenseThreads / 64) * 8 * 64 : 1];
@@ -2013,6 +2014,10 @@ k_dense(SearchArgs a)
         }
         for (int c0 = 0; c0 < U; c0 += K) {
             const int nc = min(K, U - c0);
+            // lane L tests the chunk's candidates 2 L nit ... 2 (L + 1) nit - 1, pair by pair
+            // (pair L nit + it at iteration it), so a target's accepted candidates come out
+            // in order lane by lane
+            const int nit = (nc + 127) >> 7;
             __syncthreads();
             // stage the chunk (padding tests as +inf / far away: never a neighbour)
             if (F16 && FILL && bits) {
@@ -2032,7 +2037,9 @@ k_dense(SearchArgs a)
                     }
                 }
             } else if (F16) {
-                for (int m = threadIdx.x; m < K / 2; m += kDenseThreads) {
+                // pair m goes to record slot (m mod nit) 64 + m / nit: the test reads slot
+                // it 64 + lane, consecutive lanes, at iteration it
+                for (int m = threadIdx.x; m < 64 * nit; m += kDenseThreads) {
                     uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0;
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
@@ -2069,8 +2076,9 @@ k_dense(SearchArgs a)
                             sorig[e] = -1;
                         }
                     }
-                    recA[m] = make_uint4(w0, w1, w2, w3);
-                    recB[m] = make_uint2(w4, w5);
+                    const int slot = (m % nit) * 64 + m / nit;
+                    recA[slot] = make_uint4(w0, w1, w2, w3);
+                    recB[slot] = make_uint2(w4, w5);
                 }
             } else {
                 for (int e = threadIdx.x; e < K; e += kDenseThreads) {
@@ -2088,26 +2096,25 @@ k_dense(SearchArgs a)
                 }
             }
             __syncthreads();
-            const int nit = (nc + 127) >> 7;
             // bit row of target k of this wavefront in this chunk
             auto bit_index = [&](int k) {
                 return (brow + static_cast<int64_t>(4 * k) * nchunk + c0 / K) * 64 + lane;
             };
-            // the fill's emission of target k's accepted bits in this chunk
-            auto fill_row = [&](int k, uint32_t inb, const double* pi) {
-                // ascending emission: candidate order is original-index order. Each
-                // group of 128 candidates (two per lane) appends its accepted ones to the
-                // wavefront's queue in LDS, a lane's queue position being the queue's tail
-                // plus the accepted candidates of lower lanes (ballot prefix); whenever 64
-                // are queued, lane i takes queue entry i, computes its distance and writes
-                // it to the row's next slot, so every store covers 64 consecutive slots
-                // with all lanes active. The rest is written when the chunk ends.
+            // the fill's emission of target k's accepted candidates in this chunk: bit j of
+            // M is the lane's candidate 2 lane nit + j
+            auto fill_row = [&](int k, uint32_t M, const double* pi) {
+                // ascending emission: candidate order is original-index order and a lane
+                // holds a contiguous run of it, so a lane's accepted candidates go to the row's
+                // slots after those of the lanes below it (a wave prefix of the lanes' counts).
+                // They pass through the wavefront's queue in LDS, where each lane writes its
+                // own in order; then lane i takes entries i, i + 64, ..., computes their
+                // distances and writes them, so every store covers 64 consecutive slots with
+                // all lanes active
                 const long long rs = rl64(rs_k, k);
                 const int rl = rl32(rl_k, k);
                 const int done = rl32(acc_k, k);
                 const bool room = rs + rl <= sd.capacity;
                 const double* pis = pi;
-                int w = done;  // CSR entries of this row written so far
                 // the row's output, wave-uniform: entries are addressed by a 32-bit slot
                 NNPS_GLOBAL int32_t* const rcol = uniform_ptr(sd.col + rs);
                 NNPS_GLOBAL float* const rdist = uniform_ptr(sd.dist + rs);
@@ -2140,46 +2147,34 @@ k_dense(SearchArgs a)
                 // larger original indices: the union is in original-index order, so both
                 // are a condition on the chunk position against the target's own, p
                 const int p = sself[wv + 4 * k] - c0;
-                uint32_t keep = inb;
-                if (a.half) {
-                    // lane bits: it for position it*128 + 2 lane, 16 + it for the next one
-                    const int a0 = p - 2 * lane, a1 = a0 - 1;
-                    const uint32_t m0 = a0 < 0 ? 0xFFFFu : (0xFFFEu << min(a0 >> 7, 15)) & 0xFFFFu;
-                    const uint32_t m1 = a1 < 0 ? 0xFFFFu : (0xFFFEu << min(a1 >> 7, 15)) & 0xFFFFu;
-                    keep &= m0 | (m1 << 16);
-                } else if (p >= 0 && p < nc && lane == ((p >> 1) & 63)) {
-                    keep &= ~(1u << ((p >> 7) + 16 * (p & 1)));
-                }
-                uint16_t* const q = squeue + wv * QCAP;
-                int qh = 0, qt = 0;  // queue head and tail (wave-uniform, never wrapped)
-                // writes the cnt (<= 64) entries at the queue's head to slots w, w + 1, ...
-                auto flush = [&](int cnt) {
+                const int lb = 2 * lane * nit;  // the lane's first candidate
+                const int d = p - lb;
+                if (a.half) M &= d < 0 ? 0xFFFFu : (d >= 15 ? 0u : (0xFFFEu << d) & 0xFFFFu);
+                else if (p >= 0 && p < nc && d >= 0 && d < 2 * nit) M &= ~(1u << d);
+                int tot;
+                const int base = wave_excl_scan_i32(__builtin_popcount(M), &tot);
+                if (tot <= QCAP) {
+                    uint16_t* const q = squeue + wv * QCAP;
+                    int pos = base;
+                    for (uint32_t mm = M; mm; mm &= mm - 1) q[pos++] = static_cast<uint16_t>(lb + __builtin_ctz(mm));
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                    if (lane < cnt) {
-                        const int e = q[(qh + lane) & (QCAP - 1)];
-                        emit(e, w + lane, sorig[e]);
+                    for (int q0 = 0; q0 < tot; q0 += 64) {
+                        if (q0 + lane < tot) {
+                            const int e = q[q0 + lane];
+                            emit(e, done + q0 + lane, sorig[e]);
+                        }
                     }
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                    qh += cnt;
-                    w += cnt;
-                };
-                for (int it = 0; it < nit; ++it) {
-                    const uint32_t b0 = (keep >> it) & 1u, b1 = (keep >> (16 + it)) & 1u;
-                    const uint64_t B0 = __ballot(b0);
-                    const uint64_t B1 = __ballot(b1);
-                    if ((B0 | B1) == 0) continue;
-                    // at most 63 queued before and 128 added: the queue never overruns
-                    uint32_t pre = __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(B0), static_cast<uint32_t>(qt));
-                    pre = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(B0 >> 32), pre);
-                    pre = __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(B1), pre);
-                    pre = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(B1 >> 32), pre);
-                    const int e0 = it * 128 + 2 * lane;
-                    if (b0) q[pre & (QCAP - 1)] = static_cast<uint16_t>(e0);
-                    if (b1) q[(pre + b0) & (QCAP - 1)] = static_cast<uint16_t>(e0 + 1);
-                    qt += __popcll(B0) + __popcll(B1);
-                    while (qt - qh >= 64) flush(64);
+                } else {
+                    // more than the queue holds (a chunk with most candidates accepted): each
+                    // lane writes its own entries
+                    int pos = done + base;
+                    for (uint32_t mm = M; mm; mm &= mm - 1) {
+                        const int e = lb + __builtin_ctz(mm);
+                        emit(e, pos++, sorig[e]);
+                    }
                 }
-                if (qt > qh) flush(qt - qh);
+                const int w = done + tot;
                 if (!room && lane == 0 && w > done) atomicOr(a.err, kErrCapacity);
                 if (lane == k) acc_k = w;
             };
@@ -2201,7 +2196,7 @@ k_dense(SearchArgs a)
                     double pi[3];
 #pragma unroll
                     for (int d = 0; d < 3; ++d) pi[d] = rlf64(pi_k[d], k);
-                    fill_row(k, (w16 & 0x7Fu) | ((w16 & 0x3F80u) << 9), pi);
+                    fill_row(k, w16, pi);
                 }
                 continue;
             }
@@ -2220,15 +2215,17 @@ k_dense(SearchArgs a)
                         qiy2 = splat(as_f16(static_cast<uint16_t>(q01 >> 16)));
                         qiz2 = splat(as_f16(static_cast<uint16_t>(q2 & 0xFFFF)));
                     }
-                    // candidate bits: bit it for candidate it*128 + 2 lane, bit 16 + it for the one
-                    // after it; "in" and "in or band" from the sign bits of two 16-bit subtractions
+                    // candidate bits: bit it for candidate 2 (lane nit + it), bit 16 + it for the
+                    // one after it; "in" and "in or band" from the sign bits of two 16-bit
+                    // subtractions
                     uint32_t ebits = 0;
 #pragma unroll
                     for (int it = 0; it < K / 128; ++it) {
                         if (it >= nit) break;
-                        const int m = it * 64 + lane;
+                        const int m = it * 64 + lane;  // record slot of pair lane nit + it
+                        const int e0 = 2 * (lane * nit + it);
                         if (!FILL && a.half) {  // half lists: candidates of larger original index
-                            const int2 oo = *reinterpret_cast<const int2*>(&sorig[2 * m]);
+                            const int2 oo = *reinterpret_cast<const int2*>(&sorig[e0]);
                             gt |= (oo.x > oi ? 1u << it : 0u) | (oo.y > oi ? 1u << (16 + it) : 0u);
                         }
                         if (F16) {
@@ -2255,7 +2252,7 @@ k_dense(SearchArgs a)
                         } else {
 #pragma unroll
                             for (int h = 0; h < 2; ++h)
-                                if (r2_fp64<DIM>(pi, spj + (2 * m + h) * DIM) <= R2) inb |= 1u << (it + 16 * h);
+                                if (r2_fp64<DIM>(pi, spj + (e0 + h) * DIM) <= R2) inb |= 1u << (it + 16 * h);
                         }
                     }
                     bnd = ebits & ~inb;
@@ -2274,14 +2271,14 @@ k_dense(SearchArgs a)
                         // every candidate decided in FP64; the FP16 classes are only compared
                         uint32_t all = 0;
                         for (int it = 0; it < nit; ++it) {
-                            const int e0 = it * 128 + 2 * lane;
+                            const int e0 = 2 * (lane * nit + it);
                             all |= (e0 < nc ? 1u << it : 0u) | (e0 + 1 < nc ? 1u << (16 + it) : 0u);
                         }
                         uint32_t dec = 0;
                         while (all) {
                             const int bb = __builtin_ctz(all);
                             all &= all - 1;
-                            const int e = (bb & 15) * 128 + 2 * lane + (bb >> 4);
+                            const int e = 2 * (lane * nit + (bb & 15)) + (bb >> 4);
                             const int oj = sorig[e];
                             if (oj == oi) continue;
                             const bool truth = recheck(e, oj);
@@ -2290,8 +2287,8 @@ k_dense(SearchArgs a)
                                 const bool band = (bnd >> bb) & 1u;
                                 const bool in16 = (inb >> bb) & 1u;
                                 // naive FP16 test: r2 <= RN16(4 rho^2), from the staged record
-                                const uint4 A = recA[e >> 1];
-                                const uint2 B = recB[e >> 1];
+                                const uint4 A = recA[(bb & 15) * 64 + lane];
+                                const uint2 B = recB[(bb & 15) * 64 + lane];
                                 const h2 s = qix2 - as_h2(A.x);
                                 const h2 tx = s + as_h2(A.w);
                                 const h2 ty = (qiy2 + as_h2(B.x)) - as_h2(A.y);
@@ -2318,14 +2315,14 @@ k_dense(SearchArgs a)
                         while (bb_all) {
                             const int bb = __builtin_ctz(bb_all);
                             bb_all &= bb_all - 1;
-                            const int e = (bb & 15) * 128 + 2 * lane + (bb >> 4);
+                            const int e = 2 * (lane * nit + (bb & 15)) + (bb >> 4);
                             const int oj = sorig[e];
                             if (oj == oi) continue;  // itself (a band pair only when T_lo = 0)
                             const bool truth = recheck(e, oj);
                             if (truth) inb |= 1u << bb;
                             if (!FILL) {
-                                const uint4 A = recA[e >> 1];
-                                const uint2 B = recB[e >> 1];
+                                const uint4 A = recA[(bb & 15) * 64 + lane];
+                                const uint2 B = recB[(bb & 15) * 64 + lane];
                                 const h2 s = qix2 - as_h2(A.x);
                                 const h2 tx = s + as_h2(A.w);
                                 const h2 ty = (qiy2 + as_h2(B.x)) - as_h2(A.y);
@@ -2350,7 +2347,7 @@ k_dense(SearchArgs a)
                         // the decided bits, before the half-list mask; stored eight targets at
                         // a time, so the band recheck's loads seldom wait for a store
                         uint16_t* const cb = sbits + wv * 8 * 64;
-                        cb[(k & 7) * 64 + lane] = static_cast<uint16_t>((inb & 0x7Fu) | ((inb >> 9) & 0x3F80u));
+                        cb[(k & 7) * 64 + lane] = static_cast<uint16_t>(interleave8(inb & 0x007F007Fu));
                         if ((k & 7) == 7 || k == nt - 1) {
                             const int k0 = k & ~7;
                             for (int t = 0; t <= (k & 7); ++t) a.dbits[bit_index(k0 + t)] = cb[t * 64 + lane];
@@ -2362,7 +2359,7 @@ k_dense(SearchArgs a)
                     const int tot = static_cast<int>(wave_sum_u64(static_cast<unsigned long long>(__builtin_popcount(inb))));
                     if (lane == k) acc_k += tot;
                 } else {
-                    fill_row(k, inb, pi);
+                    fill_row(k, interleave8(inb), pi);
                 }
             }
         }
