@@ -85,6 +85,13 @@ __device__ __forceinline__ int wave_excl_scan_i32(int v, int* total)
     return inc - v;
 }
 
+__device__ __forceinline__ int wave_sum_i32(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 {
 #pragma unroll
@@ -2202,9 +2209,12 @@ k_dense(SearchArgs a)
             }
             for (int k = 0; k < nt; ++k) {
                 const int oi = rl32(oi_k, k);
-                double pi[3];
+                double pi[3] = {0.0, 0.0, 0.0};
+                // the FP16 count needs the target's FP64 position only for a band recheck
+                if (!F16 || FILL) {
 #pragma unroll
-                for (int d = 0; d < 3; ++d) pi[d] = rlf64(pi_k[d], k);
+                    for (int d = 0; d < 3; ++d) pi[d] = rlf64(pi_k[d], k);
+                }
                 uint32_t inb = 0, bnd = 0, gt = 0;
                 {
                     h2 qix2, qiy2, qiz2;
@@ -2263,6 +2273,11 @@ k_dense(SearchArgs a)
 #pragma unroll
                             for (int d = 0; d < DIM; ++d) pj[d] = spj[d * K + e];
                             return r2_fp64<DIM>(pi, pj) <= R2;
+                        } else if constexpr (F16) {
+                            double pt[3];
+#pragma unroll
+                            for (int d = 0; d < 3; ++d) pt[d] = rlf64(pi_k[d], k);
+                            return recheck_g<DIM>(sd.pos, pt, oj - poff, R2);
                         } else {
                             return recheck_g<DIM>(sd.pos, pi, oj - poff, R2);
                         }
@@ -2356,7 +2371,7 @@ k_dense(SearchArgs a)
                 }
                 if constexpr (!FILL) {
                     if (a.half) inb &= gt;
-                    const int tot = static_cast<int>(wave_sum_u64(static_cast<unsigned long long>(__builtin_popcount(inb))));
+                    const int tot = wave_sum_i32(__builtin_popcount(inb));
                     if (lane == k) acc_k += tot;
                 } else {
                     fill_row(k, interleave8(inb), pi);
