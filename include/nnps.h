@@ -127,7 +127,7 @@ typedef struct nnps_stats {
  *   target of that cell must test). The dense path stages each such cell's stencil
  *   union, sorted by original index, once per chunk for all of the cell's targets.
  *   0 = default (512 in 3D, 160 in 2D); -1 = never. Valid -1..2^30.
- * dense_grid: workgroups of the dense-cell kernels (persistent). 0 = default (1024).
+ * dense_grid: workgroups of the dense-cell kernels (persistent). 0 = default (1280).
  *   Valid 0..2^20.
  * dense_max_entries: bound on the summed stencil-union sizes of dense cells per build
  *   (device scratch: 16 bytes per entry, allocated as min(3^d n, bound)). Beyond it a

@@ -24,7 +24,7 @@ DEFAULTS = {"block_target": 80, "long_rows_grid": 1024, "long_rows_keys": 0, "de
 SPACE = {
     "block_target": [32, 48, 56, 64, 72, 80, 88, 96],
     "dense_min_union": [1, 128, 256, 384, 512, 768, 1024, -1],
-    "dense_grid": [256, 512, 1024, 2048, 4096],
+    "dense_grid": [256, 512, 1024, 1280, 2048, 4096],
     "long_rows_grid": [256, 1024, 4096],
 }
 

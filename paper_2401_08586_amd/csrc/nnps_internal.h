@@ -41,7 +41,7 @@ constexpr int kDenseThreads = 256;
 constexpr int kDenseSlice = 256;
 constexpr int kDenseUnion3 = 512;
 constexpr int kDenseUnion2 = 160;
-constexpr int kDenseGrid = 1024;
+constexpr int kDenseGrid = 1280;  // five workgroups on each of the 256 compute units
 constexpr int64_t kDenseMaxEntries = int64_t(1) << 28;
 constexpr int kDenseStats = 6;  // candidates, band, false pos, false neg, outside disagree, rows
 

@@ -1895,14 +1895,18 @@ hipError_t launch_long_rows(const SearchArgs& a, int grid, hipStream_t st)
 // ---------------------------------------------------------------------------
 // Dense-cell path. A work unit is up to kDenseSlice targets of one dense cell, all with
 // the same stencil union (the cell's list, ascending original index). A workgroup of
-// four wavefronts takes units from a counter; for each chunk of candidates (kDenseChunkFill
-// in the FP16 fill) it stages their FP16 pair records and original indices (and, for the
-// fill, FP64 positions) in LDS, then each wavefront runs its targets one at a time over the
-// chunk: a lane tests two consecutive candidates per packed FP16 instruction with the same
-// op sequence as the block kernels, band pairs are settled by the FP64 recheck (on the
-// staged positions in the fill), and the fill queues the accepted candidates of each
-// 128-candidate step in order (ballot prefix) and writes them 64 at a time, so
-// consecutive lanes store consecutive CSR entries and the row comes out ascending.
+// four wavefronts takes units from a counter; for each chunk of candidates (kDenseChunkF16
+// in the FP16 modes, kDenseChunk in FP64) it stages their FP16 pair records and original
+// indices (and, for the fill, FP64 positions) in LDS, then each wavefront runs its targets
+// one at a time over the chunk. Lane L tests a contiguous run of the chunk's candidates,
+// two per packed FP16 instruction with the same op sequence as the block kernels, and band
+// pairs are settled by the FP64 recheck (on the staged positions in the fill). A target's
+// accepted candidates thus come out lane by lane in row order: the fill places them with
+// one wavefront prefix sum of the lanes' counts, queues them per lane and writes them 64 at
+// a time, so consecutive lanes store consecutive CSR entries and the row comes out
+// ascending. In the FP16 modes the count keeps each lane's accepted bits of every
+// (target, chunk) when the buffer holds them; the fill then reads them back instead of
+// testing again and stages only original indices and positions.
 // Wavefront w of a unit holds targets w, w + 4, ...: lane k keeps target w + 4k's data
 // in registers, read by the whole wavefront with readlane when its turn comes.
 __device__ __forceinline__ int rl32(int v, int k) { return __builtin_amdgcn_readlane(v, k); }
@@ -1927,20 +1931,23 @@ __device__ __forceinline__ double rlf64(double v, int k)
     return __builtin_bit_cast(double, rl64(__builtin_bit_cast(long long, v), k));
 }
 
-template <int DIM, int MODE, bool FILL>
-__global__ void __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4)))
+// BITS: the FP16 fill that takes the count's kept bits. It holds no pair records, so its
+// LDS (about 30 KB) lets five workgroups share a compute unit where the passes that test
+// hold four.
+template <int DIM, int MODE, bool FILL, bool BITS = false>
+__global__ void __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(BITS ? 5 : 4)))
 k_dense(SearchArgs a)
 {
     constexpr bool F16 = MODE != 1;
+    static_assert(!BITS || (FILL && F16), "only the FP16 fill takes the count's bits");
+    constexpr bool kTest = F16 && !BITS;  // the pass tests candidates in FP16
     constexpr int K = F16 ? kDenseChunkF16 : kDenseChunk;
     constexpr int QCAP = kDenseQueue;
     static_assert(K % 128 == 0 && K <= 2048, "whole 128-candidate groups, chunk positions fit 16 bits");
     static_assert(QCAP >= 64 && K <= 65536, "a queue holds a full store; chunk positions fit 16 bits");
     static_assert(!F16 || K / 128 <= 7, "a lane's accepted bits of a chunk fit 14 bits");
-    static_assert(!F16 || sizeof(uint4) * (K / 2) >= (kDenseThreads / 64) * 8 * 64 * sizeof(uint16_t),
-                  "the record table holds eight targets' bits per wavefront");
-    __shared__ uint4 recA[F16 ? K / 2 : 1];               // qx, qy, qz, 2(c_x - c_jx) pairs
-    __shared__ uint2 recB[F16 ? K / 2 : 1];               // 2(c_y - c_jy), 2(c_z - c_jz) pairs
+    __shared__ uint4 recA[kTest ? K / 2 : 1];             // qx, qy, qz, 2(c_x - c_jx) pairs
+    __shared__ uint2 recB[kTest ? K / 2 : 1];             // 2(c_y - c_jy), 2(c_z - c_jz) pairs
     __shared__ __attribute__((aligned(16))) int sorig[K];
     // candidates' FP64 positions: [K][DIM] (baseline), axis-major [DIM][K] (FP16 fill)
     __shared__ double sdbl[(!F16 || FILL) ? K * DIM : 1];
@@ -1961,8 +1968,11 @@ k_dense(SearchArgs a)
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const int nunits = *a.dn > 0 ? a.unit_off[a.L.ncell_tot] : 0;
     // FP16: the count keeps the accepted bits of every (target, chunk) when they fit, and
-    // the fill then takes them instead of testing again
-    const bool bits = F16 && a.dbits && nunits > 0 && a.dboff[a.L.ncell_tot] * 64 <= a.dbits_cap;
+    // the fill then takes them instead of testing again. The host launches both FP16 fills;
+    // the one that does not apply returns here.
+    const bool bits_fit = F16 && a.dbits && nunits > 0 && a.dboff[a.L.ncell_tot] * 64 <= a.dbits_cap;
+    if (FILL && F16 && bits_fit != BITS) return;
+    const bool bits = FILL ? BITS : bits_fit;
     unsigned long long tc[kDenseStats] = {0, 0, 0, 0, 0, 0};
     for (;;) {
         __syncthreads();  // the previous unit is done with s_unit and the staged chunk
@@ -2027,7 +2037,7 @@ k_dense(SearchArgs a)
             const int nit = (nc + 127) >> 7;
             __syncthreads();
             // stage the chunk (padding tests as +inf / far away: never a neighbour)
-            if (F16 && FILL && bits) {
+            if constexpr (BITS) {
                 // the fill with the count's bits: original indices and FP64 positions only
                 for (int e = threadIdx.x; e < K; e += kDenseThreads) {
                     if (e < nc) {
@@ -2043,7 +2053,7 @@ k_dense(SearchArgs a)
                         sorig[e] = -1;
                     }
                 }
-            } else if (F16) {
+            } else if constexpr (F16) {
                 // pair m goes to record slot (m mod nit) 64 + m / nit: the test reads slot
                 // it 64 + lane, consecutive lanes, at iteration it
                 for (int m = threadIdx.x; m < 64 * nit; m += kDenseThreads) {
@@ -2185,196 +2195,202 @@ k_dense(SearchArgs a)
                 if (!room && lane == 0 && w > done) atomicOr(a.err, kErrCapacity);
                 if (lane == k) acc_k = w;
             };
-            if (FILL && bits) {
-                // the count's bits, loaded for eight targets at a time (waiting for a load
-                // also waits for every store issued before it, so that wait is paid once per
-                // eight rows) and kept in LDS, in the record table this path does not use;
-                // a lane reads back only what it wrote
-                uint16_t* const wbuf = reinterpret_cast<uint16_t*>(recA) + wv * 8 * 64;
+            if constexpr (BITS) {
+                // the count's bits, loaded for eight targets at a time and packed two to a
+                // register at once (waiting for a load also waits for every store issued
+                // before it, so that wait is paid once per eight rows); each row takes the
+                // low half and the rest shift down
+                uint32_t wp0 = 0, wp1 = 0, wp2 = 0, wp3 = 0;
                 for (int k = 0; k < nt; ++k) {
                     if ((k & 7) == 0) {
                         uint32_t wb[8];
 #pragma unroll
                         for (int t = 0; t < 8; ++t) wb[t] = a.dbits[bit_index(min(k + t, nt - 1))];
-#pragma unroll
-                        for (int t = 0; t < 8; ++t) wbuf[t * 64 + lane] = static_cast<uint16_t>(wb[t]);
+                        wp0 = wb[0] | (wb[1] << 16);
+                        wp1 = wb[2] | (wb[3] << 16);
+                        wp2 = wb[4] | (wb[5] << 16);
+                        wp3 = wb[6] | (wb[7] << 16);
                     }
-                    const uint32_t w16 = wbuf[(k & 7) * 64 + lane];
+                    const uint32_t w16 = wp0 & 0xFFFFu;
+                    wp0 = (wp0 >> 16) | (wp1 << 16);
+                    wp1 = (wp1 >> 16) | (wp2 << 16);
+                    wp2 = (wp2 >> 16) | (wp3 << 16);
+                    wp3 >>= 16;
                     double pi[3];
 #pragma unroll
                     for (int d = 0; d < 3; ++d) pi[d] = rlf64(pi_k[d], k);
                     fill_row(k, w16, pi);
                 }
-                continue;
-            }
-            for (int k = 0; k < nt; ++k) {
-                const int oi = rl32(oi_k, k);
-                double pi[3] = {0.0, 0.0, 0.0};
-                // the FP16 count needs the target's FP64 position only for a band recheck
-                if (!F16 || FILL) {
+            } else {
+                for (int k = 0; k < nt; ++k) {
+                    const int oi = rl32(oi_k, k);
+                    double pi[3] = {0.0, 0.0, 0.0};
+                    // the FP16 count needs the target's FP64 position only for a band recheck
+                    if (!F16 || FILL) {
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) pi[d] = rlf64(pi_k[d], k);
-                }
-                uint32_t inb = 0, bnd = 0, gt = 0;
-                {
-                    h2 qix2, qiy2, qiz2;
-                    if (F16) {
-                        const uint32_t q01 = static_cast<uint32_t>(rl32(q01_k, k));
-                        const uint32_t q2 = static_cast<uint32_t>(rl32(q2_k, k));
-                        qix2 = splat(as_f16(static_cast<uint16_t>(q01 & 0xFFFF)));
-                        qiy2 = splat(as_f16(static_cast<uint16_t>(q01 >> 16)));
-                        qiz2 = splat(as_f16(static_cast<uint16_t>(q2 & 0xFFFF)));
+                        for (int d = 0; d < 3; ++d) pi[d] = rlf64(pi_k[d], k);
                     }
-                    // candidate bits: bit it for candidate 2 (lane nit + it), bit 16 + it for the
-                    // one after it; "in" and "in or band" from the sign bits of two 16-bit
-                    // subtractions
-                    uint32_t ebits = 0;
-#pragma unroll
-                    for (int it = 0; it < K / 128; ++it) {
-                        if (it >= nit) break;
-                        const int m = it * 64 + lane;  // record slot of pair lane nit + it
-                        const int e0 = 2 * (lane * nit + it);
-                        if (!FILL && a.half) {  // half lists: candidates of larger original index
-                            const int2 oo = *reinterpret_cast<const int2*>(&sorig[e0]);
-                            gt |= (oo.x > oi ? 1u << it : 0u) | (oo.y > oi ? 1u << (16 + it) : 0u);
-                        }
+                    uint32_t inb = 0, bnd = 0, gt = 0;
+                    {
+                        h2 qix2, qiy2, qiz2;
                         if (F16) {
-                            const uint4 A = recA[m];
-                            const uint2 B = recB[m];
-                            const h2 s = qix2 - as_h2(A.x);
-                            const h2 tx = s + as_h2(A.w);
-                            const h2 ay = qiy2 + as_h2(B.x);
-                            const h2 ty = ay - as_h2(A.y);
-                            h2 r2;
-                            if (DIM == 3) {
-                                const h2 az = qiz2 + as_h2(B.y);
-                                const h2 tz = az - as_h2(A.z);
-                                r2 = tz * tz;
-                                r2 = __builtin_elementwise_fma(ty, ty, r2);
-                            } else {
-                                r2 = ty * ty;
-                            }
-                            r2 = __builtin_elementwise_fma(tx, tx, r2);
-                            const u16x2 dd = as_u16x2(as_u32(r2)) - th.tlo2;
-                            const u16x2 ee = dd - th.w12;
-                            inb |= (u16x2_bits(dd) >> (15 - it)) & (0x10001u << it);
-                            ebits |= (u16x2_bits(ee) >> (15 - it)) & (0x10001u << it);
-                        } else {
-#pragma unroll
-                            for (int h = 0; h < 2; ++h)
-                                if (r2_fp64<DIM>(pi, spj + (e0 + h) * DIM) <= R2) inb |= 1u << (it + 16 * h);
+                            const uint32_t q01 = static_cast<uint32_t>(rl32(q01_k, k));
+                            const uint32_t q2 = static_cast<uint32_t>(rl32(q2_k, k));
+                            qix2 = splat(as_f16(static_cast<uint16_t>(q01 & 0xFFFF)));
+                            qiy2 = splat(as_f16(static_cast<uint16_t>(q01 >> 16)));
+                            qiz2 = splat(as_f16(static_cast<uint16_t>(q2 & 0xFFFF)));
                         }
-                    }
-                    bnd = ebits & ~inb;
-                    // the FP64 recheck of candidate e: from its staged position in the fill
-                    auto recheck = [&](int e, int oj) -> bool {
-                        if constexpr (FILL && F16) {
-                            double pj[3];
+                        // candidate bits: bit it for candidate 2 (lane nit + it), bit 16 + it for the
+                        // one after it; "in" and "in or band" from the sign bits of two 16-bit
+                        // subtractions
+                        uint32_t ebits = 0;
 #pragma unroll
-                            for (int d = 0; d < DIM; ++d) pj[d] = spj[d * K + e];
-                            return r2_fp64<DIM>(pi, pj) <= R2;
-                        } else if constexpr (F16) {
-                            double pt[3];
-#pragma unroll
-                            for (int d = 0; d < 3; ++d) pt[d] = rlf64(pi_k[d], k);
-                            return recheck_g<DIM>(sd.pos, pt, oj - poff, R2);
-                        } else {
-                            return recheck_g<DIM>(sd.pos, pi, oj - poff, R2);
-                        }
-                    };
-                    if (MODE == 2) {
-                        // every candidate decided in FP64; the FP16 classes are only compared
-                        uint32_t all = 0;
-                        for (int it = 0; it < nit; ++it) {
+                        for (int it = 0; it < K / 128; ++it) {
+                            if (it >= nit) break;
+                            const int m = it * 64 + lane;  // record slot of pair lane nit + it
                             const int e0 = 2 * (lane * nit + it);
-                            all |= (e0 < nc ? 1u << it : 0u) | (e0 + 1 < nc ? 1u << (16 + it) : 0u);
-                        }
-                        uint32_t dec = 0;
-                        while (all) {
-                            const int bb = __builtin_ctz(all);
-                            all &= all - 1;
-                            const int e = 2 * (lane * nit + (bb & 15)) + (bb >> 4);
-                            const int oj = sorig[e];
-                            if (oj == oi) continue;
-                            const bool truth = recheck(e, oj);
-                            if (truth) dec |= 1u << bb;
-                            if (!FILL) {
-                                const bool band = (bnd >> bb) & 1u;
-                                const bool in16 = (inb >> bb) & 1u;
-                                // naive FP16 test: r2 <= RN16(4 rho^2), from the staged record
-                                const uint4 A = recA[(bb & 15) * 64 + lane];
-                                const uint2 B = recB[(bb & 15) * 64 + lane];
+                            if (!FILL && a.half) {  // half lists: candidates of larger original index
+                                const int2 oo = *reinterpret_cast<const int2*>(&sorig[e0]);
+                                gt |= (oo.x > oi ? 1u << it : 0u) | (oo.y > oi ? 1u << (16 + it) : 0u);
+                            }
+                            if (F16) {
+                                const uint4 A = recA[m];
+                                const uint2 B = recB[m];
                                 const h2 s = qix2 - as_h2(A.x);
                                 const h2 tx = s + as_h2(A.w);
-                                const h2 ty = (qiy2 + as_h2(B.x)) - as_h2(A.y);
+                                const h2 ay = qiy2 + as_h2(B.x);
+                                const h2 ty = ay - as_h2(A.y);
                                 h2 r2;
                                 if (DIM == 3) {
-                                    const h2 tz = (qiz2 + as_h2(B.y)) - as_h2(A.z);
+                                    const h2 az = qiz2 + as_h2(B.y);
+                                    const h2 tz = az - as_h2(A.z);
                                     r2 = tz * tz;
                                     r2 = __builtin_elementwise_fma(ty, ty, r2);
                                 } else {
                                     r2 = ty * ty;
                                 }
                                 r2 = __builtin_elementwise_fma(tx, tx, r2);
-                                const uint16_t r2h = static_cast<uint16_t>((as_u32(r2) >> (16 * (e & 1))) & 0xFFFF);
-                                const bool naive = r2h <= tmid;
-                                tc[1] += band;
-                                tc[2] += naive && !truth;
-                                tc[3] += !naive && truth;
-                                tc[4] += !band && (in16 != truth);
+                                const u16x2 dd = as_u16x2(as_u32(r2)) - th.tlo2;
+                                const u16x2 ee = dd - th.w12;
+                                inb |= (u16x2_bits(dd) >> (15 - it)) & (0x10001u << it);
+                                ebits |= (u16x2_bits(ee) >> (15 - it)) & (0x10001u << it);
+                            } else {
+#pragma unroll
+                                for (int h = 0; h < 2; ++h)
+                                    if (r2_fp64<DIM>(pi, spj + (e0 + h) * DIM) <= R2) inb |= 1u << (it + 16 * h);
                             }
                         }
-                        inb = dec;
-                    } else if (MODE == 0) {
-                        uint32_t bb_all = bnd;
-                        while (bb_all) {
-                            const int bb = __builtin_ctz(bb_all);
-                            bb_all &= bb_all - 1;
-                            const int e = 2 * (lane * nit + (bb & 15)) + (bb >> 4);
-                            const int oj = sorig[e];
-                            if (oj == oi) continue;  // itself (a band pair only when T_lo = 0)
-                            const bool truth = recheck(e, oj);
-                            if (truth) inb |= 1u << bb;
-                            if (!FILL) {
-                                const uint4 A = recA[(bb & 15) * 64 + lane];
-                                const uint2 B = recB[(bb & 15) * 64 + lane];
-                                const h2 s = qix2 - as_h2(A.x);
-                                const h2 tx = s + as_h2(A.w);
-                                const h2 ty = (qiy2 + as_h2(B.x)) - as_h2(A.y);
-                                h2 r2;
-                                if (DIM == 3) {
-                                    const h2 tz = (qiz2 + as_h2(B.y)) - as_h2(A.z);
-                                    r2 = tz * tz;
-                                    r2 = __builtin_elementwise_fma(ty, ty, r2);
-                                } else {
-                                    r2 = ty * ty;
+                        bnd = ebits & ~inb;
+                        // the FP64 recheck of candidate e: from its staged position in the fill
+                        auto recheck = [&](int e, int oj) -> bool {
+                            if constexpr (FILL && F16) {
+                                double pj[3];
+#pragma unroll
+                                for (int d = 0; d < DIM; ++d) pj[d] = spj[d * K + e];
+                                return r2_fp64<DIM>(pi, pj) <= R2;
+                            } else if constexpr (F16) {
+                                double pt[3];
+#pragma unroll
+                                for (int d = 0; d < 3; ++d) pt[d] = rlf64(pi_k[d], k);
+                                return recheck_g<DIM>(sd.pos, pt, oj - poff, R2);
+                            } else {
+                                return recheck_g<DIM>(sd.pos, pi, oj - poff, R2);
+                            }
+                        };
+                        if (MODE == 2) {
+                            // every candidate decided in FP64; the FP16 classes are only compared
+                            uint32_t all = 0;
+                            for (int it = 0; it < nit; ++it) {
+                                const int e0 = 2 * (lane * nit + it);
+                                all |= (e0 < nc ? 1u << it : 0u) | (e0 + 1 < nc ? 1u << (16 + it) : 0u);
+                            }
+                            uint32_t dec = 0;
+                            while (all) {
+                                const int bb = __builtin_ctz(all);
+                                all &= all - 1;
+                                const int e = 2 * (lane * nit + (bb & 15)) + (bb >> 4);
+                                const int oj = sorig[e];
+                                if (oj == oi) continue;
+                                const bool truth = recheck(e, oj);
+                                if (truth) dec |= 1u << bb;
+                                if (!FILL) {
+                                    const bool band = (bnd >> bb) & 1u;
+                                    const bool in16 = (inb >> bb) & 1u;
+                                    // naive FP16 test: r2 <= RN16(4 rho^2), from the staged record
+                                    const uint4 A = recA[(bb & 15) * 64 + lane];
+                                    const uint2 B = recB[(bb & 15) * 64 + lane];
+                                    const h2 s = qix2 - as_h2(A.x);
+                                    const h2 tx = s + as_h2(A.w);
+                                    const h2 ty = (qiy2 + as_h2(B.x)) - as_h2(A.y);
+                                    h2 r2;
+                                    if (DIM == 3) {
+                                        const h2 tz = (qiz2 + as_h2(B.y)) - as_h2(A.z);
+                                        r2 = tz * tz;
+                                        r2 = __builtin_elementwise_fma(ty, ty, r2);
+                                    } else {
+                                        r2 = ty * ty;
+                                    }
+                                    r2 = __builtin_elementwise_fma(tx, tx, r2);
+                                    const uint16_t r2h = static_cast<uint16_t>((as_u32(r2) >> (16 * (e & 1))) & 0xFFFF);
+                                    const bool naive = r2h <= tmid;
+                                    tc[1] += band;
+                                    tc[2] += naive && !truth;
+                                    tc[3] += !naive && truth;
+                                    tc[4] += !band && (in16 != truth);
                                 }
-                                r2 = __builtin_elementwise_fma(tx, tx, r2);
-                                const uint16_t r2h = static_cast<uint16_t>((as_u32(r2) >> (16 * (e & 1))) & 0xFFFF);
-                                const bool naive = r2h <= tmid;
-                                tc[1] += 1;
-                                tc[2] += naive && !truth;
-                                tc[3] += !naive && truth;
+                            }
+                            inb = dec;
+                        } else if (MODE == 0) {
+                            uint32_t bb_all = bnd;
+                            while (bb_all) {
+                                const int bb = __builtin_ctz(bb_all);
+                                bb_all &= bb_all - 1;
+                                const int e = 2 * (lane * nit + (bb & 15)) + (bb >> 4);
+                                const int oj = sorig[e];
+                                if (oj == oi) continue;  // itself (a band pair only when T_lo = 0)
+                                const bool truth = recheck(e, oj);
+                                if (truth) inb |= 1u << bb;
+                                if (!FILL) {
+                                    const uint4 A = recA[(bb & 15) * 64 + lane];
+                                    const uint2 B = recB[(bb & 15) * 64 + lane];
+                                    const h2 s = qix2 - as_h2(A.x);
+                                    const h2 tx = s + as_h2(A.w);
+                                    const h2 ty = (qiy2 + as_h2(B.x)) - as_h2(A.y);
+                                    h2 r2;
+                                    if (DIM == 3) {
+                                        const h2 tz = (qiz2 + as_h2(B.y)) - as_h2(A.z);
+                                        r2 = tz * tz;
+                                        r2 = __builtin_elementwise_fma(ty, ty, r2);
+                                    } else {
+                                        r2 = ty * ty;
+                                    }
+                                    r2 = __builtin_elementwise_fma(tx, tx, r2);
+                                    const uint16_t r2h = static_cast<uint16_t>((as_u32(r2) >> (16 * (e & 1))) & 0xFFFF);
+                                    const bool naive = r2h <= tmid;
+                                    tc[1] += 1;
+                                    tc[2] += naive && !truth;
+                                    tc[3] += !naive && truth;
+                                }
+                            }
+                        }
+                        if (!FILL && bits) {
+                            // the decided bits, before the half-list mask; stored eight targets at
+                            // a time, so the band recheck's loads seldom wait for a store
+                            uint16_t* const cb = sbits + wv * 8 * 64;
+                            cb[(k & 7) * 64 + lane] = static_cast<uint16_t>(interleave8(inb & 0x007F007Fu));
+                            if ((k & 7) == 7 || k == nt - 1) {
+                                const int k0 = k & ~7;
+                                for (int t = 0; t <= (k & 7); ++t) a.dbits[bit_index(k0 + t)] = cb[t * 64 + lane];
                             }
                         }
                     }
-                    if (!FILL && bits) {
-                        // the decided bits, before the half-list mask; stored eight targets at
-                        // a time, so the band recheck's loads seldom wait for a store
-                        uint16_t* const cb = sbits + wv * 8 * 64;
-                        cb[(k & 7) * 64 + lane] = static_cast<uint16_t>(interleave8(inb & 0x007F007Fu));
-                        if ((k & 7) == 7 || k == nt - 1) {
-                            const int k0 = k & ~7;
-                            for (int t = 0; t <= (k & 7); ++t) a.dbits[bit_index(k0 + t)] = cb[t * 64 + lane];
-                        }
+                    if constexpr (!FILL) {
+                        if (a.half) inb &= gt;
+                        const int tot = wave_sum_i32(__builtin_popcount(inb));
+                        if (lane == k) acc_k += tot;
+                    } else {
+                        fill_row(k, interleave8(inb), pi);
                     }
-                }
-                if constexpr (!FILL) {
-                    if (a.half) inb &= gt;
-                    const int tot = wave_sum_i32(__builtin_popcount(inb));
-                    if (lane == k) acc_k += tot;
-                } else {
-                    fill_row(k, interleave8(inb), pi);
                 }
             }
         }
@@ -2404,25 +2420,32 @@ k_dense(SearchArgs a)
     }
 }
 
+template <int D, int M>
+void launch_dense_pass(const SearchArgs& a, bool fill, hipStream_t st)
+{
+    const dim3 g(a.dgrid), b(kDenseThreads);
+    if (!fill) {
+        hipLaunchKernelGGL((k_dense<D, M, false>), g, b, 0, st, a);
+        return;
+    }
+    // FP16 fills: both kernels run, and the one that does not match whether the count kept
+    // its bits returns at once
+    if constexpr (M != 1) hipLaunchKernelGGL((k_dense<D, M, true, true>), g, b, 0, st, a);
+    hipLaunchKernelGGL((k_dense<D, M, true, false>), g, b, 0, st, a);
+}
+
 hipError_t launch_dense(const SearchArgs& a, bool fill, hipStream_t st)
 {
     if (a.L.ntot == 0 || !a.wdense) return hipSuccess;
     hipError_t e = launch_fill_i32(a.ucount, 1, 0, st);
     if (e != hipSuccess) return e;
-    const dim3 g(a.dgrid), b(kDenseThreads);
     const int d = a.L.dim, m = a.L.mode == 3 ? 1 : a.L.mode;  // FP32 mode: dense cells in FP64
-#define NNPS_DENSE(D, M)                                                                      \
-    do {                                                                                      \
-        if (fill) hipLaunchKernelGGL((k_dense<D, M, true>), g, b, 0, st, a);                  \
-        else hipLaunchKernelGGL((k_dense<D, M, false>), g, b, 0, st, a);                      \
-    } while (0)
-    if (d == 2 && m == 0) NNPS_DENSE(2, 0);
-    else if (d == 3 && m == 0) NNPS_DENSE(3, 0);
-    else if (d == 2 && m == 1) NNPS_DENSE(2, 1);
-    else if (d == 3 && m == 1) NNPS_DENSE(3, 1);
-    else if (d == 2) NNPS_DENSE(2, 2);
-    else NNPS_DENSE(3, 2);
-#undef NNPS_DENSE
+    if (d == 2 && m == 0) launch_dense_pass<2, 0>(a, fill, st);
+    else if (d == 3 && m == 0) launch_dense_pass<3, 0>(a, fill, st);
+    else if (d == 2 && m == 1) launch_dense_pass<2, 1>(a, fill, st);
+    else if (d == 3 && m == 1) launch_dense_pass<3, 1>(a, fill, st);
+    else if (d == 2) launch_dense_pass<2, 2>(a, fill, st);
+    else launch_dense_pass<3, 2>(a, fill, st);
     return hipGetLastError();
 }
 
