@@ -38,6 +38,7 @@ constexpr int kDenseChunkF16 = 896;
 constexpr int kDenseBitsMiB = 16384;
 constexpr int kDenseQueue = 512;  // per-wavefront queue of a row's accepted candidates in a chunk
 constexpr int kDenseThreads = 256;
+constexpr int kDenseBitsThreads = 512;  // the dense fill that takes the count's kept bits
 constexpr int kDenseSlice = 256;
 constexpr int kDenseUnion3 = 512;
 constexpr int kDenseUnion2 = 160;

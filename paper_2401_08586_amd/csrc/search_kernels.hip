@@ -1907,7 +1907,7 @@ hipError_t launch_long_rows(const SearchArgs& a, int grid, hipStream_t st)
 // ascending. In the FP16 modes the count keeps each lane's accepted bits of every
 // (target, chunk) when the buffer holds them; the fill then reads them back instead of
 // testing again and stages only original indices and positions.
-// Wavefront w of a unit holds targets w, w + 4, ...: lane k keeps target w + 4k's data
+// Wavefront w of a unit's W holds targets w, w + W, ...: lane k keeps target w + W k's data
 // in registers, read by the whole wavefront with readlane when its turn comes.
 __device__ __forceinline__ int rl32(int v, int k) { return __builtin_amdgcn_readlane(v, k); }
 // A pointer every lane holds, marked wave-uniform (scalar registers), so that stores through
@@ -1931,13 +1931,16 @@ __device__ __forceinline__ double rlf64(double v, int k)
     return __builtin_bit_cast(double, rl64(__builtin_bit_cast(long long, v), k));
 }
 
-// BITS: the FP16 fill that takes the count's kept bits. It holds no pair records, so its
-// LDS (about 30 KB) lets five workgroups share a compute unit where the passes that test
-// hold four.
+// BITS: the FP16 fill that takes the count's kept bits. It holds no pair records, so
+// eight wavefronts share one staged chunk (about 34 KB of LDS) and six wavefronts per SIMD
+// fit, where the passes that test run four wavefronts per workgroup and four or five per
+// SIMD.
 template <int DIM, int MODE, bool FILL, bool BITS = false>
-__global__ void __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(BITS ? 5 : 4)))
-k_dense(SearchArgs a)
+__global__ void __launch_bounds__(BITS ? kDenseBitsThreads : kDenseThreads)
+    __attribute__((amdgpu_waves_per_eu(BITS ? 6 : 4))) k_dense(SearchArgs a)
 {
+    constexpr int NTH = BITS ? kDenseBitsThreads : kDenseThreads;  // threads per workgroup
+    constexpr int NWV = NTH / 64;                                  // wavefronts per workgroup
     constexpr bool F16 = MODE != 1;
     static_assert(!BITS || (FILL && F16), "only the FP16 fill takes the count's bits");
     constexpr bool kTest = F16 && !BITS;  // the pass tests candidates in FP16
@@ -1955,7 +1958,7 @@ k_dense(SearchArgs a)
     __shared__ unsigned long long s_red[FILL ? 1 : kDenseThreads / 64][kDenseStats];  // count pass only
     // fill: per-wavefront queues of a row's accepted candidates in a chunk (chunk positions,
     // in row order)
-    __shared__ uint16_t squeue[FILL ? (kDenseThreads / 64) * QCAP : 1];
+    __shared__ uint16_t squeue[FILL ? NWV * QCAP : 1];
     // FP16 count keeping its bits: eight targets' bit words per wavefront, stored together
     __shared__ uint16_t sbits[(!FILL && F16) ? (kDenseThreads / 64) * 8 * 64 : 1];
     // fill: each target's position in the union (found while staging; kNotSeen before)
@@ -1995,16 +1998,16 @@ k_dense(SearchArgs a)
         const int U = a.usz[g];
         const int64_t ub = a.uoff[g];
         const int nchunk = (U + K - 1) / K;
-        // this wavefront's first (target, chunk) bit row: targets wv + 4k of the unit
+        // this wavefront's first (target, chunk) bit row: targets wv + NWV k of the unit
         const int64_t brow = bits ? a.dboff[g] + static_cast<int64_t>(slice * kDenseSlice + wv) * nchunk : 0;
         Thresh th;
         th.init(sdesc.fr);
         const uint16_t tmid = sdesc.fr.t_mid;
         const uint16_t tlo = sdesc.fr.t_lo;
         // this lane's target (held for the wavefront)
-        const int pk = t0 + wv + 4 * lane;
+        const int pk = t0 + wv + NWV * lane;
         const bool vk = pk < t1;
-        const int nt = (t1 - t0 > wv) ? (t1 - t0 - wv + 3) / 4 : 0;
+        const int nt = (t1 - t0 > wv) ? (t1 - t0 - wv + NWV - 1) / NWV : 0;
         int oi_k = 0, q01_k = 0, q2_k = 0, acc_k = 0, rl_k = 0;
         long long rs_k = 0;
         double pi_k[3] = {0, 0, 0};
@@ -2027,7 +2030,7 @@ k_dense(SearchArgs a)
             }
         }
         if (FILL) {
-            for (int t = threadIdx.x; t < kDenseSlice; t += kDenseThreads) sself[t] = kNotSeen;
+            for (int t = threadIdx.x; t < kDenseSlice; t += NTH) sself[t] = kNotSeen;
         }
         for (int c0 = 0; c0 < U; c0 += K) {
             const int nc = min(K, U - c0);
@@ -2039,7 +2042,7 @@ k_dense(SearchArgs a)
             // stage the chunk (padding tests as +inf / far away: never a neighbour)
             if constexpr (BITS) {
                 // the fill with the count's bits: original indices and FP64 positions only
-                for (int e = threadIdx.x; e < K; e += kDenseThreads) {
+                for (int e = threadIdx.x; e < K; e += NTH) {
                     if (e < nc) {
                         const int j = a.ulist[ub + c0 + e];
                         const int oj = a.perm[j];
@@ -2056,7 +2059,7 @@ k_dense(SearchArgs a)
             } else if constexpr (F16) {
                 // pair m goes to record slot (m mod nit) 64 + m / nit: the test reads slot
                 // it 64 + lane, consecutive lanes, at iteration it
-                for (int m = threadIdx.x; m < 64 * nit; m += kDenseThreads) {
+                for (int m = threadIdx.x; m < 64 * nit; m += NTH) {
                     uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0;
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
@@ -2098,7 +2101,7 @@ k_dense(SearchArgs a)
                     recB[slot] = make_uint2(w4, w5);
                 }
             } else {
-                for (int e = threadIdx.x; e < K; e += kDenseThreads) {
+                for (int e = threadIdx.x; e < K; e += NTH) {
                     if (e < nc) {
                         const int j = a.ulist[ub + c0 + e];
                         sorig[e] = a.perm[j];
@@ -2115,7 +2118,7 @@ k_dense(SearchArgs a)
             __syncthreads();
             // bit row of target k of this wavefront in this chunk
             auto bit_index = [&](int k) {
-                return (brow + static_cast<int64_t>(4 * k) * nchunk + c0 / K) * 64 + lane;
+                return (brow + static_cast<int64_t>(NWV * k) * nchunk + c0 / K) * 64 + lane;
             };
             // the fill's emission of target k's accepted candidates in this chunk: bit j of
             // M is the lane's candidate 2 lane nit + j
@@ -2163,7 +2166,7 @@ k_dense(SearchArgs a)
                 // the target itself is never its own neighbour and half lists keep only
                 // larger original indices: the union is in original-index order, so both
                 // are a condition on the chunk position against the target's own, p
-                const int p = sself[wv + 4 * k] - c0;
+                const int p = sself[wv + NWV * k] - c0;
                 const int lb = 2 * lane * nit;  // the lane's first candidate
                 const int d = p - lb;
                 if (a.half) M &= d < 0 ? 0xFFFFu : (d >= 15 ? 0u : (0xFFFEu << d) & 0xFFFFu);
@@ -2430,7 +2433,7 @@ void launch_dense_pass(const SearchArgs& a, bool fill, hipStream_t st)
     }
     // FP16 fills: both kernels run, and the one that does not match whether the count kept
     // its bits returns at once
-    if constexpr (M != 1) hipLaunchKernelGGL((k_dense<D, M, true, true>), g, b, 0, st, a);
+    if constexpr (M != 1) hipLaunchKernelGGL((k_dense<D, M, true, true>), g, dim3(kDenseBitsThreads), 0, st, a);
     hipLaunchKernelGGL((k_dense<D, M, true, false>), g, b, 0, st, a);
 }
 
