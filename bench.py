@@ -31,13 +31,13 @@ HBM_PEAK_GBS = 8000.0
 #   FETCH_SIZE / WRITE_SIZE (KiB): the copy reads 262,144 KiB fetched and 524,288 KiB
 #     written for 524,288 KiB moved each way, so they scale by 2.000 and 1.000.
 # Reported only while the source is unchanged (the counters belong to that code).
-FILL_TRAFFIC = {"source_sha256_16": "5d4fc6f272c76065", "dram_read_bytes": 220.3e6, "dram_write_bytes": 487.2e6,
-                "fetch_kib": 108462, "write_kib": 475856, "fetch_scale": 2.0, "write_scale": 1.0}
+FILL_TRAFFIC = {"source_sha256_16": "9cf6101d64cef744", "dram_read_bytes": 220.2e6, "dram_write_bytes": 487.3e6,
+                "fetch_kib": 108373, "write_kib": 475898, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 # VALU wave-instructions per launch (SQ_INSTS_VALU) of the C2 search kernels, from the
 # profile of the same source; like the traffic, reported only while the source is unchanged
-VALU_INSTS = {"source_sha256_16": "5d4fc6f272c76065", "k_fill<3,0>": 136442612, "k_count16<3,0,false>": 129009856}
+VALU_INSTS = {"source_sha256_16": "9cf6101d64cef744", "k_fill<3,0>": 136435229, "k_count16<3,0,false>": 129009217}
 
 
 def valu_ceilings():

@@ -1894,16 +1894,17 @@ hipError_t launch_long_rows(const SearchArgs& a, int grid, hipStream_t st)
 
 // ---------------------------------------------------------------------------
 // Dense-cell path. A work unit is up to kDenseSlice targets of one dense cell, all with
-// the same stencil union (the cell's list, ascending original index). A workgroup of
-// four wavefronts takes units from a counter; for each chunk of candidates (kDenseChunkF16
-// in the FP16 modes, kDenseChunk in FP64) it stages their FP16 pair records and original
-// indices (and, for the fill, FP64 positions) in LDS, then each wavefront runs its targets
-// one at a time over the chunk. Lane L tests a contiguous run of the chunk's candidates,
-// two per packed FP16 instruction with the same op sequence as the block kernels, and band
-// pairs are settled by the FP64 recheck (on the staged positions in the fill). A target's
-// accepted candidates thus come out lane by lane in row order: the fill places them with
-// one wavefront prefix sum of the lanes' counts, queues them per lane and writes them 64 at
-// a time, so consecutive lanes store consecutive CSR entries and the row comes out
+// the same stencil union (the cell's list, ascending original index). A workgroup of four
+// wavefronts (eight in the fill that takes the count's kept bits) takes units from a
+// counter; for each chunk of candidates (kDenseChunkF16 in the FP16 modes, kDenseChunk in
+// FP64) it stages their FP16 pair records and original indices (and, for the fill, FP64
+// positions) in LDS, then each wavefront runs its targets one at a time over the chunk.
+// Lane L tests a contiguous run of the chunk's candidates, two per packed FP16
+// instruction with the same op sequence as the block kernels, and band pairs are settled
+// by the FP64 recheck (on the staged positions in the fill). A target's accepted
+// candidates thus come out lane by lane in row order: the fill places them with one
+// wavefront prefix sum of the lanes' counts, queues them per lane and writes them 64 at a
+// time, so consecutive lanes store consecutive CSR entries and the row comes out
 // ascending. In the FP16 modes the count keeps each lane's accepted bits of every
 // (target, chunk) when the buffer holds them; the fill then reads them back instead of
 // testing again and stages only original indices and positions.
